@@ -1,0 +1,219 @@
+"""Seeded synthetic particle sets for the SPH density/force path.
+
+This module only draws inputs: positions, masses, internal energies,
+velocities and a first guess of the smoothing length taken from the
+analytic number density of each sampling recipe.  It holds none of the
+SPH arithmetic (no kernel, no neighbour sums) so that both the FP64 oracle
+and the GPU path can take their inputs from here without sharing method
+code.
+
+Every position is snapped to the 2^-24 grid of the periodic unit cube and
+exact duplicates are redrawn, so that any coordinate difference between two
+particles of one top-level cell is exactly representable in FP32.
+
+Recipes (all periodic unit box, equal masses m = FP32(1/N), u = 1.5):
+
+* ``uniform``   -- N uniform points (the small constant-h case).
+* ``lattice``   -- simple-cubic lattice of n^3 points, spacing 1/n, each
+                   coordinate jittered by U(-j, +j) spacings (j = 0: perfect).
+                   Stands in for the Sedov-blast lattice of Section III-B.
+* ``plummer_mixture`` -- 64 Plummer spheres (scale radius a = 10^U(-3,-1),
+                   truncated at min(20a, 0.45)) holding 80% of the particles
+                   plus a 20% uniform background.  Stands in for the
+                   cosmological volume of Section III-B (its data are not
+                   available), reproducing its ~3 decades of smoothing length.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GRID = float(2 ** 24)          # positions live on k * 2^-24
+N_NGB = 48.0                   # target neighbour number (Section III-B constants)
+U_DEFAULT = 1.5                # uniform internal energy: P = rho for gamma = 5/3
+
+
+@dataclass
+class ParticleSet:
+    """One particle set in caller order (FP64 positions, FP32-exact scalars)."""
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    m: np.ndarray
+    u: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    vz: np.ndarray
+    h0: np.ndarray              # first guess of h (FP32-exact)
+    box: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def pos(self) -> np.ndarray:
+        return np.stack([self.x, self.y, self.z], axis=1)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _f32(a) -> np.ndarray:
+    """Round to the nearest FP32 value, returned as FP64."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _snap_unique(pos: np.ndarray, redraw, rng: np.random.Generator) -> np.ndarray:
+    """Snap positions to the 2^-24 grid (mod 1) and redraw exact duplicates."""
+    for _ in range(64):
+        k = np.floor(np.mod(pos, 1.0) * GRID).astype(np.int64) % int(GRID)
+        _, first = np.unique(k, axis=0, return_index=True)
+        dup = np.ones(pos.shape[0], dtype=bool)
+        dup[first] = False
+        if not dup.any():
+            return k.astype(np.float64) / GRID
+        idx = np.nonzero(dup)[0]
+        pos = pos.copy()
+        pos[idx] = redraw(idx, rng)
+    raise RuntimeError("could not draw unique positions")
+
+
+def _finish(pos, n, rng, h0, velocity, meta) -> ParticleSet:
+    m = np.full(n, float(np.float32(1.0 / n)))
+    u = np.full(n, U_DEFAULT)
+    if velocity:
+        v = _f32(rng.uniform(-0.1, 0.1, size=(n, 3)))
+    else:
+        v = np.zeros((n, 3))
+    return ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(),
+                       m, u, v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy(),
+                       _f32(h0), 1.0, meta)
+
+
+def h_for_density(n_density, n_ngb: float = N_NGB) -> np.ndarray:
+    """Radius of a sphere holding n_ngb points at number density n_density."""
+    return np.cbrt(3.0 * n_ngb / (4.0 * math.pi * np.asarray(n_density, dtype=np.float64)))
+
+
+def uniform(n: int, seed: int, velocity: bool = False) -> ParticleSet:
+    rng = _rng(seed)
+    pos = rng.random((n, 3))
+    pos = _snap_unique(pos, lambda idx, r: r.random((idx.size, 3)), rng)
+    h = h_for_density(float(n))
+    return _finish(pos, n, rng, np.full(n, h), velocity,
+                   {"recipe": "uniform", "seed": seed})
+
+
+def lattice(n_side: int, jitter: float, seed: int, velocity: bool = False) -> ParticleSet:
+    rng = _rng(seed)
+    d = 1.0 / n_side
+    g = (np.arange(n_side) + 0.5) * d
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    base = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    n = base.shape[0]
+    if jitter > 0:
+        pos = base + rng.uniform(-jitter, jitter, size=(n, 3)) * d
+    else:
+        pos = base
+
+    def redraw(idx, r):
+        return base[idx] + r.uniform(-jitter, jitter, size=(idx.size, 3)) * d
+
+    pos = _snap_unique(pos, redraw, rng)
+    # lattice value of h for N_w = 48 is ~2.2515 spacings; start a bit off it
+    return _finish(pos, n, rng, np.full(n, 2.2 * d), velocity,
+                   {"recipe": "lattice", "n_side": n_side, "jitter": jitter, "seed": seed})
+
+
+def _plummer_radius(rng, a, rmax, size):
+    umax = rmax ** 3 / (rmax ** 2 + a ** 2) ** 1.5
+    u = rng.uniform(0.0, umax, size=size)
+    u = np.maximum(u, 1e-300)
+    return a / np.sqrt(u ** (-2.0 / 3.0) - 1.0)
+
+
+def _iso(rng, size):
+    v = rng.normal(size=(size, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def plummer_mixture(n: int, seed: int, n_clumps: int = 64, bg_frac: float = 0.2,
+                    velocity: bool = False) -> ParticleSet:
+    rng = _rng(seed)
+    n_bg = int(round(bg_frac * n))
+    n_cl = n - n_bg
+    per = np.full(n_clumps, n_cl // n_clumps, dtype=np.int64)
+    per[: n_cl - per.sum()] += 1
+    a = 10.0 ** rng.uniform(-3.0, -1.0, size=n_clumps)
+    rmax = np.minimum(20.0 * a, 0.45)
+    centre = rng.random((n_clumps, 3))
+    parts = [rng.random((n_bg, 3))]
+    owner = [np.full(n_bg, -1, dtype=np.int64)]
+    for c in range(n_clumps):
+        r = _plummer_radius(rng, a[c], rmax[c], per[c])
+        parts.append(centre[c] + r[:, None] * _iso(rng, per[c]))
+        owner.append(np.full(per[c], c, dtype=np.int64))
+    pos = np.concatenate(parts, axis=0)
+    own = np.concatenate(owner)
+
+    def redraw(idx, r):
+        out = np.empty((idx.size, 3))
+        for k, i in enumerate(idx):
+            c = own[i]
+            if c < 0:
+                out[k] = r.random(3)
+            else:
+                rr = _plummer_radius(r, a[c], rmax[c], 1)
+                out[k] = centre[c] + rr[:, None] * _iso(r, 1)
+        return out
+
+    pos = _snap_unique(pos, redraw, rng)
+    dens = plummer_number_density(pos, n_bg, per, a, rmax, centre)
+    h0 = h_for_density(dens)
+    return _finish(pos, n, rng, h0, velocity,
+                   {"recipe": "plummer_mixture", "seed": seed, "n_clumps": n_clumps,
+                    "bg_frac": bg_frac, "a": a.tolist(), "centre": centre.tolist()})
+
+
+def plummer_number_density(pos, n_bg, per, a, rmax, centre, chunk=1 << 20):
+    """Analytic number density of the truncated-Plummer mixture at ``pos``."""
+    out = np.full(pos.shape[0], float(n_bg))
+    umax = rmax ** 3 / (rmax ** 2 + a ** 2) ** 1.5
+    for s in range(0, pos.shape[0], chunk):
+        p = pos[s:s + chunk]
+        acc = np.zeros(p.shape[0])
+        for c in range(len(a)):
+            d = p - centre[c]
+            d -= np.round(d)
+            r2 = np.einsum("ij,ij->i", d, d)
+            rho = (3.0 * per[c] / (4.0 * math.pi * a[c] ** 3 * umax[c])) * \
+                (1.0 + r2 / a[c] ** 2) ** -2.5
+            acc += np.where(r2 < rmax[c] ** 2, rho, 0.0)
+        out[s:s + chunk] += acc
+    return out
+
+
+def batch_sizes(n_sets: int = 256, lo: float = 2e3, hi: float = 2e5, seed: int = 4) -> np.ndarray:
+    """Set sizes log-uniform in [lo, hi] (the many-small-sets workload)."""
+    rng = _rng(seed)
+    return np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_sets))).astype(np.int64)
+
+
+def batch_sets(n_sets: int = 256, lo: float = 2e3, hi: float = 2e5, scale: float = 1.0):
+    """The batched workload: set s is a clump/uniform mixture with seed 1000+s."""
+    sizes = batch_sizes(n_sets, lo, hi)
+    sizes = np.maximum(np.round(sizes * scale).astype(np.int64), 256)
+    return [plummer_mixture(int(sz), 1000 + s) for s, sz in enumerate(sizes)]
+
+
+def arrivals(n_req: int, rate_hz: float, lo: float = 1e4, hi: float = 2e6, seed: int = 5):
+    """Poisson request stream: (arrival time [s], N) with N log-uniform in [lo, hi]."""
+    rng = _rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=n_req)
+    t = np.cumsum(gaps) - gaps[0]
+    n = np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), size=n_req))).astype(np.int64)
+    return t, n
