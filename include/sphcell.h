@@ -1,0 +1,206 @@
+/*
+ * sphcell.h -- C-ABI of the MI355X (gfx950) SPH density/force library.
+ *
+ * The library computes the two interaction stages of Section II
+ * (Algorithms) of Gonnet, Schaller, Theuns and Chalk, "SWIFT: Fast
+ * algorithms for multi-resolution SPH on multi-core architectures"
+ * (arXiv:1309.3783):
+ *   1. density: for every particle i, sums over all j within h_i;
+ *   2. force:   for every particle i, sums over all j within max(h_i, h_j);
+ * over a hierarchical cell decomposition (Section II-B) with sorted cell-pair
+ * interactions (Section II-C), plus the per-particle solve of h_i to a target
+ * neighbour number (N_ngb of Section III-B) and the per-cell "ghost" step
+ * between the stages (Section II-D).
+ *
+ * Conventions
+ *  - Every pointer marked [device] is a device pointer owned by the caller;
+ *    pointers marked [host] are host memory.  The library owns only the
+ *    device memory of a tree (sph_tree), which it allocates at build time and
+ *    frees in sph_tree_destroy.
+ *  - One context per HIP stream.  Every call enqueues work on the context's
+ *    stream; outputs are valid once that stream has been synchronised, except
+ *    where a host output is documented (those calls synchronise).
+ *  - Particles are given as S >= 1 independent sets concatenated in one set
+ *    of arrays; set s occupies [offsets[s], offsets[s+1]).  Each set lives in
+ *    its own periodic cube [0, box[s])^3.  All per-particle outputs are in
+ *    this caller order.
+ *  - Errors: calls return SPH_OK (0) or a negative sph_status; host-side
+ *    argument errors return before any work is enqueued.  sph_last_error()
+ *    gives a text for the last failure on a context.
+ *  - Not thread-safe for one context; distinct contexts are independent.
+ */
+#ifndef SPHCELL_H
+#define SPHCELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sph_status;
+enum {
+    SPH_OK = 0,
+    SPH_E_ARG = -1,        /* bad argument (null pointer, size, h too large for the box, ...) */
+    SPH_E_HIP = -2,        /* a HIP runtime call failed */
+    SPH_E_WORKSPACE = -3,  /* device allocation failed */
+    SPH_E_REBUILD = -4,    /* some h_i left the range its cells support: rebuild the tree */
+    SPH_E_NOCONV = -5,     /* the h solve did not converge within max_iter */
+    SPH_E_CAPACITY = -6,   /* a size limit of the key layout or of a table was exceeded */
+    SPH_E_STATE = -7       /* call out of order (e.g. force before density) */
+};
+
+typedef struct sph_ctx sph_ctx;
+typedef struct sph_tree sph_tree;
+
+/* Flags for sph_params.flags */
+#define SPH_FLAG_PAIR_HASH 1u   /* also accumulate the pair-set hashes */
+
+/* Parameters.  Defaults (sph_params_default) follow Section III-B: N_ngb = 48,
+ * gamma = 5/3, alpha = 2.0, split if more than 400 particles and more than
+ * 87.5% of them have h below half the cell edge. */
+typedef struct {
+    int32_t n_split;     /* split a cell only if it holds more than this many particles (400) */
+    float split_frac;    /* ... and more than this fraction has h < edge/2 (0.875) */
+    float h_slack;       /* decisions use h*(1+h_slack) to leave room for h to grow (0.1) */
+    int32_t max_depth;   /* levels below the top grid (12) */
+    int32_t top_grid;    /* top cells per side (power of two), 0 = largest allowed */
+    float n_target;      /* target N_w for the h solve (48) */
+    float h_tol;         /* |N_w - n_target| <= h_tol is converged (0.5) */
+    int32_t max_iter;    /* Newton iterations per sph_solve_h call (30) */
+    float gamma;         /* adiabatic index (5/3) */
+    float alpha;         /* viscosity coefficient (2.0) */
+    uint32_t flags;      /* SPH_FLAG_* */
+    int32_t reserved[5];
+} sph_params;
+
+/* Input particle sets (see Conventions).  h is the initial smoothing length
+ * used for the cell decomposition; it is copied at build time. */
+typedef struct {
+    int32_t nsets;
+    const int64_t* offsets;          /* [host]  nsets+1, offsets[0] = 0 */
+    const double* box;               /* [host]  nsets periodic box sides */
+    const double *x, *y, *z;         /* [device] positions (wrapped into [0,box) internally) */
+    const float* h;                  /* [device] smoothing lengths, 0 < h <= box/2 */
+    const float *m, *u;              /* [device] masses, specific internal energies */
+    const float *vx, *vy, *vz;       /* [device] velocities */
+} sph_input;
+
+/* Density-stage outputs (caller order); any pointer may be NULL. */
+typedef struct {
+    float* rho;          /* [device] rho_i = sum_j m_j W(r_ij, h_i), self included */
+    float* drho_dh;      /* [device] d rho_i / d h_i */
+    float* nw;           /* [device] N_w,i = (4 pi/3) h_i^3 sum_j W(r_ij, h_i) */
+    float* dnw_dh;       /* [device] d N_w,i / d h_i */
+    int32_t* nngb;       /* [device] #{j != i : r_ij < h_i} */
+    uint64_t* hash;      /* [device] sum over those j of splitmix64(j - offsets[s]) mod 2^64;
+                            needs SPH_FLAG_PAIR_HASH at build */
+    float* h;            /* [device] the smoothing lengths used (after sph_solve_h: solved) */
+} sph_density_out;
+
+/* Force-stage outputs (caller order); any pointer may be NULL. */
+typedef struct {
+    float *ax, *ay, *az; /* [device] acceleration */
+    float* dudt;         /* [device] du/dt */
+    float* vsig;         /* [device] max signal velocity over the force neighbours */
+    float* S;            /* [device] sum_j m_j |vector pair term| (error scale) */
+    int32_t* nforce;     /* [device] #{j != i : r_ij < max(h_i, h_j)} */
+    uint64_t* hash;      /* [device] pair-set hash over the same j (SPH_FLAG_PAIR_HASH) */
+    double* sums;        /* [device] 8 doubles per set: Mx, My, Mz (sum m a), E (sum
+                            m (v.a + du/dt)), sum m S, sum nngb, sum nforce (= 2 P, P the
+                            number of unordered interacting pairs), 0 */
+} sph_force_out;
+
+/* Library version string and a text for a status code. */
+const char* sph_version(void);
+const char* sph_status_str(sph_status st);
+
+/* Fill p with the defaults listed above. */
+void sph_params_default(sph_params* p);
+
+/* Create a context bound to device `device` and HIP stream `stream` (a
+ * hipStream_t, NULL = the default stream).  *out receives the context. */
+sph_status sph_ctx_create(sph_ctx** out, int device, void* stream);
+void sph_ctx_destroy(sph_ctx* ctx);
+const char* sph_last_error(const sph_ctx* ctx);
+
+/* Device bytes a tree for n particles is expected to need (admission
+ * control); an estimate from the cell/task statistics of clustered sets. */
+sph_status sph_footprint(int64_t n, const sph_params* p, size_t* bytes);
+
+/* Create an empty tree object (no device memory yet). */
+sph_status sph_tree_create(sph_ctx* ctx, sph_tree** out);
+void sph_tree_destroy(sph_ctx* ctx, sph_tree* t);
+/* Device bytes currently held by the tree. */
+sph_status sph_tree_bytes(const sph_tree* t, size_t* bytes);
+
+/* Section II-B (spatial decomposition): for every set, a top grid of cells of
+ * edge >= max h (a power of two per side, at least 2), Morton ordering of the
+ * particles, recursive bisection of cells holding more than n_split particles
+ * of which more than split_frac have h < edge/2, and the self/pair
+ * interaction lists: a self task per non-empty cell, a pair task per
+ * non-empty face/edge/corner neighbour (periodic), self tasks of split cells
+ * replaced by their children's, pair tasks of split cells replaced by the
+ * children pairs across the interface iff every particle in both has
+ * h < edge/2.  Copies the inputs into cell-ordered FP32 arrays (positions
+ * relative to the top cell origin).  Reuses the tree's device memory when it
+ * is large enough.  Synchronises the stream (level sizes are read back).
+ * Errors: SPH_E_ARG (bad sizes, h > box/2, non-positive values),
+ * SPH_E_CAPACITY (key layout or table limits), SPH_E_WORKSPACE, SPH_E_HIP. */
+sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* p);
+
+/* Section II-C (sorted cell pair interactions): for every cell that is the
+ * source side of a pair task, the particle indices sorted by their
+ * projection on the task's cell-pair axis (one of 13 directions), stored per
+ * (cell, axis) and reused by every density and force pass until the next
+ * build.  Synchronises the stream. */
+sph_status sph_sort_pairs(sph_ctx* ctx, sph_tree* t);
+
+/* Density stage (Section II, item 1) for every particle at its current h.
+ * Requires sph_sort_pairs. */
+sph_status sph_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out);
+
+/* Newton iteration on h_i until |N_w,i - n_target| <= h_tol (convergence
+ * tested in FP64), re-running the density stage on the particles not yet
+ * converged.  Writes the density outputs at the solved h.  *n_unconverged
+ * [host] receives the particles left; *iterations [host] the iterations run.
+ * Returns SPH_E_REBUILD when some h_i must grow past what the tree supports
+ * (out->h then holds the current h: rebuild with it and call again), and
+ * SPH_E_NOCONV when max_iter is reached.  Synchronises the stream. */
+sph_status sph_solve_h(sph_ctx* ctx, sph_tree* t, const sph_density_out* out,
+                       int32_t* n_unconverged, int32_t* iterations);
+
+/* Ghost step between the stages (Section II-D: all densities of a cell are
+ * complete before its forces): pressure P = (gamma-1) rho u, sound speed,
+ * grad-h factor f = 1/(1 + h/(3 rho) drho/dh), A = f P / rho^2; then the
+ * force stage (Section II, item 2) and the per-set FP64 sums.  Requires a
+ * density pass (sph_density or sph_solve_h) at the current h. */
+sph_status sph_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out);
+
+/* Enqueue the whole post-build pipeline -- density/Newton iterations with
+ * device-side early exit (k_iter of them), ghost, force and sums -- as one
+ * HIP graph on the context's stream (captured on first use, relaunched
+ * afterwards while the tree and the output pointers are unchanged).  Does
+ * not synchronise.  n_unconverged_dev [device int32[2]] receives the number
+ * of particles still unconverged after the graph and the rebuild flag (1 if
+ * some h_i outgrew the cell support: the outputs are then not valid). */
+sph_status sph_run_graph(sph_ctx* ctx, sph_tree* t, int32_t k_iter, const sph_density_out* dout,
+                         const sph_force_out* fout, int32_t* n_unconverged_dev);
+
+/* Per-kernel timing of the last pipeline run (milliseconds, from HIP events
+ * recorded on the context's stream): names[i] = stage name, ms[i] = time.
+ * Returns the number of stages written (at most cap). */
+int32_t sph_last_timings(const sph_ctx* ctx, const char** names, double* ms, int32_t cap);
+/* Enable (1) or disable (0) per-stage event timing on the context. */
+void sph_enable_timing(sph_ctx* ctx, int32_t on);
+
+/* Tree statistics (host): [0] particles, [1] cells, [2] leaves, [3] tasks
+ * (self + pair), [4] pair tasks, [5] sorted entries, [6] work chunks,
+ * [7] levels, [8] top cells per side of set 0, [9] max leaf size. */
+sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHCELL_H */

@@ -1,0 +1,337 @@
+"""ctypes binding of libsphcell.so (include/sphcell.h), same names as the C-ABI.
+
+Argument marshalling only: every step of the path runs in the HIP library.
+PyTorch provides the device memory (tensors) and the stream.  There is no
+fallback: if the library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsphcell.so")
+
+SPH_OK, SPH_E_ARG, SPH_E_HIP, SPH_E_WORKSPACE, SPH_E_REBUILD, SPH_E_NOCONV, SPH_E_CAPACITY, SPH_E_STATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+SPH_FLAG_PAIR_HASH = 1
+
+# every function the header declares
+EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
+           "sph_last_error", "sph_footprint", "sph_tree_create", "sph_tree_destroy", "sph_tree_bytes",
+           "sph_build_cells", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
+           "sph_last_timings", "sph_enable_timing", "sph_tree_stats"]
+
+
+class sph_params(C.Structure):
+    _fields_ = [("n_split", C.c_int32), ("split_frac", C.c_float), ("h_slack", C.c_float),
+                ("max_depth", C.c_int32), ("top_grid", C.c_int32), ("n_target", C.c_float),
+                ("h_tol", C.c_float), ("max_iter", C.c_int32), ("gamma", C.c_float), ("alpha", C.c_float),
+                ("flags", C.c_uint32), ("reserved", C.c_int32 * 5)]
+
+
+class sph_input(C.Structure):
+    _fields_ = [("nsets", C.c_int32), ("offsets", C.c_void_p), ("box", C.c_void_p),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("h", C.c_void_p),
+                ("m", C.c_void_p), ("u", C.c_void_p), ("vx", C.c_void_p), ("vy", C.c_void_p),
+                ("vz", C.c_void_p)]
+
+
+class sph_density_out(C.Structure):
+    _fields_ = [("rho", C.c_void_p), ("drho_dh", C.c_void_p), ("nw", C.c_void_p), ("dnw_dh", C.c_void_p),
+                ("nngb", C.c_void_p), ("hash", C.c_void_p), ("h", C.c_void_p)]
+
+
+class sph_force_out(C.Structure):
+    _fields_ = [("ax", C.c_void_p), ("ay", C.c_void_p), ("az", C.c_void_p), ("dudt", C.c_void_p),
+                ("vsig", C.c_void_p), ("S", C.c_void_p), ("nforce", C.c_void_p), ("hash", C.c_void_p),
+                ("sums", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsphcell.so; raise loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, st = C.c_void_p, C.c_int32
+        L.sph_version.restype = C.c_char_p
+        L.sph_status_str.restype = C.c_char_p
+        L.sph_status_str.argtypes = [st]
+        L.sph_params_default.argtypes = [C.POINTER(sph_params)]
+        L.sph_params_default.restype = None
+        L.sph_ctx_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+        L.sph_ctx_destroy.argtypes = [vp]
+        L.sph_ctx_destroy.restype = None
+        L.sph_last_error.argtypes = [vp]
+        L.sph_last_error.restype = C.c_char_p
+        L.sph_footprint.argtypes = [C.c_int64, C.POINTER(sph_params), C.POINTER(C.c_size_t)]
+        L.sph_tree_create.argtypes = [vp, C.POINTER(vp)]
+        L.sph_tree_destroy.argtypes = [vp, vp]
+        L.sph_tree_destroy.restype = None
+        L.sph_tree_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.sph_build_cells.argtypes = [vp, vp, C.POINTER(sph_input), C.POINTER(sph_params)]
+        L.sph_sort_pairs.argtypes = [vp, vp]
+        L.sph_density.argtypes = [vp, vp, C.POINTER(sph_density_out)]
+        L.sph_solve_h.argtypes = [vp, vp, C.POINTER(sph_density_out), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32)]
+        L.sph_force.argtypes = [vp, vp, C.POINTER(sph_force_out)]
+        L.sph_run_graph.argtypes = [vp, vp, C.c_int32, C.POINTER(sph_density_out), C.POINTER(sph_force_out),
+                                    vp]
+        L.sph_last_timings.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.c_int32]
+        L.sph_last_timings.restype = C.c_int32
+        L.sph_enable_timing.argtypes = [vp, C.c_int32]
+        L.sph_enable_timing.restype = None
+        L.sph_tree_stats.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32]
+        for name in ("sph_ctx_create", "sph_footprint", "sph_tree_create", "sph_tree_bytes", "sph_build_cells",
+                     "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
+                     "sph_tree_stats"):
+            getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+class SphError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def params(**kw) -> sph_params:
+    p = sph_params()
+    lib().sph_params_default(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def footprint(n: int, prm: sph_params | None = None) -> int:
+    b = C.c_size_t(0)
+    st = lib().sph_footprint(int(n), C.byref(prm or params()), C.byref(b))
+    if st:
+        raise SphError(st, "sph_footprint")
+    return int(b.value)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to one device and one torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the SPH library runs only on the GPU (no CPU fallback)")
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        st = lib().sph_ctx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if st:
+            raise SphError(st, "sph_ctx_create")
+        self.h = h
+
+    def check(self, st, what):
+        if st:
+            msg = lib().sph_last_error(self.h).decode(errors="replace")
+            raise SphError(st, f"{what}: {msg}")
+
+    def enable_timing(self, on=True):
+        lib().sph_enable_timing(self.h, 1 if on else 0)
+
+    def timings(self):
+        names = (C.c_char_p * 32)()
+        ms = (C.c_double * 32)()
+        k = lib().sph_last_timings(self.h, names, ms, 32)
+        return [(names[i].decode(), ms[i]) for i in range(k)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sph_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Batch:
+    """S particle sets concatenated on the device (caller order)."""
+    x: object
+    y: object
+    z: object
+    h: object
+    m: object
+    u: object
+    vx: object
+    vy: object
+    vz: object
+    offsets: np.ndarray
+    box: np.ndarray
+    keep: list = field(default_factory=list)
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def nsets(self) -> int:
+        return int(self.offsets.size - 1)
+
+    def as_input(self, h=None) -> sph_input:
+        self._off = np.ascontiguousarray(self.offsets, dtype=np.int64)
+        self._box = np.ascontiguousarray(self.box, dtype=np.float64)
+        hh = self.h if h is None else h
+        return sph_input(self.nsets, self._off.ctypes.data_as(C.c_void_p), self._box.ctypes.data_as(C.c_void_p),
+                         _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(hh), _ptr(self.m), _ptr(self.u),
+                         _ptr(self.vx), _ptr(self.vy), _ptr(self.vz))
+
+
+def batch_from_sets(sets, device="cuda", h=None) -> Batch:
+    """Upload ParticleSet-like objects (numpy, caller order) as one Batch."""
+    import torch
+    sizes = [s.n for s in sets]
+    off = np.zeros(len(sets) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+
+    def cat(attr, dt):
+        arr = np.concatenate([np.asarray(getattr(s, attr)) for s in sets]) if sets else np.zeros(0)
+        return torch.as_tensor(arr.astype(dt), device=device)
+
+    hh = (torch.as_tensor(np.concatenate([np.asarray(x) for x in h]).astype(np.float32), device=device)
+          if h is not None else cat("h0", np.float32))
+    return Batch(cat("x", np.float64), cat("y", np.float64), cat("z", np.float64), hh,
+                 cat("m", np.float32), cat("u", np.float32), cat("vx", np.float32), cat("vy", np.float32),
+                 cat("vz", np.float32), off, np.array([s.box for s in sets], dtype=np.float64))
+
+
+class DensityOut:
+    def __init__(self, n, device, hash=False):
+        import torch
+        f = dict(dtype=torch.float32, device=device)
+        self.rho = torch.empty(n, **f)
+        self.drho_dh = torch.empty(n, **f)
+        self.nw = torch.empty(n, **f)
+        self.dnw_dh = torch.empty(n, **f)
+        self.nngb = torch.empty(n, dtype=torch.int32, device=device)
+        self.hash = torch.empty(n, dtype=torch.int64, device=device) if hash else None
+        self.h = torch.empty(n, **f)
+
+    def c(self) -> sph_density_out:
+        return sph_density_out(_ptr(self.rho), _ptr(self.drho_dh), _ptr(self.nw), _ptr(self.dnw_dh),
+                               _ptr(self.nngb), _ptr(self.hash), _ptr(self.h))
+
+
+class ForceOut:
+    def __init__(self, n, nsets, device, hash=False):
+        import torch
+        f = dict(dtype=torch.float32, device=device)
+        self.ax = torch.empty(n, **f)
+        self.ay = torch.empty(n, **f)
+        self.az = torch.empty(n, **f)
+        self.dudt = torch.empty(n, **f)
+        self.vsig = torch.empty(n, **f)
+        self.S = torch.empty(n, **f)
+        self.nforce = torch.empty(n, dtype=torch.int32, device=device)
+        self.hash = torch.empty(n, dtype=torch.int64, device=device) if hash else None
+        self.sums = torch.zeros(max(nsets, 1) * 8, dtype=torch.float64, device=device)
+
+    def c(self) -> sph_force_out:
+        return sph_force_out(_ptr(self.ax), _ptr(self.ay), _ptr(self.az), _ptr(self.dudt), _ptr(self.vsig),
+                             _ptr(self.S), _ptr(self.nforce), _ptr(self.hash), _ptr(self.sums))
+
+
+class Tree:
+    """A device-resident cell tree for one Batch (kept across density -> force)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx.check(lib().sph_tree_create(ctx.h, C.byref(h)), "sph_tree_create")
+        self.h = h
+        self.batch = None
+        self.prm = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sph_tree_destroy(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_cells(self, batch: Batch, prm: sph_params | None = None, h=None):
+        self.batch = batch
+        self.prm = prm or params()
+        self._in = batch.as_input(h)
+        self.ctx.check(lib().sph_build_cells(self.ctx.h, self.h, C.byref(self._in), C.byref(self.prm)),
+                       "sph_build_cells")
+
+    def sort_pairs(self):
+        self.ctx.check(lib().sph_sort_pairs(self.ctx.h, self.h), "sph_sort_pairs")
+
+    def density(self, out: DensityOut):
+        self._dout = out.c()
+        self.ctx.check(lib().sph_density(self.ctx.h, self.h, C.byref(self._dout)), "sph_density")
+
+    def solve_h(self, out: DensityOut):
+        """Returns (status, n_unconverged, iterations); REBUILD/NOCONV are returned, not raised."""
+        self._dout = out.c()
+        nu, it = C.c_int32(0), C.c_int32(0)
+        st = lib().sph_solve_h(self.ctx.h, self.h, C.byref(self._dout), C.byref(nu), C.byref(it))
+        if st not in (SPH_OK, SPH_E_REBUILD, SPH_E_NOCONV):
+            self.ctx.check(st, "sph_solve_h")
+        return st, int(nu.value), int(it.value)
+
+    def force(self, out: ForceOut):
+        self._fout = out.c()
+        self.ctx.check(lib().sph_force(self.ctx.h, self.h, C.byref(self._fout)), "sph_force")
+
+    def run_graph(self, k_iter: int, dout: DensityOut, fout: ForceOut, unconv):
+        self._gd, self._gf = dout.c(), fout.c()
+        self.ctx.check(lib().sph_run_graph(self.ctx.h, self.h, int(k_iter), C.byref(self._gd), C.byref(self._gf),
+                                           _ptr(unconv)), "sph_run_graph")
+
+    def stats(self) -> dict:
+        v = (C.c_int64 * 10)()
+        self.ctx.check(lib().sph_tree_stats(self.h, v, 10), "sph_tree_stats")
+        keys = ["particles", "cells", "leaves", "tasks", "pair_tasks", "sorted_entries", "chunks", "levels",
+                "top_grid", "max_leaf"]
+        return dict(zip(keys, [int(x) for x in v]))
+
+    def bytes(self) -> int:
+        b = C.c_size_t(0)
+        self.ctx.check(lib().sph_tree_bytes(self.h, C.byref(b)), "sph_tree_bytes")
+        return int(b.value)
+
+
+def solve_with_rebuild(tree: Tree, batch: Batch, prm: sph_params, dout: DensityOut, max_rebuilds: int = 4):
+    """build -> sort -> solve_h, rebuilding with the current h when h outgrows
+    the cells (the library reports it; the rebuild itself runs on the GPU)."""
+    h = batch.h
+    total_it = 0
+    for _ in range(max_rebuilds + 1):
+        tree.build_cells(batch, prm, h=h)
+        tree.sort_pairs()
+        st, nu, it = tree.solve_h(dout)
+        total_it += it
+        if st == SPH_E_REBUILD:
+            h = dout.h.clone()
+            continue
+        return st, nu, total_it
+    return SPH_E_REBUILD, -1, total_it

@@ -1,0 +1,174 @@
+// C-ABI entry points (declared in include/sphcell.h).  Argument checking,
+// error codes and the context; the work itself is in sph_build.hip and
+// sph_interact.hip.
+#include <cstring>
+
+#include "sph_impl.h"
+
+using sph::Err;
+
+static sph_status fail(sph_ctx* ctx, const Err& e) {
+    if (ctx && e.st != SPH_OK) ctx->last_error = e.msg;
+    return e.st;
+}
+
+extern "C" {
+
+const char* sph_version(void) { return "sphcell 0.1 (gfx950)"; }
+
+const char* sph_status_str(sph_status st) {
+    switch (st) {
+        case SPH_OK: return "ok";
+        case SPH_E_ARG: return "invalid argument";
+        case SPH_E_HIP: return "HIP runtime error";
+        case SPH_E_WORKSPACE: return "device allocation failed";
+        case SPH_E_REBUILD: return "h outgrew the cell support: rebuild";
+        case SPH_E_NOCONV: return "h solve did not converge";
+        case SPH_E_CAPACITY: return "capacity exceeded";
+        case SPH_E_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+void sph_params_default(sph_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->n_split = 400;
+    p->split_frac = 0.875f;
+    p->h_slack = 0.1f;
+    p->max_depth = 12;
+    p->top_grid = 0;
+    p->n_target = 48.f;
+    p->h_tol = 0.5f;
+    p->max_iter = 30;
+    p->gamma = 5.f / 3.f;
+    p->alpha = 2.f;
+    p->flags = 0;
+}
+
+sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
+    if (!out) return SPH_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SPH_E_HIP;
+    if (device < 0 || device >= ndev) return SPH_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return SPH_E_HIP;
+    sph_ctx* c = new sph_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    if (hipMalloc(&c->d_counter, 64 * sizeof(int32_t)) != hipSuccess) {
+        delete c;
+        return SPH_E_WORKSPACE;
+    }
+    *out = c;
+    return SPH_OK;
+}
+
+void sph_ctx_destroy(sph_ctx* ctx) {
+    if (!ctx) return;
+    for (auto& e : ctx->ev) (void)hipEventDestroy(e.second);
+    if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+    delete ctx;
+}
+
+const char* sph_last_error(const sph_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+sph_status sph_footprint(int64_t n, const sph_params* p, size_t* bytes) {
+    if (!bytes || n < 0) return SPH_E_ARG;
+    (void)p;
+    // particles: keys x2, vals x2, perm, pos, pv, h, hdec, u, bound, mix,
+    // density (28 B), solve (9 B), force (44 B): ~180 B; sorted lists ~13
+    // entries of 8 B; cells and tasks ~60 B per particle on clustered sets.
+    const double per = 180.0 + 13.0 * 8.0 + 60.0;
+    *bytes = (size_t)(per * (double)n) + ((size_t)64 << 20);
+    return SPH_OK;
+}
+
+sph_status sph_tree_create(sph_ctx* ctx, sph_tree** out) {
+    if (!ctx || !out) return SPH_E_ARG;
+    *out = new sph_tree();
+    return SPH_OK;
+}
+
+void sph_tree_destroy(sph_ctx* ctx, sph_tree* t) {
+    (void)ctx;
+    delete t;
+}
+
+sph_status sph_tree_bytes(const sph_tree* t, size_t* bytes) {
+    if (!t || !bytes) return SPH_E_ARG;
+    *bytes = t->bytes();
+    return SPH_OK;
+}
+
+sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* p) {
+    if (!ctx || !t) return SPH_E_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPH_E_HIP;
+    t->red_chunks.clear();
+    t->nred = 0;
+    return fail(ctx, sph::build_tree(ctx, t, in, p));
+}
+
+sph_status sph_sort_pairs(sph_ctx* ctx, sph_tree* t) {
+    if (!ctx || !t) return SPH_E_ARG;
+    return fail(ctx, sph::sort_pairs(ctx, t));
+}
+
+sph_status sph_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out) {
+    if (!ctx || !t) return SPH_E_ARG;
+    return fail(ctx, sph::run_density(ctx, t, out));
+}
+
+sph_status sph_solve_h(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_unconverged,
+                       int32_t* iterations) {
+    if (!ctx || !t) return SPH_E_ARG;
+    return fail(ctx, sph::run_solve(ctx, t, out, n_unconverged, iterations));
+}
+
+sph_status sph_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
+    if (!ctx || !t) return SPH_E_ARG;
+    return fail(ctx, sph::run_force(ctx, t, out));
+}
+
+sph_status sph_run_graph(sph_ctx* ctx, sph_tree* t, int32_t k_iter, const sph_density_out* dout,
+                         const sph_force_out* fout, int32_t* n_unconverged_dev) {
+    if (!ctx || !t || k_iter < 1) return SPH_E_ARG;
+    return fail(ctx, sph::run_graph(ctx, t, k_iter, dout, fout, n_unconverged_dev));
+}
+
+int32_t sph_last_timings(const sph_ctx* ctx, const char** names, double* ms, int32_t cap) {
+    if (!ctx) return 0;
+    int32_t k = 0;
+    for (const auto& e : ctx->last_ms) {
+        if (k >= cap) break;
+        if (names) names[k] = e.first;
+        if (ms) ms[k] = e.second;
+        ++k;
+    }
+    return k;
+}
+
+void sph_enable_timing(sph_ctx* ctx, int32_t on) {
+    if (ctx) ctx->timing = on != 0;
+}
+
+sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap) {
+    if (!t || !stats) return SPH_E_ARG;
+    int64_t v[10] = {t->n,
+                     t->ncells,
+                     t->nleaves,
+                     t->ntasks,
+                     t->npairs,
+                     t->nsegent,
+                     t->nchunks,
+                     t->nlevels,
+                     t->sets.empty() ? 0 : (int64_t)1 << t->sets[0].lgG,
+                     t->max_leaf};
+    for (int i = 0; i < cap && i < 10; ++i) stats[i] = v[i];
+    return SPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,983 @@
+// Cell decomposition, interaction lists and per-(cell, axis) sorted lists.
+//
+//  * Spatial decomposition (Section II-B): per set a top grid of 2^k cells per
+//    side with edge >= max h; particles ordered by Morton key; level-by-level
+//    bisection of cells with more than n_split particles of which more than
+//    split_frac have h < edge/2 (Section III-B gives 400 and 87.5%).
+//  * Interaction lists (Section II-B): a self task per non-empty top cell and
+//    a pair task per non-empty face/edge/corner neighbour (periodic images
+//    included); a split cell's self task becomes its children's self tasks
+//    plus the 28 child pairs; a pair of split cells becomes the child pairs
+//    across the interface iff every particle of both has h < edge/2.
+//  * Sorted lists (Section II-C): for every (cell, axis) that is the source
+//    side of a pair task, the particles sorted by projection on the axis.
+//
+// Everything here is integer or compare work and bound by memory traffic;
+// the level loop reads one count back per level to size the next one.
+#include <algorithm>
+#include <cmath>
+
+#include "sph_impl.h"
+
+
+namespace sph {
+
+__device__ inline uint32_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10C30C30C30C30C3ull;
+    v = (v ^ (v >> 4)) & 0x100F00F00F00F00Full;
+    v = (v ^ (v >> 8)) & 0x1F0000FF0000FFull;
+    v = (v ^ (v >> 16)) & 0x1F00000000FFFFull;
+    v = (v ^ (v >> 32)) & 0x1FFFFFull;
+    return (uint32_t)v;
+}
+
+__device__ inline int set_of_particle(const SetInfo* sets, int nsets, int64_t i) {
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sets[mid].first <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int set_of_top(const SetInfo* sets, int nsets, int c) {
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sets[mid].top_base <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int64_t lower_bound_key(const uint64_t* key, int64_t lo, int64_t hi, uint64_t k) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (key[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline float wave_max_f(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ inline uint64_t splitmix64(uint64_t id) {
+    uint64_t z = id + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// per-set max h, and a count of invalid h (not finite, <= 0)
+__global__ __launch_bounds__(256) void k_set_hstats(const SetInfo* sets, const float* __restrict__ h,
+                                                    float* hmax_out, int* bad_out) {
+    __shared__ float s_m[4];
+    __shared__ int s_b[4];
+    const SetInfo S = sets[blockIdx.x];
+    float m = 0.f;
+    int bad = 0;
+    for (int64_t i = S.first + threadIdx.x; i < S.first + S.count; i += 256) {
+        float v = h[i];
+        if (!(v > 0.f) || !(v < INFINITY)) bad++;
+        else m = fmaxf(m, v);
+    }
+    m = wave_max_f(m);
+    bad = wave_sum_i(bad);
+    if ((threadIdx.x & 63) == 0) { s_m[threadIdx.x >> 6] = m; s_b[threadIdx.x >> 6] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        hmax_out[blockIdx.x] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+        bad_out[blockIdx.x] = s_b[0] + s_b[1] + s_b[2] + s_b[3];
+    }
+}
+
+// Integer cell coordinate at 2^(lgG+depth) cells per side (same formula in
+// k_keys and k_gather so both place a particle in the same cell).
+__device__ inline int64_t fine_coord(double x, double box, int64_t R) {
+    double w = x - box * floor(x / box);
+    int64_t k = (int64_t)floor(w / box * (double)R);
+    return k < 0 ? 0 : (k >= R ? R - 1 : k);
+}
+
+__global__ void k_keys(const SetInfo* sets, int nsets, int64_t n, const double* __restrict__ x,
+                       const double* __restrict__ y, const double* __restrict__ z, int depth, int bmax,
+                       uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int s = set_of_particle(sets, nsets, i);
+    const SetInfo S = sets[s];
+    int64_t R = (int64_t)1 << (S.lgG + depth);
+    uint64_t ix = (uint64_t)fine_coord(x[i], S.box, R);
+    uint64_t iy = (uint64_t)fine_coord(y[i], S.box, R);
+    uint64_t iz = (uint64_t)fine_coord(z[i], S.box, R);
+    key[i] = ((uint64_t)s << (3 * bmax)) | (morton3(ix, iy, iz) << S.key_shift);
+    val[i] = (uint32_t)i;
+}
+
+__global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int depth, int bmax,
+                         const uint64_t* __restrict__ key, const uint32_t* __restrict__ val,
+                         const double* __restrict__ x, const double* __restrict__ y,
+                         const double* __restrict__ z, const float* __restrict__ h,
+                         const float* __restrict__ m, const float* __restrict__ u,
+                         const float* __restrict__ vx, const float* __restrict__ vy,
+                         const float* __restrict__ vz, float slack, float4* __restrict__ pos,
+                         float* __restrict__ ph, float* __restrict__ hdec, float* __restrict__ pu,
+                         float4* __restrict__ pv, uint32_t* __restrict__ perm,
+                         uint64_t* __restrict__ mix) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t i = val[p];
+    int s = nsets > 1 ? (int)(key[p] >> (3 * bmax)) : 0;
+    const SetInfo S = sets[s];
+    int64_t R = (int64_t)1 << (S.lgG + depth);
+    double xs[3] = {x[i], y[i], z[i]};
+    float o[3];
+    for (int d = 0; d < 3; ++d) {
+        double w = xs[d] - S.box * floor(xs[d] / S.box);
+        int64_t top = fine_coord(xs[d], S.box, R) >> depth;
+        o[d] = (float)(w - (double)top * S.L0);
+    }
+    pos[p] = make_float4(o[0], o[1], o[2], m[i]);
+    float hh = h[i];
+    ph[p] = hh;
+    hdec[p] = hh * (1.0f + slack);
+    pu[p] = u[i];
+    pv[p] = make_float4(vx[i], vy[i], vz[i], 0.f);
+    perm[p] = i;
+    mix[p] = splitmix64((uint64_t)((int64_t)i - S.first));
+}
+
+__device__ inline void cell_key_range(const SetInfo& S, int bmax, int depth, int level, int ix, int iy, int iz,
+                                      int set, uint64_t* lo, uint64_t* hi) {
+    uint64_t code = morton3((uint64_t)ix, (uint64_t)iy, (uint64_t)iz);
+    int sh = S.key_shift + 3 * (depth - level);
+    uint64_t base = ((uint64_t)set << (3 * bmax));
+    *lo = base | (code << sh);
+    *hi = *lo + (1ull << sh);
+}
+
+__global__ void k_top_cells(const SetInfo* sets, int nsets, int ntop, int depth, int bmax,
+                            const uint64_t* __restrict__ key, Cell* __restrict__ cells) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ntop) return;
+    int s = set_of_top(sets, nsets, c);
+    const SetInfo S = sets[s];
+    uint64_t t = (uint64_t)(c - S.top_base);
+    Cell C;
+    C.ix = (int)compact3(t >> 2);
+    C.iy = (int)compact3(t >> 1);
+    C.iz = (int)compact3(t);
+    C.level = 0;
+    C.set = (int16_t)s;
+    C.parent = -1;
+    C.child = -1;
+    uint64_t lo, hi;
+    cell_key_range(S, bmax, depth, 0, C.ix, C.iy, C.iz, s, &lo, &hi);
+    int64_t a = lower_bound_key(key, S.first, S.first + S.count, lo);
+    int64_t b = lower_bound_key(key, a, S.first + S.count, hi);
+    C.first = (int32_t)a;
+    C.count = (int32_t)(b - a);
+    C.hmax = 0.f;
+    C.hcur = 0.f;
+    C.bound = nextafterf((float)S.L0, INFINITY);
+    C.split = 0;
+    cells[c] = C;
+}
+
+// One wave per cell of level `level`: particle range (children of a split
+// parent look theirs up inside the parent's range), max decision h, the
+// number with h < edge/2, and the split decision.
+__global__ __launch_bounds__(256) void k_cell_stats(const SetInfo* sets, int depth, int bmax, int level,
+                                                    int64_t c0, int64_t c1, const uint64_t* __restrict__ key,
+                                                    const float* __restrict__ hdec, int n_split,
+                                                    float split_frac, Cell* __restrict__ cells) {
+    const int lane = threadIdx.x & 63;
+    int64_t c = c0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= c1) return;
+    Cell C = cells[c];
+    const SetInfo S = sets[C.set];
+    if (level > 0) {
+        const Cell P = cells[C.parent];
+        uint64_t lo, hi;
+        cell_key_range(S, bmax, depth, level, C.ix, C.iy, C.iz, C.set, &lo, &hi);
+        int64_t a = lower_bound_key(key, P.first, (int64_t)P.first + P.count, lo);
+        int64_t b = lower_bound_key(key, a, (int64_t)P.first + P.count, hi);
+        C.first = (int32_t)a;
+        C.count = (int32_t)(b - a);
+    }
+    const float half = (float)(0.5 * S.L0 / (double)(1 << level));
+    float hm = 0.f;
+    int nsmall = 0;
+    for (int64_t p = C.first + lane; p < (int64_t)C.first + C.count; p += 64) {
+        float hh = hdec[p];
+        hm = fmaxf(hm, hh);
+        nsmall += hh < half ? 1 : 0;
+    }
+    hm = wave_max_f(hm);
+    nsmall = wave_sum_i(nsmall);
+    if (lane == 0) {
+        C.hmax = hm;
+        C.split = (level < depth && C.count > n_split &&
+                   (double)nsmall > (double)split_frac * (double)C.count) ? 1u : 0u;
+        cells[c] = C;
+    }
+}
+
+__global__ void k_split_flags(const Cell* __restrict__ cells, int64_t c0, int64_t c1, uint32_t* flags) {
+    int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < c1) flags[c - c0] = cells[c].split;
+}
+
+__global__ void k_make_children(int64_t c0, int64_t c1, int64_t next0, const uint32_t* __restrict__ sidx,
+                                Cell* __restrict__ cells) {
+    int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    Cell P = cells[c];
+    if (!P.split) return;
+    int64_t base = next0 + 8 * (int64_t)sidx[c - c0];
+    cells[c].child = (int32_t)base;
+    for (int o = 0; o < 8; ++o) {
+        Cell C;
+        C.first = P.first;
+        C.count = P.count;
+        C.parent = (int32_t)c;
+        C.child = -1;
+        C.ix = 2 * P.ix + ((o >> 2) & 1);
+        C.iy = 2 * P.iy + ((o >> 1) & 1);
+        C.iz = 2 * P.iz + (o & 1);
+        C.level = (int16_t)(P.level + 1);
+        C.set = P.set;
+        C.hmax = 0.f;
+        C.hcur = 0.f;
+        C.bound = INFINITY;
+        C.split = 0;
+        cells[base + o] = C;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tasks: int4 (ci, cj, offset code, 0); self tasks have ci == cj, code 13.
+// ---------------------------------------------------------------------------
+__device__ inline int top_neighbour(const SetInfo& S, const Cell& A, int ox, int oy, int oz) {
+    int G = 1 << S.lgG;
+    int bx = (A.ix + ox + G) & (G - 1), by = (A.iy + oy + G) & (G - 1), bz = (A.iz + oz + G) & (G - 1);
+    return S.top_base + (int)morton3((uint64_t)bx, (uint64_t)by, (uint64_t)bz);
+}
+
+__global__ void k_top_task_count(const SetInfo* sets, int nsets, int ntop, const Cell* __restrict__ cells,
+                                 uint32_t* cnt) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ntop) return;
+    const Cell A = cells[c];
+    if (A.count == 0) { cnt[c] = 0; return; }
+    const SetInfo S = sets[A.set];
+    uint32_t k = 1;
+    for (int a = 0; a < 13; ++a) {
+        int code = axis_code(a);
+        int B = top_neighbour(S, A, ocx(code), ocy(code), ocz(code));
+        if (cells[B].count > 0) ++k;
+    }
+    cnt[c] = k;
+}
+
+__global__ void k_top_task_emit(const SetInfo* sets, int ntop, const Cell* __restrict__ cells,
+                                const uint32_t* __restrict__ off, int4* __restrict__ out) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ntop) return;
+    const Cell A = cells[c];
+    if (A.count == 0) return;
+    const SetInfo S = sets[A.set];
+    uint32_t k = off[c];
+    out[k++] = make_int4(c, c, 13, 0);
+    for (int a = 0; a < 13; ++a) {
+        int code = axis_code(a);
+        int B = top_neighbour(S, A, ocx(code), ocy(code), ocz(code));
+        if (cells[B].count > 0) out[k++] = make_int4(c, B, code, 0);
+    }
+}
+
+__device__ inline uint32_t nonempty_children(const Cell* cells, const Cell& A) {
+    uint32_t m = 0;
+    for (int o = 0; o < 8; ++o)
+        if (cells[A.child + o].count > 0) m |= 1u << o;
+    return m;
+}
+
+__device__ inline bool child_adjacent(int ox, int oy, int oz, int a, int b, int* cx, int* cy, int* cz) {
+    *cx = 2 * ox + ((b >> 2) & 1) - ((a >> 2) & 1);
+    *cy = 2 * oy + ((b >> 1) & 1) - ((a >> 1) & 1);
+    *cz = 2 * oz + (b & 1) - (a & 1);
+    return abs(*cx) <= 1 && abs(*cy) <= 1 && abs(*cz) <= 1;
+}
+
+// Decide each task of one level: final (kept) or replaced by child tasks.
+// A pair of split cells is split iff max h (decision h) of both < edge/2;
+// the cells then record edge/2 as the bound their particles' h must stay
+// below.  All writes of one level store the same value, so races are benign.
+__global__ void k_task_decide(const SetInfo* sets, const int4* __restrict__ tasks, int64_t nt,
+                              Cell* __restrict__ cells, uint32_t* __restrict__ fin, uint32_t* __restrict__ nch) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    int4 T = tasks[t];
+    const Cell A = cells[T.x];
+    if (T.x == T.y) {
+        if (A.split) {
+            uint32_t m = nonempty_children(cells, A);
+            uint32_t k = __popc(m);
+            fin[t] = 0;
+            nch[t] = k + k * (k - 1) / 2;
+        } else {
+            fin[t] = 1;
+            nch[t] = 0;
+        }
+        return;
+    }
+    const Cell B = cells[T.y];
+    const SetInfo S = sets[A.set];
+    const float half = (float)(0.5 * S.L0 / (double)(1 << A.level));
+    if (A.split && B.split && fmaxf(A.hmax, B.hmax) < half) {
+        uint32_t ma = nonempty_children(cells, A), mb = nonempty_children(cells, B);
+        int ox = ocx(T.z), oy = ocy(T.z), oz = ocz(T.z);
+        uint32_t k = 0;
+        for (int a = 0; a < 8; ++a) {
+            if (!((ma >> a) & 1)) continue;
+            for (int b = 0; b < 8; ++b) {
+                int cx, cy, cz;
+                if (((mb >> b) & 1) && child_adjacent(ox, oy, oz, a, b, &cx, &cy, &cz)) ++k;
+            }
+        }
+        fin[t] = 0;
+        nch[t] = k;
+        cells[T.x].bound = half;
+        cells[T.y].bound = half;
+    } else {
+        fin[t] = 1;
+        nch[t] = 0;
+    }
+}
+
+__global__ void k_task_emit(const int4* __restrict__ tasks, int64_t nt, const Cell* __restrict__ cells,
+                            const uint32_t* __restrict__ fin, const uint32_t* __restrict__ fpos,
+                            const uint32_t* __restrict__ nch, const uint32_t* __restrict__ cpos,
+                            int4* __restrict__ final_out, int4* __restrict__ next_out) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    int4 T = tasks[t];
+    if (fin[t]) {
+        final_out[fpos[t]] = T;
+        return;
+    }
+    if (nch[t] == 0) return;
+    uint32_t k = cpos[t];
+    const Cell A = cells[T.x];
+    if (T.x == T.y) {
+        uint32_t m = nonempty_children(cells, A);
+        for (int a = 0; a < 8; ++a)
+            if ((m >> a) & 1) next_out[k++] = make_int4(A.child + a, A.child + a, 13, 0);
+        for (int a = 0; a < 8; ++a) {
+            if (!((m >> a) & 1)) continue;
+            for (int b = a + 1; b < 8; ++b) {
+                if (!((m >> b) & 1)) continue;
+                int code = ocode(((b >> 2) & 1) - ((a >> 2) & 1), ((b >> 1) & 1) - ((a >> 1) & 1),
+                                 (b & 1) - (a & 1));
+                next_out[k++] = make_int4(A.child + a, A.child + b, code, 0);
+            }
+        }
+        return;
+    }
+    const Cell B = cells[T.y];
+    uint32_t ma = nonempty_children(cells, A), mb = nonempty_children(cells, B);
+    int ox = ocx(T.z), oy = ocy(T.z), oz = ocz(T.z);
+    for (int a = 0; a < 8; ++a) {
+        if (!((ma >> a) & 1)) continue;
+        for (int b = 0; b < 8; ++b) {
+            int cx, cy, cz;
+            if (((mb >> b) & 1) && child_adjacent(ox, oy, oz, a, b, &cx, &cy, &cz))
+                next_out[k++] = make_int4(A.child + a, B.child + b, ocode(cx, cy, cz), 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Leaves -> work chunks of at most CHUNK particles; per-particle h bound.
+// ---------------------------------------------------------------------------
+__global__ void k_chunk_count(const Cell* __restrict__ cells, int64_t nc, uint32_t* cnt, int* max_leaf) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const Cell C = cells[c];
+    bool leaf = !C.split && C.count > 0;
+    cnt[c] = leaf ? (uint32_t)((C.count + CHUNK - 1) / CHUNK) : 0u;
+    if (leaf) atomicMax(max_leaf, C.count);
+}
+
+__global__ void k_chunk_emit(const Cell* __restrict__ cells, int64_t nc, const uint32_t* __restrict__ off,
+                             int4* __restrict__ chunks) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const Cell C = cells[c];
+    if (C.split || C.count == 0) return;
+    uint32_t k = off[c];
+    for (int s = 0; s < C.count; s += CHUNK)
+        chunks[k++] = make_int4((int)c, C.first + s, min(CHUNK, C.count - s), 0);
+}
+
+__global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__ chunks, int64_t nch,
+                                                        const Cell* __restrict__ cells,
+                                                        float* __restrict__ bound) {
+    int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nch) return;
+    const int lane = threadIdx.x & 63;
+    int4 ch = chunks[q];
+    float b = INFINITY;
+    for (int A = ch.x; A >= 0; A = cells[A].parent) b = fminf(b, cells[A].bound);
+    if (lane < ch.z) bound[ch.y + lane] = b;
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell interaction lists: each pair task (A,B,o) gives A the source
+// (B, o) and B the source (A, -o).  Keys sort by (target, source, code).
+// ---------------------------------------------------------------------------
+constexpr int CSR_SRC_SHIFT = 5;
+constexpr int CSR_TGT_SHIFT = 37;
+
+__global__ void k_csr_keys(const int4* __restrict__ tasks, int64_t nt, uint64_t* __restrict__ keys,
+                           int* __restrict__ npairs) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    int4 T = tasks[t];
+    if (T.x == T.y) {
+        keys[2 * t] = ~0ull;
+        keys[2 * t + 1] = ~0ull;
+        return;
+    }
+    atomicAdd(npairs, 1);
+    keys[2 * t] = ((uint64_t)T.x << CSR_TGT_SHIFT) | ((uint64_t)T.y << CSR_SRC_SHIFT) | (uint64_t)T.z;
+    keys[2 * t + 1] = ((uint64_t)T.y << CSR_TGT_SHIFT) | ((uint64_t)T.x << CSR_SRC_SHIFT) | (uint64_t)(26 - T.z);
+}
+
+__global__ void k_csr_count(const uint64_t* __restrict__ keys, int64_t ne, uint32_t* __restrict__ cnt) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    atomicAdd(&cnt[keys[e] >> CSR_TGT_SHIFT], 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Sorted lists per (cell, axis).
+// ---------------------------------------------------------------------------
+__global__ void k_seg_need(const uint64_t* __restrict__ ent, int64_t ne, uint32_t* __restrict__ need) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    uint64_t k = ent[e];
+    int src = (int)((k >> CSR_SRC_SHIFT) & 0xFFFFFFFFull);
+    int sg;
+    int ax = axis_of((int)(k & 31), &sg);
+    need[(int64_t)src * NAXES + ax] = 1u;
+}
+
+__global__ void k_seg_list(const uint32_t* __restrict__ need, const uint32_t* __restrict__ idx, int64_t nca,
+                           const Cell* __restrict__ cells, uint32_t* __restrict__ list,
+                           uint32_t* __restrict__ lens) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nca || !need[q]) return;
+    uint32_t k = idx[q];
+    list[k] = (uint32_t)q;
+    lens[k] = (uint32_t)cells[q / NAXES].count;
+}
+
+__global__ void k_seg_table(const uint32_t* __restrict__ list, const uint32_t* __restrict__ off, int64_t ns,
+                            uint32_t* __restrict__ table) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < ns) table[list[k]] = off[k];
+}
+
+__device__ inline float project(const float4& p, int ax) {
+    int c = axis_code(ax);
+    int dx = ocx(c), dy = ocy(c), dz = ocz(c);
+    float r = (float)dx * p.x;
+    r = r + (float)dy * p.y;
+    r = r + (float)dz * p.z;
+    return r;
+}
+
+__device__ inline float ord2f(uint32_t u) {
+    uint32_t b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    return __uint_as_float(b);
+}
+
+// One block per segment of at most SEG_LDS_MAX entries: bitonic sort of
+// (ordered projection << 32 | local index) in LDS.
+__global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict__ list,
+                                                      const uint32_t* __restrict__ off, int64_t ns,
+                                                      const Cell* __restrict__ cells,
+                                                      const float4* __restrict__ pos,
+                                                      float* __restrict__ sproj, uint32_t* __restrict__ sidx) {
+    __shared__ uint64_t s[SEG_LDS_MAX];
+    int64_t q = blockIdx.x;
+    if (q >= ns) return;
+    uint32_t ca = list[q];
+    const Cell C = cells[ca / NAXES];
+    int ax = (int)(ca % NAXES);
+    int n = C.count;
+    if (n > SEG_LDS_MAX) return;
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int e = threadIdx.x; e < P; e += blockDim.x) {
+        uint64_t k = ~0ull;
+        if (e < n) k = ((uint64_t)f2ord(project(pos[C.first + e], ax)) << 32) | (uint32_t)e;
+        s[e] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = threadIdx.x; e < P / 2; e += blockDim.x) {
+                int i = 2 * e - (e & (stride - 1));
+                int j = i + stride;
+                bool up = ((i & size) == 0);
+                uint64_t a = s[i], b = s[j];
+                if ((a > b) == up) { s[i] = b; s[j] = a; }
+            }
+            __syncthreads();
+        }
+    }
+    uint32_t o = off[q];
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        uint64_t k = s[e];
+        sproj[o + e] = ord2f((uint32_t)(k >> 32));
+        sidx[o + e] = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+    }
+}
+
+__global__ void k_big_flag(const uint32_t* __restrict__ lens, int64_t ns, uint32_t* __restrict__ flag) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < ns) flag[q] = lens[q] > (uint32_t)SEG_LDS_MAX ? 1u : 0u;
+}
+
+__global__ void k_big_list(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx, int64_t ns,
+                           const uint32_t* __restrict__ lens, uint32_t* __restrict__ big,
+                           uint32_t* __restrict__ blen) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ns || !flag[q]) return;
+    big[idx[q]] = (uint32_t)q;
+    blen[idx[q]] = lens[q];
+}
+
+__global__ __launch_bounds__(256) void k_big_keys(const uint32_t* __restrict__ big,
+                                                  const uint32_t* __restrict__ boff,
+                                                  const uint32_t* __restrict__ list,
+                                                  const Cell* __restrict__ cells, const float4* __restrict__ pos,
+                                                  uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+    uint32_t r = blockIdx.x;
+    uint32_t ca = list[big[r]];
+    const Cell C = cells[ca / NAXES];
+    int ax = (int)(ca % NAXES);
+    uint32_t o = boff[r];
+    for (int e = threadIdx.x; e < C.count; e += blockDim.x) {
+        key[o + e] = ((uint64_t)r << 32) | f2ord(project(pos[C.first + e], ax));
+        val[o + e] = (uint32_t)C.first + (uint32_t)e;
+    }
+}
+
+__global__ void k_big_write(const uint64_t* __restrict__ key, const uint32_t* __restrict__ val, int64_t ne,
+                            const uint32_t* __restrict__ boff, const uint32_t* __restrict__ big,
+                            const uint32_t* __restrict__ off, float* __restrict__ sproj,
+                            uint32_t* __restrict__ sidx) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ne) return;
+    uint64_t k = key[p];
+    uint32_t r = (uint32_t)(k >> 32);
+    uint32_t local = (uint32_t)p - boff[r];
+    uint32_t o = off[big[r]] + local;
+    sproj[o] = ord2f((uint32_t)k);
+    sidx[o] = val[p];
+}
+
+// ===========================================================================
+// Host orchestration
+// ===========================================================================
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+#define HIPTRY(x)                                                                      \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) return Err{SPH_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define ERRTRY(x)                          \
+    do {                                   \
+        Err e_ = (x);                      \
+        if (e_.st != SPH_OK) return e_;    \
+    } while (0)
+
+static Err read_u32(const uint32_t* d, uint32_t* h, hipStream_t st) {
+    HIPTRY(hipMemcpyAsync(h, d, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return Err{};
+}
+
+Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* prm) {
+    hipStream_t st = ctx->stream;
+    // ---- validate the host description ---------------------------------
+    if (!in || !prm) return Err{SPH_E_ARG, "null input or params"};
+    if (in->nsets < 1 || in->nsets > MAX_SETS) return Err{SPH_E_ARG, "nsets out of range"};
+    if (!in->offsets || !in->box) return Err{SPH_E_ARG, "null offsets or box"};
+    if (in->offsets[0] != 0) return Err{SPH_E_ARG, "offsets[0] must be 0"};
+    for (int s = 0; s < in->nsets; ++s) {
+        if (in->offsets[s + 1] < in->offsets[s]) return Err{SPH_E_ARG, "offsets must be non-decreasing"};
+        if (!(in->box[s] > 0.0) || !std::isfinite(in->box[s])) return Err{SPH_E_ARG, "box must be positive"};
+    }
+    const int64_t n = in->offsets[in->nsets];
+    if (n > ((int64_t)1 << 31) - 1) return Err{SPH_E_CAPACITY, "too many particles (limit 2^31-1)"};
+    if (n > 0 && (!in->x || !in->y || !in->z || !in->h || !in->m || !in->u || !in->vx || !in->vy || !in->vz))
+        return Err{SPH_E_ARG, "null particle array"};
+    if (prm->n_split < 1 || !(prm->split_frac >= 0.f && prm->split_frac <= 1.f) || !(prm->h_slack >= 0.f) ||
+        prm->max_depth < 0 || prm->max_depth > 16)
+        return Err{SPH_E_ARG, "bad decomposition parameters"};
+    t->prm = *prm;
+    t->nsets = in->nsets;
+    t->n = n;
+    t->off.assign(in->offsets, in->offsets + in->nsets + 1);
+    t->built = t->sorted = t->have_density = false;
+    t->hash = (prm->flags & SPH_FLAG_PAIR_HASH) != 0;
+    t->invalidate_graph();
+
+    // ---- per-set h statistics -> top grids ------------------------------
+    const int S = in->nsets;
+    float* d_hmax;
+    int* d_bad;
+    SetInfo* d_sets;
+    ERRTRY(t->alloc(t->b_sets, sizeof(SetInfo) * S, (void**)&d_sets));
+    ERRTRY(t->alloc(t->b_small, sizeof(float) * S + sizeof(int) * S + 64, (void**)&d_hmax));
+    d_bad = (int*)(d_hmax + S);
+    std::vector<SetInfo> sets(S);
+    for (int s = 0; s < S; ++s) {
+        sets[s].first = in->offsets[s];
+        sets[s].count = in->offsets[s + 1] - in->offsets[s];
+        sets[s].box = in->box[s];
+    }
+    HIPTRY(hipMemcpyAsync(d_sets, sets.data(), sizeof(SetInfo) * S, hipMemcpyHostToDevice, st));
+    std::vector<float> hmax(S, 0.f);
+    std::vector<int> bad(S, 0);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_set_hstats, dim3(S), dim3(256), 0, st, d_sets, in->h, d_hmax, d_bad);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipMemcpyAsync(hmax.data(), d_hmax, sizeof(float) * S, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(bad.data(), d_bad, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+    }
+    int max_lg = 0;
+    int64_t ntop = 0;
+    for (int s = 0; s < S; ++s) {
+        if (bad[s]) return Err{SPH_E_ARG, "set " + std::to_string(s) + ": h must be finite and > 0"};
+        double hd = (double)hmax[s] * (1.0 + (double)prm->h_slack);
+        double box = sets[s].box;
+        if (sets[s].count > 0 && !(hd <= 0.5 * box))
+            return Err{SPH_E_ARG, "set " + std::to_string(s) + ": h*(1+slack) must be <= box/2"};
+        int lg = 1;
+        if (prm->top_grid > 0) {
+            int g = prm->top_grid;
+            if ((g & (g - 1)) || g < 2) return Err{SPH_E_ARG, "top_grid must be a power of two >= 2"};
+            lg = 0;
+            while ((1 << lg) < g) ++lg;
+            if (box / g < hd) return Err{SPH_E_ARG, "top_grid cells smaller than h"};
+        } else if (sets[s].count == 0) {
+            lg = 1;
+        } else {
+            while (lg < KEY_BITS_PER_DIM && box / (double)(1 << (lg + 1)) >= hd && (1 << (3 * (lg + 1))) <= (1 << 21))
+                ++lg;
+        }
+        sets[s].lgG = lg;
+        sets[s].L0 = box / (double)(1 << lg);
+        sets[s].top_base = (int32_t)ntop;
+        ntop += (int64_t)1 << (3 * lg);
+        max_lg = std::max(max_lg, lg);
+    }
+    if (ntop > (int64_t)1 << 26) return Err{SPH_E_CAPACITY, "too many top cells"};
+    int depth = std::min(prm->max_depth, KEY_BITS_PER_DIM - max_lg);
+    if (depth < 0) return Err{SPH_E_CAPACITY, "top grid too fine for the key layout"};
+    const int bmax = max_lg + depth;
+    int setbits = 0;
+    while ((1 << setbits) < S) ++setbits;
+    if (3 * bmax + setbits > 64) return Err{SPH_E_CAPACITY, "key layout exceeds 64 bits"};
+    for (int s = 0; s < S; ++s) sets[s].key_shift = 3 * (bmax - sets[s].lgG - depth);
+    t->sets = sets;
+    t->depth = depth;
+    t->key_bits = 3 * bmax + setbits;
+    HIPTRY(hipMemcpyAsync(d_sets, sets.data(), sizeof(SetInfo) * S, hipMemcpyHostToDevice, st));
+    t->d_sets = d_sets;
+
+    // ---- particles: keys, sort, gather ----------------------------------
+    const int64_t nn = std::max<int64_t>(n, 1);
+    ERRTRY(t->alloc(t->b_key, sizeof(uint64_t) * nn, (void**)&t->key));
+    ERRTRY(t->alloc(t->b_key2, sizeof(uint64_t) * nn, (void**)&t->key2));
+    ERRTRY(t->alloc(t->b_val, sizeof(uint32_t) * nn, (void**)&t->val));
+    ERRTRY(t->alloc(t->b_val2, sizeof(uint32_t) * nn, (void**)&t->val2));
+    ERRTRY(t->alloc(t->b_perm, sizeof(uint32_t) * nn, (void**)&t->perm));
+    ERRTRY(t->alloc(t->b_pos, sizeof(float4) * nn, (void**)&t->pos));
+    ERRTRY(t->alloc(t->b_pv, sizeof(float4) * nn, (void**)&t->pv));
+    ERRTRY(t->alloc(t->b_ph, sizeof(float) * nn, (void**)&t->ph));
+    ERRTRY(t->alloc(t->b_hdec, sizeof(float) * nn, (void**)&t->hdec));
+    ERRTRY(t->alloc(t->b_pu, sizeof(float) * nn, (void**)&t->pu));
+    ERRTRY(t->alloc(t->b_bound, sizeof(float) * nn, (void**)&t->bound));
+    ERRTRY(t->alloc(t->b_mix, sizeof(uint64_t) * nn, (void**)&t->mix));
+    ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(nn), radix_tmp_words(1 << 20)),
+                    (void**)&t->rs_tmp));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, in->x, in->y, in->z,
+                           depth, bmax, t->key2, t->val2);
+        HIPTRY(hipGetLastError());
+        bool alt = false;
+        HIPTRY(radix_sort(t->key2, t->val2, t->key, t->val, n, t->key_bits, t->rs_tmp, st, &alt));
+        if (!alt) {   // result is in key2/val2: swap the roles
+            std::swap(t->key, t->key2);
+            std::swap(t->val, t->val2);
+            std::swap(t->b_key, t->b_key2);
+            std::swap(t->b_val, t->b_val2);
+        }
+        hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, depth, bmax, t->key,
+                           t->val, in->x, in->y, in->z, in->h, in->m, in->u, in->vx, in->vy, in->vz,
+                           prm->h_slack, t->pos, t->ph, t->hdec, t->pu, t->pv, t->perm, t->mix);
+        HIPTRY(hipGetLastError());
+    }
+
+    // ---- levels: cells and tasks ----------------------------------------
+    // capacity estimate; grown on demand
+    int64_t cap_cells = ntop + 8 * (n / (prm->n_split + 1) + 1) * (depth + 1) / 2 + 64;
+    ERRTRY(t->alloc(t->b_cell, sizeof(Cell) * cap_cells, (void**)&t->cells));
+    t->lvl_start.assign(1, 0);
+    t->lvl_start.push_back(ntop);
+    hipLaunchKernelGGL(k_top_cells, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, S, (int)ntop, depth, bmax,
+                       t->key, t->cells);
+    HIPTRY(hipGetLastError());
+    hipLaunchKernelGGL(k_cell_stats, dim3(nblk(ntop, 4)), dim3(256), 0, st, d_sets, depth, bmax, 0, (int64_t)0,
+                       ntop, t->key, t->hdec, prm->n_split, prm->split_frac, t->cells);
+    HIPTRY(hipGetLastError());
+
+    // top-level tasks
+    ERRTRY(t->scratch(ntop + 1));
+#define total (t->d_total)
+    hipLaunchKernelGGL(k_top_task_count, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, S, (int)ntop, t->cells,
+                       t->sc_a);
+    HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ntop, t->sc_tmp, total, st));
+    uint32_t nt0 = 0;
+    ERRTRY(read_u32(total, &nt0, st));
+    int64_t cap_tasks = std::max<int64_t>(nt0, 1);
+    ERRTRY(t->alloc(t->b_taskA, sizeof(int4) * cap_tasks, (void**)&t->taskA));
+    hipLaunchKernelGGL(k_top_task_emit, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, (int)ntop, t->cells,
+                       t->sc_b, t->taskA);
+    HIPTRY(hipGetLastError());
+    int64_t ncur = nt0;        // tasks of the current level (in taskA)
+    int64_t nfinal = 0;        // final tasks (in finals)
+    ERRTRY(t->alloc(t->b_final, sizeof(int4) * std::max<int64_t>(nt0, 1), (void**)&t->finals));
+
+    int level = 0;
+    for (;; ++level) {
+        const int64_t c0 = t->lvl_start[level], c1 = t->lvl_start[level + 1];
+        const int64_t nlev = c1 - c0;
+        // children of split cells at this level
+        ERRTRY(t->scratch(std::max(nlev, ncur) + 1));
+        hipLaunchKernelGGL(k_split_flags, dim3(nblk(nlev, 256)), dim3(256), 0, st, t->cells, c0, c1, t->sc_a);
+        HIPTRY(exclusive_scan(t->sc_a, t->sc_b, nlev, t->sc_tmp, total, st));
+        uint32_t nsplit = 0;
+        ERRTRY(read_u32(total, &nsplit, st));
+        const int64_t nnext = 8 * (int64_t)nsplit;
+        if (c1 + nnext > (int64_t)1 << 27) return Err{SPH_E_CAPACITY, "too many cells (limit 2^27)"};
+        if (c1 + nnext > cap_cells) {
+            int64_t nc = std::max<int64_t>(c1 + nnext, cap_cells * 3 / 2);
+            ERRTRY(t->grow(t->b_cell, sizeof(Cell) * c1, sizeof(Cell) * nc, (void**)&t->cells));
+            cap_cells = nc;
+        }
+        if (nsplit > 0) {
+            hipLaunchKernelGGL(k_make_children, dim3(nblk(nlev, 256)), dim3(256), 0, st, c0, c1, c1, t->sc_b,
+                               t->cells);
+            HIPTRY(hipGetLastError());
+            hipLaunchKernelGGL(k_cell_stats, dim3(nblk(nnext, 4)), dim3(256), 0, st, d_sets, depth, bmax,
+                               level + 1, c1, c1 + nnext, t->key, t->hdec, prm->n_split, prm->split_frac,
+                               t->cells);
+            HIPTRY(hipGetLastError());
+        }
+        t->lvl_start.push_back(c1 + nnext);
+        // decide this level's tasks
+        if (ncur > 0) {
+            ERRTRY(t->scratch(ncur + 1));
+            hipLaunchKernelGGL(k_task_decide, dim3(nblk(ncur, 256)), dim3(256), 0, st, d_sets, t->taskA, ncur,
+                               t->cells, t->sc_a, t->sc_c);
+            HIPTRY(hipGetLastError());
+            HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ncur, t->sc_tmp, total, st));
+            uint32_t nf = 0, nc = 0;
+            ERRTRY(read_u32(total, &nf, st));
+            HIPTRY(exclusive_scan(t->sc_c, t->sc_d, ncur, t->sc_tmp, total, st));
+            ERRTRY(read_u32(total, &nc, st));
+            if (nfinal + nf > (int64_t)0x7FFFFFFF) return Err{SPH_E_CAPACITY, "too many tasks"};
+            ERRTRY(t->grow(t->b_final, sizeof(int4) * nfinal, sizeof(int4) * std::max<int64_t>(nfinal + nf, 1),
+                           (void**)&t->finals));
+            ERRTRY(t->alloc(t->b_taskB, sizeof(int4) * std::max<int64_t>(nc, 1), (void**)&t->taskB));
+            hipLaunchKernelGGL(k_task_emit, dim3(nblk(ncur, 256)), dim3(256), 0, st, t->taskA, ncur, t->cells,
+                               t->sc_a, t->sc_b, t->sc_c, t->sc_d, t->finals + nfinal, t->taskB);
+            HIPTRY(hipGetLastError());
+            nfinal += nf;
+            std::swap(t->taskA, t->taskB);
+            std::swap(t->b_taskA, t->b_taskB);
+            ncur = nc;
+        }
+        if (nsplit == 0 && ncur == 0) break;
+        if (nsplit == 0 && ncur > 0) {
+            // no deeper cells: remaining tasks cannot split further
+            // (k_task_decide only splits tasks of split cells)
+            return Err{SPH_E_STATE, "internal: tasks left without split cells"};
+        }
+    }
+    t->nlevels = level + 1;
+    t->ncells = t->lvl_start.back();
+    t->ntasks = nfinal;
+
+    // ---- leaves -> chunks; particle h bounds ------------------------------
+    const int64_t nc = t->ncells;
+    ERRTRY(t->scratch(nc + 1));
+    HIPTRY(fill_u32((uint32_t*)t->d_maxleaf, 1, 0, st));
+    hipLaunchKernelGGL(k_chunk_count, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_a, t->d_maxleaf);
+    HIPTRY(exclusive_scan(t->sc_a, t->sc_b, nc, t->sc_tmp, total, st));
+    uint32_t nchunks = 0;
+    ERRTRY(read_u32(total, &nchunks, st));
+    static thread_local int maxleaf;
+    maxleaf = 0;
+    HIPTRY(hipMemcpyAsync(&maxleaf, t->d_maxleaf, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    ERRTRY(t->alloc(t->b_chunk, sizeof(int4) * std::max<uint32_t>(nchunks, 1), (void**)&t->chunks));
+    hipLaunchKernelGGL(k_chunk_emit, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_b, t->chunks);
+    HIPTRY(hipGetLastError());
+    t->nchunks = nchunks;
+    t->max_leaf = maxleaf;
+    if (nchunks > 0) {
+        hipLaunchKernelGGL(k_particle_bound, dim3(nblk(nchunks, 4)), dim3(256), 0, st, t->chunks, (int64_t)nchunks,
+                           t->cells, t->bound);
+        HIPTRY(hipGetLastError());
+    }
+
+    // ---- per-cell interaction lists (CSR) --------------------------------
+    const int64_t ne = 2 * nfinal;
+    ERRTRY(t->alloc(t->b_csr, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr));
+    ERRTRY(t->alloc(t->b_csr2, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr2));
+    ERRTRY(t->alloc(t->b_csroff, sizeof(uint32_t) * (nc + 1), (void**)&t->csr_off));
+    HIPTRY(fill_u32((uint32_t*)t->d_npairs, 1, 0, st));
+    int npairs = 0;
+    if (ne > 0) {
+        ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(ne), radix_tmp_words(nn)),
+                        (void**)&t->rs_tmp));
+        hipLaunchKernelGGL(k_csr_keys, dim3(nblk(nfinal, 256)), dim3(256), 0, st, t->finals, nfinal, t->csr,
+                           t->d_npairs);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipMemcpyAsync(&npairs, t->d_npairs, sizeof(int), hipMemcpyDeviceToHost, st));
+        bool alt = false;
+        HIPTRY(radix_sort(t->csr, nullptr, t->csr2, nullptr, ne, 64, t->rs_tmp, st, &alt));
+        if (alt) {
+            std::swap(t->csr, t->csr2);
+            std::swap(t->b_csr, t->b_csr2);
+        }
+        HIPTRY(hipStreamSynchronize(st));
+    }
+    t->npairs = npairs;
+    t->nleaves = nfinal - npairs;
+    HIPTRY(fill_u32(t->sc_a, nc, 0, st));
+    if (npairs > 0) {
+        hipLaunchKernelGGL(k_csr_count, dim3(nblk(2 * (int64_t)npairs, 256)), dim3(256), 0, st, t->csr,
+                           2 * (int64_t)npairs, t->sc_a);
+        HIPTRY(hipGetLastError());
+    }
+    HIPTRY(exclusive_scan(t->sc_a, t->csr_off, nc, t->sc_tmp, t->csr_off + nc, st));
+    HIPTRY(hipStreamSynchronize(st));
+    t->built = true;
+    return Err{};
+}
+
+Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
+    hipStream_t st = ctx->stream;
+    if (!t->built) return Err{SPH_E_STATE, "sort_pairs before build_cells"};
+    t->invalidate_graph();
+    const int64_t nc = t->ncells;
+    const int64_t nca = nc * NAXES;
+    ERRTRY(t->alloc(t->b_segoff, sizeof(uint32_t) * std::max<int64_t>(nca, 1), (void**)&t->segoff));
+    ERRTRY(t->scratch(nca + 1));
+    HIPTRY(fill_u32(t->sc_a, nca, 0, st));
+    HIPTRY(fill_u32(t->segoff, nca, 0xFFFFFFFFu, st));
+    const int64_t ne = 2 * t->npairs;
+    if (ne > 0) {
+        hipLaunchKernelGGL(k_seg_need, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, t->sc_a);
+        HIPTRY(hipGetLastError());
+    }
+    HIPTRY(exclusive_scan(t->sc_a, t->sc_b, nca, t->sc_tmp, total, st));
+    uint32_t ns = 0;
+    ERRTRY(read_u32(total, &ns, st));
+    t->nsegs = ns;
+    int64_t nent = 0;
+    if (ns > 0) {
+        ERRTRY(t->alloc(t->b_seglist, sizeof(uint32_t) * ns * 3, (void**)&t->seglist));
+        uint32_t* lens = t->seglist + ns;
+        uint32_t* soff = t->seglist + 2 * (int64_t)ns;
+        hipLaunchKernelGGL(k_seg_list, dim3(nblk(nca, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, nca, t->cells,
+                           t->seglist, lens);
+        HIPTRY(hipGetLastError());
+        HIPTRY(exclusive_scan(lens, soff, ns, t->sc_tmp, total, st));
+        uint32_t tot = 0;
+        ERRTRY(read_u32(total, &tot, st));
+        nent = tot;
+        hipLaunchKernelGGL(k_seg_table, dim3(nblk(ns, 256)), dim3(256), 0, st, t->seglist, soff, (int64_t)ns,
+                           t->segoff);
+        HIPTRY(hipGetLastError());
+        ERRTRY(t->alloc(t->b_segproj, sizeof(float) * std::max<int64_t>(nent, 1), (void**)&t->segproj));
+        ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
+        hipLaunchKernelGGL(k_seg_sort_lds, dim3(ns), dim3(256), 0, st, t->seglist, soff, (int64_t)ns, t->cells,
+                           t->pos, t->segproj, t->segidx);
+        HIPTRY(hipGetLastError());
+        // segments too long for LDS: one global radix sort over all of them
+        ERRTRY(t->scratch(std::max<int64_t>(nca, ns) + 1));
+        hipLaunchKernelGGL(k_big_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_a);
+        HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ns, t->sc_tmp, total, st));
+        uint32_t nbig = 0;
+        ERRTRY(read_u32(total, &nbig, st));
+        if (nbig > 0) {
+            uint32_t* big = t->sc_c;
+            uint32_t* blen = t->sc_d;
+            hipLaunchKernelGGL(k_big_list, dim3(nblk(ns, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, (int64_t)ns,
+                               lens, big, blen);
+            HIPTRY(hipGetLastError());
+            uint32_t* boff = t->sc_a;   // flags no longer needed
+            HIPTRY(exclusive_scan(blen, boff, nbig, t->sc_tmp, total, st));
+            uint32_t nbe = 0;
+            ERRTRY(read_u32(total, &nbe, st));
+            uint64_t *bk, *bk2;
+            uint32_t *bv, *bv2;
+            ERRTRY(t->alloc(t->b_bigk, sizeof(uint64_t) * nbe * 2, (void**)&bk));
+            ERRTRY(t->alloc(t->b_bigv, sizeof(uint32_t) * nbe * 2, (void**)&bv));
+            bk2 = bk + nbe;
+            bv2 = bv + nbe;
+            ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(nbe), radix_tmp_words(t->n)),
+                            (void**)&t->rs_tmp));
+            hipLaunchKernelGGL(k_big_keys, dim3(nbig), dim3(256), 0, st, big, boff, t->seglist, t->cells, t->pos,
+                               bk, bv);
+            HIPTRY(hipGetLastError());
+            int rb = 0;
+            while ((1u << rb) < nbig) ++rb;
+            bool alt = false;
+            HIPTRY(radix_sort(bk, bv, bk2, bv2, nbe, 32 + rb, t->rs_tmp, st, &alt));
+            if (alt) { bk = bk2; bv = bv2; }
+            hipLaunchKernelGGL(k_big_write, dim3(nblk(nbe, 256)), dim3(256), 0, st, bk, bv, (int64_t)nbe, boff, big,
+                               soff, t->segproj, t->segidx);
+            HIPTRY(hipGetLastError());
+        }
+    }
+    t->nsegent = nent;
+    HIPTRY(hipStreamSynchronize(st));
+    t->sorted = true;
+    return Err{};
+}
+#undef total
+
+}  // namespace sph

@@ -1,0 +1,989 @@
+// Density and force stages, the h_i Newton iteration, the ghost step and the
+// FP64 reductions.
+//
+// Work decomposition (owner computes, no floating-point atomics): one
+// wavefront owns a chunk of at most 64 particles of one leaf cell, one lane
+// per particle.  It walks, in a fixed order,
+//   * the leaf's self task (all particle pairs in the leaf), then
+//   * for the leaf and each of its ancestors, that cell's pair tasks
+//     (Section II-B lists), sweeping the partner cell's particles in their
+//     order along the cell-pair axis (Section II-C): the partner's list is
+//     staged 64 entries at a time in LDS and the sweep stops as soon as the
+//     next entry is farther along the axis than any lane's cutoff.
+// Every particle therefore meets each in-range partner exactly once per
+// stage, and sums in an order fixed by the tree alone.  Positions are FP32
+// offsets from the top cell origin; a task adds the exact top-cell shift of
+// its partner (a multiple of the top cell edge), so on inputs of the 2^-24
+// grid every coordinate difference is exact.  Sums use compensated
+// summation: Kahan for the positive density sums, Neumaier for the
+// mixed-sign force sums.
+#include <cmath>
+
+#include "sph_impl.h"
+
+namespace sph {
+
+constexpr float C8PI = 2.5464790894703255f;   // 8/pi: cubic-spline normalisation in 3-D
+constexpr int BLK = 256;                      // 4 wavefronts per block, each independent
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float unif(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ float wmax(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ void kahan(float& s, float& c, float x) {
+    float y = x - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+__device__ __forceinline__ void neumaier(float& s, float& c, float x) {
+    float t = s + x;
+    c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+}
+
+// Offset code tables: axis index and sign of each of the 27 offset codes,
+// and the components of the 13 canonical directions.
+struct AxisTab {
+    int8_t axis[27], sign[27];
+    int8_t dx[13], dy[13], dz[13];
+    float norm[13];
+};
+
+__constant__ AxisTab c_ax;
+
+static AxisTab make_axis_table() {
+    AxisTab t{};
+    for (int c = 0; c < 27; ++c) {
+        int sg = 1;
+        int k = axis_of(c, &sg);
+        t.axis[c] = (int8_t)k;
+        t.sign[c] = (int8_t)sg;
+    }
+    for (int k = 0; k < 13; ++k) {
+        int c = axis_code(k);
+        t.dx[k] = (int8_t)ocx(c);
+        t.dy[k] = (int8_t)ocy(c);
+        t.dz[k] = (int8_t)ocz(c);
+        t.norm[k] = sqrtf((float)(abs(ocx(c)) + abs(ocy(c)) + abs(ocz(c))));
+    }
+    return t;
+}
+
+// Geometry of one pair entry seen from target cell A: shift S added to the
+// partner's stored positions, axis, sign, and the partner's projection offset.
+struct PairGeo {
+    float Sx, Sy, Sz;
+    float ddx, ddy, ddz;   // canonical direction (components -1/0/1)
+    float dn;              // its length
+    float projoff;         // d . S
+    int axis, sign;
+};
+
+__device__ __forceinline__ PairGeo pair_geo(const Cell& cA, int code, float L0) {
+    PairGeo g;
+    int ox = ocx(code), oy = ocy(code), oz = ocz(code);
+    int l = cA.level;
+    int tx = ((cA.ix + ox) >> l) - (cA.ix >> l);
+    int ty = ((cA.iy + oy) >> l) - (cA.iy >> l);
+    int tz = ((cA.iz + oz) >> l) - (cA.iz >> l);
+    g.Sx = (float)tx * L0;
+    g.Sy = (float)ty * L0;
+    g.Sz = (float)tz * L0;
+    g.axis = c_ax.axis[code];
+    g.sign = c_ax.sign[code];
+    g.ddx = (float)c_ax.dx[g.axis];
+    g.ddy = (float)c_ax.dy[g.axis];
+    g.ddz = (float)c_ax.dz[g.axis];
+    g.dn = c_ax.norm[g.axis];
+    float po = g.ddx * g.Sx;
+    po = po + g.ddy * g.Sy;
+    po = po + g.ddz * g.Sz;
+    g.projoff = po;
+    return g;
+}
+
+__device__ __forceinline__ float proj3(float dx, float dy, float dz, float x, float y, float z) {
+    float r = dx * x;
+    r = r + dy * y;
+    r = r + dz * z;
+    return r;
+}
+
+struct DensArgs {
+    const Cell* cells;
+    const SetInfo* sets;
+    const int4* chunks;
+    int nchunks;
+    int* counter;
+    const float4* pos;
+    const float* ph;
+    const uint64_t* mix;
+    const uint8_t* active;
+    const uint64_t* csr;
+    const uint32_t* csr_off;
+    const uint32_t* segoff;
+    const float* segproj;
+    const uint32_t* segidx;
+    const int32_t* status;
+    float *rho, *drho, *nw, *dnw;
+    int32_t* nngb;
+    uint64_t* hash;
+};
+
+struct DensAcc {
+    float sf = 0, cf = 0, sg = 0, cg = 0, sw = 0, cw = 0, sq = 0, cq = 0;
+    int nn = 0;
+    uint64_t hs = 0;
+};
+
+__device__ __forceinline__ void dens_pair(DensAcc& a, float r2, float hinv, float mj, uint64_t mixj) {
+    float r = sqrtf(r2);
+    float q = r * hinv;
+    float q2 = q * q;
+    float t = 1.f - q;
+    float t2 = t * t;
+    bool inner = q < 0.5f;
+    float f = inner ? fmaf(6.f * q2, q - 1.f, 1.f) : 2.f * t2 * t;
+    float df = inner ? q * fmaf(18.f, q, -12.f) : -6.f * t2;
+    float g = fmaf(q, df, 3.f * f);
+    kahan(a.sf, a.cf, mj * f);
+    kahan(a.sg, a.cg, mj * g);
+    kahan(a.sw, a.cw, f);
+    kahan(a.sq, a.cq, q * df);
+    a.nn += 1;
+    a.hs += mixj;
+}
+
+template <bool SOLVE, bool HASH>
+__global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
+    __shared__ float4 s_p[BLK / 64][64];
+    __shared__ float s_t[BLK / 64][64];
+    __shared__ uint64_t s_m[BLK / 64][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (SOLVE && a.status[0]) return;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(a.counter, 1);
+        item = uni(__shfl(item, 0, 64));
+        if (item >= a.nchunks) break;
+        const int4 ch = a.chunks[item];
+        const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
+        const int p = p0 + lane;
+        const bool valid = lane < cnt;
+        bool act = valid;
+        if (SOLVE) act = valid && a.active[p];
+        if (SOLVE && __ballot(act) == 0) continue;
+        float4 xi = valid ? a.pos[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float hi = valid ? a.ph[p] : 1.f;
+        float hi2 = act ? hi * hi : -1.f;
+        float hinv = 1.f / hi;
+        DensAcc acc;
+
+        // ---- self task of the leaf ---------------------------------------
+        const Cell C = a.cells[leaf];
+        const int cend = C.first + C.count;
+        for (int base = C.first; base < cend; base += 64) {
+            const int nsrc = min(64, cend - base);
+            if (lane < nsrc) {
+                s_p[w][lane] = a.pos[base + lane];
+                if (HASH) s_m[w][lane] = a.mix[base + lane];
+            }
+            wave_lds_sync();
+            for (int jj = 0; jj < nsrc; ++jj) {
+                float4 q = s_p[w][jj];
+                float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+                float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                if (r2 < hi2 && base + jj != p) dens_pair(acc, r2, hinv, q.w, HASH ? s_m[w][jj] : 0ull);
+            }
+            wave_lds_sync();
+        }
+
+        // ---- pair tasks of the leaf and of its ancestors ------------------
+        int A = leaf;
+        while (A >= 0) {
+            const Cell cA = a.cells[A];
+            const float L0 = (float)a.sets[cA.set].L0;
+            const float tiny = 1e-5f * L0;
+            const uint32_t e1 = a.csr_off[A + 1];
+            for (uint32_t e = a.csr_off[A]; e < e1; ++e) {
+                const uint64_t key = a.csr[e];
+                const int B = (int)((key >> 5) & 0xFFFFFFFFull);
+                const PairGeo g = pair_geo(cA, (int)(key & 31), L0);
+                const Cell cB = a.cells[B];
+                const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
+                const int len = cB.count;
+                const float sgn = (float)g.sign;
+                float ti = sgn * proj3(g.ddx, g.ddy, g.ddz, xi.x, xi.y, xi.z);
+                float reach = act ? ti + fmaf(hi * g.dn, 1.000002f, tiny) : -INFINITY;
+                const float Tmax = unif(wmax(reach));
+                for (int base = 0; base < len; base += 64) {
+                    const int nsrc = min(64, len - base);
+                    bool ok = false;
+                    if (lane < nsrc) {
+                        int qq = g.sign > 0 ? base + lane : len - 1 - base - lane;
+                        uint32_t j = a.segidx[so + qq];
+                        float tj = sgn * (a.segproj[so + qq] + g.projoff);
+                        ok = tj <= Tmax;
+                        if (ok) {
+                            float4 pj = a.pos[j];
+                            s_p[w][lane] = make_float4(pj.x + g.Sx, pj.y + g.Sy, pj.z + g.Sz, pj.w);
+                            if (HASH) s_m[w][lane] = a.mix[j];
+                        }
+                    }
+                    const int nuse = __popcll(__ballot(ok));
+                    wave_lds_sync();
+                    for (int jj = 0; jj < nuse; ++jj) {
+                        float4 q = s_p[w][jj];
+                        float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+                        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        if (r2 < hi2) dens_pair(acc, r2, hinv, q.w, HASH ? s_m[w][jj] : 0ull);
+                    }
+                    wave_lds_sync();
+                    if (nuse < nsrc) break;
+                }
+            }
+            A = cA.parent;
+        }
+
+        if (act) {
+            float h3 = hi * hi * hi;
+            float mi = xi.w;
+            a.rho[p] = C8PI / h3 * (mi + (acc.sf - acc.cf));
+            a.drho[p] = -C8PI / (h3 * hi) * (3.f * mi + (acc.sg - acc.cg));
+            a.nw[p] = (32.f / 3.f) * (1.f + (acc.sw - acc.cw));
+            a.dnw[p] = -(32.f / 3.f) * hinv * (acc.sq - acc.cq);
+            a.nngb[p] = acc.nn;
+            if (HASH) a.hash[p] = acc.hs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Force stage
+// ---------------------------------------------------------------------------
+struct ForceArgs {
+    const Cell* cells;
+    const SetInfo* sets;
+    const int4* chunks;
+    int nchunks;
+    int* counter;
+    const float4* pos;
+    const float* ph;
+    const float4* pv;
+    const float* rho;
+    const float* A;
+    const float* cs;
+    const uint64_t* mix;
+    const uint64_t* csr;
+    const uint32_t* csr_off;
+    const uint32_t* segoff;
+    const float* segproj;
+    const uint32_t* segidx;
+    float alpha;
+    float *ax, *ay, *az, *du, *vsig, *S;
+    int32_t* nf;
+    uint64_t* hash;
+};
+
+struct ForceLane {
+    float4 x;      // position, mass
+    float4 v;      // velocity, rho
+    float h, hinv, K, A, c;
+};
+
+struct ForceAcc {
+    float ax = 0, cax = 0, ay = 0, cay = 0, az = 0, caz = 0, du = 0, cdu = 0, vs = 0, S = 0, cS = 0;
+    int nn = 0;
+    uint64_t hs = 0;
+};
+
+__device__ __forceinline__ float gradF(float q, float h, float rinv) {
+    // f'(q)/q of the cubic spline, zero outside the support
+    float t = 1.f - q;
+    float outer = q < 1.f ? -6.f * t * t * h * rinv : 0.f;
+    return q < 0.5f ? fmaf(18.f, q, -12.f) : outer;
+}
+
+__device__ __forceinline__ void force_pair(ForceAcc& a, const ForceLane& L, float dx, float dy, float dz,
+                                           float r2, const float4& q, const float4& sh, const float4& sv,
+                                           float cj, uint64_t mixj, float alpha) {
+    float r = sqrtf(r2);
+    float rinv = 1.f / r;
+    float ki = L.K * gradF(r * L.hinv, L.h, rinv);
+    float kj = sh.z * gradF(r * sh.y, sh.x, rinv);
+    float vdx = L.v.x - sv.x, vdy = L.v.y - sv.y, vdz = L.v.z - sv.z;
+    float vdotx = fmaf(vdx, dx, fmaf(vdy, dy, vdz * dz));
+    float wv = vdotx * rinv;
+    float visc = 0.f;
+    if (wv < 0.f) visc = -alpha * (L.c + cj - 3.f * wv) * wv / (L.v.w + sv.w);
+    float kbar = 0.5f * (ki + kj);
+    float s = fmaf(L.A, ki, fmaf(sh.w, kj, visc * kbar));
+    float ms = q.w * s;
+    neumaier(a.ax, a.cax, -ms * dx);
+    neumaier(a.ay, a.cay, -ms * dy);
+    neumaier(a.az, a.caz, -ms * dz);
+    neumaier(a.du, a.cdu, q.w * vdotx * fmaf(L.A, ki, 0.5f * visc * kbar));
+    a.vs = fmaxf(a.vs, L.c + cj - 3.f * fminf(wv, 0.f));
+    kahan(a.S, a.cS, fabsf(ms) * r);
+    a.nn += 1;
+    a.hs += mixj;
+}
+
+template <bool HASH>
+__global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
+    __shared__ float4 s_p[BLK / 64][64];   // x, y, z, m
+    __shared__ float4 s_h[BLK / 64][64];   // h, 1/h, K, A
+    __shared__ float4 s_v[BLK / 64][64];   // vx, vy, vz, rho
+    __shared__ float s_c[BLK / 64][64];
+    __shared__ uint64_t s_m[BLK / 64][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+
+    auto stage = [&](int slot, uint32_t j, float Sx, float Sy, float Sz) {
+        float4 pj = a.pos[j];
+        float hj = a.ph[j];
+        float hinv = 1.f / hj;
+        float h2 = hinv * hinv;
+        float4 vj = a.pv[j];
+        s_p[w][slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, pj.w);
+        s_h[w][slot] = make_float4(hj, hinv, C8PI * h2 * h2 * hinv, a.A[j]);
+        s_v[w][slot] = make_float4(vj.x, vj.y, vj.z, a.rho[j]);
+        s_c[w][slot] = a.cs[j];
+        if (HASH) s_m[w][slot] = a.mix[j];
+    };
+
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(a.counter, 1);
+        item = uni(__shfl(item, 0, 64));
+        if (item >= a.nchunks) break;
+        const int4 ch = a.chunks[item];
+        const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
+        const int p = p0 + lane;
+        const bool act = lane < cnt;
+        ForceLane L;
+        L.x = act ? a.pos[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+        L.h = act ? a.ph[p] : 1.f;
+        L.hinv = 1.f / L.h;
+        {
+            float h2 = L.hinv * L.hinv;
+            L.K = C8PI * h2 * h2 * L.hinv;
+        }
+        float4 vv = act ? a.pv[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+        L.v = make_float4(vv.x, vv.y, vv.z, act ? a.rho[p] : 1.f);
+        L.A = act ? a.A[p] : 0.f;
+        L.c = act ? a.cs[p] : 0.f;
+        const float hi2 = act ? L.h * L.h : -1.f;
+        ForceAcc acc;
+
+        // ---- self task of the leaf ---------------------------------------
+        const Cell C = a.cells[leaf];
+        const int cend = C.first + C.count;
+        for (int base = C.first; base < cend; base += 64) {
+            const int nsrc = min(64, cend - base);
+            if (lane < nsrc) stage(lane, (uint32_t)(base + lane), 0.f, 0.f, 0.f);
+            wave_lds_sync();
+            for (int jj = 0; jj < nsrc; ++jj) {
+                float4 q = s_p[w][jj];
+                float4 sh = s_h[w][jj];
+                float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
+                float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                if (act && r2 < fmaxf(hi2, sh.x * sh.x) && base + jj != p)
+                    force_pair(acc, L, dx, dy, dz, r2, q, sh, s_v[w][jj], s_c[w][jj], HASH ? s_m[w][jj] : 0ull,
+                               a.alpha);
+            }
+            wave_lds_sync();
+        }
+
+        // ---- pair tasks -----------------------------------------------------
+        int A = leaf;
+        while (A >= 0) {
+            const Cell cA = a.cells[A];
+            const float L0 = (float)a.sets[cA.set].L0;
+            const float tiny = 1e-5f * L0;
+            const uint32_t e1 = a.csr_off[A + 1];
+            for (uint32_t e = a.csr_off[A]; e < e1; ++e) {
+                const uint64_t key = a.csr[e];
+                const int B = (int)((key >> 5) & 0xFFFFFFFFull);
+                const PairGeo g = pair_geo(cA, (int)(key & 31), L0);
+                const Cell cB = a.cells[B];
+                const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
+                const int len = cB.count;
+                const float sgn = (float)g.sign;
+                const float cut = fmaxf(L.h, cB.hcur) * g.dn;
+                float ti = sgn * proj3(g.ddx, g.ddy, g.ddz, L.x.x, L.x.y, L.x.z);
+                float reach = act ? ti + fmaf(cut, 1.000002f, tiny) : -INFINITY;
+                const float Tmax = unif(wmax(reach));
+                for (int base = 0; base < len; base += 64) {
+                    const int nsrc = min(64, len - base);
+                    bool ok = false;
+                    if (lane < nsrc) {
+                        int qq = g.sign > 0 ? base + lane : len - 1 - base - lane;
+                        uint32_t j = a.segidx[so + qq];
+                        float tj = sgn * (a.segproj[so + qq] + g.projoff);
+                        ok = tj <= Tmax;
+                        if (ok) stage(lane, j, g.Sx, g.Sy, g.Sz);
+                    }
+                    const int nuse = __popcll(__ballot(ok));
+                    wave_lds_sync();
+                    for (int jj = 0; jj < nuse; ++jj) {
+                        float4 q = s_p[w][jj];
+                        float4 sh = s_h[w][jj];
+                        float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
+                        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        if (act && r2 < fmaxf(hi2, sh.x * sh.x))
+                            force_pair(acc, L, dx, dy, dz, r2, q, sh, s_v[w][jj], s_c[w][jj],
+                                       HASH ? s_m[w][jj] : 0ull, a.alpha);
+                    }
+                    wave_lds_sync();
+                    if (nuse < nsrc) break;
+                }
+            }
+            A = cA.parent;
+        }
+
+        if (act) {
+            a.ax[p] = acc.ax + acc.cax;
+            a.ay[p] = acc.ay + acc.cay;
+            a.az[p] = acc.az + acc.caz;
+            a.du[p] = acc.du + acc.cdu;
+            a.vsig[p] = acc.vs;
+            a.S[p] = acc.S - acc.cS;
+            a.nf[p] = acc.nn;
+            if (HASH) a.hash[p] = acc.hs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Newton step on h (per particle), ghost, per-cell current h max, scatters,
+// reductions, counters.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_i32(int32_t* p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_solve_init(int64_t n, uint8_t* active, float* lo, float* hi) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    active[p] = 1;
+    lo[p] = 0.f;
+    hi[p] = INFINITY;
+}
+
+// One safeguarded Newton step on N_w(h) = target for every active particle:
+// converged (|N_w - target| <= tol, tested in FP64) particles keep h and
+// their density; the rest move h and stay active.  status[0] is raised when
+// a new h reaches the bound its cells support; status[1] counts the
+// particles still active.
+__global__ void k_newton(int64_t n, uint8_t* __restrict__ active, const float* __restrict__ nw,
+                         const float* __restrict__ dnw, float* __restrict__ ph, const float* __restrict__ bound,
+                         float* __restrict__ lo, float* __restrict__ hi, double target, double tol,
+                         int32_t* __restrict__ status) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || !active[p]) return;
+    double err = (double)nw[p] - target;
+    if (fabs(err) <= tol) {
+        active[p] = 0;
+        return;
+    }
+    double h = ph[p];
+    double l = lo[p], u = hi[p];
+    if (err < 0) l = h; else u = h;
+    double d = dnw[p];
+    double hn = d > 0 ? h - err / d : -1.0;
+    bool bad = !(d > 0) || !(hn > l) || !(hn < u) || hn < 0.5 * h || hn > 2.0 * h;
+    if (bad) hn = isinf(u) ? 2.0 * h : 0.5 * (l + u);
+    float hf = (float)hn;
+    if (hf == (float)h) hf = err < 0 ? nextafterf((float)h, INFINITY) : nextafterf((float)h, 0.f);
+    lo[p] = (float)l;
+    hi[p] = (float)u;
+    ph[p] = hf;
+    if (!(hf < bound[p])) atomicExch(&status[0], 1);
+    atomicAdd(&status[1], 1);
+}
+
+__global__ void k_ghost(int64_t n, const float* __restrict__ ph, const float* __restrict__ rho,
+                        const float* __restrict__ drho, const float* __restrict__ u, float gamma,
+                        float* __restrict__ A, float* __restrict__ cs) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    float r = rho[p];
+    float P = (gamma - 1.f) * r * u[p];
+    float f = 1.f / (1.f + ph[p] / (3.f * r) * drho[p]);
+    A[p] = f * P / (r * r);
+    cs[p] = sqrtf(gamma * (gamma - 1.f) * u[p]);
+}
+
+__global__ __launch_bounds__(256) void k_cell_hcur(Cell* __restrict__ cells, int64_t nc, const float* __restrict__ ph) {
+    int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nc) return;
+    const int lane = threadIdx.x & 63;
+    const int first = cells[c].first, count = cells[c].count;
+    float m = 0.f;
+    for (int p = first + lane; p < first + count; p += 64) m = fmaxf(m, ph[p]);
+    m = wmax(m);
+    if (lane == 0) cells[c].hcur = m;
+}
+
+__global__ void k_scatter_density(int64_t n, const uint32_t* __restrict__ perm, const float* rho,
+                                  const float* drho, const float* nw, const float* dnw, const int32_t* nngb,
+                                  const uint64_t* hash, const float* ph, sph_density_out o) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t i = perm[p];
+    if (o.rho) o.rho[i] = rho[p];
+    if (o.drho_dh) o.drho_dh[i] = drho[p];
+    if (o.nw) o.nw[i] = nw[p];
+    if (o.dnw_dh) o.dnw_dh[i] = dnw[p];
+    if (o.nngb) o.nngb[i] = nngb[p];
+    if (o.hash && hash) o.hash[i] = hash[p];
+    if (o.h) o.h[i] = ph[p];
+}
+
+__global__ void k_scatter_force(int64_t n, const uint32_t* __restrict__ perm, const float* ax, const float* ay,
+                                const float* az, const float* du, const float* vs, const float* S,
+                                const int32_t* nf, const uint64_t* hash, sph_force_out o) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t i = perm[p];
+    if (o.ax) o.ax[i] = ax[p];
+    if (o.ay) o.ay[i] = ay[p];
+    if (o.az) o.az[i] = az[p];
+    if (o.dudt) o.dudt[i] = du[p];
+    if (o.vsig) o.vsig[i] = vs[p];
+    if (o.S) o.S[i] = S[p];
+    if (o.nforce) o.nforce[i] = nf[p];
+    if (o.hash && hash) o.hash[i] = hash[p];
+}
+
+constexpr int NRED = 8;
+
+// One block per reduction chunk (a range of one set): FP64 partial sums in a
+// fixed tree order.
+__global__ __launch_bounds__(256) void k_reduce_partial(const int4* __restrict__ red, const float4* __restrict__ pos,
+                                                        const float4* __restrict__ pv, const float* __restrict__ ax,
+                                                        const float* __restrict__ ay, const float* __restrict__ az,
+                                                        const float* __restrict__ du, const float* __restrict__ S,
+                                                        const int32_t* __restrict__ nngb,
+                                                        const int32_t* __restrict__ nf, double* __restrict__ part) {
+    __shared__ double s[NRED][256];
+    const int4 R = red[blockIdx.x];
+    double acc[NRED] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int p = R.y + threadIdx.x; p < R.y + R.z; p += 256) {
+        double m = pos[p].w;
+        float4 v = pv[p];
+        double a0 = ax[p], a1 = ay[p], a2 = az[p];
+        acc[0] += m * a0;
+        acc[1] += m * a1;
+        acc[2] += m * a2;
+        acc[3] += m * ((double)v.x * a0 + (double)v.y * a1 + (double)v.z * a2 + (double)du[p]);
+        acc[4] += m * (double)S[p];
+        acc[5] += (double)nngb[p];
+        acc[6] += (double)nf[p];
+    }
+    for (int f = 0; f < NRED; ++f) s[f][threadIdx.x] = acc[f];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int f = 0; f < NRED; ++f) s[f][threadIdx.x] += s[f][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < NRED) part[(int64_t)blockIdx.x * NRED + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_reduce_final(const int4* __restrict__ red, int nred, const double* __restrict__ part, int nsets,
+                               double* __restrict__ sums, double* __restrict__ sums2) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsets) return;
+    // chunks of a set are consecutive; find the first by binary search
+    int lo = 0, hi = nred;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (red[mid].x < s) lo = mid + 1; else hi = mid;
+    }
+    double acc[NRED] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r = lo; r < nred && red[r].x == s; ++r)
+        for (int f = 0; f < NRED; ++f) acc[f] += part[(int64_t)r * NRED + f];
+    for (int f = 0; f < NRED; ++f) {
+        if (sums) sums[(int64_t)s * NRED + f] = acc[f];
+        if (sums2) sums2[(int64_t)s * NRED + f] = acc[f];
+    }
+}
+
+// ===========================================================================
+// Host orchestration
+// ===========================================================================
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+#define HIPTRY(x)                                                                                   \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess) return Err{SPH_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+#define ERRTRY(x)                       \
+    do {                                \
+        Err e_ = (x);                   \
+        if (e_.st != SPH_OK) return e_; \
+    } while (0)
+
+static bool g_axis_ready[64] = {false};
+
+static Err ensure_axis_table(sph_ctx* ctx) {
+    if (ctx->device >= 0 && ctx->device < 64 && g_axis_ready[ctx->device]) return Err{};
+    AxisTab t = make_axis_table();
+    HIPTRY(hipMemcpyToSymbol(HIP_SYMBOL(c_ax), &t, sizeof(t)));
+    if (ctx->device >= 0 && ctx->device < 64) g_axis_ready[ctx->device] = true;
+    return Err{};
+}
+
+static Err ensure_state(sph_tree* t) {
+    const int64_t n = std::max<int64_t>(t->n, 1);
+    void* p;
+    // density: rho, drho, nw, dnw (float), nngb (int), hash (u64)
+    ERRTRY(t->alloc(t->b_dens, n * (4 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 64, &p));
+    t->hashd = (uint64_t*)p;
+    t->rho = (float*)(t->hashd + n);
+    t->drho = t->rho + n;
+    t->nw = t->drho + n;
+    t->dnw = t->nw + n;
+    t->nngb = (int32_t*)(t->dnw + n);
+    // solve: lo, hi, status, active
+    ERRTRY(t->alloc(t->b_solve, n * (2 * sizeof(float) + 1) + 256, &p));
+    t->lo = (float*)p;
+    t->hi = t->lo + n;
+    t->status = (int32_t*)(t->hi + n);
+    t->active = (uint8_t*)(t->status + 16);
+    // force: A, cs, ax, ay, az, du, vs, S (float), nf (int), hash (u64)
+    ERRTRY(t->alloc(t->b_force, n * (8 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 64, &p));
+    t->hashf = (uint64_t*)p;
+    t->A = (float*)(t->hashf + n);
+    t->cs = t->A + n;
+    t->fax = t->cs + n;
+    t->fay = t->fax + n;
+    t->faz = t->fay + n;
+    t->fdu = t->faz + n;
+    t->fvs = t->fdu + n;
+    t->fS = t->fvs + n;
+    t->fn = (int32_t*)(t->fS + n);
+    // reduction chunks
+    if (t->red_chunks.empty()) {
+        for (int s = 0; s < t->nsets; ++s) {
+            int64_t a = t->off[s], b = t->off[s + 1];
+            if (a == b) t->red_chunks.push_back(make_int4(s, (int)a, 0, 0));
+            for (int64_t q = a; q < b; q += 16384)
+                t->red_chunks.push_back(make_int4(s, (int)q, (int)std::min<int64_t>(16384, b - q), 0));
+        }
+        t->nred = (int64_t)t->red_chunks.size();
+        ERRTRY(t->alloc(t->b_red, t->nred * (sizeof(int4) + NRED * sizeof(double)) + (size_t)t->nsets * NRED * sizeof(double) + 64, &p));
+        t->partial = (double*)p;
+        t->sums_int = t->partial + t->nred * NRED;
+        t->d_red = (int4*)(t->sums_int + (int64_t)t->nsets * NRED);
+        HIPTRY(hipMemcpy(t->d_red, t->red_chunks.data(), sizeof(int4) * t->nred, hipMemcpyHostToDevice));
+    }
+    return Err{};
+}
+
+static int persistent_blocks(sph_ctx* ctx, int64_t items) {
+    int64_t want = (items + 3) / 4;
+    int64_t cap = (int64_t)ctx->n_cu * 8;
+    return (int)std::max<int64_t>(1, std::min(want, cap));
+}
+
+static DensArgs dens_args(sph_tree* t, int* counter) {
+    DensArgs a;
+    a.cells = t->cells;
+    a.sets = t->d_sets;
+    a.chunks = t->chunks;
+    a.nchunks = (int)t->nchunks;
+    a.counter = counter;
+    a.pos = t->pos;
+    a.ph = t->ph;
+    a.mix = t->mix;
+    a.active = t->active;
+    a.csr = t->csr;
+    a.csr_off = t->csr_off;
+    a.segoff = t->segoff;
+    a.segproj = t->segproj;
+    a.segidx = t->segidx;
+    a.status = t->status;
+    a.rho = t->rho;
+    a.drho = t->drho;
+    a.nw = t->nw;
+    a.dnw = t->dnw;
+    a.nngb = t->nngb;
+    a.hash = t->hashd;
+    return a;
+}
+
+static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, int* counter) {
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, counter, 1);
+    DensArgs a = dens_args(t, counter);
+    dim3 g(persistent_blocks(ctx, t->nchunks)), b(BLK);
+    if (solve) {
+        if (t->hash) hipLaunchKernelGGL((k_density<true, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_density<true, false>), g, b, 0, st, a);
+    } else {
+        if (t->hash) hipLaunchKernelGGL((k_density<false, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_density<false, false>), g, b, 0, st, a);
+    }
+}
+
+static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
+    hipStream_t st = ctx->stream;
+    const int64_t n = t->n;
+    hipLaunchKernelGGL(k_ghost, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->ph, t->rho, t->drho, t->pu,
+                       t->prm.gamma, t->A, t->cs);
+    hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, counter, 1);
+    ForceArgs a;
+    a.cells = t->cells;
+    a.sets = t->d_sets;
+    a.chunks = t->chunks;
+    a.nchunks = (int)t->nchunks;
+    a.counter = counter;
+    a.pos = t->pos;
+    a.ph = t->ph;
+    a.pv = t->pv;
+    a.rho = t->rho;
+    a.A = t->A;
+    a.cs = t->cs;
+    a.mix = t->mix;
+    a.csr = t->csr;
+    a.csr_off = t->csr_off;
+    a.segoff = t->segoff;
+    a.segproj = t->segproj;
+    a.segidx = t->segidx;
+    a.alpha = t->prm.alpha;
+    a.ax = t->fax;
+    a.ay = t->fay;
+    a.az = t->faz;
+    a.du = t->fdu;
+    a.vsig = t->fvs;
+    a.S = t->fS;
+    a.nf = t->fn;
+    a.hash = t->hashf;
+    dim3 g(persistent_blocks(ctx, t->nchunks)), b(BLK);
+    if (t->hash) hipLaunchKernelGGL((k_force<true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_force<false>), g, b, 0, st, a);
+}
+
+static void launch_reduce(sph_ctx* ctx, sph_tree* t, double* sums_out) {
+    hipStream_t st = ctx->stream;
+    if (t->nred == 0) return;
+    hipLaunchKernelGGL(k_reduce_partial, dim3((unsigned)t->nred), dim3(256), 0, st, t->d_red, t->pos, t->pv, t->fax,
+                       t->fay, t->faz, t->fdu, t->fS, t->nngb, t->fn, t->partial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(nblk(t->nsets, 64)), dim3(64), 0, st, t->d_red, (int)t->nred, t->partial,
+                       t->nsets, sums_out, t->sums_int);
+}
+
+static void launch_scatter_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* o) {
+    if (!o || t->n == 0) return;
+    hipLaunchKernelGGL(k_scatter_density, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->perm, t->rho,
+                       t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr, t->ph, *o);
+}
+
+static void launch_scatter_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* o) {
+    if (!o || t->n == 0) return;
+    hipLaunchKernelGGL(k_scatter_force, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->perm, t->fax,
+                       t->fay, t->faz, t->fdu, t->fvs, t->fS, t->fn, t->hash ? t->hashf : nullptr, *o);
+}
+
+static void ev_mark(sph_ctx* ctx, const char* name) {
+    if (!ctx->timing) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, ctx->stream);
+    ctx->ev.emplace_back(name, e);
+}
+
+static void ev_collect(sph_ctx* ctx) {
+    if (!ctx->timing || ctx->ev.empty()) return;
+    (void)hipEventSynchronize(ctx->ev.back().second);
+    ctx->last_ms.clear();
+    for (size_t i = 1; i < ctx->ev.size(); ++i) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev[i - 1].second, ctx->ev[i].second);
+        ctx->last_ms.emplace_back(ctx->ev[i].first, (double)ms);
+    }
+    for (auto& e : ctx->ev) (void)hipEventDestroy(e.second);
+    ctx->ev.clear();
+}
+
+Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out) {
+    if (!t->built || !t->sorted) return Err{SPH_E_STATE, "density before build_cells/sort_pairs"};
+    if (out && out->hash && !t->hash) return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
+    ERRTRY(ensure_axis_table(ctx));
+    ERRTRY(ensure_state(t));
+    if (t->n == 0) return Err{};
+    ev_mark(ctx, "start");
+    launch_density(ctx, t, false, ctx->d_counter);
+    ev_mark(ctx, "density");
+    launch_scatter_density(ctx, t, out);
+    HIPTRY(hipGetLastError());
+    ev_mark(ctx, "scatter");
+    ev_collect(ctx);
+    t->have_density = true;
+    return Err{};
+}
+
+Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_unconv, int32_t* iters) {
+    if (!t->built || !t->sorted) return Err{SPH_E_STATE, "solve_h before build_cells/sort_pairs"};
+    if (out && out->hash && !t->hash) return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
+    if (t->prm.max_iter < 1 || !(t->prm.h_tol > 0.f) || !(t->prm.n_target > 0.f))
+        return Err{SPH_E_ARG, "bad solve parameters"};
+    ERRTRY(ensure_axis_table(ctx));
+    ERRTRY(ensure_state(t));
+    hipStream_t st = ctx->stream;
+    const int64_t n = t->n;
+    if (n_unconv) *n_unconv = 0;
+    if (iters) *iters = 0;
+    if (n == 0) return Err{};
+    ev_mark(ctx, "start");
+    hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, t->status, 2);
+    int32_t hstat[2] = {0, 0};
+    int it = 0;
+    bool rebuild = false;
+    for (; it < t->prm.max_iter; ++it) {
+        launch_density(ctx, t, true, ctx->d_counter);
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, t->status + 1, 1);
+        hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->nw, t->dnw, t->ph,
+                           t->bound, t->lo, t->hi, (double)t->prm.n_target, (double)t->prm.h_tol, t->status);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        if (hstat[0]) { rebuild = true; ++it; break; }
+        if (hstat[1] == 0) { ++it; break; }
+    }
+    if (!rebuild && hstat[1] > 0) {
+        // unconverged particles moved h after their last density: recompute
+        // their density at the h they hold now
+        launch_density(ctx, t, true, ctx->d_counter);
+    }
+    ev_mark(ctx, "solve");
+    launch_scatter_density(ctx, t, out);
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
+    ev_mark(ctx, "scatter");
+    ev_collect(ctx);
+    if (iters) *iters = it;
+    if (n_unconv) *n_unconv = hstat[1];
+    t->have_density = !rebuild;
+    if (rebuild) return Err{SPH_E_REBUILD, "h outgrew the cell support: rebuild with the returned h"};
+    if (hstat[1] > 0) return Err{SPH_E_NOCONV, std::to_string(hstat[1]) + " particles unconverged"};
+    return Err{};
+}
+
+Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
+    if (!t->have_density) return Err{SPH_E_STATE, "force before a density pass at the current h"};
+    if (out && out->hash && !t->hash) return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
+    ERRTRY(ensure_axis_table(ctx));
+    ERRTRY(ensure_state(t));
+    if (t->n == 0) return Err{};
+    ev_mark(ctx, "start");
+    launch_force(ctx, t, ctx->d_counter + 1);
+    ev_mark(ctx, "force");
+    launch_reduce(ctx, t, out ? out->sums : nullptr);
+    launch_scatter_force(ctx, t, out);
+    HIPTRY(hipGetLastError());
+    ev_mark(ctx, "reduce+scatter");
+    ev_collect(ctx);
+    return Err{};
+}
+
+__global__ void k_copy_status(const int32_t* __restrict__ status, int32_t* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        out[0] = status[1];
+        out[1] = status[0];
+    }
+}
+
+// The post-build pipeline as one HIP graph: k_iter Newton iterations with
+// device-side early exit (chunks without active particles return at once),
+// one density pass for particles still active, ghost, force, sums and the
+// scatters to caller order.  Captured on a private stream, launched on the
+// context's stream; re-captured when the tree or the output pointers change.
+Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout, const sph_force_out* fout,
+              int32_t* n_unconv_dev) {
+    if (!t->built || !t->sorted) return Err{SPH_E_STATE, "graph before build_cells/sort_pairs"};
+    if (!n_unconv_dev) return Err{SPH_E_ARG, "null n_unconverged_dev"};
+    if (((dout && dout->hash) || (fout && fout->hash)) && !t->hash)
+        return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
+    ERRTRY(ensure_axis_table(ctx));
+    ERRTRY(ensure_state(t));
+    if (t->n == 0) return Err{};
+    std::vector<const void*> key;
+    key.push_back((const void*)(intptr_t)k_iter);
+    key.push_back(n_unconv_dev);
+    const void* dk[7] = {dout ? dout->rho : nullptr, dout ? dout->drho_dh : nullptr, dout ? dout->nw : nullptr,
+                         dout ? dout->dnw_dh : nullptr, dout ? dout->nngb : nullptr,
+                         dout ? dout->hash : nullptr, dout ? dout->h : nullptr};
+    const void* fk[9] = {fout ? fout->ax : nullptr, fout ? fout->ay : nullptr, fout ? fout->az : nullptr,
+                         fout ? fout->dudt : nullptr, fout ? fout->vsig : nullptr, fout ? fout->S : nullptr,
+                         fout ? fout->nforce : nullptr, fout ? fout->hash : nullptr, fout ? fout->sums : nullptr};
+    key.insert(key.end(), dk, dk + 7);
+    key.insert(key.end(), fk, fk + 9);
+    if (!t->gexec || key != t->gkey) {
+        t->invalidate_graph();
+        if (!ctx->cap_stream) HIPTRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = ctx->stream;
+        bool timing = ctx->timing;
+        ctx->stream = ctx->cap_stream;
+        ctx->timing = false;
+        hipStream_t st = ctx->stream;
+        const int64_t n = t->n;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi);
+            hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, t->status, 2);
+            for (int it = 0; it < k_iter; ++it) {
+                launch_density(ctx, t, true, ctx->d_counter);
+                hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, t->status + 1, 1);
+                hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->nw, t->dnw,
+                                   t->ph, t->bound, t->lo, t->hi, (double)t->prm.n_target, (double)t->prm.h_tol,
+                                   t->status);
+            }
+            launch_density(ctx, t, true, ctx->d_counter);
+            launch_force(ctx, t, ctx->d_counter + 1);
+            launch_reduce(ctx, t, fout ? fout->sums : nullptr);
+            launch_scatter_density(ctx, t, dout);
+            launch_scatter_force(ctx, t, fout);
+            hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, st, t->status, n_unconv_dev);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(st, &g);
+            if (e == hipSuccess) {
+                e = hipGraphInstantiate(&t->gexec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+            }
+        }
+        ctx->stream = user;
+        ctx->timing = timing;
+        if (e != hipSuccess) {
+            t->gexec = nullptr;
+            return Err{SPH_E_HIP, std::string("graph capture: ") + hipGetErrorString(e)};
+        }
+        t->gkey = key;
+    }
+    HIPTRY(hipGraphLaunch(t->gexec, ctx->stream));
+    t->have_density = true;
+    return Err{};
+}
+
+}  // namespace sph

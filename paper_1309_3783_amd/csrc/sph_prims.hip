@@ -1,0 +1,230 @@
+// Device-wide primitives for the cell build: exclusive scan of uint32 and a
+// stable LSD radix sort of (uint64 key, uint32 value) pairs.  Both are
+// written for 64-lane wavefronts: the scan uses wave shuffles, the radix
+// scatter ranks equal digits inside a wave with eight ballots and across the
+// four waves of a block through LDS, which keeps the sort stable.
+#include "sph_prims.h"
+
+namespace sph {
+
+// ---------------------------------------------------------------------------
+// Exclusive scan
+// ---------------------------------------------------------------------------
+constexpr int SCAN_BS = 256;
+constexpr int SCAN_IPT = 8;
+constexpr int SCAN_TILE = SCAN_BS * SCAN_IPT;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Block exclusive scan of one value per thread; returns the block total.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, uint32_t& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int k = 0; k < nw; ++k) {
+        uint32_t x = s_w[k];
+        if (k < w) base += x;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_BS) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                         uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t s_w[SCAN_BS / 64];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; ++k) {
+        int64_t i = base + (int64_t)k * SCAN_BS + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(acc, s_w, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of the block sums, sequential over chunks.
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bsum, int64_t nb,
+                                                   uint32_t* __restrict__ total) {
+    __shared__ uint32_t s_w[16];
+    uint32_t carry = 0;
+    for (int64_t s = 0; s < nb; s += 1024) {
+        int64_t i = s + threadIdx.x;
+        uint32_t v = i < nb ? bsum[i] : 0;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, s_w, tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_BS) void k_scan_apply(const uint32_t* __restrict__ in,
+                                                        uint32_t* __restrict__ out, int64_t n,
+                                                        const uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t s_w[SCAN_BS / 64];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    uint32_t v[SCAN_IPT];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        acc += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(acc, s_w, tot) + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+}
+
+size_t scan_tmp_words(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
+
+hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint32_t* total,
+                          hipStream_t st) {
+    if (n <= 0) return total ? fill_u32(total, 1, 0, st) : hipSuccess;
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BS), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tmp, nb, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BS), 0, st, in, out, n, tmp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort (LSD, 8-bit digits)
+// ---------------------------------------------------------------------------
+constexpr int RS_BS = 256;
+constexpr int RS_ROUNDS = 16;
+constexpr int RS_TILE = RS_BS * RS_ROUNDS;
+
+__global__ __launch_bounds__(RS_BS) void k_rs_hist(const uint64_t* __restrict__ key, int64_t n, int shift,
+                                                   uint32_t* __restrict__ hist, int64_t nb) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        int64_t i = base + (int64_t)r * RS_BS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(key[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+template <bool VALS>
+__global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin,
+                                                      uint64_t* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                      const uint32_t* __restrict__ offs, int64_t nb) {
+    __shared__ uint32_t g_off[256];
+    __shared__ uint32_t d_base[256];
+    __shared__ uint32_t w_cnt[RS_BS / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    g_off[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    d_base[tid] = 0;
+    for (int k = 0; k < RS_BS / 64; ++k) w_cnt[k][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        int64_t i = base + (int64_t)r * RS_BS + tid;
+        bool valid = i < n;
+        uint64_t k = valid ? kin[i] : 0;
+        uint32_t v = (VALS && valid) ? vin[i] : 0;
+        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bal = __ballot(valid && ((d >> b) & 1u));
+            match &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        uint32_t rank = __popcll(match & lt);
+        bool leader = valid && ((match & lt) == 0);
+        if (leader) w_cnt[w][d] = (uint32_t)__popcll(match);
+        __syncthreads();
+        {
+            uint32_t run = d_base[tid];
+            for (int q = 0; q < RS_BS / 64; ++q) {
+                uint32_t c = w_cnt[q][tid];
+                w_cnt[q][tid] = run;
+                run += c;
+            }
+            d_base[tid] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = g_off[d] + w_cnt[w][d] + rank;
+            kout[pos] = k;
+            if (VALS) vout[pos] = v;
+        }
+        __syncthreads();
+        for (int q = 0; q < RS_BS / 64; ++q) w_cnt[q][tid] = 0;
+        __syncthreads();
+    }
+}
+
+size_t radix_tmp_words(int64_t n) {
+    int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    return (size_t)(256 * nb) + scan_tmp_words(256 * nb) + 8;
+}
+
+hipError_t radix_sort(uint64_t* key, uint32_t* val, uint64_t* key_alt, uint32_t* val_alt, int64_t n,
+                      int nbits, uint32_t* tmp, hipStream_t st, bool* result_in_alt) {
+    *result_in_alt = false;
+    if (n <= 1 || nbits <= 0) return hipSuccess;
+    int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    uint32_t* hist = tmp;
+    uint32_t* stmp = tmp + 256 * nb;
+    uint64_t *ka = key, *kb = key_alt;
+    uint32_t *va = val, *vb = val_alt;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_BS), 0, st, ka, n, shift, hist, nb);
+        hipError_t e = exclusive_scan(hist, hist, 256 * nb, stmp, nullptr, st);
+        if (e != hipSuccess) return e;
+        if (val)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nb), dim3(RS_BS), 0, st, ka, va, kb, vb,
+                               n, shift, hist, nb);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)nb), dim3(RS_BS), 0, st, ka, va, kb,
+                               vb, n, shift, hist, nb);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+        *result_in_alt = !*result_in_alt;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace sph

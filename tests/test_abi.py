@@ -1,0 +1,55 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load and export every function include/sphcell.h declares;
+host-only calls (version, status strings, defaults, footprint, argument
+errors) are exercised without touching a device.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1309_3783_amd as sph
+from paper_1309_3783_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "sphcell.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = sph.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_host_only_calls():
+    L = sph.lib()
+    assert b"gfx950" in L.sph_version()
+    assert L.sph_status_str(-4).startswith(b"h outgrew")
+    p = sph.params()
+    # Section III-B constants as defaults
+    assert p.n_split == 400 and abs(p.split_frac - 0.875) < 1e-7
+    assert p.n_target == 48.0 and abs(p.gamma - 5 / 3) < 1e-6 and p.alpha == 2.0
+    assert sph.footprint(1_000_000) > 100 * 1_000_000
+    with pytest.raises(sph.SphError):
+        sph.footprint(-1)
+
+
+def test_null_arguments_are_rejected():
+    L = sph.lib()
+    assert L.sph_tree_create(None, None) == binding.SPH_E_ARG
+    assert L.sph_build_cells(None, None, None, None) == binding.SPH_E_ARG
+    assert L.sph_density(None, None, None) == binding.SPH_E_ARG
+    assert L.sph_force(None, None, None) == binding.SPH_E_ARG
+    assert L.sph_run_graph(None, None, 1, None, None, None) == binding.SPH_E_ARG
+    L.sph_ctx_destroy(None)

@@ -1,0 +1,301 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+Bar (see the tolerance constants): pair sets and neighbour counts bit-exact
+(counts and splitmix64 pair hashes), density <= 1e-5 relative, force
+<= 1e-4 of the per-particle term scale S_i, momentum/energy sums within
+1e-5 of sum m S.  Smoothing lengths of the fixed-h cases come from the
+oracle (tests/_inputs.py).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import _inputs as I  # noqa: E402
+
+import oracle  # noqa: E402
+import sphinputs  # noqa: E402
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-5
+FORCE_TOL = 1e-4
+SUM_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1309_3783_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(sph):
+    return sph.Context(0)
+
+
+def run_fixed(sph, ctx, sets, hs, **prm_kw):
+    """build -> sort -> density -> force at the given h; numpy results per set."""
+    prm = sph.params(flags=sph.SPH_FLAG_PAIR_HASH, **prm_kw)
+    batch = sph.batch_from_sets(sets, h=hs)
+    tree = sph.Tree(ctx)
+    tree.build_cells(batch, prm)
+    tree.sort_pairs()
+    n = batch.n
+    dout = sph.DensityOut(n, "cuda", hash=True)
+    tree.density(dout)
+    fout = sph.ForceOut(n, batch.nsets, "cuda", hash=True)
+    tree.force(fout)
+    torch.cuda.synchronize()
+    res = []
+    for s in range(batch.nsets):
+        a, b = int(batch.offsets[s]), int(batch.offsets[s + 1])
+        d = {k: getattr(dout, k)[a:b].cpu().numpy() for k in ("rho", "drho_dh", "nw", "dnw_dh", "nngb", "h")}
+        d["hash"] = dout.hash[a:b].cpu().numpy().view(np.uint64)
+        f = {k: getattr(fout, k)[a:b].cpu().numpy() for k in ("ax", "ay", "az", "dudt", "vsig", "S", "nforce")}
+        f["hash"] = fout.hash[a:b].cpu().numpy().view(np.uint64)
+        f["sums"] = fout.sums[8 * s:8 * s + 8].cpu().numpy()
+        res.append((d, f))
+    return res, tree
+
+
+def check_density(ps, h, g, r):
+    assert np.array_equal(g["nngb"], r["nngb"]), "density neighbour counts differ"
+    assert np.array_equal(g["hash"], r["hash"]), "density pair sets differ"
+    assert np.array_equal(g["h"].astype(np.float64), h)
+    rel = np.abs(g["rho"] - r["rho"]) / r["rho"]
+    assert rel.max() <= RHO_TOL, f"rho rel err {rel.max():.3g}"
+    reln = np.abs(g["nw"] - r["nw"]) / r["nw"]
+    assert reln.max() <= RHO_TOL, f"N_w rel err {reln.max():.3g}"
+    # derivatives have mixed-sign terms: scale by their natural size 3 rho / h
+    e1 = np.abs(g["drho_dh"] - r["drho_dh"]) / (3 * r["rho"] / h)
+    e2 = np.abs(g["dnw_dh"] - r["dnw_dh"]) / (3 * r["nw"] / h)
+    assert e1.max() <= RHO_TOL and e2.max() <= RHO_TOL, (e1.max(), e2.max())
+
+
+def check_force(ps, g, r, targets=None):
+    t = np.arange(ps.n) if targets is None else np.asarray(targets)
+    assert np.array_equal(g["nforce"][t], r["nforce"][t]), "force neighbour counts differ"
+    assert np.array_equal(g["hash"][t], r["hash"][t]), "force pair sets differ"
+    S = r["S"][t]
+    for k in ("ax", "ay", "az"):
+        err = np.abs(g[k][t] - r[k][t]) / np.maximum(S, 1e-300)
+        assert err.max() <= FORCE_TOL, f"{k} err/S {err.max():.3g}"
+    vmax = max(np.abs(ps.vx).max(), np.abs(ps.vy).max(), np.abs(ps.vz).max(), 1e-30)
+    err = np.abs(g["dudt"][t] - r["dudt"][t]) / np.maximum(S * 2 * np.sqrt(3) * vmax, 1e-300)
+    assert err.max() <= FORCE_TOL, f"dudt err {err.max():.3g}"
+    assert np.allclose(g["S"][t], S, rtol=RHO_TOL, atol=0)
+    assert np.allclose(g["vsig"][t], r["vsig"][t], rtol=RHO_TOL, atol=0)
+
+
+def check_sums(ps, g, r):
+    s = g["sums"]
+    scale = float(np.sum(ps.m * r["S"]))
+    assert abs(s[4] - scale) <= 1e-5 * scale
+    assert np.all(np.abs(s[:3]) <= SUM_TOL * scale), s[:3]
+    assert abs(s[3]) <= SUM_TOL * scale, s[3]
+    assert s[6] == float(r["nforce"].sum())
+
+
+def full_check(sph, ctx, ps, h, **kw):
+    (g,), tree = run_fixed(sph, ctx, [ps], [h], **kw)
+    rd, rf = I.oracle_reference(ps, h)
+    check_density(ps, h, g[0], rd)
+    check_force(ps, g[1], rf)
+    assert g[0]["nngb"].sum() == g[1]["sums"][5]
+    check_sums(ps, g[1], rf)
+    return g, rd, rf, tree
+
+
+# ---------------------------------------------------------------------------
+def test_uniform_constant_h(sph, ctx):
+    ps, h = I.cfg_small_uniform(velocity=True)
+    g, rd, rf, tree = full_check(sph, ctx, ps, h)
+    st = tree.stats()
+    assert st["top_grid"] == 4          # edge 1/4 >= h = 0.1409 * 1.1
+    # every unordered pair counted once: sum nforce = 2 P
+    assert g[1]["nforce"].sum() % 2 == 0
+
+
+def test_uniform_at_rest_has_no_heating(sph, ctx):
+    ps, h = I.cfg_small_uniform(velocity=False)
+    (g,), _ = run_fixed(sph, ctx, [ps], [h])
+    assert np.all(g[1]["dudt"] == 0.0)
+
+
+def test_perfect_lattice(sph, ctx):
+    ps = sphinputs.lattice(16, 0.0, 0)
+    h = I.solved_h(ps, tol=1e-12)
+    h = I.f32(h)
+    (g,), _ = run_fixed(sph, ctx, [ps], [h])
+    assert np.all(g[0]["nngb"] == 56)
+    amag = np.sqrt(g[1]["ax"] ** 2 + g[1]["ay"] ** 2 + g[1]["az"] ** 2)
+    assert np.all(amag <= 1e-5 * g[1]["S"])
+    assert np.all(np.abs(g[0]["nw"] - 48.0) < 1e-4)
+
+
+def test_jittered_lattice_solved_h(sph, ctx):
+    ps = sphinputs.lattice(24, 0.1, 2, velocity=True)
+    ps, h = I.fixed_h_case(ps)
+    full_check(sph, ctx, ps, h)
+
+
+@pytest.mark.parametrize("n,seed", [(20000, 3), (9000, 31)])
+def test_clumpy_wide_h_range(sph, ctx, n, seed):
+    ps = sphinputs.plummer_mixture(n, seed, velocity=True)
+    ps, h = I.fixed_h_case(ps)
+    assert h.max() / h.min() > 20
+    g, rd, rf, tree = full_check(sph, ctx, ps, h)
+    assert tree.stats()["levels"] >= 2
+
+
+def test_deep_refinement(sph, ctx):
+    # a small split count forces many levels and split pair tasks
+    ps = sphinputs.plummer_mixture(12000, 5, velocity=True)
+    ps, h = I.fixed_h_case(ps)
+    g, rd, rf, tree = full_check(sph, ctx, ps, h, n_split=24, split_frac=0.5)
+    st = tree.stats()
+    assert st["levels"] >= 4, st
+
+
+def test_large_cells_use_global_sort(sph, ctx):
+    # two top cells per side, no refinement: (cell, axis) lists of ~5000
+    # particles exceed the LDS sort and go through the radix sort
+    ps = sphinputs.uniform(40000, 8, velocity=True)
+    h0 = I.f32(np.full(ps.n, sphinputs.h_for_density(float(ps.n))))
+    ps = I.redraw_ties_uniform(ps, h0, seed=108)
+    g, rd, rf, tree = full_check(sph, ctx, ps, h0, top_grid=2, n_split=1 << 30)
+    st = tree.stats()
+    assert st["top_grid"] == 2 and st["max_leaf"] > 4096, st
+
+
+def test_two_cells_per_side_periodic_images(sph, ctx):
+    # h ~ 0.34: only 2 top cells per side, so a cell meets the same
+    # neighbour through two periodic images
+    ps = sphinputs.uniform(400, 9, velocity=True)
+    ps, h = I.fixed_h_case(ps)
+    g, rd, rf, tree = full_check(sph, ctx, ps, h)
+    assert tree.stats()["top_grid"] == 2
+
+
+def test_batch_of_uneven_sets_matches_alone(sph, ctx):
+    sets, hs = [], []
+    for k, (n, recipe) in enumerate([(3000, "p"), (1, "u"), (0, "u"), (2, "u"), (700, "u"), (15000, "p")]):
+        if n == 0:
+            ps = sphinputs.uniform(1, 40)
+            ps = sphinputs.ParticleSet(*(np.zeros(0) for _ in range(9)))
+            sets.append(ps)
+            hs.append(np.zeros(0))
+            continue
+        ps = sphinputs.plummer_mixture(n, 50 + k, velocity=True) if recipe == "p" else \
+            sphinputs.uniform(n, 60 + k, velocity=True)
+        if n <= 2:
+            h = I.f32(np.full(n, 0.3))
+        else:
+            ps, h = I.fixed_h_case(ps)
+        sets.append(ps)
+        hs.append(h)
+    res, _ = run_fixed(sph, ctx, sets, hs)
+    for ps, h, (g, gf) in zip(sets, hs, res):
+        if ps.n == 0:
+            continue
+        rd, rf = I.oracle_reference(ps, h)
+        check_density(ps, h, g, rd)
+        check_force(ps, gf, rf)
+    # the same set alone gives bitwise the same numbers as inside the batch
+    (alone,), _ = run_fixed(sph, ctx, [sets[-1]], [hs[-1]])
+    for k in ("rho", "nw", "drho_dh", "nngb", "hash"):
+        assert np.array_equal(alone[0][k], res[-1][0][k]), k
+    for k in ("ax", "ay", "az", "dudt", "S", "nforce", "hash"):
+        assert np.array_equal(alone[1][k], res[-1][1][k]), k
+
+
+def test_run_to_run_bitwise(sph, ctx):
+    ps = sphinputs.plummer_mixture(8000, 11, velocity=True)
+    ps, h = I.fixed_h_case(ps)
+    (a,), _ = run_fixed(sph, ctx, [ps], [h])
+    (b,), _ = run_fixed(sph, ctx, [ps], [h])
+    for k in ("rho", "nw", "hash"):
+        assert np.array_equal(a[0][k], b[0][k])
+    for k in ("ax", "ay", "az", "dudt", "hash"):
+        assert np.array_equal(a[1][k], b[1][k])
+
+
+def test_translation_and_permutation_invariance(sph, ctx):
+    ps = sphinputs.plummer_mixture(6000, 12)
+    ps, h = I.fixed_h_case(ps)
+    (a,), _ = run_fixed(sph, ctx, [ps], [h])
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(ps.n)
+    sh = np.array([0.125, 0.5 + 3 * 2 ** -24, 0.25])
+    q = sphinputs.ParticleSet(np.mod(ps.x[perm] + sh[0], 1.0), np.mod(ps.y[perm] + sh[1], 1.0),
+                              np.mod(ps.z[perm] + sh[2], 1.0), ps.m[perm], ps.u[perm], ps.vx[perm],
+                              ps.vy[perm], ps.vz[perm], h[perm])
+    (b,), _ = run_fixed(sph, ctx, [q], [h[perm]])
+    assert np.array_equal(a[0]["nngb"][perm], b[0]["nngb"])
+    assert np.array_equal(a[1]["nforce"][perm], b[1]["nforce"])
+    assert np.allclose(a[0]["rho"][perm], b[0]["rho"], rtol=2e-6)
+
+
+def test_solve_h_matches_oracle_root(sph, ctx):
+    ps = sphinputs.plummer_mixture(15000, 13)
+    h_ref = I.solved_h(ps, tol=1e-9)
+    batch = sph.batch_from_sets([ps])
+    dout = sph.DensityOut(ps.n, "cuda")
+    prm = sph.params(h_tol=0.01)
+    tree = sph.Tree(ctx)
+    st, nu, it = sph.solve_with_rebuild(tree, batch, prm, dout)
+    assert st == sph.SPH_OK and nu == 0
+    torch.cuda.synchronize()
+    hg = dout.h.cpu().numpy().astype(np.float64)
+    nw = dout.nw.cpu().numpy()
+    assert np.abs(nw - 48.0).max() <= 0.01 + 1e-4
+    # |dN_w/dh| >= ~N_w/h on these sets, so |N_w - 48| <= 0.01 bounds h
+    assert np.max(np.abs(hg / h_ref - 1.0)) < 2e-3
+    assert it <= 30
+
+
+def test_solve_h_config_tolerance(sph, ctx):
+    ps = sphinputs.lattice(20, 0.1, 14)
+    batch = sph.batch_from_sets([ps])
+    dout = sph.DensityOut(ps.n, "cuda")
+    tree = sph.Tree(ctx)
+    st, nu, it = sph.solve_with_rebuild(tree, batch, sph.params(), dout)
+    assert st == sph.SPH_OK and nu == 0
+    torch.cuda.synchronize()
+    assert np.abs(dout.nw.cpu().numpy() - 48.0).max() <= 0.5 + 1e-4
+
+
+def test_rebuild_is_reported(sph, ctx):
+    # start far too small: h must grow past the cells built for it
+    ps = sphinputs.uniform(5000, 15)
+    batch = sph.batch_from_sets([ps], h=[ps.h0 * 0.3])
+    dout = sph.DensityOut(ps.n, "cuda")
+    tree = sph.Tree(ctx)
+    tree.build_cells(batch, sph.params(h_slack=0.0))
+    tree.sort_pairs()
+    st, nu, it = tree.solve_h(dout)
+    assert st == sph.SPH_E_REBUILD
+    st, nu, it = sph.solve_with_rebuild(tree, batch, sph.params(h_slack=0.0), dout, max_rebuilds=8)
+    assert st == sph.SPH_OK
+
+
+def test_bad_arguments(sph, ctx):
+    ps = sphinputs.uniform(100, 16)
+    batch = sph.batch_from_sets([ps], h=[np.full(100, 0.6)])   # h > box/2
+    tree = sph.Tree(ctx)
+    with pytest.raises(sph.SphError) as e:
+        tree.build_cells(batch, sph.params())
+    assert e.value.code == -1
+    tree2 = sph.Tree(ctx)
+    with pytest.raises(sph.SphError):
+        tree2.density(sph.DensityOut(100, "cuda"))
+    batch = sph.batch_from_sets([ps], h=[np.full(100, np.nan)])
+    with pytest.raises(sph.SphError):
+        tree.build_cells(batch, sph.params())
