@@ -8,8 +8,10 @@ h (one density and one force interaction each).
 
 Default workload: 1,000,000 particles on a 100^3 lattice jittered by
 U(+-0.1) spacings (seed 2), h solved by Newton to 48 +- 0.5.
-Options: --config multires (8M clumpy set) / batched (256 sets, batched vs
-plain loop).  Prints ONE JSON line.
+The same line carries the batched comparison (256 uneven sets in one build
+and one HIP graph, autotuned, vs the plain one-set-at-a-time loop) and the
+served Poisson stream (p50/p99 latency).  --config multires times the 8M
+clumpy set instead.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -48,10 +50,6 @@ def make_workload(name):
         ps = sphinputs.plummer_mixture(8_000_000, 3)
         return [ps], {"workload": "plummer_mixture_8M", "n": ps.n, "clumps": 64, "bg_frac": 0.2, "seed": 3,
                       "h": "Newton to N_w = 48 +- 0.5"}
-    if name == "batched":
-        sets = sphinputs.batch_sets(256)
-        return sets, {"workload": "batched_256_sets", "n": int(sum(s.n for s in sets)), "sets": 256,
-                      "n_range": [2000, 200000], "seeds": "1000+s"}
     raise SystemExit(f"unknown config {name}")
 
 
@@ -79,40 +77,39 @@ def measured_traffic(kernel):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(sets, budget_s=20.0):
-    """The FP64 oracle on this host: h solve + density + force for a random
-    sample of target particles of the same workload."""
+def cpu_baseline(sets, budget_s=15.0):
+    """The FP64 oracle on this host, on a random sample of target particles
+    of the same set: h solve, density and force for the targets (the other
+    particles keep their first-guess h and the density at it, computed
+    untimed beforehand).  Rate = sum over targets of their force neighbours
+    (each target's share of 2P) / timed seconds."""
     import oracle
     ps = sets[0]
     rng = np.random.default_rng(0)
     ncores = oracle.num_threads()
-    k = 2000
-    total_pairs = 0
-    total_t = 0.0
-    h_all = None
+    t_prep = time.perf_counter()
+    d0 = oracle.density(ps.x, ps.y, ps.z, ps.h0, ps.m, ps.box)
+    t_prep = time.perf_counter() - t_prep
+    k = 1000
     while True:
         t = np.sort(rng.choice(ps.n, size=min(k, ps.n), replace=False))
         t0 = time.perf_counter()
         h, _ = oracle.solve_h(ps.x, ps.y, ps.z, ps.m, ps.h0, ps.box, targets=t, tol=0.5)
-        d = oracle.density(ps.x, ps.y, ps.z, h if h_all is None else h, ps.m, ps.box, targets=t)
-        t1 = time.perf_counter()
-        # force needs rho of the targets' neighbours: use the targets' own
-        # values for them (untimed fill); pair counts come from the timed pass
-        rho = np.where(d["rho"] > 0, d["rho"], 1.0)
-        drho = np.where(d["rho"] > 0, d["drho_dh"], -3.0)
-        hh = np.where(d["rho"] > 0, h, ps.h0)
-        t2 = time.perf_counter()
-        f = oracle.force(ps.x, ps.y, ps.z, hh, ps.m, ps.vx, ps.vy, ps.vz, ps.u, rho, drho, ps.box, targets=t)
-        t3 = time.perf_counter()
-        total_t += (t1 - t0) + (t3 - t2)
-        total_pairs += int(f["nforce"][t].sum())
-        if total_t >= budget_s or k >= ps.n:
+        d = oracle.density(ps.x, ps.y, ps.z, h, ps.m, ps.box, targets=t)
+        rho = d0["rho"].copy()
+        drho = d0["drho_dh"].copy()
+        rho[t] = d["rho"][t]
+        drho[t] = d["drho_dh"][t]
+        f = oracle.force(ps.x, ps.y, ps.z, h, ps.m, ps.vx, ps.vy, ps.vz, ps.u, rho, drho, ps.box, targets=t)
+        dt = time.perf_counter() - t0
+        pairs = int(f["nforce"][t].sum())
+        if dt >= 0.5 * budget_s or k >= ps.n:
             break
-        k = min(ps.n, int(k * max(2.0, budget_s / max(total_t, 1e-3))))
-    return {"value": total_pairs / total_t, "unit": "pair interactions/s", "cores": ncores, "kind": "oracle",
-            "sample": f"FP64 oracle h solve + density + force for random target samples of the same set "
-                      f"(last sample {k} targets, {total_t:.1f} s timed); each target counts its force "
-                      f"neighbours (= its share of 2P)"}
+        k = min(ps.n, int(k * min(16.0, max(2.0, budget_s / max(dt, 1e-3)))))
+    return {"value": pairs / dt, "unit": "pair interactions/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{k} random targets of the same {ps.n}-particle set: FP64 h solve + density + force "
+                      f"for the targets ({dt:.1f} s); other particles at their first-guess h with density "
+                      f"from an untimed pass ({t_prep:.1f} s)"}
 
 
 def run(args):
@@ -131,11 +128,21 @@ def run(args):
     fout = sph.ForceOut(n, batch.nsets, dev)
     tree = sph.Tree(ctx)
 
-    def step():
+    stage = {}
+
+    def record():
+        for name, ms in ctx.timings():
+            stage.setdefault(name, []).append(ms)
+
+    def step(timed=False):
         st, nu, it = sph.solve_with_rebuild(tree, batch, prm, dout)
         if st not in (sph.SPH_OK, sph.SPH_E_NOCONV):
             raise RuntimeError(f"solve failed: status {st}")
+        if timed:
+            record()
         tree.force(fout)
+        if timed:
+            record()
         return it, nu
 
     for w in range(args.warmup):
@@ -143,13 +150,10 @@ def run(args):
         torch.cuda.synchronize()
         log(f"[bench] warmup {w}: newton iterations {it}, unconverged {nu}")
     ctx.enable_timing(True)
-    stage = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        it, nu = step()
-        for name, ms in ctx.timings():
-            stage.setdefault(name, []).append(ms)
+        it, nu = step(timed=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.enable_timing(False)
@@ -176,9 +180,13 @@ def run(args):
            "pairs_P": P, "newton_iterations": it, "unconverged": nu,
            "stages_ms": {k: float(np.mean(v)) for k, v in stage.items()},
            "tree": st, "roofline": roof}
-    if args.config == "batched":
-        out["plain_loop"] = plain_loop(sph, ctx, sets, prm, args.steps)
-    if not args.skip_cpu:
+    if args.config == "plain" and not args.quick:
+        out["batched"] = bench_batched(sph)
+        log(f"[bench] batched {out['batched']['value']:.3g} pairs/s vs plain loop "
+            f"{out['batched']['plain_loop']['value']:.3g}")
+        out["served"] = bench_served(sph)
+        log(f"[bench] served p50 {out['served']['p50_ms']:.2f} ms p99 {out['served']['p99_ms']:.2f} ms")
+    if not args.skip_cpu and args.config == "plain":
         log("[bench] timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(sets, budget_s=args.cpu_budget)
     else:
@@ -186,24 +194,89 @@ def run(args):
     return out
 
 
-def plain_loop(sph, ctx, sets, prm, steps):
-    """The same sets one at a time (one build/solve/force per set)."""
+def plain_loop(sph, ctx, sets, prm):
+    """The same sets one at a time: one build / solve / force per set."""
     import torch
     singles = [sph.batch_from_sets([s]) for s in sets]
     douts = [sph.DensityOut(s.n, "cuda") for s in sets]
     fouts = [sph.ForceOut(s.n, 1, "cuda") for s in sets]
     tree = sph.Tree(ctx)
+    for b, d, f in zip(singles[:4], douts, fouts):      # warm-up
+        sph.solve_with_rebuild(tree, b, prm, d)
+        tree.force(f)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P = 0.0
     for b, d, f in zip(singles, douts, fouts):
         sph.solve_with_rebuild(tree, b, prm, d)
         tree.force(f)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    for f in fouts:
-        P += float(f.sums[6].item()) / 2.0
+    P = sum(float(f.sums[6].item()) / 2.0 for f in fouts)
     return {"value": 2 * P / t, "ms_per_step": t * 1e3, "pairs_P": P}
+
+
+def bench_batched(sph, n_sets=256, steps=3):
+    """Many uneven sets in one batch (one build, one graph) vs the plain loop."""
+    import torch
+    from paper_1309_3783_amd import autotune, pipeline as P
+    import sphinputs
+    t = time.perf_counter()
+    sets = sphinputs.batch_sets(n_sets)
+    log(f"[bench] batched workload: {n_sets} sets, {sum(s.n for s in sets)} particles "
+        f"({time.perf_counter() - t:.1f} s to generate)")
+    ctx = sph.Context(0)
+    batch = sph.batch_from_sets(sets)
+    best = autotune.tune(ctx, batch, k_iter=8, reps=1, label="batched", use_cache=False, log=log)
+    prm = sph.params(**best)
+    tree = sph.Tree(ctx)
+    out = P.Outputs(batch.n, batch.nsets)
+    P.run_graph(tree, batch, prm, out, 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fallbacks = 0
+    for _ in range(steps):
+        fallbacks += P.run_graph(tree, batch, prm, out, 8)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    Pp = P.pair_count(out)
+    plain = plain_loop(sph, ctx, sets, sph.params())
+    return {"workload": "batched_256_sets", "n": batch.n, "sets": n_sets, "n_range": [2000, 200000],
+            "value": 2 * Pp / (ms / 1e3), "unit": "pair interactions/s", "ms_per_step": ms, "pairs_P": Pp,
+            "autotuned": best, "eager_fallbacks": fallbacks, "plain_loop": plain,
+            "speedup_vs_plain": (2 * Pp / (ms / 1e3)) / plain["value"]}
+
+
+def bench_served(sph, n_req=400, pool_size=24, load=0.7):
+    """Poisson request stream, N log-uniform in [1e4, 2e6], continuous batching."""
+    from paper_1309_3783_amd import serve as S
+    import sphinputs
+    rng = np.random.default_rng(5)
+    t = time.perf_counter()
+    _, pool_n = sphinputs.arrivals(pool_size, 1.0)
+    pool = [sphinputs.plummer_mixture(int(n), 5000 + k) for k, n in enumerate(pool_n)]
+    log(f"[bench] served pool: {pool_size} sets, {sum(p.n for p in pool)} particles "
+        f"({time.perf_counter() - t:.1f} s to generate)")
+    prm = sph.params()
+    budget = 64 << 30
+    ex = S.GpuExecutor(prm, k_iter=8, lanes=2)
+
+    def fp(r):
+        return sph.footprint(r.n, prm)
+
+    # saturation: everything queued at t = 0
+    idx = rng.integers(0, pool_size, size=48)
+    burst = [S.Request(i, 0.0, pool[k]) for i, k in enumerate(idx)]
+    S.Scheduler(ex, budget, fp, max_batch=16).run(burst[:8])          # warm-up
+    sat = S.summary(S.Scheduler(ex, budget, fp, max_batch=16).run(burst))["requests_per_s"]
+    rate = load * sat
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    arr = np.cumsum(gaps) - gaps[0]
+    idx = rng.integers(0, pool_size, size=n_req)
+    reqs = [S.Request(i, float(a), pool[k]) for i, (a, k) in enumerate(zip(arr, idx))]
+    summ = S.summary(S.Scheduler(ex, budget, fp, max_batch=16).run(reqs))
+    summ.update({"saturation_requests_per_s": sat, "arrival_rate_per_s": rate, "load": load,
+                 "n_range": [10000, 2000000], "pool_sets": pool_size, "budget_bytes": budget})
+    return summ
 
 
 def main():
@@ -211,8 +284,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="plain", choices=["plain", "multires", "batched"])
+    ap.add_argument("--config", default="plain", choices=["plain", "multires"])
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline workload only (no batched/served)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -72,7 +72,9 @@ typedef struct {
     float gamma;         /* adiabatic index (5/3) */
     float alpha;         /* viscosity coefficient (2.0) */
     uint32_t flags;      /* SPH_FLAG_* */
-    int32_t reserved[5];
+    int32_t blocks_per_cu; /* persistent interaction kernels: blocks of 4 wavefronts per CU (0 = 8) */
+    int32_t max_replicas;  /* lanes per target particle for small chunks: 1, 2, 4, 8 or 16 (0 = 16) */
+    int32_t reserved[3];
 } sph_params;
 
 /* Input particle sets (see Conventions).  h is the initial smoothing length
@@ -182,9 +184,12 @@ sph_status sph_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out);
  * device-side early exit (k_iter of them), ghost, force and sums -- as one
  * HIP graph on the context's stream (captured on first use, relaunched
  * afterwards while the tree and the output pointers are unchanged).  Does
- * not synchronise.  n_unconverged_dev [device int32[2]] receives the number
- * of particles still unconverged after the graph and the rebuild flag (1 if
- * some h_i outgrew the cell support: the outputs are then not valid). */
+ * not synchronise.  n_unconverged_dev [device int32[2 + 2*nsets]] receives
+ * [0] the particles still unconverged after the graph, [1] 1 if some h_i
+ * outgrew its cells, then per set s: [2+2s] unconverged, [3+2s] rebuild
+ * flag.  The Newton passes of a set stop when that set's flag is raised;
+ * the outputs of a set with a non-zero word are not valid (re-run that set:
+ * rebuild with the returned h). */
 sph_status sph_run_graph(sph_ctx* ctx, sph_tree* t, int32_t k_iter, const sph_density_out* dout,
                          const sph_force_out* fout, int32_t* n_unconverged_dev);
 

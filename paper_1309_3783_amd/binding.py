@@ -30,7 +30,8 @@ class sph_params(C.Structure):
     _fields_ = [("n_split", C.c_int32), ("split_frac", C.c_float), ("h_slack", C.c_float),
                 ("max_depth", C.c_int32), ("top_grid", C.c_int32), ("n_target", C.c_float),
                 ("h_tol", C.c_float), ("max_iter", C.c_int32), ("gamma", C.c_float), ("alpha", C.c_float),
-                ("flags", C.c_uint32), ("reserved", C.c_int32 * 5)]
+                ("flags", C.c_uint32), ("blocks_per_cu", C.c_int32), ("max_replicas", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class sph_input(C.Structure):

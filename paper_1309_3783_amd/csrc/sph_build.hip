@@ -76,26 +76,25 @@ __device__ inline uint64_t splitmix64(uint64_t id) {
     return z ^ (z >> 31);
 }
 
-// per-set max h, and a count of invalid h (not finite, <= 0)
+// Per-set max h and count of invalid h (not finite or <= 0).  Grid
+// (chunks, sets); positive floats compare like their bit patterns, so the
+// max is an integer atomicMax.
 __global__ __launch_bounds__(256) void k_set_hstats(const SetInfo* sets, const float* __restrict__ h,
-                                                    float* hmax_out, int* bad_out) {
-    __shared__ float s_m[4];
-    __shared__ int s_b[4];
-    const SetInfo S = sets[blockIdx.x];
+                                                    int* __restrict__ hmax_bits, int* __restrict__ bad_out) {
+    const SetInfo S = sets[blockIdx.y];
     float m = 0.f;
     int bad = 0;
-    for (int64_t i = S.first + threadIdx.x; i < S.first + S.count; i += 256) {
+    for (int64_t i = S.first + (int64_t)blockIdx.x * 256 + threadIdx.x; i < S.first + S.count;
+         i += (int64_t)gridDim.x * 256) {
         float v = h[i];
         if (!(v > 0.f) || !(v < INFINITY)) bad++;
         else m = fmaxf(m, v);
     }
     m = wave_max_f(m);
     bad = wave_sum_i(bad);
-    if ((threadIdx.x & 63) == 0) { s_m[threadIdx.x >> 6] = m; s_b[threadIdx.x >> 6] = bad; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        hmax_out[blockIdx.x] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
-        bad_out[blockIdx.x] = s_b[0] + s_b[1] + s_b[2] + s_b[3];
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&hmax_bits[blockIdx.y], __float_as_int(m));
+        if (bad) atomicAdd(&bad_out[blockIdx.y], bad);
     }
 }
 
@@ -409,13 +408,24 @@ __global__ void k_task_emit(const int4* __restrict__ tasks, int64_t nt, const Ce
 // ---------------------------------------------------------------------------
 // Leaves -> work chunks of at most CHUNK particles; per-particle h bound.
 // ---------------------------------------------------------------------------
-__global__ void k_chunk_count(const Cell* __restrict__ cells, int64_t nc, uint32_t* cnt, int* max_leaf) {
+// Chunks per cell; also the number of non-empty leaves and the largest leaf
+// (one atomic per wave).
+__global__ void k_chunk_count(const Cell* __restrict__ cells, int64_t nc, uint32_t* cnt, int* stats) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    const Cell C = cells[c];
-    bool leaf = !C.split && C.count > 0;
-    cnt[c] = leaf ? (uint32_t)((C.count + CHUNK - 1) / CHUNK) : 0u;
-    if (leaf) atomicMax(max_leaf, C.count);
+    bool leaf = false;
+    int count = 0;
+    if (c < nc) {
+        const Cell C = cells[c];
+        leaf = !C.split && C.count > 0;
+        count = leaf ? C.count : 0;
+        cnt[c] = leaf ? (uint32_t)((C.count + CHUNK - 1) / CHUNK) : 0u;
+    }
+    int nl = __popcll(__ballot(leaf));
+    for (int d = 32; d >= 1; d >>= 1) count = max(count, __shfl_xor(count, d, 64));
+    if ((threadIdx.x & 63) == 0 && nl) {
+        atomicAdd(&stats[0], nl);
+        atomicMax(&stats[1], count);
+    }
 }
 
 __global__ void k_chunk_emit(const Cell* __restrict__ cells, int64_t nc, const uint32_t* __restrict__ off,
@@ -448,25 +458,29 @@ __global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__
 constexpr int CSR_SRC_SHIFT = 5;
 constexpr int CSR_TGT_SHIFT = 37;
 
-__global__ void k_csr_keys(const int4* __restrict__ tasks, int64_t nt, uint64_t* __restrict__ keys,
-                           int* __restrict__ npairs) {
+__global__ void k_csr_keys(const int4* __restrict__ tasks, int64_t nt, uint64_t* __restrict__ keys) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     int4 T = tasks[t];
     if (T.x == T.y) {
         keys[2 * t] = ~0ull;
         keys[2 * t + 1] = ~0ull;
-        return;
+    } else {
+        keys[2 * t] = ((uint64_t)T.x << CSR_TGT_SHIFT) | ((uint64_t)T.y << CSR_SRC_SHIFT) | (uint64_t)T.z;
+        keys[2 * t + 1] = ((uint64_t)T.y << CSR_TGT_SHIFT) | ((uint64_t)T.x << CSR_SRC_SHIFT) |
+                          (uint64_t)(26 - T.z);
     }
-    atomicAdd(npairs, 1);
-    keys[2 * t] = ((uint64_t)T.x << CSR_TGT_SHIFT) | ((uint64_t)T.y << CSR_SRC_SHIFT) | (uint64_t)T.z;
-    keys[2 * t + 1] = ((uint64_t)T.y << CSR_TGT_SHIFT) | ((uint64_t)T.x << CSR_SRC_SHIFT) | (uint64_t)(26 - T.z);
 }
 
-__global__ void k_csr_count(const uint64_t* __restrict__ keys, int64_t ne, uint32_t* __restrict__ cnt) {
+// CSR offsets from the sorted keys: off[c] = first entry with target >= c.
+__global__ void k_csr_offsets(const uint64_t* __restrict__ keys, int64_t ne, int64_t nc, uint32_t* __restrict__ off) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
-    atomicAdd(&cnt[keys[e] >> CSR_TGT_SHIFT], 1u);
+    int64_t t = (int64_t)(keys[e] >> CSR_TGT_SHIFT);
+    int64_t tp = e == 0 ? -1 : (int64_t)(keys[e - 1] >> CSR_TGT_SHIFT);
+    for (int64_t c = tp + 1; c <= t; ++c) off[c] = (uint32_t)e;
+    if (e == ne - 1)
+        for (int64_t c = t + 1; c <= nc; ++c) off[c] = (uint32_t)ne;
 }
 
 // ---------------------------------------------------------------------------
@@ -512,21 +526,59 @@ __device__ inline float ord2f(uint32_t u) {
     return __uint_as_float(b);
 }
 
-// One block per segment of at most SEG_LDS_MAX entries: bitonic sort of
-// (ordered projection << 32 | local index) in LDS.
-__global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict__ list,
-                                                      const uint32_t* __restrict__ off, int64_t ns,
+// Segments of at most 64 entries: one wavefront each, bitonic sort of
+// (ordered projection << 32 | local index) in registers with lane shuffles.
+__global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restrict__ list,
+                                                       const uint32_t* __restrict__ off, int64_t ns,
+                                                       const Cell* __restrict__ cells,
+                                                       const float4* __restrict__ pos,
+                                                       float* __restrict__ sproj, uint32_t* __restrict__ sidx) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < ns; q += (int64_t)gridDim.x * 4) {
+        uint32_t ca = list[q];
+        const Cell C = cells[ca / NAXES];
+        const int n = C.count;
+        if (n > 64) continue;
+        const int ax = (int)(ca % NAXES);
+        uint64_t k = ~0ull;
+        if (lane < n) k = ((uint64_t)f2ord(project(pos[C.first + lane], ax)) << 32) | (uint32_t)lane;
+        for (int size = 2; size <= 64; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                uint32_t lo = __shfl_xor((uint32_t)k, stride, 64);
+                uint32_t hi = __shfl_xor((uint32_t)(k >> 32), stride, 64);
+                uint64_t o = ((uint64_t)hi << 32) | lo;
+                bool up = (lane & size) == 0;
+                bool lower = (lane & stride) == 0;
+                // the lower lane of a pair keeps the min when sorting up
+                bool keep_min = (lower == up);
+                uint64_t mn = k < o ? k : o, mx = k < o ? o : k;
+                k = keep_min ? mn : mx;
+            }
+        }
+        if (lane < n) {
+            uint32_t o = off[q];
+            sproj[o + lane] = ord2f((uint32_t)(k >> 32));
+            sidx[o + lane] = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+        }
+    }
+}
+
+// Segments of 65..SEG_LDS_MAX entries (listed in sel): one block each,
+// bitonic sort in LDS.
+__global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict__ sel, int64_t nsel,
+                                                      const uint32_t* __restrict__ list,
+                                                      const uint32_t* __restrict__ off,
                                                       const Cell* __restrict__ cells,
                                                       const float4* __restrict__ pos,
                                                       float* __restrict__ sproj, uint32_t* __restrict__ sidx) {
     __shared__ uint64_t s[SEG_LDS_MAX];
-    int64_t q = blockIdx.x;
-    if (q >= ns) return;
+    for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
+    const int64_t q = sel[i];
     uint32_t ca = list[q];
     const Cell C = cells[ca / NAXES];
     int ax = (int)(ca % NAXES);
     int n = C.count;
-    if (n > SEG_LDS_MAX) return;
+    if (n <= 64 || n > SEG_LDS_MAX) continue;
     int P = 1;
     while (P < n) P <<= 1;
     for (int e = threadIdx.x; e < P; e += blockDim.x) {
@@ -553,11 +605,24 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
         sproj[o + e] = ord2f((uint32_t)(k >> 32));
         sidx[o + e] = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
     }
+    __syncthreads();
+    }
 }
 
 __global__ void k_big_flag(const uint32_t* __restrict__ lens, int64_t ns, uint32_t* __restrict__ flag) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q < ns) flag[q] = lens[q] > (uint32_t)SEG_LDS_MAX ? 1u : 0u;
+}
+
+__global__ void k_mid_flag(const uint32_t* __restrict__ lens, int64_t ns, uint32_t* __restrict__ flag) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < ns) flag[q] = (lens[q] > 64u && lens[q] <= (uint32_t)SEG_LDS_MAX) ? 1u : 0u;
+}
+
+__global__ void k_compact(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx, int64_t ns,
+                          uint32_t* __restrict__ out) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < ns && flag[q]) out[idx[q]] = (uint32_t)q;
 }
 
 __global__ void k_big_list(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx, int64_t ns,
@@ -666,7 +731,11 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     std::vector<float> hmax(S, 0.f);
     std::vector<int> bad(S, 0);
     if (n > 0) {
-        hipLaunchKernelGGL(k_set_hstats, dim3(S), dim3(256), 0, st, d_sets, in->h, d_hmax, d_bad);
+        HIPTRY(fill_u32((uint32_t*)d_hmax, 2 * (int64_t)S, 0u, st));
+        int64_t maxc = 0;
+        for (int s = 0; s < S; ++s) maxc = std::max<int64_t>(maxc, sets[s].count);
+        unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((maxc + 2047) / 2048, 1), 512);
+        hipLaunchKernelGGL(k_set_hstats, dim3(gx, S), dim3(256), 0, st, d_sets, in->h, (int*)d_hmax, d_bad);
         HIPTRY(hipGetLastError());
         HIPTRY(hipMemcpyAsync(hmax.data(), d_hmax, sizeof(float) * S, hipMemcpyDeviceToHost, st));
         HIPTRY(hipMemcpyAsync(bad.data(), d_bad, sizeof(int) * S, hipMemcpyDeviceToHost, st));
@@ -676,10 +745,11 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     int64_t ntop = 0;
     for (int s = 0; s < S; ++s) {
         if (bad[s]) return Err{SPH_E_ARG, "set " + std::to_string(s) + ": h must be finite and > 0"};
-        double hd = (double)hmax[s] * (1.0 + (double)prm->h_slack);
         double box = sets[s].box;
-        if (sets[s].count > 0 && !(hd <= 0.5 * box))
-            return Err{SPH_E_ARG, "set " + std::to_string(s) + ": h*(1+slack) must be <= box/2"};
+        if (sets[s].count > 0 && !((double)hmax[s] < 0.5 * box))
+            return Err{SPH_E_ARG, "set " + std::to_string(s) + ": h must be < box/2"};
+        // decisions use h*(1+slack), but at most box/2 (two top cells per side)
+        double hd = std::min((double)hmax[s] * (1.0 + (double)prm->h_slack), 0.5 * box);
         int lg = 1;
         if (prm->top_grid > 0) {
             int g = prm->top_grid;
@@ -841,15 +911,16 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     // ---- leaves -> chunks; particle h bounds ------------------------------
     const int64_t nc = t->ncells;
     ERRTRY(t->scratch(nc + 1));
-    HIPTRY(fill_u32((uint32_t*)t->d_maxleaf, 1, 0, st));
+    HIPTRY(fill_u32((uint32_t*)t->d_maxleaf, 2, 0, st));
     hipLaunchKernelGGL(k_chunk_count, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_a, t->d_maxleaf);
     HIPTRY(exclusive_scan(t->sc_a, t->sc_b, nc, t->sc_tmp, total, st));
     uint32_t nchunks = 0;
     ERRTRY(read_u32(total, &nchunks, st));
-    static thread_local int maxleaf;
-    maxleaf = 0;
-    HIPTRY(hipMemcpyAsync(&maxleaf, t->d_maxleaf, sizeof(int), hipMemcpyDeviceToHost, st));
+    int lstats[2] = {0, 0};
+    HIPTRY(hipMemcpyAsync(lstats, t->d_maxleaf, sizeof(lstats), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
+    const int maxleaf = lstats[1];
+    t->nleaves = lstats[0];
     ERRTRY(t->alloc(t->b_chunk, sizeof(int4) * std::max<uint32_t>(nchunks, 1), (void**)&t->chunks));
     hipLaunchKernelGGL(k_chunk_emit, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_b, t->chunks);
     HIPTRY(hipGetLastError());
@@ -866,32 +937,28 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(t->alloc(t->b_csr, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr));
     ERRTRY(t->alloc(t->b_csr2, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr2));
     ERRTRY(t->alloc(t->b_csroff, sizeof(uint32_t) * (nc + 1), (void**)&t->csr_off));
-    HIPTRY(fill_u32((uint32_t*)t->d_npairs, 1, 0, st));
-    int npairs = 0;
+    // every non-empty leaf holds exactly one final self task
+    const int64_t npairs = nfinal - t->nleaves;
     if (ne > 0) {
         ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(ne), radix_tmp_words(nn)),
                         (void**)&t->rs_tmp));
-        hipLaunchKernelGGL(k_csr_keys, dim3(nblk(nfinal, 256)), dim3(256), 0, st, t->finals, nfinal, t->csr,
-                           t->d_npairs);
+        hipLaunchKernelGGL(k_csr_keys, dim3(nblk(nfinal, 256)), dim3(256), 0, st, t->finals, nfinal, t->csr);
         HIPTRY(hipGetLastError());
-        HIPTRY(hipMemcpyAsync(&npairs, t->d_npairs, sizeof(int), hipMemcpyDeviceToHost, st));
         bool alt = false;
         HIPTRY(radix_sort(t->csr, nullptr, t->csr2, nullptr, ne, 64, t->rs_tmp, st, &alt));
         if (alt) {
             std::swap(t->csr, t->csr2);
             std::swap(t->b_csr, t->b_csr2);
         }
-        HIPTRY(hipStreamSynchronize(st));
     }
     t->npairs = npairs;
-    t->nleaves = nfinal - npairs;
-    HIPTRY(fill_u32(t->sc_a, nc, 0, st));
     if (npairs > 0) {
-        hipLaunchKernelGGL(k_csr_count, dim3(nblk(2 * (int64_t)npairs, 256)), dim3(256), 0, st, t->csr,
-                           2 * (int64_t)npairs, t->sc_a);
+        hipLaunchKernelGGL(k_csr_offsets, dim3(nblk(2 * npairs, 256)), dim3(256), 0, st, t->csr, 2 * npairs, nc,
+                           t->csr_off);
         HIPTRY(hipGetLastError());
+    } else {
+        HIPTRY(fill_u32(t->csr_off, nc + 1, 0u, st));
     }
-    HIPTRY(exclusive_scan(t->sc_a, t->csr_off, nc, t->sc_tmp, t->csr_off + nc, st));
     HIPTRY(hipStreamSynchronize(st));
     t->built = true;
     return Err{};
@@ -933,11 +1000,22 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
         HIPTRY(hipGetLastError());
         ERRTRY(t->alloc(t->b_segproj, sizeof(float) * std::max<int64_t>(nent, 1), (void**)&t->segproj));
         ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
-        hipLaunchKernelGGL(k_seg_sort_lds, dim3(ns), dim3(256), 0, st, t->seglist, soff, (int64_t)ns, t->cells,
-                           t->pos, t->segproj, t->segidx);
+        hipLaunchKernelGGL(k_seg_sort_wave, dim3((unsigned)std::min<int64_t>((ns + 3) / 4, 8192)), dim3(256), 0, st,
+                           t->seglist, soff, (int64_t)ns, t->cells, t->pos, t->segproj, t->segidx);
         HIPTRY(hipGetLastError());
-        // segments too long for LDS: one global radix sort over all of them
         ERRTRY(t->scratch(std::max<int64_t>(nca, ns) + 1));
+        hipLaunchKernelGGL(k_mid_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_a);
+        HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ns, t->sc_tmp, total, st));
+        uint32_t nmid = 0;
+        ERRTRY(read_u32(total, &nmid, st));
+        if (nmid > 0) {
+            hipLaunchKernelGGL(k_compact, dim3(nblk(ns, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, (int64_t)ns,
+                               t->sc_c);
+            hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)std::min<uint32_t>(nmid, 65535)), dim3(256), 0, st,
+                               t->sc_c, (int64_t)nmid, t->seglist, soff, t->cells, t->pos, t->segproj, t->segidx);
+            HIPTRY(hipGetLastError());
+        }
+        // segments too long for LDS: one global radix sort over all of them
         hipLaunchKernelGGL(k_big_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_a);
         HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ns, t->sc_tmp, total, st));
         uint32_t nbig = 0;

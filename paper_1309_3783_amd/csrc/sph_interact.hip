@@ -143,6 +143,7 @@ struct DensArgs {
     float *rho, *drho, *nw, *dnw;
     int32_t* nngb;
     uint64_t* hash;
+    int rmax;
 };
 
 struct DensAcc {
@@ -169,13 +170,66 @@ __device__ __forceinline__ void dens_pair(DensAcc& a, float r2, float hinv, floa
     a.hs += mixj;
 }
 
+// Lanes per target particle: small chunks spread each particle over 2 or 4
+// lanes, each taking a contiguous share of every staged tile; the shares are
+// combined in a fixed order at the end.
+__device__ __forceinline__ int replicas(int cnt, int rmax) {
+    int r = cnt <= 4 ? 16 : (cnt <= 8 ? 8 : (cnt <= 16 ? 4 : (cnt <= 32 ? 2 : 1)));
+    return r < rmax ? r : rmax;
+}
+
+// Combine the partial sums of the replicas of one particle (lanes that
+// differ in the bits above log2(T)); every replica ends with the same value.
+// Butterfly over the replica bits (32, 16, ... down to T): a fixed pairing,
+// so the result is the same on every replica and from run to run.
+__device__ __forceinline__ float comb_f(float v, int R) {
+    for (int d = 32, r = R; r > 1; d >>= 1, r >>= 1) v = v + __shfl_xor(v, d, 64);
+    return v;
+}
+__device__ __forceinline__ int comb_i(int v, int R) {
+    for (int d = 32, r = R; r > 1; d >>= 1, r >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+__device__ __forceinline__ uint64_t comb_u64(uint64_t v, int R) {
+    for (int d = 32, r = R; r > 1; d >>= 1, r >>= 1)
+        v += ((uint64_t)__shfl_xor((uint32_t)(v >> 32), d, 64) << 32) | __shfl_xor((uint32_t)v, d, 64);
+    return v;
+}
+__device__ __forceinline__ float comb_max(float v, int R) {
+    for (int d = 32, r = R; r > 1; d >>= 1, r >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Tile work shared by the self and pair sweeps: the lane's share of the
+// tile [j0, j0 + len) is tested first (one bit per entry in range), then
+// only the set bits are evaluated, so the wave does not run the pair
+// arithmetic for entries that no lane needs.
+template <bool HASH>
+__device__ __forceinline__ void dens_tile(DensAcc& acc, const float4* sp, const uint64_t* sm, int j0, int len,
+                                          const float4& xi, float hi2, float hinv, int self_j) {
+    uint64_t mask = 0;
+    for (int k = 0; k < len; ++k) {
+        float4 q = sp[j0 + k];
+        float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (r2 < hi2 && j0 + k != self_j) mask |= 1ull << k;
+    }
+    while (mask) {
+        int k = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        float4 q = sp[j0 + k];
+        float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        dens_pair(acc, r2, hinv, q.w, HASH ? sm[j0 + k] : 0ull);
+    }
+}
+
 template <bool SOLVE, bool HASH>
 __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
     __shared__ float4 s_p[BLK / 64][64];
-    __shared__ float s_t[BLK / 64][64];
     __shared__ uint64_t s_m[BLK / 64][64];
+    __shared__ int s_pick[BLK / 64][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (SOLVE && a.status[0]) return;
     for (;;) {
         int item = 0;
         if (lane == 0) item = atomicAdd(a.counter, 1);
@@ -183,11 +237,24 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
         if (item >= a.nchunks) break;
         const int4 ch = a.chunks[item];
         const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
-        const int p = p0 + lane;
-        const bool valid = lane < cnt;
-        bool act = valid;
-        if (SOLVE) act = valid && a.active[p];
-        if (SOLVE && __ballot(act) == 0) continue;
+        // a set whose h outgrew its cells stops until it is rebuilt
+        if (SOLVE && a.status[2 + 2 * a.cells[leaf].set]) continue;
+        // particles of the chunk that take part: all, or the still active
+        // ones of a Newton pass, packed into the first slots
+        uint64_t amask = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+        if (SOLVE) amask = __ballot(lane < cnt && a.active[p0 + lane]);
+        if (amask == 0) continue;
+        const int nact = __popcll(amask);
+        const int R = replicas(nact, a.rmax), T = 64 / R;
+        const int slot = lane & (T - 1), rep = lane / T;
+        // slot -> particle: the slot-th set bit of amask
+        if ((amask >> lane) & 1ull) s_pick[w][__popcll(amask & ((1ull << lane) - 1ull))] = lane;
+        wave_lds_sync();
+        const int pick = slot < nact ? s_pick[w][slot] : 0;
+        wave_lds_sync();
+        const int p = p0 + pick;
+        const bool valid = slot < nact;
+        const bool act = valid;
         float4 xi = valid ? a.pos[p] : make_float4(0.f, 0.f, 0.f, 0.f);
         float hi = valid ? a.ph[p] : 1.f;
         float hi2 = act ? hi * hi : -1.f;
@@ -204,12 +271,9 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
                 if (HASH) s_m[w][lane] = a.mix[base + lane];
             }
             wave_lds_sync();
-            for (int jj = 0; jj < nsrc; ++jj) {
-                float4 q = s_p[w][jj];
-                float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
-                float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                if (r2 < hi2 && base + jj != p) dens_pair(acc, r2, hinv, q.w, HASH ? s_m[w][jj] : 0ull);
-            }
+            const int share = (nsrc + R - 1) / R;
+            const int j0 = rep * share;
+            dens_tile<HASH>(acc, s_p[w], s_m[w], j0, max(0, min(share, nsrc - j0)), xi, hi2, hinv, p - base);
             wave_lds_sync();
         }
 
@@ -247,12 +311,9 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
                     }
                     const int nuse = __popcll(__ballot(ok));
                     wave_lds_sync();
-                    for (int jj = 0; jj < nuse; ++jj) {
-                        float4 q = s_p[w][jj];
-                        float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
-                        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        if (r2 < hi2) dens_pair(acc, r2, hinv, q.w, HASH ? s_m[w][jj] : 0ull);
-                    }
+                    const int share = (nuse + R - 1) / R;
+                    const int j0 = rep * share;
+                    dens_tile<HASH>(acc, s_p[w], s_m[w], j0, max(0, min(share, nuse - j0)), xi, hi2, hinv, -1);
                     wave_lds_sync();
                     if (nuse < nsrc) break;
                 }
@@ -260,15 +321,19 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
             A = cA.parent;
         }
 
-        if (act) {
+        const float sf = comb_f(acc.sf - acc.cf, R), sg = comb_f(acc.sg - acc.cg, R);
+        const float sw = comb_f(acc.sw - acc.cw, R), sq = comb_f(acc.sq - acc.cq, R);
+        const int nn = comb_i(acc.nn, R);
+        const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
+        if (act && rep == 0) {
             float h3 = hi * hi * hi;
             float mi = xi.w;
-            a.rho[p] = C8PI / h3 * (mi + (acc.sf - acc.cf));
-            a.drho[p] = -C8PI / (h3 * hi) * (3.f * mi + (acc.sg - acc.cg));
-            a.nw[p] = (32.f / 3.f) * (1.f + (acc.sw - acc.cw));
-            a.dnw[p] = -(32.f / 3.f) * hinv * (acc.sq - acc.cq);
-            a.nngb[p] = acc.nn;
-            if (HASH) a.hash[p] = acc.hs;
+            a.rho[p] = C8PI / h3 * (mi + sf);
+            a.drho[p] = -C8PI / (h3 * hi) * (3.f * mi + sg);
+            a.nw[p] = (32.f / 3.f) * (1.f + sw);
+            a.dnw[p] = -(32.f / 3.f) * hinv * sq;
+            a.nngb[p] = nn;
+            if (HASH) a.hash[p] = hs;
         }
     }
 }
@@ -298,6 +363,7 @@ struct ForceArgs {
     float *ax, *ay, *az, *du, *vsig, *S;
     int32_t* nf;
     uint64_t* hash;
+    int rmax;
 };
 
 struct ForceLane {
@@ -344,14 +410,41 @@ __device__ __forceinline__ void force_pair(ForceAcc& a, const ForceLane& L, floa
     a.hs += mixj;
 }
 
+struct ForceLds {
+    float4 p[64];   // x, y, z, m
+    float4 h[64];   // h, 1/h, K, A
+    float4 v[64];   // vx, vy, vz, rho
+    float c[64];
+    uint64_t m[64];
+};
+
+template <bool HASH>
+__device__ __forceinline__ void force_tile(ForceAcc& acc, const ForceLds& L_, int j0, int len, const ForceLane& L,
+                                           float hi2, int self_j, float alpha) {
+    uint64_t mask = 0;
+    for (int k = 0; k < len; ++k) {
+        float4 q = L_.p[j0 + k];
+        float hj = L_.h[j0 + k].x;
+        float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (r2 < fmaxf(hi2, hj * hj) && j0 + k != self_j) mask |= 1ull << k;
+    }
+    while (mask) {
+        int k = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const int j = j0 + k;
+        float4 q = L_.p[j];
+        float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        force_pair(acc, L, dx, dy, dz, r2, q, L_.h[j], L_.v[j], L_.c[j], HASH ? L_.m[j] : 0ull, alpha);
+    }
+}
+
 template <bool HASH>
 __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
-    __shared__ float4 s_p[BLK / 64][64];   // x, y, z, m
-    __shared__ float4 s_h[BLK / 64][64];   // h, 1/h, K, A
-    __shared__ float4 s_v[BLK / 64][64];   // vx, vy, vz, rho
-    __shared__ float s_c[BLK / 64][64];
-    __shared__ uint64_t s_m[BLK / 64][64];
+    __shared__ ForceLds s_l[BLK / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    ForceLds& S = s_l[w];
 
     auto stage = [&](int slot, uint32_t j, float Sx, float Sy, float Sz) {
         float4 pj = a.pos[j];
@@ -359,11 +452,11 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
         float hinv = 1.f / hj;
         float h2 = hinv * hinv;
         float4 vj = a.pv[j];
-        s_p[w][slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, pj.w);
-        s_h[w][slot] = make_float4(hj, hinv, C8PI * h2 * h2 * hinv, a.A[j]);
-        s_v[w][slot] = make_float4(vj.x, vj.y, vj.z, a.rho[j]);
-        s_c[w][slot] = a.cs[j];
-        if (HASH) s_m[w][slot] = a.mix[j];
+        S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, pj.w);
+        S.h[slot] = make_float4(hj, hinv, C8PI * h2 * h2 * hinv, a.A[j]);
+        S.v[slot] = make_float4(vj.x, vj.y, vj.z, a.rho[j]);
+        S.c[slot] = a.cs[j];
+        if (HASH) S.m[slot] = a.mix[j];
     };
 
     for (;;) {
@@ -373,8 +466,10 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
         if (item >= a.nchunks) break;
         const int4 ch = a.chunks[item];
         const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
-        const int p = p0 + lane;
-        const bool act = lane < cnt;
+        const int R = replicas(cnt, a.rmax), T = 64 / R;
+        const int slot = lane & (T - 1), rep = lane / T;
+        const int p = p0 + slot;
+        const bool act = slot < cnt;
         ForceLane L;
         L.x = act ? a.pos[p] : make_float4(0.f, 0.f, 0.f, 0.f);
         L.h = act ? a.ph[p] : 1.f;
@@ -397,15 +492,9 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
             const int nsrc = min(64, cend - base);
             if (lane < nsrc) stage(lane, (uint32_t)(base + lane), 0.f, 0.f, 0.f);
             wave_lds_sync();
-            for (int jj = 0; jj < nsrc; ++jj) {
-                float4 q = s_p[w][jj];
-                float4 sh = s_h[w][jj];
-                float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
-                float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                if (act && r2 < fmaxf(hi2, sh.x * sh.x) && base + jj != p)
-                    force_pair(acc, L, dx, dy, dz, r2, q, sh, s_v[w][jj], s_c[w][jj], HASH ? s_m[w][jj] : 0ull,
-                               a.alpha);
-            }
+            const int share = (nsrc + R - 1) / R;
+            const int j0 = rep * share;
+            if (act) force_tile<HASH>(acc, S, j0, max(0, min(share, nsrc - j0)), L, hi2, p - base, a.alpha);
             wave_lds_sync();
         }
 
@@ -440,15 +529,9 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
                     }
                     const int nuse = __popcll(__ballot(ok));
                     wave_lds_sync();
-                    for (int jj = 0; jj < nuse; ++jj) {
-                        float4 q = s_p[w][jj];
-                        float4 sh = s_h[w][jj];
-                        float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
-                        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        if (act && r2 < fmaxf(hi2, sh.x * sh.x))
-                            force_pair(acc, L, dx, dy, dz, r2, q, sh, s_v[w][jj], s_c[w][jj],
-                                       HASH ? s_m[w][jj] : 0ull, a.alpha);
-                    }
+                    const int share = (nuse + R - 1) / R;
+                    const int j0 = rep * share;
+                    if (act) force_tile<HASH>(acc, S, j0, max(0, min(share, nuse - j0)), L, hi2, -1, a.alpha);
                     wave_lds_sync();
                     if (nuse < nsrc) break;
                 }
@@ -456,15 +539,20 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
             A = cA.parent;
         }
 
-        if (act) {
-            a.ax[p] = acc.ax + acc.cax;
-            a.ay[p] = acc.ay + acc.cay;
-            a.az[p] = acc.az + acc.caz;
-            a.du[p] = acc.du + acc.cdu;
-            a.vsig[p] = acc.vs;
-            a.S[p] = acc.S - acc.cS;
-            a.nf[p] = acc.nn;
-            if (HASH) a.hash[p] = acc.hs;
+        const float ax = comb_f(acc.ax + acc.cax, R), ay = comb_f(acc.ay + acc.cay, R);
+        const float az = comb_f(acc.az + acc.caz, R), du = comb_f(acc.du + acc.cdu, R);
+        const float vs = comb_max(acc.vs, R), Ss = comb_f(acc.S - acc.cS, R);
+        const int nn = comb_i(acc.nn, R);
+        const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
+        if (act && rep == 0) {
+            a.ax[p] = ax;
+            a.ay[p] = ay;
+            a.az[p] = az;
+            a.du[p] = du;
+            a.vsig[p] = vs;
+            a.S[p] = Ss;
+            a.nf[p] = nn;
+            if (HASH) a.hash[p] = hs;
         }
     }
 }
@@ -486,36 +574,93 @@ __global__ void k_solve_init(int64_t n, uint8_t* active, float* lo, float* hi) {
     hi[p] = INFINITY;
 }
 
+// Status words of the h solve: [0] some set must be rebuilt, [1] particles
+// still active (all sets), then per set s: [2+2s] rebuild flag, [3+2s]
+// particles still active.
+__device__ __forceinline__ int set_of(const SetInfo* sets, int nsets, int64_t p) {
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sets[mid].first <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // One safeguarded Newton step on N_w(h) = target for every active particle:
 // converged (|N_w - target| <= tol, tested in FP64) particles keep h and
-// their density; the rest move h and stay active.  status[0] is raised when
-// a new h reaches the bound its cells support; status[1] counts the
-// particles still active.
-__global__ void k_newton(int64_t n, uint8_t* __restrict__ active, const float* __restrict__ nw,
-                         const float* __restrict__ dnw, float* __restrict__ ph, const float* __restrict__ bound,
-                         float* __restrict__ lo, float* __restrict__ hi, double target, double tol,
-                         int32_t* __restrict__ status) {
+// their density; the rest move h and stay active.  A new h that reaches the
+// bound its cells support raises the rebuild flag of its set.
+__global__ void k_newton(int64_t n, const SetInfo* __restrict__ sets, int nsets, uint8_t* __restrict__ active,
+                         const float* __restrict__ nw, const float* __restrict__ dnw, float* __restrict__ ph,
+                         const float* __restrict__ bound, float* __restrict__ lo, float* __restrict__ hi,
+                         double target, double tol, int32_t* __restrict__ status) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n || !active[p]) return;
-    double err = (double)nw[p] - target;
-    if (fabs(err) <= tol) {
-        active[p] = 0;
-        return;
+    bool still = false, rebuild = false;
+    if (p < n && active[p]) {
+        double err = (double)nw[p] - target;
+        if (fabs(err) <= tol) {
+            active[p] = 0;
+        } else {
+            double h = ph[p];
+            double l = lo[p], u = hi[p];
+            if (err < 0) l = h; else u = h;
+            double d = dnw[p];
+            double hn = d > 0 ? h - err / d : -1.0;
+            bool bad = !(d > 0) || !(hn > l) || !(hn < u) || hn < 0.5 * h || hn > 2.0 * h;
+            if (bad) hn = isinf(u) ? 2.0 * h : 0.5 * (l + u);
+            // the minimum-image convention needs h < box/2
+            const double hcap = 0.5 * sets[set_of(sets, nsets, p)].box;
+            if (hn >= hcap) hn = 0.5 * (h + hcap);
+            float hf = (float)hn;
+            if (hf == (float)h) hf = err < 0 ? nextafterf((float)h, INFINITY) : nextafterf((float)h, 0.f);
+            if (!((double)hf < hcap)) hf = nextafterf((float)hcap, 0.f);
+            // a step past the largest h the cells support first probes just
+            // below it; only if the root still lies beyond is a rebuild needed
+            const float hb = nextafterf(bound[p], 0.f);
+            if (!(hf < bound[p])) {
+                if ((float)h == hb && err < 0) rebuild = true;
+                else hf = hb;
+            }
+            lo[p] = (float)l;
+            hi[p] = (float)u;
+            ph[p] = hf;
+            still = true;
+        }
     }
-    double h = ph[p];
-    double l = lo[p], u = hi[p];
-    if (err < 0) l = h; else u = h;
-    double d = dnw[p];
-    double hn = d > 0 ? h - err / d : -1.0;
-    bool bad = !(d > 0) || !(hn > l) || !(hn < u) || hn < 0.5 * h || hn > 2.0 * h;
-    if (bad) hn = isinf(u) ? 2.0 * h : 0.5 * (l + u);
-    float hf = (float)hn;
-    if (hf == (float)h) hf = err < 0 ? nextafterf((float)h, INFINITY) : nextafterf((float)h, 0.f);
-    lo[p] = (float)l;
-    hi[p] = (float)u;
-    ph[p] = hf;
-    if (!(hf < bound[p])) atomicExch(&status[0], 1);
-    atomicAdd(&status[1], 1);
+    // one atomic per wave and set: lanes of a wave are consecutive particles
+    const int lane = threadIdx.x & 63;
+    const int64_t p0 = p - lane;
+    const int s0 = set_of(sets, nsets, p0 < n ? p0 : n - 1);
+    const int s = (p < n) ? set_of(sets, nsets, p) : s0;
+    const bool uniform_set = __ballot(s != s0) == 0;
+    if (uniform_set) {
+        int ns = __popcll(__ballot(still));
+        bool rb = __ballot(rebuild) != 0;
+        if (lane == 0 && ns) {
+            atomicAdd(&status[1], ns);
+            atomicAdd(&status[3 + 2 * s0], ns);
+        }
+        if (lane == 0 && rb) {
+            atomicExch(&status[0], 1);
+            atomicExch(&status[2 + 2 * s0], 1);
+        }
+    } else {
+        if (still) {
+            atomicAdd(&status[1], 1);
+            atomicAdd(&status[3 + 2 * s], 1);
+        }
+        if (rebuild) {
+            atomicExch(&status[0], 1);
+            atomicExch(&status[2 + 2 * s], 1);
+        }
+    }
+}
+
+// zero the counts of still-active particles (total and per set)
+__global__ void k_zero_unconv(int32_t* status, int nsets) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) status[1] = 0;
+    if (i < nsets) status[3 + 2 * i] = 0;
 }
 
 __global__ void k_ghost(int64_t n, const float* __restrict__ ph, const float* __restrict__ rho,
@@ -663,12 +808,13 @@ static Err ensure_state(sph_tree* t) {
     t->nw = t->drho + n;
     t->dnw = t->nw + n;
     t->nngb = (int32_t*)(t->dnw + n);
-    // solve: lo, hi, status, active
-    ERRTRY(t->alloc(t->b_solve, n * (2 * sizeof(float) + 1) + 256, &p));
+    // solve: lo, hi, status (2 + 2 per set), active
+    const int64_t nst = 2 + 2 * (int64_t)t->nsets;
+    ERRTRY(t->alloc(t->b_solve, n * (2 * sizeof(float) + 1) + sizeof(int32_t) * (nst + 64) + 256, &p));
     t->lo = (float*)p;
     t->hi = t->lo + n;
     t->status = (int32_t*)(t->hi + n);
-    t->active = (uint8_t*)(t->status + 16);
+    t->active = (uint8_t*)(t->status + ((nst + 63) / 64) * 64);
     // force: A, cs, ax, ay, az, du, vs, S (float), nf (int), hash (u64)
     ERRTRY(t->alloc(t->b_force, n * (8 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 64, &p));
     t->hashf = (uint64_t*)p;
@@ -699,9 +845,36 @@ static Err ensure_state(sph_tree* t) {
     return Err{};
 }
 
-static int persistent_blocks(sph_ctx* ctx, int64_t items) {
+static void ev_mark(sph_ctx* ctx, const char* name) {
+    if (!ctx->timing) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, ctx->stream);
+    ctx->ev.emplace_back(name, e);
+}
+
+static void ev_collect(sph_ctx* ctx) {
+    if (!ctx->timing || ctx->ev.empty()) return;
+    (void)hipEventSynchronize(ctx->ev.back().second);
+    ctx->last_ms.clear();
+    for (size_t i = 1; i < ctx->ev.size(); ++i) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev[i - 1].second, ctx->ev[i].second);
+        ctx->last_ms.emplace_back(ctx->ev[i].first, (double)ms);
+    }
+    for (auto& e : ctx->ev) (void)hipEventDestroy(e.second);
+    ctx->ev.clear();
+}
+
+static int rmax_of(const sph_tree* t) {
+    int r = t->prm.max_replicas;
+    return (r == 1 || r == 2 || r == 4 || r == 8 || r == 16) ? r : 16;
+}
+
+static int persistent_blocks(sph_ctx* ctx, const sph_tree* t, int64_t items) {
     int64_t want = (items + 3) / 4;
-    int64_t cap = (int64_t)ctx->n_cu * 8;
+    int bpc = t->prm.blocks_per_cu > 0 ? t->prm.blocks_per_cu : 8;
+    int64_t cap = (int64_t)ctx->n_cu * bpc;
     return (int)std::max<int64_t>(1, std::min(want, cap));
 }
 
@@ -728,6 +901,7 @@ static DensArgs dens_args(sph_tree* t, int* counter) {
     a.dnw = t->dnw;
     a.nngb = t->nngb;
     a.hash = t->hashd;
+    a.rmax = rmax_of(t);
     return a;
 }
 
@@ -735,7 +909,7 @@ static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, int* counter) 
     hipStream_t st = ctx->stream;
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, counter, 1);
     DensArgs a = dens_args(t, counter);
-    dim3 g(persistent_blocks(ctx, t->nchunks)), b(BLK);
+    dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
     if (solve) {
         if (t->hash) hipLaunchKernelGGL((k_density<true, true>), g, b, 0, st, a);
         else hipLaunchKernelGGL((k_density<true, false>), g, b, 0, st, a);
@@ -752,6 +926,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
                        t->prm.gamma, t->A, t->cs);
     hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, counter, 1);
+    ev_mark(ctx, "ghost");
     ForceArgs a;
     a.cells = t->cells;
     a.sets = t->d_sets;
@@ -779,7 +954,8 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.S = t->fS;
     a.nf = t->fn;
     a.hash = t->hashf;
-    dim3 g(persistent_blocks(ctx, t->nchunks)), b(BLK);
+    a.rmax = rmax_of(t);
+    dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
     if (t->hash) hipLaunchKernelGGL((k_force<true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_force<false>), g, b, 0, st, a);
 }
@@ -803,27 +979,6 @@ static void launch_scatter_force(sph_ctx* ctx, sph_tree* t, const sph_force_out*
     if (!o || t->n == 0) return;
     hipLaunchKernelGGL(k_scatter_force, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->perm, t->fax,
                        t->fay, t->faz, t->fdu, t->fvs, t->fS, t->fn, t->hash ? t->hashf : nullptr, *o);
-}
-
-static void ev_mark(sph_ctx* ctx, const char* name) {
-    if (!ctx->timing) return;
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
-    (void)hipEventRecord(e, ctx->stream);
-    ctx->ev.emplace_back(name, e);
-}
-
-static void ev_collect(sph_ctx* ctx) {
-    if (!ctx->timing || ctx->ev.empty()) return;
-    (void)hipEventSynchronize(ctx->ev.back().second);
-    ctx->last_ms.clear();
-    for (size_t i = 1; i < ctx->ev.size(); ++i) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, ctx->ev[i - 1].second, ctx->ev[i].second);
-        ctx->last_ms.emplace_back(ctx->ev[i].first, (double)ms);
-    }
-    for (auto& e : ctx->ev) (void)hipEventDestroy(e.second);
-    ctx->ev.clear();
 }
 
 Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out) {
@@ -857,15 +1012,17 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     if (n == 0) return Err{};
     ev_mark(ctx, "start");
     hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, t->status, 2);
+    const int nst = 2 + 2 * t->nsets;
+    hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
     int32_t hstat[2] = {0, 0};
     int it = 0;
     bool rebuild = false;
     for (; it < t->prm.max_iter; ++it) {
         launch_density(ctx, t, true, ctx->d_counter);
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, t->status + 1, 1);
-        hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->nw, t->dnw, t->ph,
-                           t->bound, t->lo, t->hi, (double)t->prm.n_target, (double)t->prm.h_tol, t->status);
+        hipLaunchKernelGGL(k_zero_unconv, dim3(nblk(t->nsets, 256)), dim3(256), 0, st, t->status, t->nsets);
+        hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->d_sets, t->nsets, t->active,
+                           t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi, (double)t->prm.n_target,
+                           (double)t->prm.h_tol, t->status);
         HIPTRY(hipGetLastError());
         HIPTRY(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
         HIPTRY(hipStreamSynchronize(st));
@@ -908,10 +1065,17 @@ Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
     return Err{};
 }
 
-__global__ void k_copy_status(const int32_t* __restrict__ status, int32_t* __restrict__ out) {
-    if (threadIdx.x == 0) {
+// caller layout: [0] unconverged total, [1] any rebuild, then per set
+// [2+2s] unconverged, [3+2s] rebuild
+__global__ void k_copy_status(const int32_t* __restrict__ status, int nsets, int32_t* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
         out[0] = status[1];
         out[1] = status[0];
+    }
+    if (i < nsets) {
+        out[2 + 2 * i] = status[3 + 2 * i];
+        out[3 + 2 * i] = status[2 + 2 * i];
     }
 }
 
@@ -952,20 +1116,23 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi);
-            hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, t->status, 2);
+            const int nst = 2 + 2 * t->nsets;
+            hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
             for (int it = 0; it < k_iter; ++it) {
                 launch_density(ctx, t, true, ctx->d_counter);
-                hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, t->status + 1, 1);
-                hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->nw, t->dnw,
-                                   t->ph, t->bound, t->lo, t->hi, (double)t->prm.n_target, (double)t->prm.h_tol,
-                                   t->status);
+                hipLaunchKernelGGL(k_zero_unconv, dim3(nblk(t->nsets, 256)), dim3(256), 0, st, t->status,
+                                   t->nsets);
+                hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->d_sets, t->nsets,
+                                   t->active, t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi,
+                                   (double)t->prm.n_target, (double)t->prm.h_tol, t->status);
             }
             launch_density(ctx, t, true, ctx->d_counter);
             launch_force(ctx, t, ctx->d_counter + 1);
             launch_reduce(ctx, t, fout ? fout->sums : nullptr);
             launch_scatter_density(ctx, t, dout);
             launch_scatter_force(ctx, t, fout);
-            hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, st, t->status, n_unconv_dev);
+            hipLaunchKernelGGL(k_copy_status, dim3(nblk(t->nsets, 256)), dim3(256), 0, st, t->status, t->nsets,
+                               n_unconv_dev);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(st, &g);
             if (e == hipSuccess) {

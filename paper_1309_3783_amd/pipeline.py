@@ -1,0 +1,104 @@
+"""Whole-pipeline drivers over the C-ABI: eager (build -> sort -> solve_h ->
+force) and graph mode (build -> sort -> one HIP graph holding the Newton
+passes, ghost, force and sums).  Argument marshalling only."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import binding as B
+
+
+class Outputs:
+    """Density and force outputs plus the device status words of a batch
+    ([0] unconverged, [1] rebuild, then per set: unconverged, rebuild)."""
+
+    def __init__(self, n: int, nsets: int, device="cuda", hash=False):
+        import torch
+        self.d = B.DensityOut(n, device, hash=hash)
+        self.f = B.ForceOut(n, nsets, device, hash=hash)
+        self.status = torch.zeros(2 + 2 * max(nsets, 1), dtype=torch.int32, device=device)
+
+
+DENSITY_FIELDS = ("rho", "drho_dh", "nw", "dnw_dh", "nngb", "h", "hash")
+FORCE_FIELDS = ("ax", "ay", "az", "dudt", "vsig", "S", "nforce", "hash")
+
+
+def sub_batch(batch: B.Batch, sets, h_full) -> B.Batch:
+    """The listed sets of a batch as a new batch, with smoothing lengths taken
+    from h_full (caller order of the full batch)."""
+    import torch
+    idx = [(int(batch.offsets[s]), int(batch.offsets[s + 1])) for s in sets]
+
+    def cat(t):
+        return torch.cat([t[a:b] for a, b in idx]) if idx else t[:0]
+
+    sizes = [b - a for a, b in idx]
+    off = np.zeros(len(sets) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return B.Batch(cat(batch.x), cat(batch.y), cat(batch.z), cat(h_full), cat(batch.m), cat(batch.u),
+                   cat(batch.vx), cat(batch.vy), cat(batch.vz), off, batch.box[list(sets)])
+
+
+def run_eager(tree: B.Tree, batch: B.Batch, prm, out: Outputs):
+    st, nu, it = B.solve_with_rebuild(tree, batch, prm, out.d)
+    if st not in (B.SPH_OK, B.SPH_E_NOCONV):
+        raise B.SphError(st, "solve_h")
+    tree.force(out.f)
+    return it, nu
+
+
+def launch_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int):
+    """build + sort (these synchronise the stream) and enqueue the graph;
+    returns without waiting for the graph."""
+    tree.build_cells(batch, prm)
+    tree.sort_pairs()
+    tree.run_graph(k_iter, out.d, out.f, out.status)
+
+
+def finish_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int):
+    """After the stream has been synchronised: the sets whose h did not
+    converge in the graph's fixed number of passes, or outgrew their cells,
+    are re-run on their own (rebuilt from the h they reached, eager solve,
+    force) and their results copied into the batch outputs.  The other sets
+    keep the graph's results, so every set ends exactly as it would alone.
+    Returns the number of sets re-run."""
+    st = out.status.cpu().numpy()
+    if st[0] == 0 and st[1] == 0:
+        return 0
+    bad = [s for s in range(batch.nsets) if st[2 + 2 * s] != 0 or st[3 + 2 * s] != 0]
+    aux = B.Tree(tree.ctx)
+    for s in bad:
+        # one set at a time: a rebuild needed by one set must not touch another
+        sub = sub_batch(batch, [s], out.d.h)
+        sub_out = Outputs(sub.n, 1, hash=out.d.hash is not None)
+        run_eager(aux, sub, prm, sub_out)
+        k = 0
+        a, b = int(batch.offsets[s]), int(batch.offsets[s + 1])
+        c, d = int(sub.offsets[k]), int(sub.offsets[k + 1])
+        for f in DENSITY_FIELDS:
+            dst, src = getattr(out.d, f), getattr(sub_out.d, f)
+            if dst is not None and src is not None:
+                dst[a:b].copy_(src[c:d])
+        for f in FORCE_FIELDS:
+            dst, src = getattr(out.f, f), getattr(sub_out.f, f)
+            if dst is not None and src is not None:
+                dst[a:b].copy_(src[c:d])
+        out.f.sums[8 * s:8 * s + 8].copy_(sub_out.f.sums[8 * k:8 * k + 8])
+    return len(bad)
+
+
+def run_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int = 8):
+    import torch
+    launch_graph(tree, batch, prm, out, k_iter)
+    tree.ctx.stream.synchronize() if hasattr(tree.ctx.stream, "synchronize") else torch.cuda.synchronize()
+    return finish_graph(tree, batch, prm, out, k_iter)
+
+
+def pair_count(out: Outputs) -> float:
+    s = out.f.sums.view(-1, 8).cpu().numpy()
+    return float(s[:, 6].sum()) / 2.0
+
+
+def per_set(batch: B.Batch, t, s: int) -> np.ndarray:
+    a, b = int(batch.offsets[s]), int(batch.offsets[s + 1])
+    return t[a:b].cpu().numpy()

@@ -71,15 +71,24 @@ def _snap_unique(pos: np.ndarray, redraw, rng: np.random.Generator) -> np.ndarra
     """Snap positions to the 2^-24 grid (mod 1) and redraw exact duplicates."""
     for _ in range(64):
         k = np.floor(np.mod(pos, 1.0) * GRID).astype(np.int64) % int(GRID)
-        _, first = np.unique(k, axis=0, return_index=True)
-        dup = np.ones(pos.shape[0], dtype=bool)
-        dup[first] = False
+        dup = _duplicates(k)
         if not dup.any():
             return k.astype(np.float64) / GRID
         idx = np.nonzero(dup)[0]
         pos = pos.copy()
         pos[idx] = redraw(idx, rng)
     raise RuntimeError("could not draw unique positions")
+
+
+def _duplicates(k: np.ndarray) -> np.ndarray:
+    """Mask of rows of k (integer triples) equal to an earlier row in sort
+    order (every duplicate but one)."""
+    order = np.lexsort((k[:, 2], k[:, 1], k[:, 0]))
+    ks = k[order]
+    same = np.all(ks[1:] == ks[:-1], axis=1)
+    dup = np.zeros(k.shape[0], dtype=bool)
+    dup[order[1:][same]] = True
+    return dup
 
 
 def _finish(pos, n, rng, h0, velocity, meta) -> ParticleSet:
@@ -124,8 +133,7 @@ def lattice(n_side: int, jitter: float, seed: int, velocity: bool = False) -> Pa
         return base[idx] + r.uniform(-jitter, jitter, size=(idx.size, 3)) * d
 
     pos = _snap_unique(pos, redraw, rng)
-    # lattice value of h for N_w = 48 is ~2.2515 spacings; start a bit off it
-    return _finish(pos, n, rng, np.full(n, 2.2 * d), velocity,
+    return _finish(pos, n, rng, np.full(n, h_for_density(float(n))), velocity,
                    {"recipe": "lattice", "n_side": n_side, "jitter": jitter, "seed": seed})
 
 
@@ -179,21 +187,30 @@ def plummer_mixture(n: int, seed: int, n_clumps: int = 64, bg_frac: float = 0.2,
                     "bg_frac": bg_frac, "a": a.tolist(), "centre": centre.tolist()})
 
 
-def plummer_number_density(pos, n_bg, per, a, rmax, centre, chunk=1 << 20):
-    """Analytic number density of the truncated-Plummer mixture at ``pos``."""
+def plummer_number_density(pos, n_bg, per, a, rmax, centre):
+    """Analytic number density of the truncated-Plummer mixture at ``pos``
+    (each clump contributes only inside its truncation radius, so only the
+    particles in the periodic x-slab around its centre are visited)."""
     out = np.full(pos.shape[0], float(n_bg))
     umax = rmax ** 3 / (rmax ** 2 + a ** 2) ** 1.5
-    for s in range(0, pos.shape[0], chunk):
-        p = pos[s:s + chunk]
-        acc = np.zeros(p.shape[0])
-        for c in range(len(a)):
-            d = p - centre[c]
-            d -= np.round(d)
-            r2 = np.einsum("ij,ij->i", d, d)
-            rho = (3.0 * per[c] / (4.0 * math.pi * a[c] ** 3 * umax[c])) * \
-                (1.0 + r2 / a[c] ** 2) ** -2.5
-            acc += np.where(r2 < rmax[c] ** 2, rho, 0.0)
-        out[s:s + chunk] += acc
+    xs_order = np.argsort(pos[:, 0], kind="stable")
+    xs = pos[xs_order, 0]
+    for c in range(len(a)):
+        lo, hi = centre[c, 0] - rmax[c], centre[c, 0] + rmax[c]
+        spans = []
+        for sh in (-1.0, 0.0, 1.0):
+            a0, b0 = max(lo + sh, 0.0), min(hi + sh, 1.0)
+            if a0 < b0:
+                spans.append(xs_order[np.searchsorted(xs, a0):np.searchsorted(xs, b0, side="right")])
+        if not spans:
+            continue
+        idx = np.unique(np.concatenate(spans))
+        d = pos[idx] - centre[c]
+        d -= np.round(d)
+        r2 = np.einsum("ij,ij->i", d, d)
+        t = 1.0 / (1.0 + r2 * (1.0 / a[c] ** 2))
+        rho = (3.0 * per[c] / (4.0 * math.pi * a[c] ** 3 * umax[c])) * (t * t * np.sqrt(t))
+        out[idx] += np.where(r2 < rmax[c] ** 2, rho, 0.0)
     return out
 
 

@@ -1,0 +1,152 @@
+"""GPU tests of the batched (graph) and served paths.
+
+* the HIP-graph pipeline gives bitwise the results of the eager calls, and
+  every graph replay (with eager work in between) matches;
+* a set inside a batch of uneven sets is bitwise the same as alone;
+* the served loop: every request's results are bitwise the same alone and in
+  the mix, and its solved h satisfies the neighbour target (checked in FP64
+  by the oracle's root of N_w for a sample).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import _inputs as I  # noqa: E402
+
+import oracle  # noqa: E402
+import sphinputs  # noqa: E402
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1309_3783_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(sph):
+    return sph.Context(0)
+
+
+def grab(out, batch, s):
+    from paper_1309_3783_amd import pipeline as P
+    r = {k: P.per_set(batch, getattr(out.d, k), s) for k in ("rho", "h", "nngb", "nw")}
+    r.update({k: P.per_set(batch, getattr(out.f, k), s) for k in ("ax", "ay", "az", "dudt", "S", "nforce")})
+    r["sums"] = out.f.sums.view(-1, 8)[s].cpu().numpy()
+    return r
+
+
+def same(a, b, keys=None):
+    for k in keys or a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_graph_equals_eager(sph, ctx):
+    from paper_1309_3783_amd import pipeline as P
+    ps = sphinputs.plummer_mixture(20000, 21, velocity=True)
+    batch = sph.batch_from_sets([ps])
+    prm = sph.params()
+    te, tg = sph.Tree(ctx), sph.Tree(ctx)
+    oe, og = P.Outputs(ps.n, 1), P.Outputs(ps.n, 1)
+    P.run_eager(te, batch, prm, oe)
+    assert P.run_graph(tg, batch, prm, og, k_iter=12) == 0
+    torch.cuda.synchronize()
+    same(grab(oe, batch, 0), grab(og, batch, 0))
+
+
+def test_graph_replays_match(sph, ctx):
+    # A replay re-runs the captured pipeline from the tree's current state
+    # (h already solved).  Every replay, with eager work in between, must
+    # equal the eager calls making the same transition on the same tree.
+    from paper_1309_3783_amd import pipeline as P
+    ps = sphinputs.plummer_mixture(12000, 22, velocity=True)
+    batch = sph.batch_from_sets([ps])
+    prm = sph.params()
+    tree = sph.Tree(ctx)
+    out = P.Outputs(ps.n, 1)
+    P.launch_graph(tree, batch, prm, out, 12)
+    torch.cuda.synchronize()
+    g0 = grab(out, batch, 0)
+    eager = P.Outputs(ps.n, 1)
+    st, nu, it = tree.solve_h(eager.d)
+    assert st == sph.SPH_OK and nu == 0
+    tree.force(eager.f)
+    torch.cuda.synchronize()
+    e1 = grab(eager, batch, 0)
+    assert np.array_equal(e1["h"], g0["h"])
+    assert np.allclose(e1["rho"], g0["rho"], rtol=2e-6)
+    for rep in range(3):
+        tree.run_graph(12, out.d, out.f, out.status)      # replay of the captured graph
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()    # eager work between replays
+        torch.cuda.synchronize()
+        assert not out.status.any()
+        same(e1, grab(out, batch, 0))
+        del junk
+
+
+def test_batched_sets_equal_alone(sph, ctx):
+    from paper_1309_3783_amd import pipeline as P
+    sets = [sphinputs.plummer_mixture(int(n), 1000 + k) for k, n in enumerate([2000, 31000, 5000, 120000, 2600])]
+    prm = sph.params()
+    batch = sph.batch_from_sets(sets)
+    out = P.Outputs(batch.n, batch.nsets)
+    P.run_graph(sph.Tree(ctx), batch, prm, out, 12)
+    torch.cuda.synchronize()
+    for s, ps in enumerate(sets):
+        b1 = sph.batch_from_sets([ps])
+        o1 = P.Outputs(ps.n, 1)
+        P.run_graph(sph.Tree(ctx), b1, prm, o1, 12)
+        torch.cuda.synchronize()
+        a, b = grab(out, batch, s), grab(o1, b1, 0)
+        same(a, b)
+        nw = a["nw"]
+        assert np.abs(nw - 48.0).max() <= 0.5 + 1e-4
+
+
+def test_served_mix_equals_alone(sph):
+    from paper_1309_3783_amd import serve as S
+    rng = np.random.default_rng(5)
+    ns = np.round(np.exp(rng.uniform(np.log(2e3), np.log(6e4), 14))).astype(int)
+    arr = np.cumsum(rng.exponential(0.002, len(ns)))
+    pool = [sphinputs.plummer_mixture(int(n), 500 + k) for k, n in enumerate(ns)]
+    prm = sph.params()
+    ex = S.GpuExecutor(prm, k_iter=12, lanes=2, keep_results=True)
+    reqs = [S.Request(i, float(a), pool[i]) for i, a in enumerate(arr)]
+    sch = S.Scheduler(ex, budget_bytes=2 << 30, footprint=lambda r: sph.footprint(r.n), max_batch=8)
+    sch.run(reqs)
+    assert max(r.batch_size for r in reqs) >= 2           # some requests were batched
+    summ = S.summary(reqs)
+    assert summ["p99_ms"] >= summ["p50_ms"] > 0
+    alone_ex = S.GpuExecutor(prm, k_iter=12, lanes=1, keep_results=True)
+    for r in reqs:
+        q = S.Request(r.rid, 0.0, r.ps)
+        S.Scheduler(alone_ex, budget_bytes=2 << 30, footprint=lambda x: 1, max_batch=1).run([q])
+        same(r.result, q.result)
+        assert q.batch_size == 1
+    # the solved h against the oracle's own FP64 root on a sample of the
+    # smallest requests (|N_w - 48| <= 0.5 bounds h to well under 1.5%)
+    for r in sorted(reqs, key=lambda x: x.n)[:3]:
+        ps = r.ps
+        t = np.arange(0, ps.n, max(1, ps.n // 300))
+        h_ref, _ = oracle.solve_h(ps.x, ps.y, ps.z, ps.m, ps.h0, targets=t, tol=1e-9)
+        assert np.abs(np.asarray(r.result["h"], dtype=np.float64)[t] / h_ref[t] - 1.0).max() < 1.5e-2
+        assert np.abs(r.result["nw"] - 48.0).max() <= 0.5 + 1e-4
+
+
+def test_autotune_picks_a_candidate(sph, ctx):
+    from paper_1309_3783_amd import autotune
+    sets = [sphinputs.plummer_mixture(3000, 900 + k) for k in range(4)]
+    batch = sph.batch_from_sets(sets)
+    best = autotune.tune(ctx, batch, k_iter=10, reps=1, grid={"blocks_per_cu": [4, 8], "max_replicas": [4, 16]},
+                         use_cache=False)
+    assert best["blocks_per_cu"] in (4, 8) and best["max_replicas"] in (4, 16)

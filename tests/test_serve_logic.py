@@ -1,0 +1,71 @@
+"""CPU tests of the served-mode scheduler against a simulated executor:
+admission by footprint, head-of-line bypass and its limit, slot reuse,
+latency bookkeeping and the p50/p99 summary."""
+import numpy as np
+
+from paper_1309_3783_amd.serve import FakeExecutor, Request, Scheduler, summary
+
+
+class PS:
+    def __init__(self, n):
+        self.n = n
+
+
+def fp(r):
+    return r.n * 100
+
+
+def make(ns, arrivals):
+    return [Request(i, float(a), PS(n)) for i, (n, a) in enumerate(zip(ns, arrivals))]
+
+
+def test_all_requests_complete_and_latency_positive():
+    rng = np.random.default_rng(0)
+    ns = np.round(np.exp(rng.uniform(np.log(1e4), np.log(2e6), 300))).astype(int)
+    arr = np.cumsum(rng.exponential(0.002, 300))
+    reqs = make(ns, arr)
+    sch = Scheduler(FakeExecutor(lanes=2), budget_bytes=400_000_000, footprint=fp)
+    out = sch.run(reqs)
+    assert all(r.t_done >= r.t_start >= r.arrival for r in out)
+    s = summary(out)
+    assert s["requests"] == 300 and s["p99_ms"] >= s["p50_ms"] > 0
+    # memory in flight never exceeds the budget
+    assert max(u for _, _, u in sch.log) <= 400_000_000
+    assert sch.in_use == 0
+
+
+def test_admission_respects_budget_and_batches_arrivals():
+    # five small requests arriving together fit in one batch; budget allows 3
+    reqs = make([1000] * 5, [0.0] * 5)
+    sch = Scheduler(FakeExecutor(lanes=1, base=1.0, per_particle=0.0), budget_bytes=3 * 1000 * 100,
+                    footprint=fp)
+    sch.run(reqs)
+    sizes = [n for _, n, _ in sch.log]
+    assert sizes == [3, 2]
+    assert reqs[3].t_start == 1.0 and reqs[0].t_done == 1.0
+
+
+def test_head_of_line_bypass_is_bounded():
+    # a big head request that does not fit next to a running one: smaller
+    # requests behind it go first, at most max_bypass times
+    ns = [600, 900] + [100] * 20
+    arr = [0.0, 0.001] + [0.002 + 0.0001 * k for k in range(20)]
+    reqs = make(ns, arr)
+    sch = Scheduler(FakeExecutor(lanes=2, base=0.01, per_particle=0.0), budget_bytes=1000 * 100,
+                    footprint=fp, max_batch=1, max_bypass=3)
+    sch.run(reqs)
+    big = reqs[1]
+    smaller_first = [r for r in reqs[2:] if r.t_start < big.t_start]
+    assert 1 <= len(smaller_first) <= 3 + 1
+    assert all(r.t_done > 0 for r in reqs)
+
+
+def test_request_larger_than_budget_is_rejected():
+    reqs = make([10_000], [0.0])
+    sch = Scheduler(FakeExecutor(), budget_bytes=100, footprint=fp)
+    try:
+        sch.run(reqs)
+    except RuntimeError as e:
+        assert "exceeds the whole budget" in str(e)
+    else:
+        raise AssertionError("expected a rejection")
