@@ -62,7 +62,8 @@ def lib():
         L.ora_ghost.argtypes = [i64, vp, vp, vp, vp, d, vp, vp, vp, vp]
         L.ora_force.argtypes = [i64, vp, vp, vp, d] + [vp] * 8 + [d, d, i64, vp, C.c_int] + [vp] * 8
         L.ora_sums.argtypes = [i64] + [vp] * 10
-        L.ora_near_cutoff.argtypes = [i64, vp, vp, vp, d, vp, d, C.c_int, vp]
+        L.ora_near_cutoff.argtypes = [i64, vp, vp, vp, d, vp, d, C.c_int, i64, vp, vp]
+        L.ora_force_neighbours.argtypes = [i64, vp, vp, vp, d, vp, i64, vp, vp]
         L.ora_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -196,16 +197,32 @@ def sums(m, vx, vy, vz, ax, ay, az, dudt, S):
     return {"M": out[:3].copy(), "E": float(out[3]), "scale": float(out[4])}
 
 
-def near_cutoff(x, y, z, h, box=1.0, rel=1e-6, brute=False):
+def near_cutoff(x, y, z, h, box=1.0, rel=1e-6, brute=False, targets=None):
+    """Per particle (or per target): True if some pair lies within rel of
+    its own or the partner's cutoff."""
     x, y, z = _f64(x), _f64(y), _f64(z)
     n = x.size
     h = _f64(h, n)
+    nt, t = _targets(targets)
     flag = np.zeros(n, dtype=np.uint8)
-    st = lib().ora_near_cutoff(n, _ptr(x), _ptr(y), _ptr(z), box, _ptr(h), float(rel), int(brute),
+    st = lib().ora_near_cutoff(n, _ptr(x), _ptr(y), _ptr(z), box, _ptr(h), float(rel), int(brute), nt, _ptr(t),
                                _ptr(flag))
     if st:
         raise OracleError(st, "near_cutoff")
     return flag.astype(bool)
+
+
+def force_neighbours(x, y, z, h, targets, box=1.0):
+    """Mask of the targets and of all their force neighbours."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    h = _f64(h, n)
+    nt, t = _targets(targets)
+    mark = np.zeros(n, dtype=np.uint8)
+    st = lib().ora_force_neighbours(n, _ptr(x), _ptr(y), _ptr(z), box, _ptr(h), nt, _ptr(t), _ptr(mark))
+    if st:
+        raise OracleError(st, "force_neighbours")
+    return mark.astype(bool)
 
 
 def run_all(ps, h, gamma=GAMMA, alpha=ALPHA, brute=False, targets=None):

@@ -485,14 +485,16 @@ static void tie_visit(int64_t j, void* vctx) {
 }
 
 int ora_near_cutoff(int64_t n, const double* x, const double* y, const double* z, double box,
-                    const double* h, double rel, int brute, uint8_t* flag) {
+                    const double* h, double rel, int brute, int64_t nt, const int64_t* targets, uint8_t* flag) {
     ora_pos p = { n, x, y, z, box };
-    int st = check_set(&p, h, 0, NULL);
+    int st = check_set(&p, h, nt, targets);
     if (st) return st;
     ora_grid g;
     if (!brute && (st = grid_build(&g, &p, h, 1))) return st;
+    int64_t cnt = targets ? nt : n;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = 0; k < cnt; ++k) {
+        int64_t i = targets ? targets[k] : k;
         tie_ctx c = { &p, h, i, rel, 0 };
         if (brute) {
             for (int64_t j = 0; j < n; ++j) tie_visit(j, &c);
@@ -505,6 +507,44 @@ int ora_near_cutoff(int64_t n, const double* x, const double* y, const double* z
         flag[i] = (uint8_t)c.flag;
     }
     if (!brute) grid_free(&g);
+    return ORA_OK;
+}
+
+/* Mark every particle that is a force neighbour (r < max(h_i, h_j)) of one
+ * of the targets, and the targets themselves (to know whose densities a
+ * sampled force evaluation needs). */
+typedef struct { const ora_pos* p; const double* h; int64_t i; uint8_t* mark; } nb_ctx;
+
+static void nb_visit(int64_t j, void* vctx) {
+    nb_ctx* c = (nb_ctx*)vctx;
+    const ora_pos* p = c->p;
+    double dx = min_image(p->x[c->i] - p->x[j], p->box);
+    double dy = min_image(p->y[c->i] - p->y[j], p->box);
+    double dz = min_image(p->z[c->i] - p->z[j], p->box);
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double a = c->h[c->i], b = c->h[j];
+    if (r < (a > b ? a : b)) c->mark[j] = 1;
+}
+
+int ora_force_neighbours(int64_t n, const double* x, const double* y, const double* z, double box,
+                         const double* h, int64_t nt, const int64_t* targets, uint8_t* mark) {
+    ora_pos p = { n, x, y, z, box };
+    int st = check_set(&p, h, nt, targets);
+    if (st) return st;
+    if (!targets) return ORA_E_ARG;
+    ora_grid g;
+    if ((st = grid_build(&g, &p, h, 1))) return st;
+    /* serial over targets: marks are written by many targets */
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = targets[k];
+        nb_ctx c = { &p, h, i, mark };
+        mark[i] = 1;
+        for (int cl = 0; cl < g.ncls; ++cl) {
+            double R = h[i] > g.hmax[cl] ? h[i] : g.hmax[cl];
+            grid_query(&g, &p, cl, x[i], y[i], z[i], R, nb_visit, &c);
+        }
+    }
+    grid_free(&g);
     return ORA_OK;
 }
 

@@ -55,36 +55,65 @@ def launch_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int):
     tree.run_graph(k_iter, out.d, out.f, out.status)
 
 
-def finish_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int):
-    """After the stream has been synchronised: the sets whose h did not
-    converge in the graph's fixed number of passes, or outgrew their cells,
-    are re-run on their own (rebuilt from the h they reached, eager solve,
-    force) and their results copied into the batch outputs.  The other sets
-    keep the graph's results, so every set ends exactly as it would alone.
-    Returns the number of sets re-run."""
+def _copy_set(out: Outputs, batch: B.Batch, s: int, sub_out: Outputs, sub: B.Batch, k: int):
+    a, b = int(batch.offsets[s]), int(batch.offsets[s + 1])
+    c, d = int(sub.offsets[k]), int(sub.offsets[k + 1])
+    for f in DENSITY_FIELDS:
+        dst, src = getattr(out.d, f), getattr(sub_out.d, f)
+        if dst is not None and src is not None:
+            dst[a:b].copy_(src[c:d])
+    for f in FORCE_FIELDS:
+        dst, src = getattr(out.f, f), getattr(sub_out.f, f)
+        if dst is not None and src is not None:
+            dst[a:b].copy_(src[c:d])
+    out.f.sums[8 * s:8 * s + 8].copy_(sub_out.f.sums[8 * k:8 * k + 8])
+
+
+def failing_sets(out: Outputs, nsets: int) -> list:
     st = out.status.cpu().numpy()
     if st[0] == 0 and st[1] == 0:
+        return []
+    return [s for s in range(nsets) if st[2 + 2 * s] != 0 or st[3 + 2 * s] != 0]
+
+
+def finish_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int, max_rounds: int = 4):
+    """After the stream has been synchronised: the sets whose h did not
+    converge in the graph's fixed number of passes, or outgrew their cells,
+    are rebuilt from the h they reached and run again through the graph,
+    together (the graph keeps sets independent: per-set status words), for
+    up to max_rounds rounds; a set still failing then finishes with the eager
+    calls on its own.  Results are copied into the batch outputs; the other
+    sets keep theirs, so every set ends exactly as it would alone.
+    Returns the number of set re-runs."""
+    bad = failing_sets(out, batch.nsets)
+    if not bad:
         return 0
-    bad = [s for s in range(batch.nsets) if st[2 + 2 * s] != 0 or st[3 + 2 * s] != 0]
+    reruns = 0
     aux = B.Tree(tree.ctx)
-    for s in bad:
-        # one set at a time: a rebuild needed by one set must not touch another
-        sub = sub_batch(batch, [s], out.d.h)
-        sub_out = Outputs(sub.n, 1, hash=out.d.hash is not None)
-        run_eager(aux, sub, prm, sub_out)
-        k = 0
-        a, b = int(batch.offsets[s]), int(batch.offsets[s + 1])
-        c, d = int(sub.offsets[k]), int(sub.offsets[k + 1])
-        for f in DENSITY_FIELDS:
-            dst, src = getattr(out.d, f), getattr(sub_out.d, f)
-            if dst is not None and src is not None:
-                dst[a:b].copy_(src[c:d])
-        for f in FORCE_FIELDS:
-            dst, src = getattr(out.f, f), getattr(sub_out.f, f)
-            if dst is not None and src is not None:
-                dst[a:b].copy_(src[c:d])
-        out.f.sums[8 * s:8 * s + 8].copy_(sub_out.f.sums[8 * k:8 * k + 8])
-    return len(bad)
+    cur_batch, cur_out, ids = batch, out, list(range(batch.nsets))
+    for _ in range(max_rounds):
+        sub = sub_batch(cur_batch, bad, cur_out.d.h)
+        sub_out = Outputs(sub.n, sub.nsets, hash=out.d.hash is not None)
+        launch_graph(aux, sub, prm, sub_out, k_iter)
+        aux.ctx.stream.synchronize()
+        reruns += len(bad)
+        ids = [ids[s] for s in bad]
+        still = set(failing_sets(sub_out, sub.nsets))
+        for k, s in enumerate(ids):
+            if k not in still:
+                _copy_set(out, batch, s, sub_out, sub, k)
+        if not still:
+            return reruns
+        cur_batch, cur_out = sub, sub_out
+        bad = sorted(still)
+    ids = [ids[s] for s in bad]
+    for k0, s in zip(bad, ids):
+        one = sub_batch(cur_batch, [k0], cur_out.d.h)
+        one_out = Outputs(one.n, 1, hash=out.d.hash is not None)
+        run_eager(aux, one, prm, one_out)
+        _copy_set(out, batch, s, one_out, one, 0)
+        reruns += 1
+    return reruns
 
 
 def run_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int = 8):

@@ -1,0 +1,127 @@
+"""Parity at the benchmark sizes, in the benchmark's launch configuration.
+
+The full sets (1M jittered lattice, 8M clumpy mixture) run on the GPU at a
+fixed h (the generator's first guess, so no oracle solve of every particle
+is needed); the oracle recomputes a random sample of targets one by one
+(with the densities of exactly their force neighbours).  Targets having a
+pair within 1e-6 of a cutoff are left out of the sample (their pair-set
+membership would hinge on rounding).  The h solve is checked by comparing
+the GPU's solved h with the oracle's own FP64 root for the sampled targets.
+Sums of momentum and energy rate must vanish to 1e-5 of sum m S at any size.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import _inputs as I  # noqa: E402
+
+import oracle  # noqa: E402
+import sphinputs  # noqa: E402
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NSAMPLE = 1500
+
+
+@pytest.fixture(scope="module")
+def sph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1309_3783_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(sph):
+    return sph.Context(0)
+
+
+_cache = {}
+
+
+def workload(name):
+    if name not in _cache:
+        if name == "lattice_1M":
+            ps = sphinputs.lattice(100, 0.1, 2)
+        else:
+            ps = sphinputs.plummer_mixture(8_000_000, 3)
+        _cache.clear()
+        _cache[name] = ps
+    return _cache[name]
+
+
+def sample(ps, h, seed=7):
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.choice(ps.n, size=NSAMPLE, replace=False))
+    ties = oracle.near_cutoff(ps.x, ps.y, ps.z, h, ps.box, targets=t)
+    return t[~ties[t]]
+
+
+@pytest.mark.parametrize("name", ["lattice_1M", "plummer_8M"])
+def test_fullsize_fixed_h_sampled(sph, ctx, name):
+    ps = workload(name)
+    h = I.f32(ps.h0)
+    t = sample(ps, h)
+    assert t.size > NSAMPLE * 0.9
+    # GPU: the benchmark's parameters (no pair hashes), then with hashes
+    res = {}
+    for flags in (0, sph.SPH_FLAG_PAIR_HASH):
+        batch = sph.batch_from_sets([ps], h=[h])
+        tree = sph.Tree(ctx)
+        tree.build_cells(batch, sph.params(flags=flags))
+        tree.sort_pairs()
+        d = sph.DensityOut(ps.n, "cuda", hash=bool(flags))
+        f = sph.ForceOut(ps.n, 1, "cuda", hash=bool(flags))
+        tree.density(d)
+        tree.force(f)
+        torch.cuda.synchronize()
+        res[flags] = (d, f, tree.stats())
+        del batch
+    d, f, st = res[0]
+    dh, fh, _ = res[sph.SPH_FLAG_PAIR_HASH]
+    # oracle: densities of the targets and their force neighbours, then forces
+    mark = oracle.force_neighbours(ps.x, ps.y, ps.z, h, t, ps.box)
+    nb = np.nonzero(mark)[0]
+    od = oracle.density(ps.x, ps.y, ps.z, h, ps.m, ps.box, targets=nb)
+    of = oracle.force(ps.x, ps.y, ps.z, h, ps.m, ps.vx, ps.vy, ps.vz, ps.u, od["rho"], od["drho_dh"], ps.box,
+                      targets=t)
+    g_nngb = d.nngb.cpu().numpy()[t]
+    assert np.array_equal(g_nngb, od["nngb"][t])
+    assert np.array_equal(dh.hash.cpu().numpy().view(np.uint64)[t], od["hash"][t])
+    rho = d.rho.cpu().numpy()[t]
+    assert np.max(np.abs(rho - od["rho"][t]) / od["rho"][t]) <= 1e-5
+    assert np.array_equal(f.nforce.cpu().numpy()[t], of["nforce"][t])
+    assert np.array_equal(fh.hash.cpu().numpy().view(np.uint64)[t], of["hash"][t])
+    S = of["S"][t]
+    for k in ("ax", "ay", "az"):
+        err = np.abs(getattr(f, k).cpu().numpy()[t] - of[k][t]) / S
+        assert err.max() <= 1e-4, (k, err.max())
+    # the hash variant computes the same numbers
+    assert torch.equal(d.rho, dh.rho) and torch.equal(f.ax, fh.ax)
+    # conservation over the whole set
+    s = f.sums.cpu().numpy()
+    assert np.all(np.abs(s[:3]) <= 1e-5 * s[4]) and abs(s[3]) <= 1e-5 * s[4]
+    assert s[6] == float(f.nforce.sum().item())
+
+
+@pytest.mark.parametrize("name", ["lattice_1M", "plummer_8M"])
+def test_fullsize_solve_sampled(sph, ctx, name):
+    ps = workload(name)
+    batch = sph.batch_from_sets([ps])
+    dout = sph.DensityOut(ps.n, "cuda")
+    tree = sph.Tree(ctx)
+    st, nu, it = sph.solve_with_rebuild(tree, batch, sph.params(), dout)
+    assert st == sph.SPH_OK and nu == 0
+    torch.cuda.synchronize()
+    nw = dout.nw.cpu().numpy()
+    assert np.abs(nw - 48.0).max() <= 0.5 + 1e-4
+    rng = np.random.default_rng(11)
+    t = np.sort(rng.choice(ps.n, size=400, replace=False))
+    h_ref, _ = oracle.solve_h(ps.x, ps.y, ps.z, ps.m, ps.h0, ps.box, targets=t, tol=1e-9)
+    hg = dout.h.cpu().numpy().astype(np.float64)[t]
+    assert np.max(np.abs(hg / h_ref[t] - 1.0)) < 1.5e-2
