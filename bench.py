@@ -122,7 +122,7 @@ def run(args):
     ctx = sph.Context(0)
     stream = ctx.stream
     batch = sph.batch_from_sets(sets, device=dev)
-    prm = sph.params()
+    prm = sph.params(**({"h_slack": args.slack} if args.slack is not None else {}))
     n = batch.n
     dout = sph.DensityOut(n, dev)
     fout = sph.ForceOut(n, batch.nsets, dev)
@@ -167,6 +167,7 @@ def run(args):
     log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, P = {P:.4g}, stages {{"
         + ", ".join(f"{k}: {np.mean(v):.3f}" for k, v in stage.items()) + "}")
     log(f"[bench] tree {st}")
+    log(f"[bench] newton iterations {it} (incl. rebuilds)")
 
     ach = P * OPS_FORCE / (force_ms / 1e3)
     roof = {"kernel": "k_force", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK / 1e12,
@@ -288,6 +289,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only (no batched/served)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--slack", type=float, default=None, help="h slack of the cell decisions (default: library's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

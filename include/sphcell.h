@@ -56,6 +56,9 @@ typedef struct sph_tree sph_tree;
 
 /* Flags for sph_params.flags */
 #define SPH_FLAG_PAIR_HASH 1u   /* also accumulate the pair-set hashes */
+#define SPH_FLAG_RESUME 2u      /* sph_solve_h after this build continues the Newton state saved when
+                                   the previous sph_solve_h on the same tree returned SPH_E_REBUILD
+                                   (same particles); converged particles keep their density */
 
 /* Parameters.  Defaults (sph_params_default) follow Section III-B: N_ngb = 48,
  * gamma = 5/3, alpha = 2.0, split if more than 400 particles and more than

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsphcell.so")
 SPH_OK, SPH_E_ARG, SPH_E_HIP, SPH_E_WORKSPACE, SPH_E_REBUILD, SPH_E_NOCONV, SPH_E_CAPACITY, SPH_E_STATE = \
     0, -1, -2, -3, -4, -5, -6, -7
 SPH_FLAG_PAIR_HASH = 1
+SPH_FLAG_RESUME = 2
 
 # every function the header declares
 EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
@@ -326,13 +327,17 @@ def solve_with_rebuild(tree: Tree, batch: Batch, prm: sph_params, dout: DensityO
     the cells (the library reports it; the rebuild itself runs on the GPU)."""
     h = batch.h
     total_it = 0
+    p = prm
     for _ in range(max_rebuilds + 1):
-        tree.build_cells(batch, prm, h=h)
+        tree.build_cells(batch, p, h=h)
         tree.sort_pairs()
         st, nu, it = tree.solve_h(dout)
         total_it += it
         if st == SPH_E_REBUILD:
+            # rebuild from the h reached and continue the same Newton state
             h = dout.h.clone()
+            p = sph_params.from_buffer_copy(prm)
+            p.flags |= SPH_FLAG_RESUME
             continue
         return st, nu, total_it
     return SPH_E_REBUILD, -1, total_it

@@ -186,8 +186,11 @@ __global__ void k_top_cells(const SetInfo* sets, int nsets, int ntop, int depth,
     C.count = (int32_t)(b - a);
     C.hmax = 0.f;
     C.hcur = 0.f;
+    C.hcur_l = 0.f;
     C.bound = nextafterf((float)S.L0, INFINITY);
     C.split = 0;
+    C.nsmall = 0;
+    C.pad[0] = C.pad[1] = 0;
     cells[c] = C;
 }
 
@@ -256,8 +259,11 @@ __global__ void k_make_children(int64_t c0, int64_t c1, int64_t next0, const uin
         C.set = P.set;
         C.hmax = 0.f;
         C.hcur = 0.f;
+        C.hcur_l = 0.f;
         C.bound = INFINITY;
         C.split = 0;
+        C.nsmall = 0;
+        C.pad[0] = C.pad[1] = 0;
         cells[base + o] = C;
     }
 }
@@ -526,12 +532,36 @@ __device__ inline float ord2f(uint32_t u) {
     return __uint_as_float(b);
 }
 
+// Sorted lists are split into a small-h part (h <= edge/8 at sort time)
+// and a large-h part, each ordered by projection, so that a force sweep can
+// bound its reach by the largest h of each part separately.
+__device__ inline float small_h_limit(const SetInfo* sets, const Cell& C) {
+    return (float)(sets[C.set].L0 / (double)(1 << C.level) / (double)SMALL_H_DIV);
+}
+
+__global__ __launch_bounds__(256) void k_cell_nsmall(const SetInfo* sets, Cell* __restrict__ cells, int64_t nc,
+                                                     const float* __restrict__ ph) {
+    int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= nc) return;
+    const int lane = threadIdx.x & 63;
+    const Cell C = cells[c];
+    const float lim = small_h_limit(sets, C);
+    int k = 0;
+    for (int p = C.first + lane; p < C.first + C.count; p += 64) k += ph[p] <= lim ? 1 : 0;
+    k = wave_sum_i(k);
+    if (lane == 0) cells[c].nsmall = k;
+}
+
+__device__ inline uint64_t seg_key(float proj, int cls, uint32_t e) {
+    return ((uint64_t)cls << 63) | ((uint64_t)(f2ord(proj) >> 1) << 32) | e;
+}
+
 // Segments of at most 64 entries: one wavefront each, bitonic sort of
 // (ordered projection << 32 | local index) in registers with lane shuffles.
 __global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restrict__ list,
                                                        const uint32_t* __restrict__ off, int64_t ns,
-                                                       const Cell* __restrict__ cells,
-                                                       const float4* __restrict__ pos,
+                                                       const SetInfo* sets, const Cell* __restrict__ cells,
+                                                       const float4* __restrict__ pos, const float* __restrict__ ph,
                                                        float* __restrict__ sproj, uint32_t* __restrict__ sidx) {
     const int lane = threadIdx.x & 63;
     for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < ns; q += (int64_t)gridDim.x * 4) {
@@ -540,8 +570,10 @@ __global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restric
         const int n = C.count;
         if (n > 64) continue;
         const int ax = (int)(ca % NAXES);
+        const float lim = small_h_limit(sets, C);
         uint64_t k = ~0ull;
-        if (lane < n) k = ((uint64_t)f2ord(project(pos[C.first + lane], ax)) << 32) | (uint32_t)lane;
+        if (lane < n)
+            k = seg_key(project(pos[C.first + lane], ax), ph[C.first + lane] > lim ? 1 : 0, (uint32_t)lane);
         for (int size = 2; size <= 64; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
                 uint32_t lo = __shfl_xor((uint32_t)k, stride, 64);
@@ -557,8 +589,9 @@ __global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restric
         }
         if (lane < n) {
             uint32_t o = off[q];
-            sproj[o + lane] = ord2f((uint32_t)(k >> 32));
-            sidx[o + lane] = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+            uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+            sproj[o + lane] = project(pos[j], ax);
+            sidx[o + lane] = j;
         }
     }
 }
@@ -567,9 +600,9 @@ __global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restric
 // bitonic sort in LDS.
 __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict__ sel, int64_t nsel,
                                                       const uint32_t* __restrict__ list,
-                                                      const uint32_t* __restrict__ off,
+                                                      const uint32_t* __restrict__ off, const SetInfo* sets,
                                                       const Cell* __restrict__ cells,
-                                                      const float4* __restrict__ pos,
+                                                      const float4* __restrict__ pos, const float* __restrict__ ph,
                                                       float* __restrict__ sproj, uint32_t* __restrict__ sidx) {
     __shared__ uint64_t s[SEG_LDS_MAX];
     for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
@@ -581,9 +614,10 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
     if (n <= 64 || n > SEG_LDS_MAX) continue;
     int P = 1;
     while (P < n) P <<= 1;
+    const float lim = small_h_limit(sets, C);
     for (int e = threadIdx.x; e < P; e += blockDim.x) {
         uint64_t k = ~0ull;
-        if (e < n) k = ((uint64_t)f2ord(project(pos[C.first + e], ax)) << 32) | (uint32_t)e;
+        if (e < n) k = seg_key(project(pos[C.first + e], ax), ph[C.first + e] > lim ? 1 : 0, (uint32_t)e);
         s[e] = k;
     }
     __syncthreads();
@@ -602,8 +636,9 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
     uint32_t o = off[q];
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         uint64_t k = s[e];
-        sproj[o + e] = ord2f((uint32_t)(k >> 32));
-        sidx[o + e] = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+        uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+        sproj[o + e] = project(pos[j], ax);
+        sidx[o + e] = j;
     }
     __syncthreads();
     }
@@ -636,16 +671,19 @@ __global__ void k_big_list(const uint32_t* __restrict__ flag, const uint32_t* __
 
 __global__ __launch_bounds__(256) void k_big_keys(const uint32_t* __restrict__ big,
                                                   const uint32_t* __restrict__ boff,
-                                                  const uint32_t* __restrict__ list,
+                                                  const uint32_t* __restrict__ list, const SetInfo* sets,
                                                   const Cell* __restrict__ cells, const float4* __restrict__ pos,
+                                                  const float* __restrict__ ph,
                                                   uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
     uint32_t r = blockIdx.x;
     uint32_t ca = list[big[r]];
     const Cell C = cells[ca / NAXES];
     int ax = (int)(ca % NAXES);
+    const float lim = small_h_limit(sets, C);
     uint32_t o = boff[r];
     for (int e = threadIdx.x; e < C.count; e += blockDim.x) {
-        key[o + e] = ((uint64_t)r << 32) | f2ord(project(pos[C.first + e], ax));
+        const uint64_t cls = ph[C.first + e] > lim ? 1ull : 0ull;
+        key[o + e] = ((uint64_t)r << 33) | (cls << 32) | f2ord(project(pos[C.first + e], ax));
         val[o + e] = (uint32_t)C.first + (uint32_t)e;
     }
 }
@@ -657,7 +695,7 @@ __global__ void k_big_write(const uint64_t* __restrict__ key, const uint32_t* __
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ne) return;
     uint64_t k = key[p];
-    uint32_t r = (uint32_t)(k >> 32);
+    uint32_t r = (uint32_t)(k >> 33);
     uint32_t local = (uint32_t)p - boff[r];
     uint32_t o = off[big[r]] + local;
     sproj[o] = ord2f((uint32_t)k);
@@ -1000,8 +1038,10 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
         HIPTRY(hipGetLastError());
         ERRTRY(t->alloc(t->b_segproj, sizeof(float) * std::max<int64_t>(nent, 1), (void**)&t->segproj));
         ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
+        hipLaunchKernelGGL(k_cell_nsmall, dim3(nblk(nc, 4)), dim3(256), 0, st, t->d_sets, t->cells, nc, t->ph);
         hipLaunchKernelGGL(k_seg_sort_wave, dim3((unsigned)std::min<int64_t>((ns + 3) / 4, 8192)), dim3(256), 0, st,
-                           t->seglist, soff, (int64_t)ns, t->cells, t->pos, t->segproj, t->segidx);
+                           t->seglist, soff, (int64_t)ns, t->d_sets, t->cells, t->pos, t->ph, t->segproj,
+                           t->segidx);
         HIPTRY(hipGetLastError());
         ERRTRY(t->scratch(std::max<int64_t>(nca, ns) + 1));
         hipLaunchKernelGGL(k_mid_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_a);
@@ -1012,7 +1052,8 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
             hipLaunchKernelGGL(k_compact, dim3(nblk(ns, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, (int64_t)ns,
                                t->sc_c);
             hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)std::min<uint32_t>(nmid, 65535)), dim3(256), 0, st,
-                               t->sc_c, (int64_t)nmid, t->seglist, soff, t->cells, t->pos, t->segproj, t->segidx);
+                               t->sc_c, (int64_t)nmid, t->seglist, soff, t->d_sets, t->cells, t->pos, t->ph,
+                               t->segproj, t->segidx);
             HIPTRY(hipGetLastError());
         }
         // segments too long for LDS: one global radix sort over all of them
@@ -1038,13 +1079,13 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
             bv2 = bv + nbe;
             ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(nbe), radix_tmp_words(t->n)),
                             (void**)&t->rs_tmp));
-            hipLaunchKernelGGL(k_big_keys, dim3(nbig), dim3(256), 0, st, big, boff, t->seglist, t->cells, t->pos,
-                               bk, bv);
+            hipLaunchKernelGGL(k_big_keys, dim3(nbig), dim3(256), 0, st, big, boff, t->seglist, t->d_sets, t->cells,
+                               t->pos, t->ph, bk, bv);
             HIPTRY(hipGetLastError());
             int rb = 0;
             while ((1u << rb) < nbig) ++rb;
             bool alt = false;
-            HIPTRY(radix_sort(bk, bv, bk2, bv2, nbe, 32 + rb, t->rs_tmp, st, &alt));
+            HIPTRY(radix_sort(bk, bv, bk2, bv2, nbe, 33 + rb, t->rs_tmp, st, &alt));
             if (alt) { bk = bk2; bv = bv2; }
             hipLaunchKernelGGL(k_big_write, dim3(nblk(nbe, 256)), dim3(256), 0, st, bk, bv, (int64_t)nbe, boff, big,
                                soff, t->segproj, t->segidx);

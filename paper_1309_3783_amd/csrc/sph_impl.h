@@ -36,7 +36,7 @@ struct sph_tree {
     sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_pv, b_ph, b_hdec, b_pu,
         b_bound, b_mix, b_rs, b_cell, b_taskA, b_taskB, b_final, b_chunk, b_csr, b_csr2, b_csroff,
         b_segoff, b_seglist, b_segproj, b_segidx, b_bigk, b_bigv, b_sc, b_dens, b_force, b_solve,
-        b_red, b_misc;
+        b_red, b_misc, b_saved;
 
     // ---- sizes (host) --------------------------------------------------
     int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nsegs = 0, nchunks = 0, max_leaf = 0;
@@ -74,6 +74,11 @@ struct sph_tree {
     int32_t* fn = nullptr;
     uint64_t* hashf = nullptr;
     double* partial = nullptr;
+    int32_t* part_cnt = nullptr;
+    // Newton state saved when a solve stops for a rebuild (caller order)
+    bool saved = false;
+    int64_t saved_n = 0;
+    sph::SolveState sv{};
     double* sums_int = nullptr;   // per-set sums of the last force pass
     int4* d_red = nullptr;
 
@@ -98,7 +103,7 @@ struct sph_tree {
         return {&b_sets, &b_small, &b_key, &b_key2, &b_val, &b_val2, &b_perm, &b_pos, &b_pv, &b_ph, &b_hdec,
                 &b_pu, &b_bound, &b_mix, &b_rs, &b_cell, &b_taskA, &b_taskB, &b_final, &b_chunk, &b_csr,
                 &b_csr2, &b_csroff, &b_segoff, &b_seglist, &b_segproj, &b_segidx, &b_bigk, &b_bigv, &b_sc,
-                &b_dens, &b_force, &b_solve, &b_red, &b_misc};
+                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved};
     }
 
     void release() {
@@ -152,6 +157,25 @@ struct sph_tree {
         b.p = np;
         b.cap = want;
         *out = np;
+        return sph::Err{};
+    }
+
+    sph::SolveState saved_state() const { return sv; }
+
+    sph::Err ensure_saved() {
+        const int64_t m = std::max<int64_t>(n, 1);
+        void* p;
+        sph::Err e = alloc(b_saved, (size_t)m * (1 + 6 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 256, &p);
+        if (e.st) return e;
+        sv.hash = (uint64_t*)p;
+        sv.lo = (float*)(sv.hash + m);
+        sv.hi = sv.lo + m;
+        sv.rho = sv.hi + m;
+        sv.drho = sv.rho + m;
+        sv.nw = sv.drho + m;
+        sv.dnw = sv.nw + m;
+        sv.nngb = (int32_t*)(sv.dnw + m);
+        sv.active = (uint8_t*)(sv.nngb + m);
         return sph::Err{};
     }
 

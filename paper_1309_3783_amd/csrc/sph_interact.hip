@@ -237,12 +237,11 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
         if (item >= a.nchunks) break;
         const int4 ch = a.chunks[item];
         const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
-        // a set whose h outgrew its cells stops until it is rebuilt
-        if (SOLVE && a.status[2 + 2 * a.cells[leaf].set]) continue;
         // particles of the chunk that take part: all, or the still active
-        // ones of a Newton pass, packed into the first slots
+        // ones of a Newton pass (state 1; 2 = parked until a rebuild),
+        // packed into the first slots
         uint64_t amask = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
-        if (SOLVE) amask = __ballot(lane < cnt && a.active[p0 + lane]);
+        if (SOLVE) amask = __ballot(lane < cnt && a.active[p0 + lane] == 1);
         if (amask == 0) continue;
         const int nact = __popcll(amask);
         const int R = replicas(nact, a.rmax), T = 64 / R;
@@ -290,32 +289,38 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
                 const PairGeo g = pair_geo(cA, (int)(key & 31), L0);
                 const Cell cB = a.cells[B];
                 const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
-                const int len = cB.count;
                 const float sgn = (float)g.sign;
                 float ti = sgn * proj3(g.ddx, g.ddy, g.ddz, xi.x, xi.y, xi.z);
                 float reach = act ? ti + fmaf(hi * g.dn, 1.000002f, tiny) : -INFINITY;
                 const float Tmax = unif(wmax(reach));
-                for (int base = 0; base < len; base += 64) {
-                    const int nsrc = min(64, len - base);
-                    bool ok = false;
-                    if (lane < nsrc) {
-                        int qq = g.sign > 0 ? base + lane : len - 1 - base - lane;
-                        uint32_t j = a.segidx[so + qq];
-                        float tj = sgn * (a.segproj[so + qq] + g.projoff);
-                        ok = tj <= Tmax;
-                        if (ok) {
-                            float4 pj = a.pos[j];
-                            s_p[w][lane] = make_float4(pj.x + g.Sx, pj.y + g.Sy, pj.z + g.Sz, pj.w);
-                            if (HASH) s_m[w][lane] = a.mix[j];
+                // the list has a small-h part [0, nsmall) and a large-h part;
+                // each is ordered by projection and swept on its own
+                for (int part = 0; part < 2; ++part) {
+                    const int lo = part ? cB.nsmall : 0;
+                    const int len = part ? cB.count - cB.nsmall : cB.nsmall;
+                    for (int base = 0; base < len; base += 64) {
+                        const int nsrc = min(64, len - base);
+                        bool ok = false;
+                        if (lane < nsrc) {
+                            int qq = lo + (g.sign > 0 ? base + lane : len - 1 - base - lane);
+                            uint32_t j = a.segidx[so + qq];
+                            float tj = sgn * (a.segproj[so + qq] + g.projoff);
+                            ok = tj <= Tmax;
+                            if (ok) {
+                                float4 pj = a.pos[j];
+                                s_p[w][lane] = make_float4(pj.x + g.Sx, pj.y + g.Sy, pj.z + g.Sz, pj.w);
+                                if (HASH) s_m[w][lane] = a.mix[j];
+                            }
                         }
+                        const uint64_t okm = __ballot(ok);
+                        const int nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);   // prefix in sorted order
+                        wave_lds_sync();
+                        const int share = (nuse + R - 1) / R;
+                        const int j0 = rep * share;
+                        dens_tile<HASH>(acc, s_p[w], s_m[w], j0, max(0, min(share, nuse - j0)), xi, hi2, hinv, -1);
+                        wave_lds_sync();
+                        if (nuse < nsrc) break;
                     }
-                    const int nuse = __popcll(__ballot(ok));
-                    wave_lds_sync();
-                    const int share = (nuse + R - 1) / R;
-                    const int j0 = rep * share;
-                    dens_tile<HASH>(acc, s_p[w], s_m[w], j0, max(0, min(share, nuse - j0)), xi, hi2, hinv, -1);
-                    wave_lds_sync();
-                    if (nuse < nsrc) break;
                 }
             }
             A = cA.parent;
@@ -511,29 +516,35 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
                 const PairGeo g = pair_geo(cA, (int)(key & 31), L0);
                 const Cell cB = a.cells[B];
                 const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
-                const int len = cB.count;
                 const float sgn = (float)g.sign;
-                const float cut = fmaxf(L.h, cB.hcur) * g.dn;
                 float ti = sgn * proj3(g.ddx, g.ddy, g.ddz, L.x.x, L.x.y, L.x.z);
-                float reach = act ? ti + fmaf(cut, 1.000002f, tiny) : -INFINITY;
-                const float Tmax = unif(wmax(reach));
-                for (int base = 0; base < len; base += 64) {
-                    const int nsrc = min(64, len - base);
-                    bool ok = false;
-                    if (lane < nsrc) {
-                        int qq = g.sign > 0 ? base + lane : len - 1 - base - lane;
-                        uint32_t j = a.segidx[so + qq];
-                        float tj = sgn * (a.segproj[so + qq] + g.projoff);
-                        ok = tj <= Tmax;
-                        if (ok) stage(lane, j, g.Sx, g.Sy, g.Sz);
+                for (int part = 0; part < 2; ++part) {
+                    const int lo = part ? cB.nsmall : 0;
+                    const int len = part ? cB.count - cB.nsmall : cB.nsmall;
+                    if (len == 0) continue;
+                    // reach: max(h_i, largest h of this part) along the axis
+                    const float cut = fmaxf(L.h, part ? cB.hcur_l : cB.hcur) * g.dn;
+                    float reach = act ? ti + fmaf(cut, 1.000002f, tiny) : -INFINITY;
+                    const float Tmax = unif(wmax(reach));
+                    for (int base = 0; base < len; base += 64) {
+                        const int nsrc = min(64, len - base);
+                        bool ok = false;
+                        if (lane < nsrc) {
+                            int qq = lo + (g.sign > 0 ? base + lane : len - 1 - base - lane);
+                            uint32_t j = a.segidx[so + qq];
+                            float tj = sgn * (a.segproj[so + qq] + g.projoff);
+                            ok = tj <= Tmax;
+                            if (ok) stage(lane, j, g.Sx, g.Sy, g.Sz);
+                        }
+                        const uint64_t okm = __ballot(ok);
+                        const int nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);
+                        wave_lds_sync();
+                        const int share = (nuse + R - 1) / R;
+                        const int j0 = rep * share;
+                        if (act) force_tile<HASH>(acc, S, j0, max(0, min(share, nuse - j0)), L, hi2, -1, a.alpha);
+                        wave_lds_sync();
+                        if (nuse < nsrc) break;
                     }
-                    const int nuse = __popcll(__ballot(ok));
-                    wave_lds_sync();
-                    const int share = (nuse + R - 1) / R;
-                    const int j0 = rep * share;
-                    if (act) force_tile<HASH>(acc, S, j0, max(0, min(share, nuse - j0)), L, hi2, -1, a.alpha);
-                    wave_lds_sync();
-                    if (nuse < nsrc) break;
                 }
             }
             A = cA.parent;
@@ -586,17 +597,19 @@ __device__ __forceinline__ int set_of(const SetInfo* sets, int nsets, int64_t p)
     return lo;
 }
 
-// One safeguarded Newton step on N_w(h) = target for every active particle:
-// converged (|N_w - target| <= tol, tested in FP64) particles keep h and
-// their density; the rest move h and stay active.  A new h that reaches the
-// bound its cells support raises the rebuild flag of its set.
+// One safeguarded Newton step on N_w(h) = target (in logarithms) for every
+// active particle (state 1): converged (|N_w - target| <= tol, tested in FP64) particles
+// keep h and their density (state 0); the rest move h and stay active.  A
+// particle whose root lies beyond the largest h its cells support is parked
+// (state 2, no more density passes) and raises the rebuild flag of its set;
+// the other particles go on converging.
 __global__ void k_newton(int64_t n, const SetInfo* __restrict__ sets, int nsets, uint8_t* __restrict__ active,
                          const float* __restrict__ nw, const float* __restrict__ dnw, float* __restrict__ ph,
                          const float* __restrict__ bound, float* __restrict__ lo, float* __restrict__ hi,
                          double target, double tol, int32_t* __restrict__ status) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool still = false, rebuild = false;
-    if (p < n && active[p]) {
+    if (p < n && active[p] == 1) {
         double err = (double)nw[p] - target;
         if (fabs(err) <= tol) {
             active[p] = 0;
@@ -604,8 +617,12 @@ __global__ void k_newton(int64_t n, const SetInfo* __restrict__ sets, int nsets,
             double h = ph[p];
             double l = lo[p], u = hi[p];
             if (err < 0) l = h; else u = h;
+            // Newton step on ln N_w against ln h: exact wherever N_w is a
+            // power of h, so far-off first guesses converge in few steps
             double d = dnw[p];
-            double hn = d > 0 ? h - err / d : -1.0;
+            double Nw = (double)nw[p];
+            double slope = d * h / Nw;
+            double hn = (d > 0 && Nw > 0) ? h * exp(-log(Nw / target) / slope) : -1.0;
             bool bad = !(d > 0) || !(hn > l) || !(hn < u) || hn < 0.5 * h || hn > 2.0 * h;
             if (bad) hn = isinf(u) ? 2.0 * h : 0.5 * (l + u);
             // the minimum-image convention needs h < box/2
@@ -625,35 +642,81 @@ __global__ void k_newton(int64_t n, const SetInfo* __restrict__ sets, int nsets,
             hi[p] = (float)u;
             ph[p] = hf;
             still = true;
+            // parked: no density passes until the tree is rebuilt for it
+            if (rebuild) active[p] = 2;
         }
     }
-    // one atomic per wave and set: lanes of a wave are consecutive particles
-    const int lane = threadIdx.x & 63;
-    const int64_t p0 = p - lane;
-    const int s0 = set_of(sets, nsets, p0 < n ? p0 : n - 1);
-    const int s = (p < n) ? set_of(sets, nsets, p) : s0;
-    const bool uniform_set = __ballot(s != s0) == 0;
-    if (uniform_set) {
-        int ns = __popcll(__ballot(still));
-        bool rb = __ballot(rebuild) != 0;
-        if (lane == 0 && ns) {
-            atomicAdd(&status[1], ns);
-            atomicAdd(&status[3 + 2 * s0], ns);
-        }
-        if (lane == 0 && rb) {
-            atomicExch(&status[0], 1);
-            atomicExch(&status[2 + 2 * s0], 1);
-        }
-    } else {
-        if (still) {
-            atomicAdd(&status[1], 1);
-            atomicAdd(&status[3 + 2 * s], 1);
-        }
-        if (rebuild) {
-            atomicExch(&status[0], 1);
-            atomicExch(&status[2 + 2 * s], 1);
-        }
+    // still-active particles are counted afterwards (k_count_active); only
+    // the rare rebuild flag is raised here
+    (void)still;
+    if (rebuild) {
+        const int s = set_of(sets, nsets, p);
+        atomicExch(&status[0], 1);
+        atomicExch(&status[2 + 2 * s], 1);
     }
+}
+
+// Particles still active, per reduction chunk (one block each) ...
+__global__ __launch_bounds__(256) void k_count_active(const int4* __restrict__ red, const uint8_t* __restrict__ active,
+                                                      int32_t* __restrict__ part) {
+    __shared__ int s_w[4];
+    const int4 R = red[blockIdx.x];
+    int c = 0;
+    for (int p = R.y + threadIdx.x; p < R.y + R.z; p += 256) c += active[p] == 1 ? 1 : 0;
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// ... then per set (chunks of a set are consecutive) and in total.
+__global__ void k_count_final(const int4* __restrict__ red, int nred, const int32_t* __restrict__ part, int nsets,
+                              int32_t* __restrict__ status) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsets) return;
+    int lo = 0, hi = nred;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (red[mid].x < s) lo = mid + 1; else hi = mid;
+    }
+    int c = 0;
+    for (int r = lo; r < nred && red[r].x == s; ++r) c += part[r];
+    status[3 + 2 * s] = c;
+    if (c) atomicAdd(&status[1], c);
+}
+
+__global__ void k_save_state(int64_t n, const uint32_t* __restrict__ perm, const uint8_t* active, const float* lo,
+                             const float* hi, const float* rho, const float* drho, const float* nw, const float* dnw,
+                             const int32_t* nngb, const uint64_t* hash, SolveState sv) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t i = perm[p];
+    sv.active[i] = active[p];
+    sv.lo[i] = lo[p];
+    sv.hi[i] = hi[p];
+    sv.rho[i] = rho[p];
+    sv.drho[i] = drho[p];
+    sv.nw[i] = nw[p];
+    sv.dnw[i] = dnw[p];
+    sv.nngb[i] = nngb[p];
+    if (hash) sv.hash[i] = hash[p];
+}
+
+__global__ void k_load_state(int64_t n, const uint32_t* __restrict__ perm, uint8_t* active, float* lo, float* hi,
+                             float* rho, float* drho, float* nw, float* dnw, int32_t* nngb, uint64_t* hash,
+                             SolveState sv) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t i = perm[p];
+    active[p] = sv.active[i] ? 1 : 0;   // parked particles resume
+    lo[p] = sv.lo[i];
+    hi[p] = sv.hi[i];
+    rho[p] = sv.rho[i];
+    drho[p] = sv.drho[i];
+    nw[p] = sv.nw[i];
+    dnw[p] = sv.dnw[i];
+    nngb[p] = sv.nngb[i];
+    if (hash) hash[p] = sv.hash[i];
 }
 
 // zero the counts of still-active particles (total and per set)
@@ -675,15 +738,35 @@ __global__ void k_ghost(int64_t n, const float* __restrict__ ph, const float* __
     cs[p] = sqrtf(gamma * (gamma - 1.f) * u[p]);
 }
 
-__global__ __launch_bounds__(256) void k_cell_hcur(Cell* __restrict__ cells, int64_t nc, const float* __restrict__ ph) {
+// Largest current h of the small-h and of the large-h entries of each
+// cell's sorted lists (any axis holds the same entries); cells without a
+// list get the largest h of all their particles in both.
+__global__ __launch_bounds__(256) void k_cell_hcur(Cell* __restrict__ cells, int64_t nc, const float* __restrict__ ph,
+                                                   const uint32_t* __restrict__ segoff,
+                                                   const uint32_t* __restrict__ segidx) {
     int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= nc) return;
     const int lane = threadIdx.x & 63;
-    const int first = cells[c].first, count = cells[c].count;
-    float m = 0.f;
-    for (int p = first + lane; p < first + count; p += 64) m = fmaxf(m, ph[p]);
-    m = wmax(m);
-    if (lane == 0) cells[c].hcur = m;
+    const int first = cells[c].first, count = cells[c].count, ns = cells[c].nsmall;
+    uint32_t so = 0xFFFFFFFFu;
+    for (int k = 0; k < NAXES && so == 0xFFFFFFFFu; ++k) so = segoff[c * NAXES + k];
+    float ms = 0.f, ml = 0.f;
+    if (so == 0xFFFFFFFFu) {
+        for (int p = first + lane; p < first + count; p += 64) ms = fmaxf(ms, ph[p]);
+        ms = wmax(ms);
+        ml = ms;
+    } else {
+        for (int q = lane; q < count; q += 64) {
+            float hv = ph[segidx[so + q]];
+            if (q < ns) ms = fmaxf(ms, hv); else ml = fmaxf(ml, hv);
+        }
+        ms = wmax(ms);
+        ml = wmax(ml);
+    }
+    if (lane == 0) {
+        cells[c].hcur = ms;
+        cells[c].hcur_l = ml;
+    }
 }
 
 __global__ void k_scatter_density(int64_t n, const uint32_t* __restrict__ perm, const float* rho,
@@ -836,10 +919,12 @@ static Err ensure_state(sph_tree* t) {
                 t->red_chunks.push_back(make_int4(s, (int)q, (int)std::min<int64_t>(16384, b - q), 0));
         }
         t->nred = (int64_t)t->red_chunks.size();
-        ERRTRY(t->alloc(t->b_red, t->nred * (sizeof(int4) + NRED * sizeof(double)) + (size_t)t->nsets * NRED * sizeof(double) + 64, &p));
+        ERRTRY(t->alloc(t->b_red, t->nred * (sizeof(int4) + NRED * sizeof(double) + sizeof(int32_t)) +
+                                      (size_t)t->nsets * NRED * sizeof(double) + 64, &p));
         t->partial = (double*)p;
         t->sums_int = t->partial + t->nred * NRED;
         t->d_red = (int4*)(t->sums_int + (int64_t)t->nsets * NRED);
+        t->part_cnt = (int32_t*)(t->d_red + t->nred);
         HIPTRY(hipMemcpy(t->d_red, t->red_chunks.data(), sizeof(int4) * t->nred, hipMemcpyHostToDevice));
     }
     return Err{};
@@ -924,7 +1009,8 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     const int64_t n = t->n;
     hipLaunchKernelGGL(k_ghost, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->ph, t->rho, t->drho, t->pu,
                        t->prm.gamma, t->A, t->cs);
-    hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph);
+    hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph, t->segoff,
+                       t->segidx);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, counter, 1);
     ev_mark(ctx, "ghost");
     ForceArgs a;
@@ -958,6 +1044,15 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
     if (t->hash) hipLaunchKernelGGL((k_force<true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_force<false>), g, b, 0, st, a);
+}
+
+// status[1] and status[3+2s] = particles still active after a Newton step
+static void launch_count(sph_ctx* ctx, sph_tree* t) {
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_zero_unconv, dim3(nblk(t->nsets, 256)), dim3(256), 0, st, t->status, t->nsets);
+    hipLaunchKernelGGL(k_count_active, dim3((unsigned)t->nred), dim3(256), 0, st, t->d_red, t->active, t->part_cnt);
+    hipLaunchKernelGGL(k_count_final, dim3(nblk(t->nsets, 64)), dim3(64), 0, st, t->d_red, (int)t->nred, t->part_cnt,
+                       t->nsets, t->status);
 }
 
 static void launch_reduce(sph_ctx* ctx, sph_tree* t, double* sums_out) {
@@ -1011,7 +1106,14 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     if (iters) *iters = 0;
     if (n == 0) return Err{};
     ev_mark(ctx, "start");
-    hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi);
+    const bool resume = (t->prm.flags & SPH_FLAG_RESUME) && t->saved && t->saved_n == n;
+    if (resume) {
+        hipLaunchKernelGGL(k_load_state, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->perm, t->active, t->lo, t->hi,
+                           t->rho, t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr, t->saved_state());
+    } else {
+        hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi);
+    }
+    t->saved = false;
     const int nst = 2 + 2 * t->nsets;
     hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
     int32_t hstat[2] = {0, 0};
@@ -1019,16 +1121,16 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     bool rebuild = false;
     for (; it < t->prm.max_iter; ++it) {
         launch_density(ctx, t, true, ctx->d_counter);
-        hipLaunchKernelGGL(k_zero_unconv, dim3(nblk(t->nsets, 256)), dim3(256), 0, st, t->status, t->nsets);
         hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->d_sets, t->nsets, t->active,
                            t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi, (double)t->prm.n_target,
                            (double)t->prm.h_tol, t->status);
+        launch_count(ctx, t);
         HIPTRY(hipGetLastError());
         HIPTRY(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
         HIPTRY(hipStreamSynchronize(st));
-        if (hstat[0]) { rebuild = true; ++it; break; }
         if (hstat[1] == 0) { ++it; break; }
     }
+    rebuild = hstat[0] != 0;
     if (!rebuild && hstat[1] > 0) {
         // unconverged particles moved h after their last density: recompute
         // their density at the h they hold now
@@ -1036,6 +1138,13 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     }
     ev_mark(ctx, "solve");
     launch_scatter_density(ctx, t, out);
+    if (rebuild) {
+        ERRTRY(t->ensure_saved());
+        hipLaunchKernelGGL(k_save_state, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->perm, t->active, t->lo, t->hi,
+                           t->rho, t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr, t->saved_state());
+        t->saved = true;
+        t->saved_n = n;
+    }
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
     ev_mark(ctx, "scatter");
@@ -1120,11 +1229,10 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
             hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
             for (int it = 0; it < k_iter; ++it) {
                 launch_density(ctx, t, true, ctx->d_counter);
-                hipLaunchKernelGGL(k_zero_unconv, dim3(nblk(t->nsets, 256)), dim3(256), 0, st, t->status,
-                                   t->nsets);
                 hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->d_sets, t->nsets,
                                    t->active, t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi,
                                    (double)t->prm.n_target, (double)t->prm.h_tol, t->status);
+                launch_count(ctx, t);
             }
             launch_density(ctx, t, true, ctx->d_counter);
             launch_force(ctx, t, ctx->d_counter + 1);

@@ -17,6 +17,7 @@ constexpr int MAX_SETS = 1 << 12;     // set id bits in the particle key
 constexpr int KEY_BITS_PER_DIM = 17;  // log2(top grid) + max depth must fit
 constexpr int SEG_LDS_MAX = 4096;     // largest (cell, axis) list sorted in LDS
 constexpr int CHUNK = 64;             // target particles per work item (one wave)
+constexpr int SMALL_H_DIV = 8;        // sorted lists split at h = cell edge / 8
 
 // ------------------------------------------------------------------------
 // Cell-pair axes (Section II-C: 13 possible axes).  Offsets o in {-1,0,1}^3
@@ -96,11 +97,23 @@ struct Cell {
     int32_t ix, iy, iz;      // integer coordinates at this level
     int16_t level, set;
     float hmax;              // largest decision h (h * (1 + slack)) in the cell
-    float hcur;              // largest current h in the cell
+    float hcur;              // largest current h among the small-h entries of its sorted lists
+    float hcur_l;            // largest current h among the large-h entries
     float bound;             // h must stay below this for the tasks built at this level
     uint32_t split;          // 1 if bisected
+    int32_t nsmall;          // sorted lists: entries [0, nsmall) have h <= edge/8 at sort time
+    int32_t pad[2];
 };
-static_assert(sizeof(Cell) == 48, "Cell layout");
+static_assert(sizeof(Cell) == 64, "Cell layout");
+
+// Newton state of a solve interrupted by a rebuild, kept in caller order so
+// that the solve on the rebuilt tree continues where it stopped.
+struct SolveState {
+    uint8_t* active;
+    float *lo, *hi, *rho, *drho, *nw, *dnw;
+    int32_t* nngb;
+    uint64_t* hash;
+};
 
 // Grow-only device buffer.
 struct DevBuf {

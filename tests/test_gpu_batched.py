@@ -50,17 +50,33 @@ def same(a, b, keys=None):
         assert np.array_equal(a[k], b[k]), k
 
 
-def test_graph_equals_eager(sph, ctx):
+@pytest.mark.parametrize("recipe", ["lattice", "clumpy"])
+def test_graph_equals_eager(sph, ctx, recipe):
+    # Same kernels, same Newton sequence: bitwise equal unless the h solve
+    # needed a rebuild (the eager path then resumes the Newton state on the
+    # rebuilt tree, the graph path re-solves the set from the h it reached),
+    # in which case both must agree to the parity tolerances.
     from paper_1309_3783_amd import pipeline as P
-    ps = sphinputs.plummer_mixture(20000, 21, velocity=True)
+    ps = sphinputs.lattice(24, 0.1, 21, velocity=True) if recipe == "lattice" else \
+        sphinputs.plummer_mixture(20000, 21, velocity=True)
     batch = sph.batch_from_sets([ps])
     prm = sph.params()
     te, tg = sph.Tree(ctx), sph.Tree(ctx)
     oe, og = P.Outputs(ps.n, 1), P.Outputs(ps.n, 1)
-    P.run_eager(te, batch, prm, oe)
-    assert P.run_graph(tg, batch, prm, og, k_iter=12) == 0
+    st, nu, it = sph.solve_with_rebuild(te, batch, prm, oe.d)
+    assert st == sph.SPH_OK
+    te.force(oe.f)
+    reruns = P.run_graph(tg, batch, prm, og, k_iter=12)
     torch.cuda.synchronize()
-    same(grab(oe, batch, 0), grab(og, batch, 0))
+    a, b = grab(oe, batch, 0), grab(og, batch, 0)
+    if reruns == 0 and te.stats()["cells"] == tg.stats()["cells"]:
+        same(a, b)
+    else:
+        assert np.abs(a["nw"] - 48).max() <= 0.5 + 1e-4 and np.abs(b["nw"] - 48).max() <= 0.5 + 1e-4
+        assert np.allclose(a["h"], b["h"], rtol=1.5e-2)
+    if recipe == "lattice":
+        assert reruns == 0
+        same(a, b)
 
 
 def test_graph_replays_match(sph, ctx):
