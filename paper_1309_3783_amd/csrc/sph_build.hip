@@ -562,7 +562,7 @@ __global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restric
                                                        const uint32_t* __restrict__ off, int64_t ns,
                                                        const SetInfo* sets, const Cell* __restrict__ cells,
                                                        const float4* __restrict__ pos, const float* __restrict__ ph,
-                                                       float* __restrict__ sproj, uint32_t* __restrict__ sidx) {
+                                                       float4* __restrict__ sproj, uint32_t* __restrict__ sidx) {
     const int lane = threadIdx.x & 63;
     for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < ns; q += (int64_t)gridDim.x * 4) {
         uint32_t ca = list[q];
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restric
         if (lane < n) {
             uint32_t o = off[q];
             uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
-            sproj[o + lane] = project(pos[j], ax);
+            sproj[o + lane] = pos[j];
             sidx[o + lane] = j;
         }
     }
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ off, const SetInfo* sets,
                                                       const Cell* __restrict__ cells,
                                                       const float4* __restrict__ pos, const float* __restrict__ ph,
-                                                      float* __restrict__ sproj, uint32_t* __restrict__ sidx) {
+                                                      float4* __restrict__ sproj, uint32_t* __restrict__ sidx) {
     __shared__ uint64_t s[SEG_LDS_MAX];
     for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
     const int64_t q = sel[i];
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         uint64_t k = s[e];
         uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
-        sproj[o + e] = project(pos[j], ax);
+        sproj[o + e] = pos[j];
         sidx[o + e] = j;
     }
     __syncthreads();
@@ -690,7 +690,8 @@ __global__ __launch_bounds__(256) void k_big_keys(const uint32_t* __restrict__ b
 
 __global__ void k_big_write(const uint64_t* __restrict__ key, const uint32_t* __restrict__ val, int64_t ne,
                             const uint32_t* __restrict__ boff, const uint32_t* __restrict__ big,
-                            const uint32_t* __restrict__ off, float* __restrict__ sproj,
+                            const uint32_t* __restrict__ off, const float4* __restrict__ pos,
+                            float4* __restrict__ sproj,
                             uint32_t* __restrict__ sidx) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ne) return;
@@ -698,7 +699,7 @@ __global__ void k_big_write(const uint64_t* __restrict__ key, const uint32_t* __
     uint32_t r = (uint32_t)(k >> 33);
     uint32_t local = (uint32_t)p - boff[r];
     uint32_t o = off[big[r]] + local;
-    sproj[o] = ord2f((uint32_t)k);
+    sproj[o] = pos[val[p]];
     sidx[o] = val[p];
 }
 
@@ -1036,11 +1037,11 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
         hipLaunchKernelGGL(k_seg_table, dim3(nblk(ns, 256)), dim3(256), 0, st, t->seglist, soff, (int64_t)ns,
                            t->segoff);
         HIPTRY(hipGetLastError());
-        ERRTRY(t->alloc(t->b_segproj, sizeof(float) * std::max<int64_t>(nent, 1), (void**)&t->segproj));
+        ERRTRY(t->alloc(t->b_segproj, sizeof(float4) * std::max<int64_t>(nent, 1), (void**)&t->segpos));
         ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
         hipLaunchKernelGGL(k_cell_nsmall, dim3(nblk(nc, 4)), dim3(256), 0, st, t->d_sets, t->cells, nc, t->ph);
         hipLaunchKernelGGL(k_seg_sort_wave, dim3((unsigned)std::min<int64_t>((ns + 3) / 4, 8192)), dim3(256), 0, st,
-                           t->seglist, soff, (int64_t)ns, t->d_sets, t->cells, t->pos, t->ph, t->segproj,
+                           t->seglist, soff, (int64_t)ns, t->d_sets, t->cells, t->pos, t->ph, t->segpos,
                            t->segidx);
         HIPTRY(hipGetLastError());
         ERRTRY(t->scratch(std::max<int64_t>(nca, ns) + 1));
@@ -1053,7 +1054,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
                                t->sc_c);
             hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)std::min<uint32_t>(nmid, 65535)), dim3(256), 0, st,
                                t->sc_c, (int64_t)nmid, t->seglist, soff, t->d_sets, t->cells, t->pos, t->ph,
-                               t->segproj, t->segidx);
+                               t->segpos, t->segidx);
             HIPTRY(hipGetLastError());
         }
         // segments too long for LDS: one global radix sort over all of them
@@ -1088,7 +1089,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
             HIPTRY(radix_sort(bk, bv, bk2, bv2, nbe, 33 + rb, t->rs_tmp, st, &alt));
             if (alt) { bk = bk2; bv = bv2; }
             hipLaunchKernelGGL(k_big_write, dim3(nblk(nbe, 256)), dim3(256), 0, st, bk, bv, (int64_t)nbe, boff, big,
-                               soff, t->segproj, t->segidx);
+                               soff, t->pos, t->segpos, t->segidx);
             HIPTRY(hipGetLastError());
         }
     }

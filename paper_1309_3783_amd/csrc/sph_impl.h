@@ -55,7 +55,7 @@ struct sph_tree {
     sph::Cell* cells = nullptr;
     int4 *taskA = nullptr, *taskB = nullptr, *finals = nullptr, *chunks = nullptr;
     uint32_t *csr_off = nullptr, *segoff = nullptr, *seglist = nullptr, *segidx = nullptr;
-    float* segproj = nullptr;
+    float4* segpos = nullptr;   // sorted lists: the particle records (x, y, z, m) in list order
     uint32_t *sc_a = nullptr, *sc_b = nullptr, *sc_c = nullptr, *sc_d = nullptr, *sc_tmp = nullptr;
     uint32_t* d_total = nullptr;
     int* d_maxleaf = nullptr;

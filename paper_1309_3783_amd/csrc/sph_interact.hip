@@ -33,6 +33,17 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Hardware square root and reciprocal (1 ulp): the arguments here are
+// normal numbers (r^2 >= 2^-48 for distinct particles), and 1-ulp results
+// are far inside the stated tolerances.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Staged tiles hold TILE_PAD extra slots of far-away points, so that every
+// lane's share of a tile has the same length and the test loops are
+// uniform (scalar) loops.
+constexpr int TILE = 64 + 16;
+constexpr float FAR = 1.0e18f;
 __device__ __forceinline__ float unif(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
@@ -137,7 +148,7 @@ struct DensArgs {
     const uint64_t* csr;
     const uint32_t* csr_off;
     const uint32_t* segoff;
-    const float* segproj;
+    const float4* segpos;
     const uint32_t* segidx;
     const int32_t* status;
     float *rho, *drho, *nw, *dnw;
@@ -153,7 +164,7 @@ struct DensAcc {
 };
 
 __device__ __forceinline__ void dens_pair(DensAcc& a, float r2, float hinv, float mj, uint64_t mixj) {
-    float r = sqrtf(r2);
+    float r = fsqrt(r2);
     float q = r * hinv;
     float q2 = q * q;
     float t = 1.f - q;
@@ -201,19 +212,40 @@ __device__ __forceinline__ float comb_max(float v, int R) {
 }
 
 // Tile work shared by the self and pair sweeps: the lane's share of the
-// tile [j0, j0 + len) is tested first (one bit per entry in range), then
-// only the set bits are evaluated, so the wave does not run the pair
-// arithmetic for entries that no lane needs.
-template <bool HASH>
-__device__ __forceinline__ void dens_tile(DensAcc& acc, const float4* sp, const uint64_t* sm, int j0, int len,
-                                          const float4& xi, float hi2, float hinv, int self_j) {
-    uint64_t mask = 0;
-    for (int k = 0; k < len; ++k) {
+// tile, entries [j0, j0 + share) (padded with far-away points), is tested
+// first -- one bit per entry in range -- then only the set bits are
+// evaluated, so the wave does not run the pair arithmetic for entries that
+// no lane needs.
+template <bool SELF>
+__device__ __forceinline__ uint64_t tile_mask(const float4* sp, int j0, int share, const float4& xi, float hi2,
+                                              int self_j) {
+    uint32_t lo = 0, hi = 0;
+    const int n0 = share < 32 ? share : 32;
+#pragma unroll 4
+    for (int k = 0; k < n0; ++k) {
         float4 q = sp[j0 + k];
         float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
         float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (r2 < hi2 && j0 + k != self_j) mask |= 1ull << k;
+        bool in = r2 < hi2;
+        if (SELF) in = in && (j0 + k != self_j);
+        lo = in ? (lo | (1u << k)) : lo;
     }
+#pragma unroll 4
+    for (int k = 32; k < share; ++k) {
+        float4 q = sp[j0 + k];
+        float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        bool in = r2 < hi2;
+        if (SELF) in = in && (j0 + k != self_j);
+        hi = in ? (hi | (1u << (k - 32))) : hi;
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <bool HASH, bool SELF>
+__device__ __forceinline__ void dens_tile(DensAcc& acc, const float4* sp, const uint64_t* sm, int j0, int share,
+                                          const float4& xi, float hi2, float hinv, int self_j) {
+    uint64_t mask = tile_mask<SELF>(sp, j0, share, xi, hi2, self_j);
     while (mask) {
         int k = __builtin_ctzll(mask);
         mask &= mask - 1;
@@ -226,10 +258,14 @@ __device__ __forceinline__ void dens_tile(DensAcc& acc, const float4* sp, const 
 
 template <bool SOLVE, bool HASH>
 __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
-    __shared__ float4 s_p[BLK / 64][64];
-    __shared__ uint64_t s_m[BLK / 64][64];
+    __shared__ float4 s_p[BLK / 64][TILE];
+    __shared__ uint64_t s_m[BLK / 64][TILE];
     __shared__ int s_pick[BLK / 64][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane < TILE - 64) {
+        s_p[w][64 + lane] = make_float4(FAR, FAR, FAR, 0.f);
+        s_m[w][64 + lane] = 0ull;
+    }
     for (;;) {
         int item = 0;
         if (lane == 0) item = atomicAdd(a.counter, 1);
@@ -265,14 +301,11 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
         const int cend = C.first + C.count;
         for (int base = C.first; base < cend; base += 64) {
             const int nsrc = min(64, cend - base);
-            if (lane < nsrc) {
-                s_p[w][lane] = a.pos[base + lane];
-                if (HASH) s_m[w][lane] = a.mix[base + lane];
-            }
+            s_p[w][lane] = lane < nsrc ? a.pos[base + lane] : make_float4(FAR, FAR, FAR, 0.f);
+            if (HASH) s_m[w][lane] = lane < nsrc ? a.mix[base + lane] : 0ull;
             wave_lds_sync();
             const int share = (nsrc + R - 1) / R;
-            const int j0 = rep * share;
-            dens_tile<HASH>(acc, s_p[w], s_m[w], j0, max(0, min(share, nsrc - j0)), xi, hi2, hinv, p - base);
+            dens_tile<HASH, true>(acc, s_p[w], s_m[w], rep * share, share, xi, hi2, hinv, p - base);
             wave_lds_sync();
         }
 
@@ -301,23 +334,27 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
                     for (int base = 0; base < len; base += 64) {
                         const int nsrc = min(64, len - base);
                         bool ok = false;
+                        float4 rec = make_float4(FAR, FAR, FAR, 0.f);
+                        uint64_t mixj = 0ull;
                         if (lane < nsrc) {
                             int qq = lo + (g.sign > 0 ? base + lane : len - 1 - base - lane);
-                            uint32_t j = a.segidx[so + qq];
-                            float tj = sgn * (a.segproj[so + qq] + g.projoff);
+                            float4 pj = a.segpos[so + qq];
+                            float tj = sgn * (proj3(g.ddx, g.ddy, g.ddz, pj.x, pj.y, pj.z) + g.projoff);
                             ok = tj <= Tmax;
                             if (ok) {
-                                float4 pj = a.pos[j];
-                                s_p[w][lane] = make_float4(pj.x + g.Sx, pj.y + g.Sy, pj.z + g.Sz, pj.w);
-                                if (HASH) s_m[w][lane] = a.mix[j];
+                                rec = make_float4(pj.x + g.Sx, pj.y + g.Sy, pj.z + g.Sz, pj.w);
+                                if (HASH) mixj = a.mix[a.segidx[so + qq]];
                             }
                         }
                         const uint64_t okm = __ballot(ok);
                         const int nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);   // prefix in sorted order
+                        // entries past the prefix are padding, whatever their test said
+                        if (lane >= nuse) rec = make_float4(FAR, FAR, FAR, 0.f);
+                        s_p[w][lane] = rec;
+                        if (HASH) s_m[w][lane] = mixj;
                         wave_lds_sync();
                         const int share = (nuse + R - 1) / R;
-                        const int j0 = rep * share;
-                        dens_tile<HASH>(acc, s_p[w], s_m[w], j0, max(0, min(share, nuse - j0)), xi, hi2, hinv, -1);
+                        dens_tile<HASH, false>(acc, s_p[w], s_m[w], rep * share, share, xi, hi2, hinv, -1);
                         wave_lds_sync();
                         if (nuse < nsrc) break;
                     }
@@ -362,7 +399,7 @@ struct ForceArgs {
     const uint64_t* csr;
     const uint32_t* csr_off;
     const uint32_t* segoff;
-    const float* segproj;
+    const float4* segpos;
     const uint32_t* segidx;
     float alpha;
     float *ax, *ay, *az, *du, *vsig, *S;
@@ -393,47 +430,63 @@ __device__ __forceinline__ float gradF(float q, float h, float rinv) {
 __device__ __forceinline__ void force_pair(ForceAcc& a, const ForceLane& L, float dx, float dy, float dz,
                                            float r2, const float4& q, const float4& sh, const float4& sv,
                                            float cj, uint64_t mixj, float alpha) {
-    float r = sqrtf(r2);
-    float rinv = 1.f / r;
+    float r = fsqrt(r2);
+    float rinv = frcp(r);
     float ki = L.K * gradF(r * L.hinv, L.h, rinv);
-    float kj = sh.z * gradF(r * sh.y, sh.x, rinv);
+    float kj = sh.z * gradF(r * sh.y, q.w, rinv);
     float vdx = L.v.x - sv.x, vdy = L.v.y - sv.y, vdz = L.v.z - sv.z;
     float vdotx = fmaf(vdx, dx, fmaf(vdy, dy, vdz * dz));
     float wv = vdotx * rinv;
     float visc = 0.f;
-    if (wv < 0.f) visc = -alpha * (L.c + cj - 3.f * wv) * wv / (L.v.w + sv.w);
+    if (wv < 0.f) visc = -alpha * (L.c + cj - 3.f * wv) * wv * frcp(L.v.w + sv.w);
     float kbar = 0.5f * (ki + kj);
     float s = fmaf(L.A, ki, fmaf(sh.w, kj, visc * kbar));
-    float ms = q.w * s;
+    const float mj = sh.x;
+    float ms = mj * s;
     neumaier(a.ax, a.cax, -ms * dx);
     neumaier(a.ay, a.cay, -ms * dy);
     neumaier(a.az, a.caz, -ms * dz);
-    neumaier(a.du, a.cdu, q.w * vdotx * fmaf(L.A, ki, 0.5f * visc * kbar));
+    neumaier(a.du, a.cdu, mj * vdotx * fmaf(L.A, ki, 0.5f * visc * kbar));
     a.vs = fmaxf(a.vs, L.c + cj - 3.f * fminf(wv, 0.f));
     kahan(a.S, a.cS, fabsf(ms) * r);
     a.nn += 1;
     a.hs += mixj;
 }
 
+// Force tile records: p = (x, y, z, h) for the test, h = (m, 1/h, K, A),
+// v = (vx, vy, vz, rho), c = sound speed.
 struct ForceLds {
-    float4 p[64];   // x, y, z, m
-    float4 h[64];   // h, 1/h, K, A
-    float4 v[64];   // vx, vy, vz, rho
-    float c[64];
-    uint64_t m[64];
+    float4 p[TILE];
+    float4 h[TILE];
+    float4 v[TILE];
+    float c[TILE];
+    uint64_t m[TILE];
 };
 
-template <bool HASH>
-__device__ __forceinline__ void force_tile(ForceAcc& acc, const ForceLds& L_, int j0, int len, const ForceLane& L,
+template <bool HASH, bool SELF>
+__device__ __forceinline__ void force_tile(ForceAcc& acc, const ForceLds& L_, int j0, int share, const ForceLane& L,
                                            float hi2, int self_j, float alpha) {
-    uint64_t mask = 0;
-    for (int k = 0; k < len; ++k) {
+    uint32_t lo = 0, hi = 0;
+    const int n0 = share < 32 ? share : 32;
+#pragma unroll 4
+    for (int k = 0; k < n0; ++k) {
         float4 q = L_.p[j0 + k];
-        float hj = L_.h[j0 + k].x;
         float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
         float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (r2 < fmaxf(hi2, hj * hj) && j0 + k != self_j) mask |= 1ull << k;
+        bool in = r2 < fmaxf(hi2, q.w * q.w);
+        if (SELF) in = in && (j0 + k != self_j);
+        lo = in ? (lo | (1u << k)) : lo;
     }
+#pragma unroll 4
+    for (int k = 32; k < share; ++k) {
+        float4 q = L_.p[j0 + k];
+        float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        bool in = r2 < fmaxf(hi2, q.w * q.w);
+        if (SELF) in = in && (j0 + k != self_j);
+        hi = in ? (hi | (1u << (k - 32))) : hi;
+    }
+    uint64_t mask = ((uint64_t)hi << 32) | lo;
     while (mask) {
         int k = __builtin_ctzll(mask);
         mask &= mask - 1;
@@ -451,18 +504,18 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     ForceLds& S = s_l[w];
 
-    auto stage = [&](int slot, uint32_t j, float Sx, float Sy, float Sz) {
-        float4 pj = a.pos[j];
+    auto stage = [&](int slot, uint32_t j, const float4& pj, float Sx, float Sy, float Sz) {
         float hj = a.ph[j];
         float hinv = 1.f / hj;
         float h2 = hinv * hinv;
         float4 vj = a.pv[j];
-        S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, pj.w);
-        S.h[slot] = make_float4(hj, hinv, C8PI * h2 * h2 * hinv, a.A[j]);
+        S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, hj);
+        S.h[slot] = make_float4(pj.w, hinv, C8PI * h2 * h2 * hinv, a.A[j]);
         S.v[slot] = make_float4(vj.x, vj.y, vj.z, a.rho[j]);
         S.c[slot] = a.cs[j];
         if (HASH) S.m[slot] = a.mix[j];
     };
+    if (lane < TILE - 64) S.p[64 + lane] = make_float4(FAR, FAR, FAR, 0.f);
 
     for (;;) {
         int item = 0;
@@ -476,7 +529,8 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
         const int p = p0 + slot;
         const bool act = slot < cnt;
         ForceLane L;
-        L.x = act ? a.pos[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+        // an idle lane sits far away so no entry is ever in its range
+        L.x = act ? a.pos[p] : make_float4(-FAR, -FAR, -FAR, 0.f);
         L.h = act ? a.ph[p] : 1.f;
         L.hinv = 1.f / L.h;
         {
@@ -495,11 +549,11 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
         const int cend = C.first + C.count;
         for (int base = C.first; base < cend; base += 64) {
             const int nsrc = min(64, cend - base);
-            if (lane < nsrc) stage(lane, (uint32_t)(base + lane), 0.f, 0.f, 0.f);
+            if (lane < nsrc) stage(lane, (uint32_t)(base + lane), a.pos[base + lane], 0.f, 0.f, 0.f);
+            else S.p[lane] = make_float4(FAR, FAR, FAR, 0.f);
             wave_lds_sync();
             const int share = (nsrc + R - 1) / R;
-            const int j0 = rep * share;
-            if (act) force_tile<HASH>(acc, S, j0, max(0, min(share, nsrc - j0)), L, hi2, p - base, a.alpha);
+            force_tile<HASH, true>(acc, S, rep * share, share, L, hi2, p - base, a.alpha);
             wave_lds_sync();
         }
 
@@ -531,17 +585,17 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
                         bool ok = false;
                         if (lane < nsrc) {
                             int qq = lo + (g.sign > 0 ? base + lane : len - 1 - base - lane);
-                            uint32_t j = a.segidx[so + qq];
-                            float tj = sgn * (a.segproj[so + qq] + g.projoff);
+                            float4 pj = a.segpos[so + qq];
+                            float tj = sgn * (proj3(g.ddx, g.ddy, g.ddz, pj.x, pj.y, pj.z) + g.projoff);
                             ok = tj <= Tmax;
-                            if (ok) stage(lane, j, g.Sx, g.Sy, g.Sz);
+                            if (ok) stage(lane, a.segidx[so + qq], pj, g.Sx, g.Sy, g.Sz);
                         }
                         const uint64_t okm = __ballot(ok);
                         const int nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);
+                        if (lane >= nuse) S.p[lane] = make_float4(FAR, FAR, FAR, 0.f);
                         wave_lds_sync();
                         const int share = (nuse + R - 1) / R;
-                        const int j0 = rep * share;
-                        if (act) force_tile<HASH>(acc, S, j0, max(0, min(share, nuse - j0)), L, hi2, -1, a.alpha);
+                        force_tile<HASH, false>(acc, S, rep * share, share, L, hi2, -1, a.alpha);
                         wave_lds_sync();
                         if (nuse < nsrc) break;
                     }
@@ -977,7 +1031,7 @@ static DensArgs dens_args(sph_tree* t, int* counter) {
     a.csr = t->csr;
     a.csr_off = t->csr_off;
     a.segoff = t->segoff;
-    a.segproj = t->segproj;
+    a.segpos = t->segpos;
     a.segidx = t->segidx;
     a.status = t->status;
     a.rho = t->rho;
@@ -1029,7 +1083,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.csr = t->csr;
     a.csr_off = t->csr_off;
     a.segoff = t->segoff;
-    a.segproj = t->segproj;
+    a.segpos = t->segpos;
     a.segidx = t->segidx;
     a.alpha = t->prm.alpha;
     a.ax = t->fax;
