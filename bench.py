@@ -280,6 +280,17 @@ def bench_served(sph, n_req=400, pool_size=24, load=0.7):
     return summ
 
 
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, to scale the HBM byte counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,7 +301,12 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only (no batched/served)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--slack", type=float, default=None, help="h slack of the cell decisions (default: library's)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
