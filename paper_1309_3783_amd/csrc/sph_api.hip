@@ -59,7 +59,7 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;
-    if (hipMalloc(&c->d_counter, 64 * sizeof(int32_t)) != hipSuccess) {
+    if (hipMalloc(&c->d_counter, 1024 * sizeof(int32_t)) != hipSuccess) {
         delete c;
         return SPH_E_WORKSPACE;
     }

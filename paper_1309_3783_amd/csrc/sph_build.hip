@@ -92,7 +92,17 @@ __global__ __launch_bounds__(256) void k_set_hstats(const SetInfo* sets, const f
     }
     m = wave_max_f(m);
     bad = wave_sum_i(bad);
+    // one atomic per block: many blocks update the same word
+    __shared__ float s_m[4];
+    __shared__ int s_b[4];
     if ((threadIdx.x & 63) == 0) {
+        s_m[threadIdx.x >> 6] = m;
+        s_b[threadIdx.x >> 6] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+        bad = s_b[0] + s_b[1] + s_b[2] + s_b[3];
         atomicMax(&hmax_bits[blockIdx.y], __float_as_int(m));
         if (bad) atomicAdd(&bad_out[blockIdx.y], bad);
     }
@@ -415,8 +425,9 @@ __global__ void k_task_emit(const int4* __restrict__ tasks, int64_t nt, const Ce
 // Leaves -> work chunks of at most CHUNK particles; per-particle h bound.
 // ---------------------------------------------------------------------------
 // Chunks per cell; also the number of non-empty leaves and the largest leaf
-// (one atomic per wave).
-__global__ void k_chunk_count(const Cell* __restrict__ cells, int64_t nc, uint32_t* cnt, int* stats) {
+// (one atomic per block).
+__global__ __launch_bounds__(256) void k_chunk_count(const Cell* __restrict__ cells, int64_t nc, uint32_t* cnt,
+                                                     int* stats) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool leaf = false;
     int count = 0;
@@ -428,21 +439,41 @@ __global__ void k_chunk_count(const Cell* __restrict__ cells, int64_t nc, uint32
     }
     int nl = __popcll(__ballot(leaf));
     for (int d = 32; d >= 1; d >>= 1) count = max(count, __shfl_xor(count, d, 64));
-    if ((threadIdx.x & 63) == 0 && nl) {
-        atomicAdd(&stats[0], nl);
-        atomicMax(&stats[1], count);
+    __shared__ int s_n[4], s_c[4];
+    if ((threadIdx.x & 63) == 0) {
+        s_n[threadIdx.x >> 6] = nl;
+        s_c[threadIdx.x >> 6] = count;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        nl = s_n[0] + s_n[1] + s_n[2] + s_n[3];
+        count = max(max(s_c[0], s_c[1]), max(s_c[2], s_c[3]));
+        if (nl) {
+            atomicAdd(&stats[0], nl);
+            atomicMax(&stats[1], count);
+        }
     }
 }
 
-__global__ void k_chunk_emit(const Cell* __restrict__ cells, int64_t nc, const uint32_t* __restrict__ off,
+// The chunks are numbered in particle (cell) order, so that the chunk list
+// runs through space in Morton order: a leaf marks the first particle of each
+// of its chunks, a scan of the marks gives the chunk numbers.
+__global__ void k_chunk_mark(const Cell* __restrict__ cells, int64_t nc, uint32_t* __restrict__ mark) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const Cell C = cells[c];
+    if (C.split || C.count == 0) return;
+    for (int s = 0; s < C.count; s += CHUNK) mark[C.first + s] = 1u;
+}
+
+__global__ void k_chunk_emit(const Cell* __restrict__ cells, int64_t nc, const uint32_t* __restrict__ num,
                              int4* __restrict__ chunks) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     const Cell C = cells[c];
     if (C.split || C.count == 0) return;
-    uint32_t k = off[c];
     for (int s = 0; s < C.count; s += CHUNK)
-        chunks[k++] = make_int4((int)c, C.first + s, min(CHUNK, C.count - s), 0);
+        chunks[num[C.first + s]] = make_int4((int)c, C.first + s, min(CHUNK, C.count - s), 0);
 }
 
 __global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__ chunks, int64_t nch,
@@ -773,7 +804,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         HIPTRY(fill_u32((uint32_t*)d_hmax, 2 * (int64_t)S, 0u, st));
         int64_t maxc = 0;
         for (int s = 0; s < S; ++s) maxc = std::max<int64_t>(maxc, sets[s].count);
-        unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((maxc + 2047) / 2048, 1), 512);
+        unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((maxc + 8191) / 8192, 1), 256);
         hipLaunchKernelGGL(k_set_hstats, dim3(gx, S), dim3(256), 0, st, d_sets, in->h, (int*)d_hmax, d_bad);
         HIPTRY(hipGetLastError());
         HIPTRY(hipMemcpyAsync(hmax.data(), d_hmax, sizeof(float) * S, hipMemcpyDeviceToHost, st));
@@ -949,10 +980,12 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
 
     // ---- leaves -> chunks; particle h bounds ------------------------------
     const int64_t nc = t->ncells;
-    ERRTRY(t->scratch(nc + 1));
+    ERRTRY(t->scratch(std::max<int64_t>(nc, t->n) + 1));
     HIPTRY(fill_u32((uint32_t*)t->d_maxleaf, 2, 0, st));
     hipLaunchKernelGGL(k_chunk_count, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_a, t->d_maxleaf);
-    HIPTRY(exclusive_scan(t->sc_a, t->sc_b, nc, t->sc_tmp, total, st));
+    HIPTRY(fill_u32(t->sc_c, t->n, 0u, st));
+    hipLaunchKernelGGL(k_chunk_mark, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_c);
+    HIPTRY(exclusive_scan(t->sc_c, t->sc_d, t->n, t->sc_tmp, total, st));
     uint32_t nchunks = 0;
     ERRTRY(read_u32(total, &nchunks, st));
     int lstats[2] = {0, 0};
@@ -961,7 +994,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     const int maxleaf = lstats[1];
     t->nleaves = lstats[0];
     ERRTRY(t->alloc(t->b_chunk, sizeof(int4) * std::max<uint32_t>(nchunks, 1), (void**)&t->chunks));
-    hipLaunchKernelGGL(k_chunk_emit, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_b, t->chunks);
+    hipLaunchKernelGGL(k_chunk_emit, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_d, t->chunks);
     HIPTRY(hipGetLastError());
     t->nchunks = nchunks;
     t->max_leaf = maxleaf;

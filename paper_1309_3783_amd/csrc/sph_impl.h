@@ -66,7 +66,7 @@ struct sph_tree {
     uint64_t* hashd = nullptr;
     // solve state
     uint8_t* active = nullptr;
-    float *lo = nullptr, *hi = nullptr;
+    float *lo = nullptr, *hi = nullptr, *dstep = nullptr;
     int32_t* status = nullptr;   // [0] rebuild flag, [1] unconverged count
     // ghost + force state (cell order)
     float *A = nullptr, *cs = nullptr;
@@ -165,12 +165,13 @@ struct sph_tree {
     sph::Err ensure_saved() {
         const int64_t m = std::max<int64_t>(n, 1);
         void* p;
-        sph::Err e = alloc(b_saved, (size_t)m * (1 + 6 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 256, &p);
+        sph::Err e = alloc(b_saved, (size_t)m * (1 + 7 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 256, &p);
         if (e.st) return e;
         sv.hash = (uint64_t*)p;
         sv.lo = (float*)(sv.hash + m);
         sv.hi = sv.lo + m;
-        sv.rho = sv.hi + m;
+        sv.dstep = sv.hi + m;
+        sv.rho = sv.dstep + m;
         sv.drho = sv.rho + m;
         sv.nw = sv.drho + m;
         sv.dnw = sv.nw + m;

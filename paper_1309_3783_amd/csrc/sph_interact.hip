@@ -39,6 +39,32 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Work distribution of the persistent interaction kernels.  The chunk list
+// runs through space in Morton order; it is cut into NGRP contiguous ranges,
+// one per XCD.  Block b starts on range b mod NGRP (workgroups are handed to
+// the XCDs in turn), so the chunks one XCD works on at a time are neighbours
+// and share partner data in that XCD's L2; a wave whose range is exhausted
+// moves on to the following ranges.  ctr holds NGRP counters (CSTRIDE
+// words apart), zero at launch.  Which wave takes which chunk changes no result.
+constexpr int NGRP = 8;
+// the counters sit 128 bytes apart: atomics on one cache line from all XCDs
+// serialise
+constexpr int CSTRIDE = 32;
+__device__ __forceinline__ int next_chunk(int* __restrict__ ctr, int nchunks, int home, int& k) {
+    const int lane = threadIdx.x & 63;
+    while (k < NGRP) {
+        const int g = (home + k) & (NGRP - 1);
+        const int lo = (int)((int64_t)nchunks * g / NGRP);
+        const int hi = (int)((int64_t)nchunks * (g + 1) / NGRP);
+        int item = 0;
+        if (lane == 0) item = atomicAdd(&ctr[g * CSTRIDE], 1);
+        item = uni(__shfl(item, 0, 64));
+        if (lo + item < hi) return lo + item;
+        ++k;
+    }
+    return -1;
+}
+
 // Staged tiles hold TILE_PAD extra slots of far-away points, so that every
 // lane's share of a tile has the same length and the test loops are
 // uniform (scalar) loops.
@@ -266,11 +292,11 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
         s_p[w][64 + lane] = make_float4(FAR, FAR, FAR, 0.f);
         s_m[w][64 + lane] = 0ull;
     }
+    const int home = blockIdx.x & (NGRP - 1);
+    int grp = 0;
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(a.counter, 1);
-        item = uni(__shfl(item, 0, 64));
-        if (item >= a.nchunks) break;
+        const int item = next_chunk(a.counter, a.nchunks, home, grp);
+        if (item < 0) break;
         const int4 ch = a.chunks[item];
         const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
         // particles of the chunk that take part: all, or the still active
@@ -517,11 +543,11 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
     };
     if (lane < TILE - 64) S.p[64 + lane] = make_float4(FAR, FAR, FAR, 0.f);
 
+    const int home = blockIdx.x & (NGRP - 1);
+    int grp = 0;
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(a.counter, 1);
-        item = uni(__shfl(item, 0, 64));
-        if (item >= a.nchunks) break;
+        const int item = next_chunk(a.counter, a.nchunks, home, grp);
+        if (item < 0) break;
         const int4 ch = a.chunks[item];
         const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
         const int R = replicas(cnt, a.rmax), T = 64 / R;
@@ -631,12 +657,13 @@ __global__ void k_zero_i32(int32_t* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-__global__ void k_solve_init(int64_t n, uint8_t* active, float* lo, float* hi) {
+__global__ void k_solve_init(int64_t n, uint8_t* active, float* lo, float* hi, float* dstep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     active[p] = 1;
     lo[p] = 0.f;
     hi[p] = INFINITY;
+    dstep[p] = INFINITY;
 }
 
 // Status words of the h solve: [0] some set must be rebuilt, [1] particles
@@ -651,34 +678,40 @@ __device__ __forceinline__ int set_of(const SetInfo* sets, int nsets, int64_t p)
     return lo;
 }
 
-// One safeguarded Newton step on N_w(h) = target (in logarithms) for every
-// active particle (state 1): converged (|N_w - target| <= tol, tested in FP64) particles
-// keep h and their density (state 0); the rest move h and stay active.  A
+// One safeguarded Newton step on N_w(h) = target, taken on ln N_w against
+// ln h (exact wherever N_w is a power of h), for every active particle
+// (state 1).  Converged particles (|N_w - target| <= tol, tested in FP64)
+// keep h and their density (state 0).  For the others the bracket [lo, hi]
+// of the root is narrowed, and the Newton step is taken only if it stays in
+// the bracket, changes h by at most a factor 2 and is shorter than half the
+// previous step; otherwise the bracket is bisected (geometric mean; h is
+// doubled or halved while a side is open).  The step-length rule keeps a
+// particle whose N_w rises steeply over a short range of h (a dense clump
+// entering its support) from alternating between the two sides.  A
 // particle whose root lies beyond the largest h its cells support is parked
 // (state 2, no more density passes) and raises the rebuild flag of its set;
 // the other particles go on converging.
 __global__ void k_newton(int64_t n, const SetInfo* __restrict__ sets, int nsets, uint8_t* __restrict__ active,
                          const float* __restrict__ nw, const float* __restrict__ dnw, float* __restrict__ ph,
                          const float* __restrict__ bound, float* __restrict__ lo, float* __restrict__ hi,
-                         double target, double tol, int32_t* __restrict__ status) {
+                         float* __restrict__ dstep, double target, double tol, int32_t* __restrict__ status) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool still = false, rebuild = false;
+    bool rebuild = false;
     if (p < n && active[p] == 1) {
-        double err = (double)nw[p] - target;
+        const double err = (double)nw[p] - target;
         if (fabs(err) <= tol) {
             active[p] = 0;
         } else {
-            double h = ph[p];
+            const double h = ph[p];
             double l = lo[p], u = hi[p];
             if (err < 0) l = h; else u = h;
-            // Newton step on ln N_w against ln h: exact wherever N_w is a
-            // power of h, so far-off first guesses converge in few steps
-            double d = dnw[p];
-            double Nw = (double)nw[p];
-            double slope = d * h / Nw;
-            double hn = (d > 0 && Nw > 0) ? h * exp(-log(Nw / target) / slope) : -1.0;
-            bool bad = !(d > 0) || !(hn > l) || !(hn < u) || hn < 0.5 * h || hn > 2.0 * h;
-            if (bad) hn = isinf(u) ? 2.0 * h : 0.5 * (l + u);
+            const double d = dnw[p];
+            const double Nw = (double)nw[p];
+            const bool slope_ok = d > 0 && Nw > 0;
+            const double dl = slope_ok ? -log(Nw / target) / (d * h / Nw) : 0.0;
+            double hn = h * exp(dl);
+            const bool newton = slope_ok && hn > l && hn < u && fabs(dl) <= M_LN2 && fabs(dl) < 0.5 * (double)dstep[p];
+            if (!newton) hn = isinf(u) ? 2.0 * h : (l > 0 ? sqrt(l * u) : 0.5 * h);
             // the minimum-image convention needs h < box/2
             const double hcap = 0.5 * sets[set_of(sets, nsets, p)].box;
             if (hn >= hcap) hn = 0.5 * (h + hcap);
@@ -686,7 +719,9 @@ __global__ void k_newton(int64_t n, const SetInfo* __restrict__ sets, int nsets,
             if (hf == (float)h) hf = err < 0 ? nextafterf((float)h, INFINITY) : nextafterf((float)h, 0.f);
             if (!((double)hf < hcap)) hf = nextafterf((float)hcap, 0.f);
             // a step past the largest h the cells support first probes just
-            // below it; only if the root still lies beyond is a rebuild needed
+            // below it; only if the root still lies beyond is a rebuild
+            // needed, and the particle then keeps the step it would take, so
+            // that the rebuilt cells are sized for it
             const float hb = nextafterf(bound[p], 0.f);
             if (!(hf < bound[p])) {
                 if ((float)h == hb && err < 0) rebuild = true;
@@ -694,15 +729,14 @@ __global__ void k_newton(int64_t n, const SetInfo* __restrict__ sets, int nsets,
             }
             lo[p] = (float)l;
             hi[p] = (float)u;
+            dstep[p] = (float)fabs(log((double)hf / h));
             ph[p] = hf;
-            still = true;
             // parked: no density passes until the tree is rebuilt for it
             if (rebuild) active[p] = 2;
         }
     }
     // still-active particles are counted afterwards (k_count_active); only
     // the rare rebuild flag is raised here
-    (void)still;
     if (rebuild) {
         const int s = set_of(sets, nsets, p);
         atomicExch(&status[0], 1);
@@ -723,31 +757,43 @@ __global__ __launch_bounds__(256) void k_count_active(const int4* __restrict__ r
     if (threadIdx.x == 0) part[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
-// ... then per set (chunks of a set are consecutive) and in total.
-__global__ void k_count_final(const int4* __restrict__ red, int nred, const int32_t* __restrict__ part, int nsets,
-                              int32_t* __restrict__ status) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsets) return;
+// First reduction chunk of set s (the chunks of a set are consecutive).
+__device__ __forceinline__ int first_red_chunk(const int4* __restrict__ red, int nred, int s) {
     int lo = 0, hi = nred;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
         if (red[mid].x < s) lo = mid + 1; else hi = mid;
     }
+    return lo;
+}
+
+// ... then per set and in total: one wavefront per set, lanes striding over
+// the set's chunks, combined in a fixed butterfly.
+__global__ __launch_bounds__(256) void k_count_final(const int4* __restrict__ red, int nred,
+                                                     const int32_t* __restrict__ part, int nsets,
+                                                     int32_t* __restrict__ status) {
+    const int s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (s >= nsets) return;
     int c = 0;
-    for (int r = lo; r < nred && red[r].x == s; ++r) c += part[r];
-    status[3 + 2 * s] = c;
-    if (c) atomicAdd(&status[1], c);
+    for (int r = first_red_chunk(red, nred, s) + lane; r < nred && red[r].x == s; r += 64) c += part[r];
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (lane == 0) {
+        status[3 + 2 * s] = c;
+        if (c) atomicAdd(&status[1], c);
+    }
 }
 
 __global__ void k_save_state(int64_t n, const uint32_t* __restrict__ perm, const uint8_t* active, const float* lo,
-                             const float* hi, const float* rho, const float* drho, const float* nw, const float* dnw,
-                             const int32_t* nngb, const uint64_t* hash, SolveState sv) {
+                             const float* hi, const float* dstep, const float* rho, const float* drho,
+                             const float* nw, const float* dnw, const int32_t* nngb, const uint64_t* hash,
+                             SolveState sv) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     uint32_t i = perm[p];
     sv.active[i] = active[p];
     sv.lo[i] = lo[p];
     sv.hi[i] = hi[p];
+    sv.dstep[i] = dstep[p];
     sv.rho[i] = rho[p];
     sv.drho[i] = drho[p];
     sv.nw[i] = nw[p];
@@ -757,14 +803,15 @@ __global__ void k_save_state(int64_t n, const uint32_t* __restrict__ perm, const
 }
 
 __global__ void k_load_state(int64_t n, const uint32_t* __restrict__ perm, uint8_t* active, float* lo, float* hi,
-                             float* rho, float* drho, float* nw, float* dnw, int32_t* nngb, uint64_t* hash,
-                             SolveState sv) {
+                             float* dstep, float* rho, float* drho, float* nw, float* dnw, int32_t* nngb,
+                             uint64_t* hash, SolveState sv) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     uint32_t i = perm[p];
     active[p] = sv.active[i] ? 1 : 0;   // parked particles resume
     lo[p] = sv.lo[i];
     hi[p] = sv.hi[i];
+    dstep[p] = sv.dstep[i];
     rho[p] = sv.rho[i];
     drho[p] = sv.drho[i];
     nw[p] = sv.nw[i];
@@ -855,6 +902,7 @@ __global__ void k_scatter_force(int64_t n, const uint32_t* __restrict__ perm, co
 }
 
 constexpr int NRED = 8;
+constexpr int RED_CHUNK = 2048;   // particles per reduction block
 
 // One block per reduction chunk (a range of one set): FP64 partial sums in a
 // fixed tree order.
@@ -889,22 +937,23 @@ __global__ __launch_bounds__(256) void k_reduce_partial(const int4* __restrict__
     if (threadIdx.x < NRED) part[(int64_t)blockIdx.x * NRED + threadIdx.x] = s[threadIdx.x][0];
 }
 
-__global__ void k_reduce_final(const int4* __restrict__ red, int nred, const double* __restrict__ part, int nsets,
-                               double* __restrict__ sums, double* __restrict__ sums2) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+// Per-set totals: one wavefront per set, lanes striding over the set's
+// chunks, combined in a fixed butterfly (deterministic).
+__global__ __launch_bounds__(256) void k_reduce_final(const int4* __restrict__ red, int nred,
+                                                      const double* __restrict__ part, int nsets,
+                                                      double* __restrict__ sums, double* __restrict__ sums2) {
+    const int s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (s >= nsets) return;
-    // chunks of a set are consecutive; find the first by binary search
-    int lo = 0, hi = nred;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (red[mid].x < s) lo = mid + 1; else hi = mid;
-    }
     double acc[NRED] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int r = lo; r < nred && red[r].x == s; ++r)
+    for (int r = first_red_chunk(red, nred, s) + lane; r < nred && red[r].x == s; r += 64)
         for (int f = 0; f < NRED; ++f) acc[f] += part[(int64_t)r * NRED + f];
-    for (int f = 0; f < NRED; ++f) {
-        if (sums) sums[(int64_t)s * NRED + f] = acc[f];
-        if (sums2) sums2[(int64_t)s * NRED + f] = acc[f];
+    for (int f = 0; f < NRED; ++f)
+        for (int d = 32; d >= 1; d >>= 1) acc[f] += __shfl_xor(acc[f], d, 64);
+    if (lane < NRED) {
+        double v = acc[0];
+        for (int f = 1; f < NRED; ++f) v = lane == f ? acc[f] : v;
+        if (sums) sums[(int64_t)s * NRED + lane] = v;
+        if (sums2) sums2[(int64_t)s * NRED + lane] = v;
     }
 }
 
@@ -945,12 +994,13 @@ static Err ensure_state(sph_tree* t) {
     t->nw = t->drho + n;
     t->dnw = t->nw + n;
     t->nngb = (int32_t*)(t->dnw + n);
-    // solve: lo, hi, status (2 + 2 per set), active
+    // solve: lo, hi, dstep, status (2 + 2 per set), active
     const int64_t nst = 2 + 2 * (int64_t)t->nsets;
-    ERRTRY(t->alloc(t->b_solve, n * (2 * sizeof(float) + 1) + sizeof(int32_t) * (nst + 64) + 256, &p));
+    ERRTRY(t->alloc(t->b_solve, n * (3 * sizeof(float) + 1) + sizeof(int32_t) * (nst + 64) + 256, &p));
     t->lo = (float*)p;
     t->hi = t->lo + n;
-    t->status = (int32_t*)(t->hi + n);
+    t->dstep = t->hi + n;
+    t->status = (int32_t*)(t->dstep + n);
     t->active = (uint8_t*)(t->status + ((nst + 63) / 64) * 64);
     // force: A, cs, ax, ay, az, du, vs, S (float), nf (int), hash (u64)
     ERRTRY(t->alloc(t->b_force, n * (8 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 64, &p));
@@ -964,13 +1014,13 @@ static Err ensure_state(sph_tree* t) {
     t->fvs = t->fdu + n;
     t->fS = t->fvs + n;
     t->fn = (int32_t*)(t->fS + n);
-    // reduction chunks
+    // reduction chunks: RED_CHUNK particles of one set each
     if (t->red_chunks.empty()) {
         for (int s = 0; s < t->nsets; ++s) {
             int64_t a = t->off[s], b = t->off[s + 1];
             if (a == b) t->red_chunks.push_back(make_int4(s, (int)a, 0, 0));
-            for (int64_t q = a; q < b; q += 16384)
-                t->red_chunks.push_back(make_int4(s, (int)q, (int)std::min<int64_t>(16384, b - q), 0));
+            for (int64_t q = a; q < b; q += RED_CHUNK)
+                t->red_chunks.push_back(make_int4(s, (int)q, (int)std::min<int64_t>(RED_CHUNK, b - q), 0));
         }
         t->nred = (int64_t)t->red_chunks.size();
         ERRTRY(t->alloc(t->b_red, t->nred * (sizeof(int4) + NRED * sizeof(double) + sizeof(int32_t)) +
@@ -1046,7 +1096,7 @@ static DensArgs dens_args(sph_tree* t, int* counter) {
 
 static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, int* counter) {
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, counter, 1);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
     DensArgs a = dens_args(t, counter);
     dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
     if (solve) {
@@ -1065,7 +1115,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
                        t->prm.gamma, t->A, t->cs);
     hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph, t->segoff,
                        t->segidx);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, counter, 1);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
     ev_mark(ctx, "ghost");
     ForceArgs a;
     a.cells = t->cells;
@@ -1105,7 +1155,7 @@ static void launch_count(sph_ctx* ctx, sph_tree* t) {
     hipStream_t st = ctx->stream;
     hipLaunchKernelGGL(k_zero_unconv, dim3(nblk(t->nsets, 256)), dim3(256), 0, st, t->status, t->nsets);
     hipLaunchKernelGGL(k_count_active, dim3((unsigned)t->nred), dim3(256), 0, st, t->d_red, t->active, t->part_cnt);
-    hipLaunchKernelGGL(k_count_final, dim3(nblk(t->nsets, 64)), dim3(64), 0, st, t->d_red, (int)t->nred, t->part_cnt,
+    hipLaunchKernelGGL(k_count_final, dim3(nblk(t->nsets, 4)), dim3(256), 0, st, t->d_red, (int)t->nred, t->part_cnt,
                        t->nsets, t->status);
 }
 
@@ -1114,7 +1164,7 @@ static void launch_reduce(sph_ctx* ctx, sph_tree* t, double* sums_out) {
     if (t->nred == 0) return;
     hipLaunchKernelGGL(k_reduce_partial, dim3((unsigned)t->nred), dim3(256), 0, st, t->d_red, t->pos, t->pv, t->fax,
                        t->fay, t->faz, t->fdu, t->fS, t->nngb, t->fn, t->partial);
-    hipLaunchKernelGGL(k_reduce_final, dim3(nblk(t->nsets, 64)), dim3(64), 0, st, t->d_red, (int)t->nred, t->partial,
+    hipLaunchKernelGGL(k_reduce_final, dim3(nblk(t->nsets, 4)), dim3(256), 0, st, t->d_red, (int)t->nred, t->partial,
                        t->nsets, sums_out, t->sums_int);
 }
 
@@ -1163,9 +1213,11 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     const bool resume = (t->prm.flags & SPH_FLAG_RESUME) && t->saved && t->saved_n == n;
     if (resume) {
         hipLaunchKernelGGL(k_load_state, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->perm, t->active, t->lo, t->hi,
-                           t->rho, t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr, t->saved_state());
+                           t->dstep, t->rho, t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr,
+                           t->saved_state());
     } else {
-        hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi);
+        hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi,
+                           t->dstep);
     }
     t->saved = false;
     const int nst = 2 + 2 * t->nsets;
@@ -1176,7 +1228,7 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     for (; it < t->prm.max_iter; ++it) {
         launch_density(ctx, t, true, ctx->d_counter);
         hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->d_sets, t->nsets, t->active,
-                           t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi, (double)t->prm.n_target,
+                           t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi, t->dstep, (double)t->prm.n_target,
                            (double)t->prm.h_tol, t->status);
         launch_count(ctx, t);
         HIPTRY(hipGetLastError());
@@ -1195,7 +1247,8 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     if (rebuild) {
         ERRTRY(t->ensure_saved());
         hipLaunchKernelGGL(k_save_state, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->perm, t->active, t->lo, t->hi,
-                           t->rho, t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr, t->saved_state());
+                           t->dstep, t->rho, t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr,
+                           t->saved_state());
         t->saved = true;
         t->saved_n = n;
     }
@@ -1218,7 +1271,7 @@ Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
     ERRTRY(ensure_state(t));
     if (t->n == 0) return Err{};
     ev_mark(ctx, "start");
-    launch_force(ctx, t, ctx->d_counter + 1);
+    launch_force(ctx, t, ctx->d_counter + NGRP * CSTRIDE);
     ev_mark(ctx, "force");
     launch_reduce(ctx, t, out ? out->sums : nullptr);
     launch_scatter_force(ctx, t, out);
@@ -1278,18 +1331,19 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
         const int64_t n = t->n;
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi);
+            hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi,
+                               t->dstep);
             const int nst = 2 + 2 * t->nsets;
             hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
             for (int it = 0; it < k_iter; ++it) {
                 launch_density(ctx, t, true, ctx->d_counter);
                 hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->d_sets, t->nsets,
-                                   t->active, t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi,
+                                   t->active, t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi, t->dstep,
                                    (double)t->prm.n_target, (double)t->prm.h_tol, t->status);
                 launch_count(ctx, t);
             }
             launch_density(ctx, t, true, ctx->d_counter);
-            launch_force(ctx, t, ctx->d_counter + 1);
+            launch_force(ctx, t, ctx->d_counter + NGRP * CSTRIDE);
             launch_reduce(ctx, t, fout ? fout->sums : nullptr);
             launch_scatter_density(ctx, t, dout);
             launch_scatter_force(ctx, t, fout);

@@ -110,7 +110,7 @@ static_assert(sizeof(Cell) == 64, "Cell layout");
 // that the solve on the rebuilt tree continues where it stopped.
 struct SolveState {
     uint8_t* active;
-    float *lo, *hi, *rho, *drho, *nw, *dnw;
+    float *lo, *hi, *dstep, *rho, *drho, *nw, *dnw;
     int32_t* nngb;
     uint64_t* hash;
 };
