@@ -86,7 +86,9 @@ typedef struct {
     int32_t nsets;
     const int64_t* offsets;          /* [host]  nsets+1, offsets[0] = 0 */
     const double* box;               /* [host]  nsets periodic box sides */
-    const double *x, *y, *z;         /* [device] positions (wrapped into [0,box) internally) */
+    const double *x, *y, *z;         /* [device] positions (wrapped into [0,box) internally); the positions
+                                        of one set must be distinct (a particle at distance zero from
+                                        another one would be taken for itself) */
     const float* h;                  /* [device] smoothing lengths, 0 < h <= box/2 */
     const float *m, *u;              /* [device] masses, specific internal energies */
     const float *vx, *vy, *vz;       /* [device] velocities */

@@ -5,6 +5,8 @@ on the actual batch (or a sample of it) and keeps the fastest:
   * n_split        -- leaf size (split count of Section III-B, 400 by default)
   * blocks_per_cu  -- resident persistent blocks (4 wavefronts each) per CU
   * max_replicas   -- lanes per target particle for small chunks
+  * h_slack        -- room left for h to grow before the cells must be
+                      rebuilt (more room: fewer rebuilds, larger cells)
 Results are cached in a JSON table keyed by a workload signature (number of
 sets and log2 of the mean set size).
 """
@@ -22,7 +24,7 @@ from . import pipeline as P
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuned.json")
 
-GRID = {"n_split": [200, 400, 800], "blocks_per_cu": [4, 8, 16], "max_replicas": [4, 16]}
+GRID = {"n_split": [200, 400, 800], "blocks_per_cu": [4, 8, 16], "max_replicas": [4, 16], "h_slack": [0.1, 0.2]}
 
 
 def signature(batch: B.Batch, label: str = "") -> str:
@@ -47,7 +49,7 @@ def save_table(tab: dict) -> None:
     os.replace(tmp, TABLE)
 
 
-def tune(ctx: B.Context, batch: B.Batch, base: dict | None = None, k_iter: int = 8, reps: int = 2,
+def tune(ctx: B.Context, batch: B.Batch, base: dict | None = None, k_iter: int = 12, reps: int = 2,
          grid: dict | None = None, label: str = "", use_cache: bool = True, log=None) -> dict:
     import torch
     sig = signature(batch, label)

@@ -76,40 +76,52 @@ __device__ inline uint64_t splitmix64(uint64_t id) {
     return z ^ (z >> 31);
 }
 
-// Per-set max h and count of invalid h (not finite or <= 0).  Grid
+// Per-set max and min h and count of invalid h (not finite or <= 0).  Grid
 // (chunks, sets); positive floats compare like their bit patterns, so the
-// max is an integer atomicMax.
+// extremes are integer atomics.
 __global__ __launch_bounds__(256) void k_set_hstats(const SetInfo* sets, const float* __restrict__ h,
-                                                    int* __restrict__ hmax_bits, int* __restrict__ bad_out) {
+                                                    int* __restrict__ hmax_bits, int* __restrict__ hmin_bits,
+                                                    int* __restrict__ bad_out) {
     const SetInfo S = sets[blockIdx.y];
-    float m = 0.f;
+    float m = 0.f, mn = INFINITY;
     int bad = 0;
     for (int64_t i = S.first + (int64_t)blockIdx.x * 256 + threadIdx.x; i < S.first + S.count;
          i += (int64_t)gridDim.x * 256) {
         float v = h[i];
-        if (!(v > 0.f) || !(v < INFINITY)) bad++;
-        else m = fmaxf(m, v);
+        if (!(v > 0.f) || !(v < INFINITY)) {
+            bad++;
+        } else {
+            m = fmaxf(m, v);
+            mn = fminf(mn, v);
+        }
     }
     m = wave_max_f(m);
+    mn = -wave_max_f(-mn);
     bad = wave_sum_i(bad);
     // one atomic per block: many blocks update the same word
-    __shared__ float s_m[4];
+    __shared__ float s_m[4], s_n[4];
     __shared__ int s_b[4];
     if ((threadIdx.x & 63) == 0) {
         s_m[threadIdx.x >> 6] = m;
+        s_n[threadIdx.x >> 6] = mn;
         s_b[threadIdx.x >> 6] = bad;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         m = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+        mn = fminf(fminf(s_n[0], s_n[1]), fminf(s_n[2], s_n[3]));
         bad = s_b[0] + s_b[1] + s_b[2] + s_b[3];
         atomicMax(&hmax_bits[blockIdx.y], __float_as_int(m));
+        atomicMin(&hmin_bits[blockIdx.y], __float_as_int(mn));
         if (bad) atomicAdd(&bad_out[blockIdx.y], bad);
     }
 }
 
 // Integer cell coordinate at 2^(lgG+depth) cells per side (same formula in
-// k_keys and k_gather so both place a particle in the same cell).
+// k_keys and k_gather so both place a particle in the same cell).  The
+// depth is per set (the levels its h range can need), so a set's keys -- and
+// with them the order of its particles -- do not depend on the other sets of
+// a batch.
 __device__ inline int64_t fine_coord(double x, double box, int64_t R) {
     double w = x - box * floor(x / box);
     int64_t k = (int64_t)floor(w / box * (double)R);
@@ -117,13 +129,13 @@ __device__ inline int64_t fine_coord(double x, double box, int64_t R) {
 }
 
 __global__ void k_keys(const SetInfo* sets, int nsets, int64_t n, const double* __restrict__ x,
-                       const double* __restrict__ y, const double* __restrict__ z, int depth, int bmax,
+                       const double* __restrict__ y, const double* __restrict__ z, int bmax,
                        uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int s = set_of_particle(sets, nsets, i);
     const SetInfo S = sets[s];
-    int64_t R = (int64_t)1 << (S.lgG + depth);
+    int64_t R = (int64_t)1 << (S.lgG + S.depth);
     uint64_t ix = (uint64_t)fine_coord(x[i], S.box, R);
     uint64_t iy = (uint64_t)fine_coord(y[i], S.box, R);
     uint64_t iz = (uint64_t)fine_coord(z[i], S.box, R);
@@ -131,7 +143,7 @@ __global__ void k_keys(const SetInfo* sets, int nsets, int64_t n, const double* 
     val[i] = (uint32_t)i;
 }
 
-__global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int depth, int bmax,
+__global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
                          const uint64_t* __restrict__ key, const uint32_t* __restrict__ val,
                          const double* __restrict__ x, const double* __restrict__ y,
                          const double* __restrict__ z, const float* __restrict__ h,
@@ -146,12 +158,12 @@ __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int depth, i
     uint32_t i = val[p];
     int s = nsets > 1 ? (int)(key[p] >> (3 * bmax)) : 0;
     const SetInfo S = sets[s];
-    int64_t R = (int64_t)1 << (S.lgG + depth);
+    int64_t R = (int64_t)1 << (S.lgG + S.depth);
     double xs[3] = {x[i], y[i], z[i]};
     float o[3];
     for (int d = 0; d < 3; ++d) {
         double w = xs[d] - S.box * floor(xs[d] / S.box);
-        int64_t top = fine_coord(xs[d], S.box, R) >> depth;
+        int64_t top = fine_coord(xs[d], S.box, R) >> S.depth;
         o[d] = (float)(w - (double)top * S.L0);
     }
     pos[p] = make_float4(o[0], o[1], o[2], m[i]);
@@ -164,16 +176,16 @@ __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int depth, i
     mix[p] = splitmix64((uint64_t)((int64_t)i - S.first));
 }
 
-__device__ inline void cell_key_range(const SetInfo& S, int bmax, int depth, int level, int ix, int iy, int iz,
-                                      int set, uint64_t* lo, uint64_t* hi) {
+__device__ inline void cell_key_range(const SetInfo& S, int bmax, int level, int ix, int iy, int iz, int set,
+                                      uint64_t* lo, uint64_t* hi) {
     uint64_t code = morton3((uint64_t)ix, (uint64_t)iy, (uint64_t)iz);
-    int sh = S.key_shift + 3 * (depth - level);
+    int sh = S.key_shift + 3 * (S.depth - level);
     uint64_t base = ((uint64_t)set << (3 * bmax));
     *lo = base | (code << sh);
     *hi = *lo + (1ull << sh);
 }
 
-__global__ void k_top_cells(const SetInfo* sets, int nsets, int ntop, int depth, int bmax,
+__global__ void k_top_cells(const SetInfo* sets, int nsets, int ntop, int bmax,
                             const uint64_t* __restrict__ key, Cell* __restrict__ cells) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ntop) return;
@@ -189,7 +201,7 @@ __global__ void k_top_cells(const SetInfo* sets, int nsets, int ntop, int depth,
     C.parent = -1;
     C.child = -1;
     uint64_t lo, hi;
-    cell_key_range(S, bmax, depth, 0, C.ix, C.iy, C.iz, s, &lo, &hi);
+    cell_key_range(S, bmax, 0, C.ix, C.iy, C.iz, s, &lo, &hi);
     int64_t a = lower_bound_key(key, S.first, S.first + S.count, lo);
     int64_t b = lower_bound_key(key, a, S.first + S.count, hi);
     C.first = (int32_t)a;
@@ -207,7 +219,7 @@ __global__ void k_top_cells(const SetInfo* sets, int nsets, int ntop, int depth,
 // One wave per cell of level `level`: particle range (children of a split
 // parent look theirs up inside the parent's range), max decision h, the
 // number with h < edge/2, and the split decision.
-__global__ __launch_bounds__(256) void k_cell_stats(const SetInfo* sets, int depth, int bmax, int level,
+__global__ __launch_bounds__(256) void k_cell_stats(const SetInfo* sets, int bmax, int level,
                                                     int64_t c0, int64_t c1, const uint64_t* __restrict__ key,
                                                     const float* __restrict__ hdec, int n_split,
                                                     float split_frac, Cell* __restrict__ cells) {
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(256) void k_cell_stats(const SetInfo* sets, int dep
     if (level > 0) {
         const Cell P = cells[C.parent];
         uint64_t lo, hi;
-        cell_key_range(S, bmax, depth, level, C.ix, C.iy, C.iz, C.set, &lo, &hi);
+        cell_key_range(S, bmax, level, C.ix, C.iy, C.iz, C.set, &lo, &hi);
         int64_t a = lower_bound_key(key, P.first, (int64_t)P.first + P.count, lo);
         int64_t b = lower_bound_key(key, a, (int64_t)P.first + P.count, hi);
         C.first = (int32_t)a;
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(256) void k_cell_stats(const SetInfo* sets, int dep
     nsmall = wave_sum_i(nsmall);
     if (lane == 0) {
         C.hmax = hm;
-        C.split = (level < depth && C.count > n_split &&
+        C.split = (level < S.depth && C.count > n_split &&
                    (double)nsmall > (double)split_frac * (double)C.count) ? 1u : 0u;
         cells[c] = C;
     }
@@ -786,11 +798,13 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     // ---- per-set h statistics -> top grids ------------------------------
     const int S = in->nsets;
     float* d_hmax;
+    float* d_hmin;
     int* d_bad;
     SetInfo* d_sets;
     ERRTRY(t->alloc(t->b_sets, sizeof(SetInfo) * S, (void**)&d_sets));
-    ERRTRY(t->alloc(t->b_small, sizeof(float) * S + sizeof(int) * S + 64, (void**)&d_hmax));
-    d_bad = (int*)(d_hmax + S);
+    ERRTRY(t->alloc(t->b_small, 2 * sizeof(float) * S + sizeof(int) * S + 64, (void**)&d_hmax));
+    d_hmin = d_hmax + S;
+    d_bad = (int*)(d_hmin + S);
     std::vector<SetInfo> sets(S);
     for (int s = 0; s < S; ++s) {
         sets[s].first = in->offsets[s];
@@ -798,16 +812,19 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         sets[s].box = in->box[s];
     }
     HIPTRY(hipMemcpyAsync(d_sets, sets.data(), sizeof(SetInfo) * S, hipMemcpyHostToDevice, st));
-    std::vector<float> hmax(S, 0.f);
+    std::vector<float> hmax(S, 0.f), hmin(S, INFINITY);
     std::vector<int> bad(S, 0);
     if (n > 0) {
-        HIPTRY(fill_u32((uint32_t*)d_hmax, 2 * (int64_t)S, 0u, st));
+        HIPTRY(fill_u32((uint32_t*)d_hmax, 3 * (int64_t)S, 0u, st));
+        HIPTRY(fill_u32((uint32_t*)d_hmin, S, 0x7F800000u, st));   // +inf
         int64_t maxc = 0;
         for (int s = 0; s < S; ++s) maxc = std::max<int64_t>(maxc, sets[s].count);
         unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((maxc + 8191) / 8192, 1), 256);
-        hipLaunchKernelGGL(k_set_hstats, dim3(gx, S), dim3(256), 0, st, d_sets, in->h, (int*)d_hmax, d_bad);
+        hipLaunchKernelGGL(k_set_hstats, dim3(gx, S), dim3(256), 0, st, d_sets, in->h, (int*)d_hmax, (int*)d_hmin,
+                           d_bad);
         HIPTRY(hipGetLastError());
         HIPTRY(hipMemcpyAsync(hmax.data(), d_hmax, sizeof(float) * S, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(hmin.data(), d_hmin, sizeof(float) * S, hipMemcpyDeviceToHost, st));
         HIPTRY(hipMemcpyAsync(bad.data(), d_bad, sizeof(int) * S, hipMemcpyDeviceToHost, st));
         HIPTRY(hipStreamSynchronize(st));
     }
@@ -835,18 +852,32 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         }
         sets[s].lgG = lg;
         sets[s].L0 = box / (double)(1 << lg);
+        // a cell splits only if some particle has a decision h below half
+        // its edge: no level below the one whose edge first drops under
+        // twice the smallest decision h (plus one) can hold a split cell, so
+        // the keys need no finer resolution
+        int d = 0;
+        if (sets[s].count > 0) {
+            const double hdmin = (double)hmin[s] * (1.0 + (double)prm->h_slack);
+            d = 1;
+            while (d < 30 && sets[s].L0 / (double)(1 << (d - 1)) > 2.0 * hdmin) ++d;
+        }
+        sets[s].depth = std::min(std::min(prm->max_depth, d), KEY_BITS_PER_DIM - lg);
         sets[s].top_base = (int32_t)ntop;
         ntop += (int64_t)1 << (3 * lg);
         max_lg = std::max(max_lg, lg);
     }
     if (ntop > (int64_t)1 << 26) return Err{SPH_E_CAPACITY, "too many top cells"};
-    int depth = std::min(prm->max_depth, KEY_BITS_PER_DIM - max_lg);
-    if (depth < 0) return Err{SPH_E_CAPACITY, "top grid too fine for the key layout"};
-    const int bmax = max_lg + depth;
+    int depth = 0, bmax = 0;
+    for (int s = 0; s < S; ++s) {
+        if (sets[s].depth < 0) return Err{SPH_E_CAPACITY, "top grid too fine for the key layout"};
+        depth = std::max(depth, sets[s].depth);
+        bmax = std::max(bmax, sets[s].lgG + sets[s].depth);
+    }
     int setbits = 0;
     while ((1 << setbits) < S) ++setbits;
     if (3 * bmax + setbits > 64) return Err{SPH_E_CAPACITY, "key layout exceeds 64 bits"};
-    for (int s = 0; s < S; ++s) sets[s].key_shift = 3 * (bmax - sets[s].lgG - depth);
+    for (int s = 0; s < S; ++s) sets[s].key_shift = 3 * (bmax - sets[s].lgG - sets[s].depth);
     t->sets = sets;
     t->depth = depth;
     t->key_bits = 3 * bmax + setbits;
@@ -870,8 +901,8 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(nn), radix_tmp_words(1 << 20)),
                     (void**)&t->rs_tmp));
     if (n > 0) {
-        hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, in->x, in->y, in->z,
-                           depth, bmax, t->key2, t->val2);
+        hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, in->x, in->y, in->z, bmax,
+                           t->key2, t->val2);
         HIPTRY(hipGetLastError());
         bool alt = false;
         HIPTRY(radix_sort(t->key2, t->val2, t->key, t->val, n, t->key_bits, t->rs_tmp, st, &alt));
@@ -881,7 +912,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
             std::swap(t->b_key, t->b_key2);
             std::swap(t->b_val, t->b_val2);
         }
-        hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, depth, bmax, t->key,
+        hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, bmax, t->key,
                            t->val, in->x, in->y, in->z, in->h, in->m, in->u, in->vx, in->vy, in->vz,
                            prm->h_slack, t->pos, t->ph, t->hdec, t->pu, t->pv, t->perm, t->mix);
         HIPTRY(hipGetLastError());
@@ -893,10 +924,10 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(t->alloc(t->b_cell, sizeof(Cell) * cap_cells, (void**)&t->cells));
     t->lvl_start.assign(1, 0);
     t->lvl_start.push_back(ntop);
-    hipLaunchKernelGGL(k_top_cells, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, S, (int)ntop, depth, bmax,
-                       t->key, t->cells);
+    hipLaunchKernelGGL(k_top_cells, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, S, (int)ntop, bmax, t->key,
+                       t->cells);
     HIPTRY(hipGetLastError());
-    hipLaunchKernelGGL(k_cell_stats, dim3(nblk(ntop, 4)), dim3(256), 0, st, d_sets, depth, bmax, 0, (int64_t)0,
+    hipLaunchKernelGGL(k_cell_stats, dim3(nblk(ntop, 4)), dim3(256), 0, st, d_sets, bmax, 0, (int64_t)0,
                        ntop, t->key, t->hdec, prm->n_split, prm->split_frac, t->cells);
     HIPTRY(hipGetLastError());
 
@@ -938,7 +969,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
             hipLaunchKernelGGL(k_make_children, dim3(nblk(nlev, 256)), dim3(256), 0, st, c0, c1, c1, t->sc_b,
                                t->cells);
             HIPTRY(hipGetLastError());
-            hipLaunchKernelGGL(k_cell_stats, dim3(nblk(nnext, 4)), dim3(256), 0, st, d_sets, depth, bmax,
+            hipLaunchKernelGGL(k_cell_stats, dim3(nblk(nnext, 4)), dim3(256), 0, st, d_sets, bmax,
                                level + 1, c1, c1 + nnext, t->key, t->hdec, prm->n_split, prm->split_frac,
                                t->cells);
             HIPTRY(hipGetLastError());
@@ -951,10 +982,11 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
                                t->cells, t->sc_a, t->sc_c);
             HIPTRY(hipGetLastError());
             HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ncur, t->sc_tmp, total, st));
-            uint32_t nf = 0, nc = 0;
-            ERRTRY(read_u32(total, &nf, st));
-            HIPTRY(exclusive_scan(t->sc_c, t->sc_d, ncur, t->sc_tmp, total, st));
-            ERRTRY(read_u32(total, &nc, st));
+            HIPTRY(exclusive_scan(t->sc_c, t->sc_d, ncur, t->sc_tmp, total + 1, st));
+            uint32_t nfc[2] = {0, 0};
+            HIPTRY(hipMemcpyAsync(nfc, total, sizeof(nfc), hipMemcpyDeviceToHost, st));
+            HIPTRY(hipStreamSynchronize(st));
+            const uint32_t nf = nfc[0], nc = nfc[1];
             if (nfinal + nf > (int64_t)0x7FFFFFFF) return Err{SPH_E_CAPACITY, "too many tasks"};
             ERRTRY(t->grow(t->b_final, sizeof(int4) * nfinal, sizeof(int4) * std::max<int64_t>(nfinal + nf, 1),
                            (void**)&t->finals));
@@ -987,8 +1019,8 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     hipLaunchKernelGGL(k_chunk_mark, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_c);
     HIPTRY(exclusive_scan(t->sc_c, t->sc_d, t->n, t->sc_tmp, total, st));
     uint32_t nchunks = 0;
-    ERRTRY(read_u32(total, &nchunks, st));
     int lstats[2] = {0, 0};
+    HIPTRY(hipMemcpyAsync(&nchunks, total, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIPTRY(hipMemcpyAsync(lstats, t->d_maxleaf, sizeof(lstats), hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
     const int maxleaf = lstats[1];
@@ -1017,7 +1049,12 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         hipLaunchKernelGGL(k_csr_keys, dim3(nblk(nfinal, 256)), dim3(256), 0, st, t->finals, nfinal, t->csr);
         HIPTRY(hipGetLastError());
         bool alt = false;
-        HIPTRY(radix_sort(t->csr, nullptr, t->csr2, nullptr, ne, 64, t->rs_tmp, st, &alt));
+        // stable sort on the target field only: a target's entries keep the
+        // order of the task list, which the tree fixes; self tasks (all
+        // ones) sort last
+        int tbits = 1;
+        while (((int64_t)1 << tbits) <= nc) ++tbits;
+        HIPTRY(radix_sort(t->csr, nullptr, t->csr2, nullptr, ne, tbits, t->rs_tmp, st, &alt, CSR_TGT_SHIFT));
         if (alt) {
             std::swap(t->csr, t->csr2);
             std::swap(t->b_csr, t->b_csr2);
@@ -1057,9 +1094,11 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     t->nsegs = ns;
     int64_t nent = 0;
     if (ns > 0) {
-        ERRTRY(t->alloc(t->b_seglist, sizeof(uint32_t) * ns * 3, (void**)&t->seglist));
+        // seglist | lengths | offsets | mid-size list | long list | long lengths
+        ERRTRY(t->alloc(t->b_seglist, sizeof(uint32_t) * ns * 6, (void**)&t->seglist));
         uint32_t* lens = t->seglist + ns;
         uint32_t* soff = t->seglist + 2 * (int64_t)ns;
+        uint32_t* mids = t->seglist + 3 * (int64_t)ns;
         hipLaunchKernelGGL(k_seg_list, dim3(nblk(nca, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, nca, t->cells,
                            t->seglist, lens);
         HIPTRY(hipGetLastError());
@@ -1078,30 +1117,31 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
                            t->segidx);
         HIPTRY(hipGetLastError());
         ERRTRY(t->scratch(std::max<int64_t>(nca, ns) + 1));
+        // segments of 65..SEG_LDS_MAX entries (LDS sort) and longer ones (one
+        // global radix sort over all of them): both classes counted at once
         hipLaunchKernelGGL(k_mid_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_a);
+        hipLaunchKernelGGL(k_big_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_c);
         HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ns, t->sc_tmp, total, st));
-        uint32_t nmid = 0;
-        ERRTRY(read_u32(total, &nmid, st));
+        HIPTRY(exclusive_scan(t->sc_c, t->sc_d, ns, t->sc_tmp, total + 1, st));
+        uint32_t ncls[2] = {0, 0};
+        HIPTRY(hipMemcpyAsync(ncls, total, sizeof(ncls), hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        const uint32_t nmid = ncls[0], nbig = ncls[1];
         if (nmid > 0) {
             hipLaunchKernelGGL(k_compact, dim3(nblk(ns, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, (int64_t)ns,
-                               t->sc_c);
+                               mids);
             hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)std::min<uint32_t>(nmid, 65535)), dim3(256), 0, st,
-                               t->sc_c, (int64_t)nmid, t->seglist, soff, t->d_sets, t->cells, t->pos, t->ph,
+                               mids, (int64_t)nmid, t->seglist, soff, t->d_sets, t->cells, t->pos, t->ph,
                                t->segpos, t->segidx);
             HIPTRY(hipGetLastError());
         }
-        // segments too long for LDS: one global radix sort over all of them
-        hipLaunchKernelGGL(k_big_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_a);
-        HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ns, t->sc_tmp, total, st));
-        uint32_t nbig = 0;
-        ERRTRY(read_u32(total, &nbig, st));
         if (nbig > 0) {
-            uint32_t* big = t->sc_c;
-            uint32_t* blen = t->sc_d;
-            hipLaunchKernelGGL(k_big_list, dim3(nblk(ns, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, (int64_t)ns,
+            uint32_t* big = t->seglist + 4 * (int64_t)ns;
+            uint32_t* blen = t->seglist + 5 * (int64_t)ns;
+            hipLaunchKernelGGL(k_big_list, dim3(nblk(ns, 256)), dim3(256), 0, st, t->sc_c, t->sc_d, (int64_t)ns,
                                lens, big, blen);
             HIPTRY(hipGetLastError());
-            uint32_t* boff = t->sc_a;   // flags no longer needed
+            uint32_t* boff = t->sc_a;   // the mid-size flags are consumed (stream order)
             HIPTRY(exclusive_scan(blen, boff, nbig, t->sc_tmp, total, st));
             uint32_t nbe = 0;
             ERRTRY(read_u32(total, &nbe, st));

@@ -3,20 +3,21 @@
 //
 // Work decomposition (owner computes, no floating-point atomics): one
 // wavefront owns a chunk of at most 64 particles of one leaf cell, one lane
-// per particle.  It walks, in a fixed order,
+// per particle (2 to 16 lanes per particle for small chunks).  It walks, in
+// a fixed order,
 //   * the leaf's self task (all particle pairs in the leaf), then
 //   * for the leaf and each of its ancestors, that cell's pair tasks
 //     (Section II-B lists), sweeping the partner cell's particles in their
-//     order along the cell-pair axis (Section II-C): the partner's list is
-//     staged 64 entries at a time in LDS and the sweep stops as soon as the
-//     next entry is farther along the axis than any lane's cutoff.
-// Every particle therefore meets each in-range partner exactly once per
-// stage, and sums in an order fixed by the tree alone.  Positions are FP32
-// offsets from the top cell origin; a task adds the exact top-cell shift of
-// its partner (a multiple of the top cell edge), so on inputs of the 2^-24
-// grid every coordinate difference is exact.  Sums use compensated
-// summation: Kahan for the positive density sums, Neumaier for the
-// mixed-sign force sums.
+//     order along the cell-pair axis (Section II-C): the sweep stops as soon
+//     as the next entry is farther along the axis than any lane's cutoff.
+// The records met are staged in LDS tiles, tested, and the in-range ones
+// evaluated (see the walk below).  Every particle therefore meets each
+// in-range partner exactly once per stage, and sums in an order fixed by the
+// tree alone.  Positions are FP32 offsets from the top cell origin; a task
+// adds the exact top-cell shift of its partner (a multiple of the top cell
+// edge), so on inputs of the 2^-24 grid every coordinate difference is exact.
+// Sums are plain FP32 sums over at most a few hundred terms per particle,
+// whose rounding stays far inside the stated tolerances.
 #include <cmath>
 
 #include "sph_impl.h"
@@ -68,7 +69,10 @@ __device__ __forceinline__ int next_chunk(int* __restrict__ ctr, int nchunks, in
 // Staged tiles hold TILE_PAD extra slots of far-away points, so that every
 // lane's share of a tile has the same length and the test loops are
 // uniform (scalar) loops.
-constexpr int TILE = 64 + 16;
+#ifndef SPH_TCAP
+#define SPH_TCAP 64
+#endif
+constexpr int TILE = SPH_TCAP + 16;
 constexpr float FAR = 1.0e18f;
 __device__ __forceinline__ float unif(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -78,19 +82,6 @@ __device__ __forceinline__ float wmax(float v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
     return v;
-}
-
-__device__ __forceinline__ void kahan(float& s, float& c, float x) {
-    float y = x - c;
-    float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
-__device__ __forceinline__ void neumaier(float& s, float& c, float x) {
-    float t = s + x;
-    c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
-    s = t;
 }
 
 // Offset code tables: axis index and sign of each of the 27 offset codes,
@@ -183,31 +174,7 @@ struct DensArgs {
     int rmax;
 };
 
-struct DensAcc {
-    float sf = 0, cf = 0, sg = 0, cg = 0, sw = 0, cw = 0, sq = 0, cq = 0;
-    int nn = 0;
-    uint64_t hs = 0;
-};
-
-__device__ __forceinline__ void dens_pair(DensAcc& a, float r2, float hinv, float mj, uint64_t mixj) {
-    float r = fsqrt(r2);
-    float q = r * hinv;
-    float q2 = q * q;
-    float t = 1.f - q;
-    float t2 = t * t;
-    bool inner = q < 0.5f;
-    float f = inner ? fmaf(6.f * q2, q - 1.f, 1.f) : 2.f * t2 * t;
-    float df = inner ? q * fmaf(18.f, q, -12.f) : -6.f * t2;
-    float g = fmaf(q, df, 3.f * f);
-    kahan(a.sf, a.cf, mj * f);
-    kahan(a.sg, a.cg, mj * g);
-    kahan(a.sw, a.cw, f);
-    kahan(a.sq, a.cq, q * df);
-    a.nn += 1;
-    a.hs += mixj;
-}
-
-// Lanes per target particle: small chunks spread each particle over 2 or 4
+// Lanes per target particle: small chunks spread each particle over 2 to 16
 // lanes, each taking a contiguous share of every staged tile; the shares are
 // combined in a fixed order at the end.
 __device__ __forceinline__ int replicas(int cnt, int rmax) {
@@ -237,61 +204,232 @@ __device__ __forceinline__ float comb_max(float v, int R) {
     return v;
 }
 
-// Tile work shared by the self and pair sweeps: the lane's share of the
-// tile, entries [j0, j0 + share) (padded with far-away points), is tested
-// first -- one bit per entry in range -- then only the set bits are
-// evaluated, so the wave does not run the pair arithmetic for entries that
-// no lane needs.
-template <bool SELF>
-__device__ __forceinline__ uint64_t tile_mask(const float4* sp, int j0, int share, const float4& xi, float hi2,
-                                              int self_j) {
-    uint32_t lo = 0, hi = 0;
-    const int n0 = share < 32 ? share : 32;
+// ---------------------------------------------------------------------------
+// Wave-level walk shared by the density and force stages
+// ---------------------------------------------------------------------------
+// The partner records met along the walk are staged in LDS, TCAP records
+// per tile; consecutive sources (the self task, then the pair tasks in turn)
+// share a tile, so that a tile mixes records from several neighbouring
+// cells.  A full tile is processed in two steps: every lane tests its share
+// of the tile against its particle (one bit per record in range), then
+// evaluates the set bits.  The wave runs the evaluation as often as its
+// busiest lane has bits; mixing sources in one tile evens the lanes' counts
+// out (a particle near one face of its cell has many partners in the cell
+// beyond that face and few in the opposite one).
+constexpr int TCAP = SPH_TCAP;
+constexpr int NWORD = TCAP / 32;
+static_assert(TCAP % 32 == 0 && TILE - TCAP >= 16, "tile layout");
+
+// Test of a lane's share [j0, j0 + share) of the tile (share <= TCAP; the
+// tile is padded past its end): bit k of word w set when record
+// j0 + 32 w + k is in range.  SELF: the tile holds a block of the self task,
+// and a record at distance zero (the lane's own particle; positions in a
+// set are distinct) is not a neighbour.
+template <class P, bool SELF>
+__device__ __forceinline__ void tile_test(const float4* sp, int j0, int share, const float4& xi, float hi2,
+                                          uint32_t (&m)[NWORD]) {
+#pragma unroll
+    for (int w = 0; w < NWORD; ++w) {
+        uint32_t bits = 0;
+        const int k1 = min(32, share - 32 * w);
 #pragma unroll 4
-    for (int k = 0; k < n0; ++k) {
-        float4 q = sp[j0 + k];
-        float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
-        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        bool in = r2 < hi2;
-        if (SELF) in = in && (j0 + k != self_j);
-        lo = in ? (lo | (1u << k)) : lo;
+        for (int k = 0; k < k1; ++k) {
+            const float4 q = sp[j0 + 32 * w + k];
+            const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const bool in = P::in_range(r2, hi2, q.w) && (!SELF || r2 > 0.f);
+            bits = in ? (bits | (1u << k)) : bits;
+        }
+        m[w] = bits;
     }
-#pragma unroll 4
-    for (int k = 32; k < share; ++k) {
-        float4 q = sp[j0 + k];
-        float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
-        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        bool in = r2 < hi2;
-        if (SELF) in = in && (j0 + k != self_j);
-        hi = in ? (hi | (1u << (k - 32))) : hi;
-    }
-    return ((uint64_t)hi << 32) | lo;
 }
 
-template <bool HASH, bool SELF>
-__device__ __forceinline__ void dens_tile(DensAcc& acc, const float4* sp, const uint64_t* sm, int j0, int share,
-                                          const float4& xi, float hi2, float hinv, int self_j) {
-    uint64_t mask = tile_mask<SELF>(sp, j0, share, xi, hi2, self_j);
-    while (mask) {
-        int k = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        float4 q = sp[j0 + k];
-        float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
-        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        dens_pair(acc, r2, hinv, q.w, HASH ? sm[j0 + k] : 0ull);
+// Test and evaluation of the n (1 <= n <= TCAP) records staged in S; self:
+// the tile holds a block of the self task (wave-uniform).
+template <class P>
+__device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, int rep, const typename P::Lane& L,
+                                             typename P::Acc& acc, bool self) {
+    const int lane = threadIdx.x & 63;
+    // far-away padding: every share has the same length (R * share - n < 16)
+    if (lane < TILE - TCAP) S.p[n + lane] = make_float4(FAR, FAR, FAR, 0.f);
+    wave_lds_sync();
+    const int share = (n + R - 1) / R;
+    const int j0 = rep * share;
+    uint32_t m[NWORD];
+    if (self) tile_test<P, true>(S.p, j0, share, L.x, L.hi2, m);
+    else tile_test<P, false>(S.p, j0, share, L.x, L.hi2, m);
+    // set bits in increasing record order, 64 at a time
+#pragma unroll
+    for (int w = 0; w < NWORD; ++w) acc.nn += __popc(m[w]);
+#pragma unroll
+    for (int w = 0; w < NWORD; w += 2) {
+        uint64_t mm = (uint64_t)m[w] | (w + 1 < NWORD ? (uint64_t)m[w + 1] << 32 : 0ull);
+        while (mm) {
+            const int k = __builtin_ctzll(mm);
+            mm &= mm - 1ull;
+            P::pair(acc, S, j0 + 32 * w + k, L);
+        }
+    }
+    wave_lds_sync();   // the tile is overwritten next
+}
+
+// The walk of one chunk: the leaf's self task, then the pair tasks of the
+// leaf and of its ancestors; each pair task sweeps the partner's sorted
+// list (small-h part, then large-h part) up to the wave's largest reach
+// along the axis.  Written as one loop over blocks of up to 64 records, so
+// that the tile processing is inlined once.
+template <class P>
+__device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds& S, const typename P::Lane& L,
+                                     typename P::Acc& acc, int leaf, int R, int rep, bool act) {
+    const int lane = threadIdx.x & 63;
+    const Cell C = a.cells[leaf];
+    int sbase = C.first;                 // next record of the self task
+    const int cend = C.first + C.count;
+    int A = leaf;                        // cell whose pair tasks are walked
+    uint32_t e = a.csr_off[A], e1 = a.csr_off[A + 1];
+    // the current pair task and part of the partner's list
+    PairGeo g{};
+    Cell cB{};
+    float L0 = 0.f, tiny = 0.f, ti = 0.f, Tmax = 0.f;
+    uint32_t so = 0;
+    int part = 2, lo = 0, len = 0, base = 0;   // part 2: no task loaded
+    int fill = 0;
+    bool tself = false;   // the current tile holds a self-task block
+    for (;;) {
+        bool done = false;
+        bool self = false;
+        int nuse = 0;
+        uint32_t qq = 0;
+        float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
+        float Sx = 0.f, Sy = 0.f, Sz = 0.f;
+        if (sbase < cend) {
+            nuse = min(64, cend - sbase);
+            qq = (uint32_t)(sbase + lane);
+            if (lane < nuse) pj = a.pos[qq];
+            self = true;
+            sbase += nuse;
+        } else {
+            // the next part with records left
+            while (!(part < 2 && base < len)) {
+                if (part < 1) {
+                    ++part;
+                } else {
+                    while (e >= e1 && A >= 0) {
+                        A = a.cells[A].parent;
+                        if (A >= 0) {
+                            e = a.csr_off[A];
+                            e1 = a.csr_off[A + 1];
+                        }
+                    }
+                    if (A < 0) {
+                        done = true;
+                        break;
+                    }
+                    const Cell cA = a.cells[A];
+                    L0 = (float)a.sets[cA.set].L0;
+                    tiny = 1e-5f * L0;
+                    const uint64_t key = a.csr[e];
+                    ++e;
+                    const int B = (int)((key >> 5) & 0xFFFFFFFFull);
+                    g = pair_geo(cA, (int)(key & 31), L0);
+                    cB = a.cells[B];
+                    so = a.segoff[(int64_t)B * NAXES + g.axis];
+                    ti = (float)g.sign * proj3(g.ddx, g.ddy, g.ddz, L.x.x, L.x.y, L.x.z);
+                    part = 0;
+                }
+                lo = part ? cB.nsmall : 0;
+                len = part ? cB.count - cB.nsmall : cB.nsmall;
+                base = 0;
+                if (len > 0) {
+                    const float cut = P::cut(L, part ? cB.hcur_l : cB.hcur) * g.dn;
+                    const float reach = act ? ti + fmaf(cut, 1.000002f, tiny) : -INFINITY;
+                    Tmax = unif(wmax(reach));
+                }
+            }
+            if (!done) {
+                const int nsrc = min(64, len - base);
+                bool ok = false;
+                if (lane < nsrc) {
+                    const uint32_t q = so + (uint32_t)(lo + (g.sign > 0 ? base + lane : len - 1 - base - lane));
+                    pj = a.segpos[q];
+                    const float tj = (float)g.sign * (proj3(g.ddx, g.ddy, g.ddz, pj.x, pj.y, pj.z) + g.projoff);
+                    ok = tj <= Tmax;
+                    qq = a.segidx[q];
+                }
+                const uint64_t okm = __ballot(ok);
+                // the prefix in sweep order is staged; the sweep ends at its end
+                nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);
+                base = nuse < nsrc ? len : base + 64;
+                Sx = g.Sx;
+                Sy = g.Sy;
+                Sz = g.Sz;
+            }
+        }
+        if (done || fill + nuse > TCAP) {
+            if (fill > 0) process_tile<P>(S, fill, R, rep, L, acc, tself);
+            fill = 0;
+            tself = false;
+        }
+        if (done) break;
+        if (lane < nuse) P::stage(S, fill + lane, qq, pj, Sx, Sy, Sz, a);
+        tself = tself || self;
+        fill += nuse;
     }
 }
+
+// ---------------------------------------------------------------------------
+// Density stage: rho, drho/dh, N_w, dN_w/dh, neighbour count, pair hash
+// ---------------------------------------------------------------------------
+template <bool HASH>
+struct DensP {
+    using Args = DensArgs;
+    struct Lane {
+        float4 x;   // position, mass
+        float h, hinv, hi2;
+    };
+    struct Acc {
+        float sf = 0, sg = 0, sw = 0, sq = 0;   // sums of m f, m (3f + q f'), f, q f'
+        int nn = 0;
+        uint64_t hs = 0;
+    };
+    struct Lds {
+        float4 p[TILE];     // x, y, z (shifted into the target's frame), m
+        uint64_t m[TILE];   // pair-hash terms
+    };
+    static __device__ __forceinline__ float cut(const Lane& L, float) { return L.h; }
+    static __device__ __forceinline__ bool in_range(float r2, float hi2, float) { return r2 < hi2; }
+    static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
+                                                 float Sz, const Args& a) {
+        S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, pj.w);
+        if (HASH) S.m[slot] = a.mix[j];
+    }
+    static __device__ __forceinline__ void pair(Acc& A, const Lds& S, int j, const Lane& L) {
+        const float4 q = S.p[j];
+        const float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
+        const float r = fsqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        const float u = r * L.hinv;
+        // the two pieces of the cubic spline without a branch:
+        // f = 2 (1-u)^3 - 8 max(0, 1/2-u)^3,  f' = -6 (1-u)^2 + 24 max(0, 1/2-u)^2
+        const float t1 = 1.f - u, s1 = fmaxf(0.5f - u, 0.f);
+        const float t2 = t1 * t1, s2 = s1 * s1;
+        const float f = fmaf(2.f * t2, t1, -8.f * s2 * s1);
+        const float df = fmaf(24.f, s2, -6.f * t2);
+        const float g = fmaf(u, df, 3.f * f);
+        A.sf = fmaf(q.w, f, A.sf);
+        A.sg = fmaf(q.w, g, A.sg);
+        A.sw += f;
+        A.sq = fmaf(u, df, A.sq);
+        if (HASH) A.hs += S.m[j];
+    }
+};
 
 template <bool SOLVE, bool HASH>
 __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
-    __shared__ float4 s_p[BLK / 64][TILE];
-    __shared__ uint64_t s_m[BLK / 64][TILE];
+    using P = DensP<HASH>;
+    __shared__ typename P::Lds s_l[BLK / 64];
     __shared__ int s_pick[BLK / 64][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane < TILE - 64) {
-        s_p[w][64 + lane] = make_float4(FAR, FAR, FAR, 0.f);
-        s_m[w][64 + lane] = 0ull;
-    }
+    typename P::Lds& S = s_l[w];
     const int home = blockIdx.x & (NGRP - 1);
     int grp = 0;
     for (;;) {
@@ -314,88 +452,23 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
         const int pick = slot < nact ? s_pick[w][slot] : 0;
         wave_lds_sync();
         const int p = p0 + pick;
-        const bool valid = slot < nact;
-        const bool act = valid;
-        float4 xi = valid ? a.pos[p] : make_float4(0.f, 0.f, 0.f, 0.f);
-        float hi = valid ? a.ph[p] : 1.f;
-        float hi2 = act ? hi * hi : -1.f;
-        float hinv = 1.f / hi;
-        DensAcc acc;
+        const bool act = slot < nact;
+        typename P::Lane L;
+        L.x = act ? a.pos[p] : make_float4(-FAR, -FAR, -FAR, 0.f);
+        L.h = act ? a.ph[p] : 1.f;
+        L.hinv = 1.f / L.h;
+        L.hi2 = act ? L.h * L.h : -1.f;
+        typename P::Acc acc;
+        walk<P>(a, S, L, acc, leaf, R, rep, act);
 
-        // ---- self task of the leaf ---------------------------------------
-        const Cell C = a.cells[leaf];
-        const int cend = C.first + C.count;
-        for (int base = C.first; base < cend; base += 64) {
-            const int nsrc = min(64, cend - base);
-            s_p[w][lane] = lane < nsrc ? a.pos[base + lane] : make_float4(FAR, FAR, FAR, 0.f);
-            if (HASH) s_m[w][lane] = lane < nsrc ? a.mix[base + lane] : 0ull;
-            wave_lds_sync();
-            const int share = (nsrc + R - 1) / R;
-            dens_tile<HASH, true>(acc, s_p[w], s_m[w], rep * share, share, xi, hi2, hinv, p - base);
-            wave_lds_sync();
-        }
-
-        // ---- pair tasks of the leaf and of its ancestors ------------------
-        int A = leaf;
-        while (A >= 0) {
-            const Cell cA = a.cells[A];
-            const float L0 = (float)a.sets[cA.set].L0;
-            const float tiny = 1e-5f * L0;
-            const uint32_t e1 = a.csr_off[A + 1];
-            for (uint32_t e = a.csr_off[A]; e < e1; ++e) {
-                const uint64_t key = a.csr[e];
-                const int B = (int)((key >> 5) & 0xFFFFFFFFull);
-                const PairGeo g = pair_geo(cA, (int)(key & 31), L0);
-                const Cell cB = a.cells[B];
-                const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
-                const float sgn = (float)g.sign;
-                float ti = sgn * proj3(g.ddx, g.ddy, g.ddz, xi.x, xi.y, xi.z);
-                float reach = act ? ti + fmaf(hi * g.dn, 1.000002f, tiny) : -INFINITY;
-                const float Tmax = unif(wmax(reach));
-                // the list has a small-h part [0, nsmall) and a large-h part;
-                // each is ordered by projection and swept on its own
-                for (int part = 0; part < 2; ++part) {
-                    const int lo = part ? cB.nsmall : 0;
-                    const int len = part ? cB.count - cB.nsmall : cB.nsmall;
-                    for (int base = 0; base < len; base += 64) {
-                        const int nsrc = min(64, len - base);
-                        bool ok = false;
-                        float4 rec = make_float4(FAR, FAR, FAR, 0.f);
-                        uint64_t mixj = 0ull;
-                        if (lane < nsrc) {
-                            int qq = lo + (g.sign > 0 ? base + lane : len - 1 - base - lane);
-                            float4 pj = a.segpos[so + qq];
-                            float tj = sgn * (proj3(g.ddx, g.ddy, g.ddz, pj.x, pj.y, pj.z) + g.projoff);
-                            ok = tj <= Tmax;
-                            if (ok) {
-                                rec = make_float4(pj.x + g.Sx, pj.y + g.Sy, pj.z + g.Sz, pj.w);
-                                if (HASH) mixj = a.mix[a.segidx[so + qq]];
-                            }
-                        }
-                        const uint64_t okm = __ballot(ok);
-                        const int nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);   // prefix in sorted order
-                        // entries past the prefix are padding, whatever their test said
-                        if (lane >= nuse) rec = make_float4(FAR, FAR, FAR, 0.f);
-                        s_p[w][lane] = rec;
-                        if (HASH) s_m[w][lane] = mixj;
-                        wave_lds_sync();
-                        const int share = (nuse + R - 1) / R;
-                        dens_tile<HASH, false>(acc, s_p[w], s_m[w], rep * share, share, xi, hi2, hinv, -1);
-                        wave_lds_sync();
-                        if (nuse < nsrc) break;
-                    }
-                }
-            }
-            A = cA.parent;
-        }
-
-        const float sf = comb_f(acc.sf - acc.cf, R), sg = comb_f(acc.sg - acc.cg, R);
-        const float sw = comb_f(acc.sw - acc.cw, R), sq = comb_f(acc.sq - acc.cq, R);
+        const float sf = comb_f(acc.sf, R), sg = comb_f(acc.sg, R);
+        const float sw = comb_f(acc.sw, R), sq = comb_f(acc.sq, R);
         const int nn = comb_i(acc.nn, R);
         const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
         if (act && rep == 0) {
-            float h3 = hi * hi * hi;
-            float mi = xi.w;
+            const float hi = L.h, hinv = L.hinv;
+            const float h3 = hi * hi * hi;
+            const float mi = L.x.w;
             a.rho[p] = C8PI / h3 * (mi + sf);
             a.drho[p] = -C8PI / (h3 * hi) * (3.f * mi + sg);
             a.nw[p] = (32.f / 3.f) * (1.f + sw);
@@ -416,11 +489,8 @@ struct ForceArgs {
     int nchunks;
     int* counter;
     const float4* pos;
-    const float* ph;
     const float4* pv;
-    const float* rho;
-    const float* A;
-    const float* cs;
+    const float4* frec;   // h, A, sound speed, rho
     const uint64_t* mix;
     const uint64_t* csr;
     const uint32_t* csr_off;
@@ -434,18 +504,6 @@ struct ForceArgs {
     int rmax;
 };
 
-struct ForceLane {
-    float4 x;      // position, mass
-    float4 v;      // velocity, rho
-    float h, hinv, K, A, c;
-};
-
-struct ForceAcc {
-    float ax = 0, cax = 0, ay = 0, cay = 0, az = 0, caz = 0, du = 0, cdu = 0, vs = 0, S = 0, cS = 0;
-    int nn = 0;
-    uint64_t hs = 0;
-};
-
 __device__ __forceinline__ float gradF(float q, float h, float rinv) {
     // f'(q)/q of the cubic spline, zero outside the support
     float t = 1.f - q;
@@ -453,96 +511,79 @@ __device__ __forceinline__ float gradF(float q, float h, float rinv) {
     return q < 0.5f ? fmaf(18.f, q, -12.f) : outer;
 }
 
-__device__ __forceinline__ void force_pair(ForceAcc& a, const ForceLane& L, float dx, float dy, float dz,
-                                           float r2, const float4& q, const float4& sh, const float4& sv,
-                                           float cj, uint64_t mixj, float alpha) {
-    float r = fsqrt(r2);
-    float rinv = frcp(r);
-    float ki = L.K * gradF(r * L.hinv, L.h, rinv);
-    float kj = sh.z * gradF(r * sh.y, q.w, rinv);
-    float vdx = L.v.x - sv.x, vdy = L.v.y - sv.y, vdz = L.v.z - sv.z;
-    float vdotx = fmaf(vdx, dx, fmaf(vdy, dy, vdz * dz));
-    float wv = vdotx * rinv;
-    float visc = 0.f;
-    if (wv < 0.f) visc = -alpha * (L.c + cj - 3.f * wv) * wv * frcp(L.v.w + sv.w);
-    float kbar = 0.5f * (ki + kj);
-    float s = fmaf(L.A, ki, fmaf(sh.w, kj, visc * kbar));
-    const float mj = sh.x;
-    float ms = mj * s;
-    neumaier(a.ax, a.cax, -ms * dx);
-    neumaier(a.ay, a.cay, -ms * dy);
-    neumaier(a.az, a.caz, -ms * dz);
-    neumaier(a.du, a.cdu, mj * vdotx * fmaf(L.A, ki, 0.5f * visc * kbar));
-    a.vs = fmaxf(a.vs, L.c + cj - 3.f * fminf(wv, 0.f));
-    kahan(a.S, a.cS, fabsf(ms) * r);
-    a.nn += 1;
-    a.hs += mixj;
-}
-
-// Force tile records: p = (x, y, z, h) for the test, h = (m, 1/h, K, A),
-// v = (vx, vy, vz, rho), c = sound speed.
-struct ForceLds {
-    float4 p[TILE];
-    float4 h[TILE];
-    float4 v[TILE];
-    float c[TILE];
-    uint64_t m[TILE];
+template <bool HASH>
+struct ForceP {
+    using Args = ForceArgs;
+    struct Lane {
+        float4 x;   // position, mass
+        float4 v;   // velocity, rho
+        float h, hinv, K, A, c, hi2, alpha;
+    };
+    struct Acc {
+        float ax = 0, ay = 0, az = 0, du = 0, vs = 0, S = 0;
+        int nn = 0;
+        uint64_t hs = 0;
+    };
+    struct Lds {
+        float4 p[TILE];    // x, y, z (shifted into the target's frame), h
+        float4 h[TILE];    // m, 1/h, K = 8/(pi h^5), A
+        float4 v[TILE];    // vx, vy, vz, rho
+        float c[TILE];     // sound speed
+        uint64_t m[TILE];  // pair-hash terms
+    };
+    static __device__ __forceinline__ float cut(const Lane& L, float hpart) { return fmaxf(L.h, hpart); }
+    static __device__ __forceinline__ bool in_range(float r2, float hi2, float hj) {
+        return r2 < fmaxf(hi2, hj * hj);
+    }
+    static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
+                                                 float Sz, const Args& a) {
+        const float4 fj = a.frec[j];
+        const float hinv = 1.f / fj.x;
+        const float h2 = hinv * hinv;
+        const float4 vj = a.pv[j];
+        S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, fj.x);
+        S.h[slot] = make_float4(pj.w, hinv, C8PI * h2 * h2 * hinv, fj.y);
+        S.v[slot] = make_float4(vj.x, vj.y, vj.z, fj.w);
+        S.c[slot] = fj.z;
+        if (HASH) S.m[slot] = a.mix[j];
+    }
+    static __device__ __forceinline__ void pair(Acc& A, const Lds& S, int j, const Lane& L) {
+        const float4 q = S.p[j];
+        const float4 sh = S.h[j];
+        const float4 sv = S.v[j];
+        const float cj = S.c[j];
+        const float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
+        const float r = fsqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        const float rinv = frcp(r);
+        const float ki = L.K * gradF(r * L.hinv, L.h, rinv);
+        const float kj = sh.z * gradF(r * sh.y, q.w, rinv);
+        const float vdx = L.v.x - sv.x, vdy = L.v.y - sv.y, vdz = L.v.z - sv.z;
+        const float vdotx = fmaf(vdx, dx, fmaf(vdy, dy, vdz * dz));
+        // approaching pairs only (w < 0): with w clamped at 0 the term
+        // vanishes exactly, without a branch
+        const float wn = fminf(vdotx * rinv, 0.f);
+        const float vsig = fmaf(-3.f, wn, L.c + cj);
+        const float visc = -L.alpha * vsig * wn * frcp(L.v.w + sv.w);
+        const float kbar = 0.5f * (ki + kj);
+        const float s = fmaf(L.A, ki, fmaf(sh.w, kj, visc * kbar));
+        const float mj = sh.x;
+        const float ms = mj * s;
+        A.ax = fmaf(-ms, dx, A.ax);
+        A.ay = fmaf(-ms, dy, A.ay);
+        A.az = fmaf(-ms, dz, A.az);
+        A.du = fmaf(mj * vdotx, fmaf(L.A, ki, 0.5f * visc * kbar), A.du);
+        A.vs = fmaxf(A.vs, vsig);
+        A.S = fmaf(fabsf(ms), r, A.S);
+        if (HASH) A.hs += S.m[j];
+    }
 };
-
-template <bool HASH, bool SELF>
-__device__ __forceinline__ void force_tile(ForceAcc& acc, const ForceLds& L_, int j0, int share, const ForceLane& L,
-                                           float hi2, int self_j, float alpha) {
-    uint32_t lo = 0, hi = 0;
-    const int n0 = share < 32 ? share : 32;
-#pragma unroll 4
-    for (int k = 0; k < n0; ++k) {
-        float4 q = L_.p[j0 + k];
-        float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
-        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        bool in = r2 < fmaxf(hi2, q.w * q.w);
-        if (SELF) in = in && (j0 + k != self_j);
-        lo = in ? (lo | (1u << k)) : lo;
-    }
-#pragma unroll 4
-    for (int k = 32; k < share; ++k) {
-        float4 q = L_.p[j0 + k];
-        float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
-        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        bool in = r2 < fmaxf(hi2, q.w * q.w);
-        if (SELF) in = in && (j0 + k != self_j);
-        hi = in ? (hi | (1u << (k - 32))) : hi;
-    }
-    uint64_t mask = ((uint64_t)hi << 32) | lo;
-    while (mask) {
-        int k = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        const int j = j0 + k;
-        float4 q = L_.p[j];
-        float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
-        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        force_pair(acc, L, dx, dy, dz, r2, q, L_.h[j], L_.v[j], L_.c[j], HASH ? L_.m[j] : 0ull, alpha);
-    }
-}
 
 template <bool HASH>
 __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
-    __shared__ ForceLds s_l[BLK / 64];
+    using P = ForceP<HASH>;
+    __shared__ typename P::Lds s_l[BLK / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    ForceLds& S = s_l[w];
-
-    auto stage = [&](int slot, uint32_t j, const float4& pj, float Sx, float Sy, float Sz) {
-        float hj = a.ph[j];
-        float hinv = 1.f / hj;
-        float h2 = hinv * hinv;
-        float4 vj = a.pv[j];
-        S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, hj);
-        S.h[slot] = make_float4(pj.w, hinv, C8PI * h2 * h2 * hinv, a.A[j]);
-        S.v[slot] = make_float4(vj.x, vj.y, vj.z, a.rho[j]);
-        S.c[slot] = a.cs[j];
-        if (HASH) S.m[slot] = a.mix[j];
-    };
-    if (lane < TILE - 64) S.p[64 + lane] = make_float4(FAR, FAR, FAR, 0.f);
-
+    typename P::Lds& S = s_l[w];
     const int home = blockIdx.x & (NGRP - 1);
     int grp = 0;
     for (;;) {
@@ -554,85 +595,28 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
         const int slot = lane & (T - 1), rep = lane / T;
         const int p = p0 + slot;
         const bool act = slot < cnt;
-        ForceLane L;
-        // an idle lane sits far away so no entry is ever in its range
+        typename P::Lane L;
+        // an idle lane sits far away so no record is ever in its range
         L.x = act ? a.pos[p] : make_float4(-FAR, -FAR, -FAR, 0.f);
-        L.h = act ? a.ph[p] : 1.f;
+        const float4 fi = act ? a.frec[p] : make_float4(1.f, 0.f, 0.f, 1.f);
+        L.h = fi.x;
         L.hinv = 1.f / L.h;
         {
-            float h2 = L.hinv * L.hinv;
+            const float h2 = L.hinv * L.hinv;
             L.K = C8PI * h2 * h2 * L.hinv;
         }
-        float4 vv = act ? a.pv[p] : make_float4(0.f, 0.f, 0.f, 0.f);
-        L.v = make_float4(vv.x, vv.y, vv.z, act ? a.rho[p] : 1.f);
-        L.A = act ? a.A[p] : 0.f;
-        L.c = act ? a.cs[p] : 0.f;
-        const float hi2 = act ? L.h * L.h : -1.f;
-        ForceAcc acc;
+        const float4 vv = act ? a.pv[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+        L.v = make_float4(vv.x, vv.y, vv.z, fi.w);
+        L.A = fi.y;
+        L.c = fi.z;
+        L.hi2 = act ? L.h * L.h : -1.f;
+        L.alpha = a.alpha;
+        typename P::Acc acc;
+        walk<P>(a, S, L, acc, leaf, R, rep, act);
 
-        // ---- self task of the leaf ---------------------------------------
-        const Cell C = a.cells[leaf];
-        const int cend = C.first + C.count;
-        for (int base = C.first; base < cend; base += 64) {
-            const int nsrc = min(64, cend - base);
-            if (lane < nsrc) stage(lane, (uint32_t)(base + lane), a.pos[base + lane], 0.f, 0.f, 0.f);
-            else S.p[lane] = make_float4(FAR, FAR, FAR, 0.f);
-            wave_lds_sync();
-            const int share = (nsrc + R - 1) / R;
-            force_tile<HASH, true>(acc, S, rep * share, share, L, hi2, p - base, a.alpha);
-            wave_lds_sync();
-        }
-
-        // ---- pair tasks -----------------------------------------------------
-        int A = leaf;
-        while (A >= 0) {
-            const Cell cA = a.cells[A];
-            const float L0 = (float)a.sets[cA.set].L0;
-            const float tiny = 1e-5f * L0;
-            const uint32_t e1 = a.csr_off[A + 1];
-            for (uint32_t e = a.csr_off[A]; e < e1; ++e) {
-                const uint64_t key = a.csr[e];
-                const int B = (int)((key >> 5) & 0xFFFFFFFFull);
-                const PairGeo g = pair_geo(cA, (int)(key & 31), L0);
-                const Cell cB = a.cells[B];
-                const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
-                const float sgn = (float)g.sign;
-                float ti = sgn * proj3(g.ddx, g.ddy, g.ddz, L.x.x, L.x.y, L.x.z);
-                for (int part = 0; part < 2; ++part) {
-                    const int lo = part ? cB.nsmall : 0;
-                    const int len = part ? cB.count - cB.nsmall : cB.nsmall;
-                    if (len == 0) continue;
-                    // reach: max(h_i, largest h of this part) along the axis
-                    const float cut = fmaxf(L.h, part ? cB.hcur_l : cB.hcur) * g.dn;
-                    float reach = act ? ti + fmaf(cut, 1.000002f, tiny) : -INFINITY;
-                    const float Tmax = unif(wmax(reach));
-                    for (int base = 0; base < len; base += 64) {
-                        const int nsrc = min(64, len - base);
-                        bool ok = false;
-                        if (lane < nsrc) {
-                            int qq = lo + (g.sign > 0 ? base + lane : len - 1 - base - lane);
-                            float4 pj = a.segpos[so + qq];
-                            float tj = sgn * (proj3(g.ddx, g.ddy, g.ddz, pj.x, pj.y, pj.z) + g.projoff);
-                            ok = tj <= Tmax;
-                            if (ok) stage(lane, a.segidx[so + qq], pj, g.Sx, g.Sy, g.Sz);
-                        }
-                        const uint64_t okm = __ballot(ok);
-                        const int nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);
-                        if (lane >= nuse) S.p[lane] = make_float4(FAR, FAR, FAR, 0.f);
-                        wave_lds_sync();
-                        const int share = (nuse + R - 1) / R;
-                        force_tile<HASH, false>(acc, S, rep * share, share, L, hi2, -1, a.alpha);
-                        wave_lds_sync();
-                        if (nuse < nsrc) break;
-                    }
-                }
-            }
-            A = cA.parent;
-        }
-
-        const float ax = comb_f(acc.ax + acc.cax, R), ay = comb_f(acc.ay + acc.cay, R);
-        const float az = comb_f(acc.az + acc.caz, R), du = comb_f(acc.du + acc.cdu, R);
-        const float vs = comb_max(acc.vs, R), Ss = comb_f(acc.S - acc.cS, R);
+        const float ax = comb_f(acc.ax, R), ay = comb_f(acc.ay, R);
+        const float az = comb_f(acc.az, R), du = comb_f(acc.du, R);
+        const float vs = comb_max(acc.vs, R), Ss = comb_f(acc.S, R);
         const int nn = comb_i(acc.nn, R);
         const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
         if (act && rep == 0) {
@@ -829,14 +813,13 @@ __global__ void k_zero_unconv(int32_t* status, int nsets) {
 
 __global__ void k_ghost(int64_t n, const float* __restrict__ ph, const float* __restrict__ rho,
                         const float* __restrict__ drho, const float* __restrict__ u, float gamma,
-                        float* __restrict__ A, float* __restrict__ cs) {
+                        float4* __restrict__ frec) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    float r = rho[p];
-    float P = (gamma - 1.f) * r * u[p];
-    float f = 1.f / (1.f + ph[p] / (3.f * r) * drho[p]);
-    A[p] = f * P / (r * r);
-    cs[p] = sqrtf(gamma * (gamma - 1.f) * u[p]);
+    const float r = rho[p], h = ph[p];
+    const float P = (gamma - 1.f) * r * u[p];
+    const float f = 1.f / (1.f + h / (3.f * r) * drho[p]);
+    frec[p] = make_float4(h, f * P / (r * r), sqrtf(gamma * (gamma - 1.f) * u[p]), r);
 }
 
 // Largest current h of the small-h and of the large-h entries of each
@@ -1002,12 +985,12 @@ static Err ensure_state(sph_tree* t) {
     t->dstep = t->hi + n;
     t->status = (int32_t*)(t->dstep + n);
     t->active = (uint8_t*)(t->status + ((nst + 63) / 64) * 64);
-    // force: A, cs, ax, ay, az, du, vs, S (float), nf (int), hash (u64)
-    ERRTRY(t->alloc(t->b_force, n * (8 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 64, &p));
-    t->hashf = (uint64_t*)p;
-    t->A = (float*)(t->hashf + n);
-    t->cs = t->A + n;
-    t->fax = t->cs + n;
+    // force: frec (float4), ax, ay, az, du, vs, S (float), nf (int), hash (u64)
+    ERRTRY(t->alloc(t->b_force, n * (sizeof(float4) + 6 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 64,
+                    &p));
+    t->frec = (float4*)p;
+    t->hashf = (uint64_t*)(t->frec + n);
+    t->fax = (float*)(t->hashf + n);
     t->fay = t->fax + n;
     t->faz = t->fay + n;
     t->fdu = t->faz + n;
@@ -1112,7 +1095,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     hipStream_t st = ctx->stream;
     const int64_t n = t->n;
     hipLaunchKernelGGL(k_ghost, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->ph, t->rho, t->drho, t->pu,
-                       t->prm.gamma, t->A, t->cs);
+                       t->prm.gamma, t->frec);
     hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph, t->segoff,
                        t->segidx);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
@@ -1124,11 +1107,8 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.nchunks = (int)t->nchunks;
     a.counter = counter;
     a.pos = t->pos;
-    a.ph = t->ph;
     a.pv = t->pv;
-    a.rho = t->rho;
-    a.A = t->A;
-    a.cs = t->cs;
+    a.frec = t->frec;
     a.mix = t->mix;
     a.csr = t->csr;
     a.csr_off = t->csr_off;

@@ -85,7 +85,7 @@ struct SetInfo {
     int32_t lgG;       // log2 of top cells per side
     int32_t top_base;  // id of the first top cell of this set
     int32_t key_shift; // left shift that aligns this set's Morton code in the key
-    int32_t pad;
+    int32_t depth;     // levels below the top grid the keys resolve for this set
 };
 
 // One cell of the hierarchy (all levels and sets in one table).  Cells of a

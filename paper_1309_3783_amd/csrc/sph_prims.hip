@@ -188,15 +188,16 @@ size_t radix_tmp_words(int64_t n) {
 }
 
 hipError_t radix_sort(uint64_t* key, uint32_t* val, uint64_t* key_alt, uint32_t* val_alt, int64_t n,
-                      int nbits, uint32_t* tmp, hipStream_t st, bool* result_in_alt) {
+                      int nbits, uint32_t* tmp, hipStream_t st, bool* result_in_alt, int lo_bit) {
     *result_in_alt = false;
     if (n <= 1 || nbits <= 0) return hipSuccess;
+    if (lo_bit < 0 || lo_bit + nbits > 64) return hipErrorInvalidValue;
     int64_t nb = (n + RS_TILE - 1) / RS_TILE;
     uint32_t* hist = tmp;
     uint32_t* stmp = tmp + 256 * nb;
     uint64_t *ka = key, *kb = key_alt;
     uint32_t *va = val, *vb = val_alt;
-    for (int shift = 0; shift < nbits; shift += 8) {
+    for (int shift = lo_bit; shift < lo_bit + nbits; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_BS), 0, st, ka, n, shift, hist, nb);
         hipError_t e = exclusive_scan(hist, hist, 256 * nb, stmp, nullptr, st);
         if (e != hipSuccess) return e;
