@@ -599,42 +599,65 @@ __device__ inline uint64_t seg_key(float proj, int cls, uint32_t e) {
     return ((uint64_t)cls << 63) | ((uint64_t)(f2ord(proj) >> 1) << 32) | e;
 }
 
-// Segments of at most 64 entries: one wavefront each, bitonic sort of
-// (ordered projection << 32 | local index) in registers with lane shuffles.
+// Segments of at most 64 entries, taken two at a time by one wavefront:
+// when both fit in 64 lanes they are sorted side by side, else one after
+// the other.  Each lane holds one entry, key (class, ordered projection,
+// local index) -- unique within a segment -- and counts the keys of its
+// segment below its own: that count is its place in the sorted list.  The
+// keys are read back from LDS as broadcasts, so a segment of n entries
+// costs n steps.
 __global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restrict__ list,
                                                        const uint32_t* __restrict__ off, int64_t ns,
                                                        const SetInfo* sets, const Cell* __restrict__ cells,
                                                        const float4* __restrict__ pos, const float* __restrict__ ph,
                                                        float4* __restrict__ sproj, uint32_t* __restrict__ sidx) {
-    const int lane = threadIdx.x & 63;
-    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < ns; q += (int64_t)gridDim.x * 4) {
-        uint32_t ca = list[q];
-        const Cell C = cells[ca / NAXES];
-        const int n = C.count;
-        if (n > 64) continue;
-        const int ax = (int)(ca % NAXES);
-        const float lim = small_h_limit(sets, C);
-        uint64_t k = ~0ull;
-        if (lane < n)
-            k = seg_key(project(pos[C.first + lane], ax), ph[C.first + lane] > lim ? 1 : 0, (uint32_t)lane);
-        for (int size = 2; size <= 64; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                uint32_t lo = __shfl_xor((uint32_t)k, stride, 64);
-                uint32_t hi = __shfl_xor((uint32_t)(k >> 32), stride, 64);
-                uint64_t o = ((uint64_t)hi << 32) | lo;
-                bool up = (lane & size) == 0;
-                bool lower = (lane & stride) == 0;
-                // the lower lane of a pair keeps the min when sorting up
-                bool keep_min = (lower == up);
-                uint64_t mn = k < o ? k : o, mx = k < o ? o : k;
-                k = keep_min ? mn : mx;
+    __shared__ uint64_t s_key[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t npair = (ns + 1) / 2;
+    for (int64_t g = (int64_t)blockIdx.x * 4 + w; g < npair; g += (int64_t)gridDim.x * 4) {
+        const int64_t qa = 2 * g, qb = 2 * g + 1;
+        const uint32_t ca = list[qa];
+        const uint32_t cb = qb < ns ? list[qb] : ca;
+        const Cell Ca = cells[ca / NAXES];
+        const Cell Cb = cells[cb / NAXES];
+        // longer segments are sorted by the LDS and global paths
+        const int na = Ca.count <= 64 ? Ca.count : 0;
+        const int nb = (qb < ns && Cb.count <= 64) ? Cb.count : 0;
+        const bool packed = na + nb <= 64;
+        for (int pass = 0; pass < (packed ? 1 : 2); ++pass) {
+            // this lane's segment (0: a, 1: b, -1: none), its first lane and length
+            int seg = -1, first = 0, len = 0;
+            if (packed) {
+                if (lane < na) { seg = 0; first = 0; len = na; }
+                else if (lane < na + nb) { seg = 1; first = na; len = nb; }
+            } else if (lane < (pass ? nb : na)) {
+                seg = pass;
+                len = pass ? nb : na;
             }
-        }
-        if (lane < n) {
-            uint32_t o = off[q];
-            uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
-            sproj[o + lane] = pos[j];
-            sidx[o + lane] = j;
+            const Cell& C = seg == 1 ? Cb : Ca;
+            const int ax = (int)((seg == 1 ? cb : ca) % NAXES);
+            const int e = lane - first;
+            uint64_t k = ~0ull;
+            float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (seg >= 0) {
+                rec = pos[C.first + e];
+                const float lim = small_h_limit(sets, C);
+                k = seg_key(project(rec, ax), ph[C.first + e] > lim ? 1 : 0, (uint32_t)e);
+            }
+            s_key[w][lane] = k;
+            wave_lds_sync();
+            const int nloop = packed ? max(na, nb) : (pass ? nb : na);
+            int rank = 0;
+            for (int t = 0; t < nloop; ++t) {
+                const uint64_t kt = s_key[w][first + min(t, max(len - 1, 0))];
+                rank += (t < len && kt < k) ? 1 : 0;
+            }
+            if (seg >= 0) {
+                const uint32_t o = off[seg == 1 ? qb : qa];
+                sproj[o + rank] = rec;
+                sidx[o + rank] = (uint32_t)(C.first + e);
+            }
+            wave_lds_sync();
         }
     }
 }
@@ -1112,7 +1135,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
         ERRTRY(t->alloc(t->b_segproj, sizeof(float4) * std::max<int64_t>(nent, 1), (void**)&t->segpos));
         ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
         hipLaunchKernelGGL(k_cell_nsmall, dim3(nblk(nc, 4)), dim3(256), 0, st, t->d_sets, t->cells, nc, t->ph);
-        hipLaunchKernelGGL(k_seg_sort_wave, dim3((unsigned)std::min<int64_t>((ns + 3) / 4, 8192)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_seg_sort_wave, dim3((unsigned)std::min<int64_t>((ns + 7) / 8, 8192)), dim3(256), 0, st,
                            t->seglist, soff, (int64_t)ns, t->d_sets, t->cells, t->pos, t->ph, t->segpos,
                            t->segidx);
         HIPTRY(hipGetLastError());

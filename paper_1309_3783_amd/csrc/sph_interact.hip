@@ -27,12 +27,6 @@ namespace sph {
 constexpr float C8PI = 2.5464790894703255f;   // 8/pi: cubic-spline normalisation in 3-D
 constexpr int BLK = 256;                      // 4 wavefronts per block, each independent
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 // Hardware square root and reciprocal (1 ulp): the arguments here are
 // normal numbers (r^2 >= 2^-48 for distinct particles), and 1-ulp results

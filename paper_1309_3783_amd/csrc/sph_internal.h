@@ -19,6 +19,14 @@ constexpr int SEG_LDS_MAX = 4096;     // largest (cell, axis) list sorted in LDS
 constexpr int CHUNK = 64;             // target particles per work item (one wave)
 constexpr int SMALL_H_DIV = 8;        // sorted lists split at h = cell edge / 8
 
+// Orders a wavefront's LDS writes before its later LDS reads (the wave runs
+// in lockstep; the fences keep the compiler from reordering across it).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------------
 // Cell-pair axes (Section II-C: 13 possible axes).  Offsets o in {-1,0,1}^3
 // are coded as (ox+1)*9 + (oy+1)*3 + (oz+1); code 13 is the zero offset.

@@ -96,12 +96,90 @@ __global__ __launch_bounds__(SCAN_BS) void k_scan_apply(const uint32_t* __restri
     }
 }
 
+// Inputs up to SCAN_SMALL elements: one block stages them in LDS with
+// coalesced loads, each thread scans a contiguous run of SCAN_SMALL / 1024,
+// and the results go back coalesced (one launch instead of three).
+constexpr int64_t SCAN_SMALL = 8192;
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_t* out, int64_t n,
+                                                     uint32_t* __restrict__ total) {
+    __shared__ uint32_t s_v[SCAN_SMALL];
+    __shared__ uint32_t s_w[16];
+    for (int64_t i = threadIdx.x; i < n; i += 1024) s_v[i] = in[i];
+    __syncthreads();
+    constexpr int PER = (int)(SCAN_SMALL / 1024);
+    const int base = (int)threadIdx.x * PER;
+    uint32_t v[PER];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = base + k < n ? s_v[base + k] : 0u;
+        acc += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(acc, s_w, tot);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (base + k < n) s_v[base + k] = ex;
+        ex += v[k];
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += 1024) out[i] = s_v[i];
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
+// Up to SCAN_MID_BLOCKS tiles: the apply step sums the partial sums of the
+// tiles before its own (two launches instead of three).
+constexpr int64_t SCAN_MID_BLOCKS = 1024;
+__global__ __launch_bounds__(SCAN_BS) void k_scan_apply_mid(const uint32_t* __restrict__ in,
+                                                            uint32_t* __restrict__ out, int64_t n,
+                                                            const uint32_t* __restrict__ bsum, int64_t nb,
+                                                            uint32_t* __restrict__ total) {
+    __shared__ uint32_t s_w[SCAN_BS / 64];
+    // offset of this tile: sum of the partial sums of the tiles before it
+    uint32_t pre = 0, all = 0;
+    for (int64_t k = threadIdx.x; k < nb; k += SCAN_BS) {
+        const uint32_t x = bsum[k];
+        if (k < (int64_t)blockIdx.x) pre += x;
+        all += x;
+    }
+    uint32_t tp, ta;
+    block_excl_scan(pre, s_w, tp);
+    block_excl_scan(all, s_w, ta);
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0 && total) *total = ta;
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    uint32_t v[SCAN_IPT];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        acc += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(acc, s_w, tot) + tp;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+}
+
 size_t scan_tmp_words(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
 
 hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint32_t* total,
                           hipStream_t st) {
     if (n <= 0) return total ? fill_u32(total, 1, 0, st) : hipSuccess;
+    if (n <= SCAN_SMALL) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, in, out, n, total);
+        return hipGetLastError();
+    }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb <= SCAN_MID_BLOCKS) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BS), 0, st, in, n, tmp);
+        hipLaunchKernelGGL(k_scan_apply_mid, dim3((unsigned)nb), dim3(SCAN_BS), 0, st, in, out, n, tmp, nb, total);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BS), 0, st, in, n, tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tmp, nb, total);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BS), 0, st, in, out, n, tmp);
