@@ -78,6 +78,26 @@ __device__ __forceinline__ float wmax(float v) {
     return v;
 }
 
+// Largest value over the 64 lanes, returned on every lane: DPP row shifts
+// and row broadcasts (no LDS round trips), on floats mapped to integers that
+// order like them.
+__device__ __forceinline__ int f2key(float v) {
+    const int b = __float_as_int(v);
+    return b ^ ((b >> 31) & 0x7FFFFFFF);
+}
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    constexpr int ID = (int)0x80000000;
+    int x = f2key(v);
+    x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x111, 0xF, 0xF, false));   // row_shr:1
+    x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x112, 0xF, 0xF, false));   // row_shr:2
+    x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x114, 0xF, 0xF, false));   // row_shr:4
+    x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x118, 0xF, 0xF, false));   // row_shr:8
+    x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    x = max(x, __builtin_amdgcn_update_dpp(ID, x, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    const int m = __builtin_amdgcn_readlane(x, 63);
+    return __int_as_float(m ^ ((m >> 31) & 0x7FFFFFFF));
+}
+
 // Offset code tables: axis index and sign of each of the 27 offset codes,
 // and the components of the 13 canonical directions.
 struct AxisTab {
@@ -116,22 +136,28 @@ struct PairGeo {
     int axis, sign;
 };
 
+// Canonical axis (0..12) of the offset codes 14..26, 4 bits each; code c and
+// 26 - c share an axis, with opposite signs (codes below 13 have the sign -1).
+constexpr uint64_t AXIS_OF_CODE = 0x93a506b4c7182ull;
+
 __device__ __forceinline__ PairGeo pair_geo(const Cell& cA, int code, float L0) {
     PairGeo g;
-    int ox = ocx(code), oy = ocy(code), oz = ocz(code);
-    int l = cA.level;
-    int tx = ((cA.ix + ox) >> l) - (cA.ix >> l);
-    int ty = ((cA.iy + oy) >> l) - (cA.iy >> l);
-    int tz = ((cA.iz + oz) >> l) - (cA.iz >> l);
+    const int ox = ocx(code), oy = ocy(code), oz = ocz(code);
+    const int l = cA.level;
+    const int tx = ((cA.ix + ox) >> l) - (cA.ix >> l);
+    const int ty = ((cA.iy + oy) >> l) - (cA.iy >> l);
+    const int tz = ((cA.iz + oz) >> l) - (cA.iz >> l);
     g.Sx = (float)tx * L0;
     g.Sy = (float)ty * L0;
     g.Sz = (float)tz * L0;
-    g.axis = c_ax.axis[code];
-    g.sign = c_ax.sign[code];
-    g.ddx = (float)c_ax.dx[g.axis];
-    g.ddy = (float)c_ax.dy[g.axis];
-    g.ddz = (float)c_ax.dz[g.axis];
-    g.dn = c_ax.norm[g.axis];
+    g.sign = code >= 13 ? 1 : -1;
+    const int c2 = code >= 13 ? code : 26 - code;
+    g.axis = (int)((AXIS_OF_CODE >> (4 * (c2 - 14))) & 15u);
+    g.ddx = (float)(g.sign * ox);
+    g.ddy = (float)(g.sign * oy);
+    g.ddz = (float)(g.sign * oz);
+    const int nz = abs(ox) + abs(oy) + abs(oz);
+    g.dn = nz == 1 ? 1.f : (nz == 2 ? 1.41421356f : 1.73205081f);
     float po = g.ddx * g.Sx;
     po = po + g.ddy * g.Sy;
     po = po + g.ddz * g.Sz;
@@ -269,8 +295,9 @@ __device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, i
 
 // The walk of one chunk: the leaf's self task, then the pair tasks of the
 // leaf and of its ancestors; each pair task sweeps the partner's sorted
-// list (small-h part, then large-h part) up to the wave's largest reach
-// along the axis.  Written as one loop over blocks of up to 64 records, so
+// list (small-h part, then large-h part) up to the largest reach of the
+// chunk along the axis, bounded by the bounding box of its particles plus
+// the largest cutoff.  Written as one loop over blocks of up to 64 records, so
 // that the tile processing is inlined once.
 template <class P>
 __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds& S, const typename P::Lane& L,
@@ -281,10 +308,16 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
     const int cend = C.first + C.count;
     int A = leaf;                        // cell whose pair tasks are walked
     uint32_t e = a.csr_off[A], e1 = a.csr_off[A + 1];
+    // bounding box and largest h of the lanes' particles: a pair task's
+    // sweep reaches at most (largest projection over the box) + cutoff
+    const float bxmax = wave_max_dpp(act ? L.x.x : -INFINITY), bxmin = -wave_max_dpp(act ? -L.x.x : -INFINITY);
+    const float bymax = wave_max_dpp(act ? L.x.y : -INFINITY), bymin = -wave_max_dpp(act ? -L.x.y : -INFINITY);
+    const float bzmax = wave_max_dpp(act ? L.x.z : -INFINITY), bzmin = -wave_max_dpp(act ? -L.x.z : -INFINITY);
+    const float hmax = wave_max_dpp(act ? L.h : 0.f);
     // the current pair task and part of the partner's list
     PairGeo g{};
     Cell cB{};
-    float L0 = 0.f, tiny = 0.f, ti = 0.f, Tmax = 0.f;
+    float L0 = 0.f, tiny = 0.f, tmax = 0.f, Tmax = 0.f;
     uint32_t so = 0;
     int part = 2, lo = 0, len = 0, base = 0;   // part 2: no task loaded
     int fill = 0;
@@ -325,19 +358,23 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
                     const uint64_t key = a.csr[e];
                     ++e;
                     const int B = (int)((key >> 5) & 0xFFFFFFFFull);
-                    g = pair_geo(cA, (int)(key & 31), L0);
+                    const int code = (int)(key & 31);
+                    g = pair_geo(cA, code, L0);
                     cB = a.cells[B];
                     so = a.segoff[(int64_t)B * NAXES + g.axis];
-                    ti = (float)g.sign * proj3(g.ddx, g.ddy, g.ddz, L.x.x, L.x.y, L.x.z);
+                    // largest sign * (d . x) over the box: d . x signed is the
+                    // offset direction o . x
+                    const int ox = ocx(code), oy = ocy(code), oz = ocz(code);
+                    tmax = (ox > 0 ? bxmax : (ox < 0 ? -bxmin : 0.f)) + (oy > 0 ? bymax : (oy < 0 ? -bymin : 0.f)) +
+                           (oz > 0 ? bzmax : (oz < 0 ? -bzmin : 0.f));
                     part = 0;
                 }
                 lo = part ? cB.nsmall : 0;
                 len = part ? cB.count - cB.nsmall : cB.nsmall;
                 base = 0;
                 if (len > 0) {
-                    const float cut = P::cut(L, part ? cB.hcur_l : cB.hcur) * g.dn;
-                    const float reach = act ? ti + fmaf(cut, 1.000002f, tiny) : -INFINITY;
-                    Tmax = unif(wmax(reach));
+                    const float cut = P::cut(hmax, part ? cB.hcur_l : cB.hcur) * g.dn;
+                    Tmax = tmax + fmaf(cut, 1.000002f, tiny);
                 }
             }
             if (!done) {
@@ -390,7 +427,7 @@ struct DensP {
         float4 p[TILE];     // x, y, z (shifted into the target's frame), m
         uint64_t m[TILE];   // pair-hash terms
     };
-    static __device__ __forceinline__ float cut(const Lane& L, float) { return L.h; }
+    static __device__ __forceinline__ float cut(float hmax, float) { return hmax; }
     static __device__ __forceinline__ bool in_range(float r2, float hi2, float) { return r2 < hi2; }
     static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
                                                  float Sz, const Args& a) {
@@ -525,7 +562,7 @@ struct ForceP {
         float c[TILE];     // sound speed
         uint64_t m[TILE];  // pair-hash terms
     };
-    static __device__ __forceinline__ float cut(const Lane& L, float hpart) { return fmaxf(L.h, hpart); }
+    static __device__ __forceinline__ float cut(float hmax, float hpart) { return fmaxf(hmax, hpart); }
     static __device__ __forceinline__ bool in_range(float r2, float hi2, float hj) {
         return r2 < fmaxf(hi2, hj * hj);
     }
