@@ -293,38 +293,85 @@ __device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, i
     wave_lds_sync();   // the tile is overwritten next
 }
 
+// Sweep descriptors of the pair tasks being walked: for up to DBATCH
+// interaction-list entries of one cell at a time, built with one entry per
+// lane (all the loads and the geometry of the batch in one round instead of
+// a chain of dependent loads and uniform float arithmetic per entry), two
+// descriptors per entry (small-h and large-h part of the partner's list):
+//   q: first list position, length, sweep direction (+1/-1), offset code;
+//   f: shift S added to the partner's positions, and the sweep limit -- the
+//      largest o.y that a point y within the cutoff of a particle of the
+//      chunk can have, o the offset direction of the pair (a record is a
+//      candidate while o.(p + S) stays below it).
+constexpr int DBATCH = 32;
+struct SweepTab {
+    int4 q[2 * DBATCH];
+    float4 f[2 * DBATCH];
+};
+
+// Builds the descriptors of entries [e0, e0 + n) of cell cA (n <= DBATCH).
+// box: largest o_k x_k over the chunk's particles per axis and sign
+// (bx[0..2] = max x, bx[3..5] = -min x); hmax: largest h of the chunk.
+template <class P>
+__device__ __forceinline__ void build_sweeps(const typename P::Args& a, const Cell& cA, float L0, uint32_t e0, int n,
+                                             const float (&bx)[6], float hmax, SweepTab& T) {
+    const int lane = threadIdx.x & 63;
+    if (lane < n) {
+        const uint64_t key = a.csr[e0 + lane];
+        const int B = (int)((key >> 5) & 0xFFFFFFFFull);
+        const int code = (int)(key & 31);
+        const PairGeo g = pair_geo(cA, code, L0);
+        const Cell cB = a.cells[B];
+        const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
+        const int ox = ocx(code), oy = ocy(code), oz = ocz(code);
+        // largest o . x over the box (x and the shifted records share the
+        // target's frame), plus the cutoff along the axis
+        const float tb = (ox > 0 ? bx[0] : (ox < 0 ? bx[3] : 0.f)) + (oy > 0 ? bx[1] : (oy < 0 ? bx[4] : 0.f)) +
+                         (oz > 0 ? bx[2] : (oz < 0 ? bx[5] : 0.f));
+        const float tiny = 1e-5f * L0;
+        const float t0 = tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny);
+        const float t1 = tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny);
+        T.q[2 * lane] = make_int4((int)so, cB.nsmall, g.sign, code);
+        T.q[2 * lane + 1] = make_int4((int)so + cB.nsmall, cB.count - cB.nsmall, g.sign, code);
+        T.f[2 * lane] = make_float4(g.Sx, g.Sy, g.Sz, t0);
+        T.f[2 * lane + 1] = make_float4(g.Sx, g.Sy, g.Sz, t1);
+    }
+    wave_lds_sync();
+}
+
 // The walk of one chunk: the leaf's self task, then the pair tasks of the
 // leaf and of its ancestors; each pair task sweeps the partner's sorted
 // list (small-h part, then large-h part) up to the largest reach of the
-// chunk along the axis, bounded by the bounding box of its particles plus
-// the largest cutoff.  Written as one loop over blocks of up to 64 records, so
-// that the tile processing is inlined once.
+// chunk along the pair axis, bounded by the bounding box of its particles
+// plus the largest cutoff.  Written as one loop over blocks of up to 64
+// records, so that the tile processing is inlined once.
 template <class P>
-__device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds& S, const typename P::Lane& L,
-                                     typename P::Acc& acc, int leaf, int R, int rep, bool act) {
+__device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds& S, SweepTab& T,
+                                     const typename P::Lane& L, typename P::Acc& acc, int leaf, int R, int rep,
+                                     bool act) {
     const int lane = threadIdx.x & 63;
     const Cell C = a.cells[leaf];
     int sbase = C.first;                 // next record of the self task
     const int cend = C.first + C.count;
-    int A = leaf;                        // cell whose pair tasks are walked
-    uint32_t e = a.csr_off[A], e1 = a.csr_off[A + 1];
-    // bounding box and largest h of the lanes' particles: a pair task's
-    // sweep reaches at most (largest projection over the box) + cutoff
-    const float bxmax = wave_max_dpp(act ? L.x.x : -INFINITY), bxmin = -wave_max_dpp(act ? -L.x.x : -INFINITY);
-    const float bymax = wave_max_dpp(act ? L.x.y : -INFINITY), bymin = -wave_max_dpp(act ? -L.x.y : -INFINITY);
-    const float bzmax = wave_max_dpp(act ? L.x.z : -INFINITY), bzmin = -wave_max_dpp(act ? -L.x.z : -INFINITY);
+    // bounding box and largest h of the lanes' particles
+    float bx[6];
+    bx[0] = wave_max_dpp(act ? L.x.x : -INFINITY);
+    bx[1] = wave_max_dpp(act ? L.x.y : -INFINITY);
+    bx[2] = wave_max_dpp(act ? L.x.z : -INFINITY);
+    bx[3] = wave_max_dpp(act ? -L.x.x : -INFINITY);
+    bx[4] = wave_max_dpp(act ? -L.x.y : -INFINITY);
+    bx[5] = wave_max_dpp(act ? -L.x.z : -INFINITY);
     const float hmax = wave_max_dpp(act ? L.h : 0.f);
-    // the current pair task and part of the partner's list
-    PairGeo g{};
-    Cell cB{};
-    float L0 = 0.f, tiny = 0.f, tmax = 0.f, Tmax = 0.f;
-    uint32_t so = 0;
-    int part = 2, lo = 0, len = 0, base = 0;   // part 2: no task loaded
+    // the cell whose pair tasks are walked and its entries still to load
+    int A = leaf;
+    Cell cA = C;
+    float L0 = (float)a.sets[C.set].L0;
+    uint32_t e = a.csr_off[A], e1 = a.csr_off[A + 1];
+    int nd = 0, di = 0, base = 0;        // descriptors loaded, current one, position in it
     int fill = 0;
     bool tself = false;   // the current tile holds a self-task block
     for (;;) {
-        bool done = false;
-        bool self = false;
+        bool done = false, self = false;
         int nuse = 0;
         uint32_t qq = 0;
         float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -336,64 +383,58 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
             self = true;
             sbase += nuse;
         } else {
-            // the next part with records left
-            while (!(part < 2 && base < len)) {
-                if (part < 1) {
-                    ++part;
-                } else {
-                    while (e >= e1 && A >= 0) {
-                        A = a.cells[A].parent;
-                        if (A >= 0) {
-                            e = a.csr_off[A];
-                            e1 = a.csr_off[A + 1];
-                        }
-                    }
-                    if (A < 0) {
-                        done = true;
-                        break;
-                    }
-                    const Cell cA = a.cells[A];
-                    L0 = (float)a.sets[cA.set].L0;
-                    tiny = 1e-5f * L0;
-                    const uint64_t key = a.csr[e];
-                    ++e;
-                    const int B = (int)((key >> 5) & 0xFFFFFFFFull);
-                    const int code = (int)(key & 31);
-                    g = pair_geo(cA, code, L0);
-                    cB = a.cells[B];
-                    so = a.segoff[(int64_t)B * NAXES + g.axis];
-                    // largest sign * (d . x) over the box: d . x signed is the
-                    // offset direction o . x
-                    const int ox = ocx(code), oy = ocy(code), oz = ocz(code);
-                    tmax = (ox > 0 ? bxmax : (ox < 0 ? -bxmin : 0.f)) + (oy > 0 ? bymax : (oy < 0 ? -bymin : 0.f)) +
-                           (oz > 0 ? bzmax : (oz < 0 ? -bzmin : 0.f));
-                    part = 0;
+            int4 dq = make_int4(0, 0, 0, 0);
+            for (;;) {
+                if (di < nd) {
+                    dq = T.q[di];
+                    dq = make_int4(uni(dq.x), uni(dq.y), uni(dq.z), uni(dq.w));
+                    if (base < dq.y) break;
+                    ++di;
+                    base = 0;
+                    continue;
                 }
-                lo = part ? cB.nsmall : 0;
-                len = part ? cB.count - cB.nsmall : cB.nsmall;
+                // next batch of entries: of this cell, or of its ancestors
+                while (e >= e1 && A >= 0) {
+                    A = cA.parent;
+                    if (A >= 0) {
+                        cA = a.cells[A];
+                        L0 = (float)a.sets[cA.set].L0;
+                        e = a.csr_off[A];
+                        e1 = a.csr_off[A + 1];
+                    }
+                }
+                if (A < 0) {
+                    done = true;
+                    break;
+                }
+                const int n = (int)min(e1 - e, (uint32_t)DBATCH);
+                build_sweeps<P>(a, cA, L0, e, n, bx, hmax, T);
+                e += n;
+                nd = 2 * n;
+                di = 0;
                 base = 0;
-                if (len > 0) {
-                    const float cut = P::cut(hmax, part ? cB.hcur_l : cB.hcur) * g.dn;
-                    Tmax = tmax + fmaf(cut, 1.000002f, tiny);
-                }
             }
             if (!done) {
+                const float4 df = T.f[di];
+                Sx = unif(df.x);
+                Sy = unif(df.y);
+                Sz = unif(df.z);
+                const float tlim = unif(df.w);
+                const int len = dq.y;
                 const int nsrc = min(64, len - base);
+                const float fox = (float)ocx(dq.w), foy = (float)ocy(dq.w), foz = (float)ocz(dq.w);
                 bool ok = false;
                 if (lane < nsrc) {
-                    const uint32_t q = so + (uint32_t)(lo + (g.sign > 0 ? base + lane : len - 1 - base - lane));
+                    const uint32_t q = (uint32_t)dq.x + (uint32_t)(dq.z > 0 ? base + lane : len - 1 - base - lane);
                     pj = a.segpos[q];
-                    const float tj = (float)g.sign * (proj3(g.ddx, g.ddy, g.ddz, pj.x, pj.y, pj.z) + g.projoff);
-                    ok = tj <= Tmax;
+                    const float t = fmaf(fox, pj.x + Sx, fmaf(foy, pj.y + Sy, foz * (pj.z + Sz)));
+                    ok = t <= tlim;
                     qq = a.segidx[q];
                 }
                 const uint64_t okm = __ballot(ok);
                 // the prefix in sweep order is staged; the sweep ends at its end
                 nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);
                 base = nuse < nsrc ? len : base + 64;
-                Sx = g.Sx;
-                Sy = g.Sy;
-                Sz = g.Sz;
             }
         }
         if (done || fill + nuse > TCAP) {
@@ -458,6 +499,7 @@ template <bool SOLVE, bool HASH>
 __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
     using P = DensP<HASH>;
     __shared__ typename P::Lds s_l[BLK / 64];
+    __shared__ SweepTab s_t[BLK / 64];
     __shared__ int s_pick[BLK / 64][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     typename P::Lds& S = s_l[w];
@@ -490,7 +532,7 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
         L.hinv = 1.f / L.h;
         L.hi2 = act ? L.h * L.h : -1.f;
         typename P::Acc acc;
-        walk<P>(a, S, L, acc, leaf, R, rep, act);
+        walk<P>(a, S, s_t[w], L, acc, leaf, R, rep, act);
 
         const float sf = comb_f(acc.sf, R), sg = comb_f(acc.sg, R);
         const float sw = comb_f(acc.sw, R), sq = comb_f(acc.sq, R);
@@ -613,6 +655,7 @@ template <bool HASH>
 __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
     using P = ForceP<HASH>;
     __shared__ typename P::Lds s_l[BLK / 64];
+    __shared__ SweepTab s_t[BLK / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     typename P::Lds& S = s_l[w];
     const int home = blockIdx.x & (NGRP - 1);
@@ -643,7 +686,7 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
         L.hi2 = act ? L.h * L.h : -1.f;
         L.alpha = a.alpha;
         typename P::Acc acc;
-        walk<P>(a, S, L, acc, leaf, R, rep, act);
+        walk<P>(a, S, s_t[w], L, acc, leaf, R, rep, act);
 
         const float ax = comb_f(acc.ax, R), ay = comb_f(acc.ay, R);
         const float az = comb_f(acc.az, R), du = comb_f(acc.du, R);
