@@ -69,7 +69,7 @@ struct sph_tree {
     float *lo = nullptr, *hi = nullptr, *dstep = nullptr;
     int32_t* status = nullptr;   // [0] rebuild flag, [1] unconverged count
     // ghost + force state (cell order)
-    float4* frec = nullptr;   // per particle after the ghost step: h, A, sound speed, rho
+    float4* frec = nullptr;   // per particle after the ghost step: h, A, sound speed, 8/(pi h^5)
     float *fax = nullptr, *fay = nullptr, *faz = nullptr, *fdu = nullptr, *fvs = nullptr, *fS = nullptr;
     int32_t* fn = nullptr;
     uint64_t* hashf = nullptr;

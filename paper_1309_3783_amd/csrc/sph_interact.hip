@@ -197,9 +197,11 @@ struct DensArgs {
 // Lanes per target particle: small chunks spread each particle over 2 to 16
 // lanes, each taking a contiguous share of every staged tile; the shares are
 // combined in a fixed order at the end.
-__device__ __forceinline__ int replicas(int cnt, int rmax) {
-    int r = cnt <= 4 ? 16 : (cnt <= 8 ? 8 : (cnt <= 16 ? 4 : (cnt <= 32 ? 2 : 1)));
-    return r < rmax ? r : rmax;
+// (log2 of the count; rmax is a power of two)
+__device__ __forceinline__ int replicas_lg(int cnt, int rmax) {
+    const int lg = cnt <= 4 ? 4 : (cnt <= 8 ? 3 : (cnt <= 16 ? 2 : (cnt <= 32 ? 1 : 0)));
+    const int lgmax = 31 - __builtin_clz(rmax);
+    return lg < lgmax ? lg : lgmax;
 }
 
 // Combine the partial sums of the replicas of one particle (lanes that
@@ -273,7 +275,7 @@ __device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, i
     // far-away padding: every share has the same length (R * share - n < 16)
     if (lane < TILE - TCAP) S.p[n + lane] = make_float4(FAR, FAR, FAR, 0.f);
     wave_lds_sync();
-    const int share = (n + R - 1) / R;
+    const int share = (n + R - 1) >> (31 - __builtin_clz(R));
     const int j0 = rep * share;
     uint32_t m[NWORD];
     if (self) tile_test<P, true>(S.p, j0, share, L.x, L.hi2, m);
@@ -517,8 +519,8 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
         if (SOLVE) amask = __ballot(lane < cnt && a.active[p0 + lane] == 1);
         if (amask == 0) continue;
         const int nact = __popcll(amask);
-        const int R = replicas(nact, a.rmax), T = 64 / R;
-        const int slot = lane & (T - 1), rep = lane / T;
+        const int lgR = replicas_lg(nact, a.rmax), R = 1 << lgR, T = 64 >> lgR;
+        const int slot = lane & (T - 1), rep = lane >> (6 - lgR);
         // slot -> particle: the slot-th set bit of amask
         if ((amask >> lane) & 1ull) s_pick[w][__popcll(amask & ((1ull << lane) - 1ull))] = lane;
         wave_lds_sync();
@@ -563,7 +565,7 @@ struct ForceArgs {
     int* counter;
     const float4* pos;
     const float4* pv;
-    const float4* frec;   // h, A, sound speed, rho
+    const float4* frec;   // h, A, sound speed, K = 8/(pi h^5); pv.w holds rho
     const uint64_t* mix;
     const uint64_t* csr;
     const uint32_t* csr_off;
@@ -611,12 +613,9 @@ struct ForceP {
     static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
                                                  float Sz, const Args& a) {
         const float4 fj = a.frec[j];
-        const float hinv = 1.f / fj.x;
-        const float h2 = hinv * hinv;
-        const float4 vj = a.pv[j];
         S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, fj.x);
-        S.h[slot] = make_float4(pj.w, hinv, C8PI * h2 * h2 * hinv, fj.y);
-        S.v[slot] = make_float4(vj.x, vj.y, vj.z, fj.w);
+        S.h[slot] = make_float4(pj.w, frcp(fj.x), fj.w, fj.y);
+        S.v[slot] = a.pv[j];
         S.c[slot] = fj.z;
         if (HASH) S.m[slot] = a.mix[j];
     }
@@ -665,22 +664,20 @@ __global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
         if (item < 0) break;
         const int4 ch = a.chunks[item];
         const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
-        const int R = replicas(cnt, a.rmax), T = 64 / R;
-        const int slot = lane & (T - 1), rep = lane / T;
+        const int lgR = replicas_lg(cnt, a.rmax), R = 1 << lgR, T = 64 >> lgR;
+        const int slot = lane & (T - 1), rep = lane >> (6 - lgR);
         const int p = p0 + slot;
         const bool act = slot < cnt;
         typename P::Lane L;
         // an idle lane sits far away so no record is ever in its range
         L.x = act ? a.pos[p] : make_float4(-FAR, -FAR, -FAR, 0.f);
-        const float4 fi = act ? a.frec[p] : make_float4(1.f, 0.f, 0.f, 1.f);
+        // the same records as the staged partners: the two sides of a pair
+        // see identical values
+        const float4 fi = act ? a.frec[p] : make_float4(1.f, 0.f, 0.f, 0.f);
         L.h = fi.x;
-        L.hinv = 1.f / L.h;
-        {
-            const float h2 = L.hinv * L.hinv;
-            L.K = C8PI * h2 * h2 * L.hinv;
-        }
-        const float4 vv = act ? a.pv[p] : make_float4(0.f, 0.f, 0.f, 0.f);
-        L.v = make_float4(vv.x, vv.y, vv.z, fi.w);
+        L.hinv = frcp(L.h);
+        L.K = fi.w;
+        L.v = act ? a.pv[p] : make_float4(0.f, 0.f, 0.f, 1.f);
         L.A = fi.y;
         L.c = fi.z;
         L.hi2 = act ? L.h * L.h : -1.f;
@@ -887,13 +884,17 @@ __global__ void k_zero_unconv(int32_t* status, int nsets) {
 
 __global__ void k_ghost(int64_t n, const float* __restrict__ ph, const float* __restrict__ rho,
                         const float* __restrict__ drho, const float* __restrict__ u, float gamma,
-                        float4* __restrict__ frec) {
+                        float4* __restrict__ frec, float4* __restrict__ pv) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const float r = rho[p], h = ph[p];
     const float P = (gamma - 1.f) * r * u[p];
     const float f = 1.f / (1.f + h / (3.f * r) * drho[p]);
-    frec[p] = make_float4(h, f * P / (r * r), sqrtf(gamma * (gamma - 1.f) * u[p]), r);
+    const float hinv = 1.f / h;
+    const float h2 = hinv * hinv;
+    // h, A = f P / rho^2, sound speed, K = 8 / (pi h^5); rho beside the velocity
+    frec[p] = make_float4(h, f * P / (r * r), sqrtf(gamma * (gamma - 1.f) * u[p]), C8PI * h2 * h2 * hinv);
+    pv[p].w = r;
 }
 
 // Largest current h of the small-h and of the large-h entries of each
@@ -1169,7 +1170,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     hipStream_t st = ctx->stream;
     const int64_t n = t->n;
     hipLaunchKernelGGL(k_ghost, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->ph, t->rho, t->drho, t->pu,
-                       t->prm.gamma, t->frec);
+                       t->prm.gamma, t->frec, t->pv);
     hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph, t->segoff,
                        t->segidx);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
