@@ -599,63 +599,55 @@ __device__ inline uint64_t seg_key(float proj, int cls, uint32_t e) {
     return ((uint64_t)cls << 63) | ((uint64_t)(f2ord(proj) >> 1) << 32) | e;
 }
 
-// Segments of at most 64 entries, taken two at a time by one wavefront:
-// when both fit in 64 lanes they are sorted side by side, else one after
-// the other.  Each lane holds one entry, key (class, ordered projection,
-// local index) -- unique within a segment -- and counts the keys of its
-// segment below its own: that count is its place in the sorted list.  The
-// keys are read back from LDS as broadcasts, so a segment of n entries
-// costs n steps.
-__global__ __launch_bounds__(256) void k_seg_sort_wave(const uint32_t* __restrict__ list,
-                                                       const uint32_t* __restrict__ off, int64_t ns,
-                                                       const SetInfo* sets, const Cell* __restrict__ cells,
+// Cells of at most 64 particles: one wavefront per cell sorts every list
+// the cell needs (axes whose offset is set), loading the particles once.
+// Lists of at most 32 entries go two at a time, one per half-wave.  Each
+// lane holds one entry, key (class, ordered projection, local index) --
+// unique within a list -- and counts the keys of its list below its own:
+// that count is its place in the sorted list.
+__global__ __launch_bounds__(256) void k_seg_sort_cell(int64_t nc, const SetInfo* sets,
+                                                       const Cell* __restrict__ cells,
+                                                       const uint32_t* __restrict__ segoff,
                                                        const float4* __restrict__ pos, const float* __restrict__ ph,
                                                        float4* __restrict__ sproj, uint32_t* __restrict__ sidx) {
     __shared__ uint64_t s_key[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t npair = (ns + 1) / 2;
-    for (int64_t g = (int64_t)blockIdx.x * 4 + w; g < npair; g += (int64_t)gridDim.x * 4) {
-        const int64_t qa = 2 * g, qb = 2 * g + 1;
-        const uint32_t ca = list[qa];
-        const uint32_t cb = qb < ns ? list[qb] : ca;
-        const Cell Ca = cells[ca / NAXES];
-        const Cell Cb = cells[cb / NAXES];
-        // longer segments are sorted by the LDS and global paths
-        const int na = Ca.count <= 64 ? Ca.count : 0;
-        const int nb = (qb < ns && Cb.count <= 64) ? Cb.count : 0;
-        const bool packed = na + nb <= 64;
-        for (int pass = 0; pass < (packed ? 1 : 2); ++pass) {
-            // this lane's segment (0: a, 1: b, -1: none), its first lane and length
-            int seg = -1, first = 0, len = 0;
-            if (packed) {
-                if (lane < na) { seg = 0; first = 0; len = na; }
-                else if (lane < na + nb) { seg = 1; first = na; len = nb; }
-            } else if (lane < (pass ? nb : na)) {
-                seg = pass;
-                len = pass ? nb : na;
+    for (int64_t c = (int64_t)blockIdx.x * 4 + w; c < nc; c += (int64_t)gridDim.x * 4) {
+        const Cell C = cells[c];
+        const int n = C.count;
+        if (n == 0 || n > 64) continue;
+        const uint32_t so_l = lane < NAXES ? segoff[c * NAXES + lane] : 0xFFFFFFFFu;
+        uint64_t need = __ballot(so_l != 0xFFFFFFFFu);
+        if (need == 0) continue;
+        const bool two = n <= 32;
+        const bool upper = two && lane >= 32;
+        const int e = two ? (lane & 31) : lane;
+        const bool valid = e < n;
+        const float4 rec = valid ? pos[C.first + e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float lim = small_h_limit(sets, C);
+        const int cls = (valid && ph[C.first + e] > lim) ? 1 : 0;
+        while (need != 0) {
+            const int a0 = __builtin_ctzll(need);
+            need &= need - 1ull;
+            int a1 = -1;
+            if (two && need != 0) {
+                a1 = __builtin_ctzll(need);
+                need &= need - 1ull;
             }
-            const Cell& C = seg == 1 ? Cb : Ca;
-            const int ax = (int)((seg == 1 ? cb : ca) % NAXES);
-            const int e = lane - first;
-            uint64_t k = ~0ull;
-            float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (seg >= 0) {
-                rec = pos[C.first + e];
-                const float lim = small_h_limit(sets, C);
-                k = seg_key(project(rec, ax), ph[C.first + e] > lim ? 1 : 0, (uint32_t)e);
-            }
+            const int ax = upper ? a1 : a0;
+            const bool act = valid && ax >= 0;
+            const uint64_t k = act ? seg_key(project(rec, ax), cls, (uint32_t)e) : ~0ull;
             s_key[w][lane] = k;
             wave_lds_sync();
-            const int nloop = packed ? max(na, nb) : (pass ? nb : na);
+            const int first = upper ? 32 : 0;
             int rank = 0;
-            for (int t = 0; t < nloop; ++t) {
-                const uint64_t kt = s_key[w][first + min(t, max(len - 1, 0))];
-                rank += (t < len && kt < k) ? 1 : 0;
-            }
-            if (seg >= 0) {
-                const uint32_t o = off[seg == 1 ? qb : qa];
-                sproj[o + rank] = rec;
-                sidx[o + rank] = (uint32_t)(C.first + e);
+            for (int t = 0; t < n; ++t) rank += s_key[w][first + t] < k ? 1 : 0;
+            const uint32_t o0 = (uint32_t)__builtin_amdgcn_readlane((int)so_l, a0);
+            const uint32_t o1 = a1 >= 0 ? (uint32_t)__builtin_amdgcn_readlane((int)so_l, a1) : 0u;
+            if (act) {
+                const uint32_t o = (upper ? o1 : o0) + (uint32_t)rank;
+                sproj[o] = rec;
+                sidx[o] = (uint32_t)(C.first + e);
             }
             wave_lds_sync();
         }
@@ -1135,9 +1127,8 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
         ERRTRY(t->alloc(t->b_segproj, sizeof(float4) * std::max<int64_t>(nent, 1), (void**)&t->segpos));
         ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
         hipLaunchKernelGGL(k_cell_nsmall, dim3(nblk(nc, 4)), dim3(256), 0, st, t->d_sets, t->cells, nc, t->ph);
-        hipLaunchKernelGGL(k_seg_sort_wave, dim3((unsigned)std::min<int64_t>((ns + 7) / 8, 8192)), dim3(256), 0, st,
-                           t->seglist, soff, (int64_t)ns, t->d_sets, t->cells, t->pos, t->ph, t->segpos,
-                           t->segidx);
+        hipLaunchKernelGGL(k_seg_sort_cell, dim3((unsigned)std::min<int64_t>((nc + 3) / 4, 16384)), dim3(256), 0,
+                           st, nc, t->d_sets, t->cells, t->segoff, t->pos, t->ph, t->segpos, t->segidx);
         HIPTRY(hipGetLastError());
         ERRTRY(t->scratch(std::max<int64_t>(nca, ns) + 1));
         // segments of 65..SEG_LDS_MAX entries (LDS sort) and longer ones (one
