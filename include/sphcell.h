@@ -198,10 +198,12 @@ sph_status sph_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out);
 sph_status sph_run_graph(sph_ctx* ctx, sph_tree* t, int32_t k_iter, const sph_density_out* dout,
                          const sph_force_out* fout, int32_t* n_unconverged_dev);
 
-/* Per-kernel timing of the last pipeline run (milliseconds, from HIP events
- * recorded on the context's stream): names[i] = stage name, ms[i] = time.
- * Returns the number of stages written (at most cap). */
-int32_t sph_last_timings(const sph_ctx* ctx, const char** names, double* ms, int32_t cap);
+/* Per-stage timing (milliseconds, from HIP events recorded on the context's
+ * stream while timing is enabled) of every call since the timings were last
+ * read, in call order: names[i] = stage name, ms[i] = time.  Reading
+ * synchronises with the last recorded event; recording does not.  Returns
+ * the number of stages written (at most cap). */
+int32_t sph_last_timings(sph_ctx* ctx, const char** names, double* ms, int32_t cap);
 /* Enable (1) or disable (0) per-stage event timing on the context. */
 void sph_enable_timing(sph_ctx* ctx, int32_t on);
 

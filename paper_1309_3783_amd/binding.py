@@ -151,9 +151,9 @@ class Context:
         lib().sph_enable_timing(self.h, 1 if on else 0)
 
     def timings(self):
-        names = (C.c_char_p * 32)()
-        ms = (C.c_double * 32)()
-        k = lib().sph_last_timings(self.h, names, ms, 32)
+        names = (C.c_char_p * 4096)()
+        ms = (C.c_double * 4096)()
+        k = lib().sph_last_timings(self.h, names, ms, 4096)
         return [(names[i].decode(), ms[i]) for i in range(k)]
 
     def close(self):

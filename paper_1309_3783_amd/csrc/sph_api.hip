@@ -69,7 +69,7 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
 
 void sph_ctx_destroy(sph_ctx* ctx) {
     if (!ctx) return;
-    for (auto& e : ctx->ev) (void)hipEventDestroy(e.second);
+    for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
     delete ctx;
 }
@@ -139,8 +139,20 @@ sph_status sph_run_graph(sph_ctx* ctx, sph_tree* t, int32_t k_iter, const sph_de
     return fail(ctx, sph::run_graph(ctx, t, k_iter, dout, fout, n_unconverged_dev));
 }
 
-int32_t sph_last_timings(const sph_ctx* ctx, const char** names, double* ms, int32_t cap) {
+int32_t sph_last_timings(sph_ctx* ctx, const char** names, double* ms, int32_t cap) {
     if (!ctx) return 0;
+    if (ctx->nev > 0) {
+        // intervals between consecutive stage events of one call
+        (void)hipEventSynchronize(ctx->ev_pool[ctx->nev - 1]);
+        ctx->last_ms.clear();
+        for (size_t i = 1; i < ctx->nev; ++i) {
+            if (std::strcmp(ctx->ev_name[i], "start") == 0) continue;
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ctx->ev_pool[i - 1], ctx->ev_pool[i]);
+            ctx->last_ms.emplace_back(ctx->ev_name[i], (double)t);
+        }
+        ctx->nev = 0;
+    }
     int32_t k = 0;
     for (const auto& e : ctx->last_ms) {
         if (k >= cap) break;

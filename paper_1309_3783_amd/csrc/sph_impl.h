@@ -16,7 +16,12 @@ struct sph_ctx {
     int n_cu = 256;
     std::string last_error;
     bool timing = false;
-    std::vector<std::pair<const char*, hipEvent_t>> ev;
+    // stage events of the calls since the timings were last read: a pool
+    // of events reused across calls (no create/destroy per stage, no
+    // synchronisation until the timings are read)
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<const char*> ev_name;
+    size_t nev = 0;
     std::vector<std::pair<const char*, double>> last_ms;
     int32_t* d_counter = nullptr;   // persistent-kernel work counters
     hipStream_t cap_stream = nullptr; // private stream used only to capture graphs

@@ -1092,25 +1092,20 @@ static Err ensure_state(sph_tree* t) {
     return Err{};
 }
 
+// Stage events: ev_mark records the end of a stage (a call's first mark,
+// "start", opens it); nothing is synchronised here, the intervals are
+// computed when the timings are read.
 static void ev_mark(sph_ctx* ctx, const char* name) {
     if (!ctx->timing) return;
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
-    (void)hipEventRecord(e, ctx->stream);
-    ctx->ev.emplace_back(name, e);
-}
-
-static void ev_collect(sph_ctx* ctx) {
-    if (!ctx->timing || ctx->ev.empty()) return;
-    (void)hipEventSynchronize(ctx->ev.back().second);
-    ctx->last_ms.clear();
-    for (size_t i = 1; i < ctx->ev.size(); ++i) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, ctx->ev[i - 1].second, ctx->ev[i].second);
-        ctx->last_ms.emplace_back(ctx->ev[i].first, (double)ms);
+    if (ctx->nev == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        ctx->ev_pool.push_back(e);
+        ctx->ev_name.push_back(name);
     }
-    for (auto& e : ctx->ev) (void)hipEventDestroy(e.second);
-    ctx->ev.clear();
+    ctx->ev_name[ctx->nev] = name;
+    (void)hipEventRecord(ctx->ev_pool[ctx->nev], ctx->stream);
+    ++ctx->nev;
 }
 
 static int rmax_of(const sph_tree* t) {
@@ -1247,7 +1242,6 @@ Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out) {
     launch_scatter_density(ctx, t, out);
     HIPTRY(hipGetLastError());
     ev_mark(ctx, "scatter");
-    ev_collect(ctx);
     t->have_density = true;
     return Err{};
 }
@@ -1310,7 +1304,6 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
     ev_mark(ctx, "scatter");
-    ev_collect(ctx);
     if (iters) *iters = it;
     if (n_unconv) *n_unconv = hstat[1];
     t->have_density = !rebuild;
@@ -1332,7 +1325,6 @@ Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
     launch_scatter_force(ctx, t, out);
     HIPTRY(hipGetLastError());
     ev_mark(ctx, "reduce+scatter");
-    ev_collect(ctx);
     return Err{};
 }
 
