@@ -311,13 +311,17 @@ struct SweepTab {
     float4 f[2 * DBATCH];
 };
 
-// Builds the descriptors of entries [e0, e0 + n) of cell cA (n <= DBATCH).
-// box: largest o_k x_k over the chunk's particles per axis and sign
-// (bx[0..2] = max x, bx[3..5] = -min x); hmax: largest h of the chunk.
+// Builds the descriptors of entries [e0, e0 + n) of cell cA (n <= DBATCH)
+// and returns their number (parts without records get none; the others keep
+// the entry order, part 0 first).  box: largest o_k x_k over the chunk's
+// particles per axis and sign (bx[0..2] = max x, bx[3..5] = -min x); hmax:
+// largest h of the chunk.
 template <class P>
-__device__ __forceinline__ void build_sweeps(const typename P::Args& a, const Cell& cA, float L0, uint32_t e0, int n,
-                                             const float (&bx)[6], float hmax, SweepTab& T) {
+__device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cell& cA, float L0, uint32_t e0, int n,
+                                            const float (&bx)[6], float hmax, SweepTab& T) {
     const int lane = threadIdx.x & 63;
+    int4 q0 = make_int4(0, 0, 0, 0), q1 = q0;
+    float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0;
     if (lane < n) {
         const uint64_t key = a.csr[e0 + lane];
         const int B = (int)((key >> 5) & 0xFFFFFFFFull);
@@ -331,14 +335,25 @@ __device__ __forceinline__ void build_sweeps(const typename P::Args& a, const Ce
         const float tb = (ox > 0 ? bx[0] : (ox < 0 ? bx[3] : 0.f)) + (oy > 0 ? bx[1] : (oy < 0 ? bx[4] : 0.f)) +
                          (oz > 0 ? bx[2] : (oz < 0 ? bx[5] : 0.f));
         const float tiny = 1e-5f * L0;
-        const float t0 = tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny);
-        const float t1 = tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny);
-        T.q[2 * lane] = make_int4((int)so, cB.nsmall, g.sign, code);
-        T.q[2 * lane + 1] = make_int4((int)so + cB.nsmall, cB.count - cB.nsmall, g.sign, code);
-        T.f[2 * lane] = make_float4(g.Sx, g.Sy, g.Sz, t0);
-        T.f[2 * lane + 1] = make_float4(g.Sx, g.Sy, g.Sz, t1);
+        q0 = make_int4((int)so, cB.nsmall, g.sign, code);
+        q1 = make_int4((int)so + cB.nsmall, cB.count - cB.nsmall, g.sign, code);
+        f0 = make_float4(g.Sx, g.Sy, g.Sz, tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny));
+        f1 = make_float4(g.Sx, g.Sy, g.Sz, tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny));
+    }
+    const bool ne0 = q0.y > 0, ne1 = q1.y > 0;
+    const uint64_t b0 = __ballot(ne0), b1 = __ballot(ne1);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int pos = __popcll(b0 & below) + __popcll(b1 & below);
+    if (ne0) {
+        T.q[pos] = q0;
+        T.f[pos] = f0;
+    }
+    if (ne1) {
+        T.q[pos + (ne0 ? 1 : 0)] = q1;
+        T.f[pos + (ne0 ? 1 : 0)] = f1;
     }
     wave_lds_sync();
+    return __popcll(b0) + __popcll(b1);
 }
 
 // The walk of one chunk: the leaf's self task, then the pair tasks of the
@@ -372,6 +387,20 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
     int nd = 0, di = 0, base = 0;        // descriptors loaded, current one, position in it
     int fill = 0;
     bool tself = false;   // the current tile holds a self-task block
+    // the records of the next block are loaded one block ahead (pdi, pbase:
+    // its descriptor and position; pdi < 0: none in flight)
+    int pdi = -1, pbase = 0;
+    float4 ppj = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t pqq = 0;
+    auto load_block = [&](int d, int b, float4& pj, uint32_t& qq) {
+        const int4 dq = T.q[d];
+        const int qs = uni(dq.x), len = uni(dq.y), dir = uni(dq.z);
+        if (lane < min(64, len - b)) {
+            const uint32_t q = (uint32_t)qs + (uint32_t)(dir > 0 ? b + lane : len - 1 - b - lane);
+            pj = a.segpos[q];
+            qq = a.segidx[q];
+        }
+    };
     for (;;) {
         bool done = false, self = false;
         int nuse = 0;
@@ -385,58 +414,69 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
             self = true;
             sbase += nuse;
         } else {
-            int4 dq = make_int4(0, 0, 0, 0);
-            for (;;) {
-                if (di < nd) {
-                    dq = T.q[di];
-                    dq = make_int4(uni(dq.x), uni(dq.y), uni(dq.z), uni(dq.w));
-                    if (base < dq.y) break;
-                    ++di;
-                    base = 0;
-                    continue;
-                }
+            if (di >= nd) {
                 // next batch of entries: of this cell, or of its ancestors
-                while (e >= e1 && A >= 0) {
-                    A = cA.parent;
-                    if (A >= 0) {
-                        cA = a.cells[A];
-                        L0 = (float)a.sets[cA.set].L0;
-                        e = a.csr_off[A];
-                        e1 = a.csr_off[A + 1];
+                // (a batch may have no records at all)
+                while (di >= nd) {
+                    while (e >= e1 && A >= 0) {
+                        A = cA.parent;
+                        if (A >= 0) {
+                            cA = a.cells[A];
+                            L0 = (float)a.sets[cA.set].L0;
+                            e = a.csr_off[A];
+                            e1 = a.csr_off[A + 1];
+                        }
                     }
+                    if (A < 0) {
+                        done = true;
+                        break;
+                    }
+                    const int n = (int)min(e1 - e, (uint32_t)DBATCH);
+                    nd = build_sweeps<P>(a, cA, L0, e, n, bx, hmax, T);
+                    e += n;
+                    di = 0;
+                    base = 0;
+                    pdi = -1;
                 }
-                if (A < 0) {
-                    done = true;
-                    break;
-                }
-                const int n = (int)min(e1 - e, (uint32_t)DBATCH);
-                build_sweeps<P>(a, cA, L0, e, n, bx, hmax, T);
-                e += n;
-                nd = 2 * n;
-                di = 0;
-                base = 0;
             }
             if (!done) {
+                const int4 dq = T.q[di];
+                const int len = uni(dq.y), code = uni(dq.w);
                 const float4 df = T.f[di];
                 Sx = unif(df.x);
                 Sy = unif(df.y);
                 Sz = unif(df.z);
                 const float tlim = unif(df.w);
-                const int len = dq.y;
                 const int nsrc = min(64, len - base);
-                const float fox = (float)ocx(dq.w), foy = (float)ocy(dq.w), foz = (float)ocz(dq.w);
+                if (pdi == di && pbase == base) {
+                    pj = ppj;
+                    qq = pqq;
+                } else {
+                    load_block(di, base, pj, qq);
+                }
+                // the next block: further along this list, or the next list
+                pdi = di;
+                pbase = base + 64;
+                if (pbase >= len) {
+                    pdi = di + 1;
+                    pbase = 0;
+                }
+                if (pdi < nd) load_block(pdi, pbase, ppj, pqq);
+                else pdi = -1;
+                const float fox = (float)ocx(code), foy = (float)ocy(code), foz = (float)ocz(code);
                 bool ok = false;
                 if (lane < nsrc) {
-                    const uint32_t q = (uint32_t)dq.x + (uint32_t)(dq.z > 0 ? base + lane : len - 1 - base - lane);
-                    pj = a.segpos[q];
                     const float t = fmaf(fox, pj.x + Sx, fmaf(foy, pj.y + Sy, foz * (pj.z + Sz)));
                     ok = t <= tlim;
-                    qq = a.segidx[q];
                 }
                 const uint64_t okm = __ballot(ok);
                 // the prefix in sweep order is staged; the sweep ends at its end
                 nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);
                 base = nuse < nsrc ? len : base + 64;
+                if (base >= len) {
+                    ++di;
+                    base = 0;
+                }
             }
         }
         if (done || fill + nuse > TCAP) {
