@@ -161,7 +161,8 @@ sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const
  * source side of a pair task, the particle indices sorted by their
  * projection on the task's cell-pair axis (one of 13 directions), stored per
  * (cell, axis) and reused by every density and force pass until the next
- * build.  Synchronises the stream. */
+ * build.  Synchronises the stream once, to read the list sizes back; the
+ * sorts themselves are enqueued after that and not waited for. */
 sph_status sph_sort_pairs(sph_ctx* ctx, sph_tree* t);
 
 /* Density stage (Section II, item 1) for every particle at its current h.

@@ -63,6 +63,12 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
         delete c;
         return SPH_E_WORKSPACE;
     }
+    if (hipHostMalloc(&c->h_pin, sph_ctx::PIN_BYTES, hipHostMallocDefault) != hipSuccess) {
+        c->h_pin = nullptr;
+        (void)hipFree(c->d_counter);
+        delete c;
+        return SPH_E_WORKSPACE;
+    }
     *out = c;
     return SPH_OK;
 }
@@ -71,6 +77,7 @@ void sph_ctx_destroy(sph_ctx* ctx) {
     if (!ctx) return;
     for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+    if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
     delete ctx;
 }
 

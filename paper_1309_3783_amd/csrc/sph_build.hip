@@ -16,6 +16,7 @@
 // the level loop reads one count back per level to size the next one.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "sph_impl.h"
 
@@ -436,10 +437,8 @@ __global__ void k_task_emit(const int4* __restrict__ tasks, int64_t nt, const Ce
 // ---------------------------------------------------------------------------
 // Leaves -> work chunks of at most CHUNK particles; per-particle h bound.
 // ---------------------------------------------------------------------------
-// Chunks per cell; also the number of non-empty leaves and the largest leaf
-// (one atomic per block).
-__global__ __launch_bounds__(256) void k_chunk_count(const Cell* __restrict__ cells, int64_t nc, uint32_t* cnt,
-                                                     int* stats) {
+// The number of non-empty leaves and the largest leaf (one atomic per block).
+__global__ __launch_bounds__(256) void k_chunk_count(const Cell* __restrict__ cells, int64_t nc, int* stats) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool leaf = false;
     int count = 0;
@@ -447,7 +446,6 @@ __global__ __launch_bounds__(256) void k_chunk_count(const Cell* __restrict__ ce
         const Cell C = cells[c];
         leaf = !C.split && C.count > 0;
         count = leaf ? C.count : 0;
-        cnt[c] = leaf ? (uint32_t)((C.count + CHUNK - 1) / CHUNK) : 0u;
     }
     int nl = __popcll(__ballot(leaf));
     for (int d = 32; d >= 1; d >>= 1) count = max(count, __shfl_xor(count, d, 64));
@@ -488,16 +486,19 @@ __global__ void k_chunk_emit(const Cell* __restrict__ cells, int64_t nc, const u
         chunks[num[C.first + s]] = make_int4((int)c, C.first + s, min(CHUNK, C.count - s), 0);
 }
 
-__global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__ chunks, int64_t nch,
+// One wave per chunk (the chunk count is read on the device).
+__global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__ chunks,
+                                                        const uint32_t* __restrict__ nch_dev,
                                                         const Cell* __restrict__ cells,
                                                         float* __restrict__ bound) {
-    int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= nch) return;
+    const int64_t nch = *nch_dev;
     const int lane = threadIdx.x & 63;
-    int4 ch = chunks[q];
-    float b = INFINITY;
-    for (int A = ch.x; A >= 0; A = cells[A].parent) b = fminf(b, cells[A].bound);
-    if (lane < ch.z) bound[ch.y + lane] = b;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nch; q += (int64_t)gridDim.x * 4) {
+        const int4 ch = chunks[q];
+        float b = INFINITY;
+        for (int A = ch.x; A >= 0; A = cells[A].parent) b = fminf(b, cells[A].bound);
+        if (lane < ch.z) bound[ch.y + lane] = b;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -522,11 +523,13 @@ __global__ void k_csr_keys(const int4* __restrict__ tasks, int64_t nt, uint64_t*
 }
 
 // CSR offsets from the sorted keys: off[c] = first entry with target >= c.
+// The self entries (all ones, sorted last) count as target nc, so off[nc]
+// is the number of pair entries.
 __global__ void k_csr_offsets(const uint64_t* __restrict__ keys, int64_t ne, int64_t nc, uint32_t* __restrict__ off) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
-    int64_t t = (int64_t)(keys[e] >> CSR_TGT_SHIFT);
-    int64_t tp = e == 0 ? -1 : (int64_t)(keys[e - 1] >> CSR_TGT_SHIFT);
+    int64_t t = min((int64_t)(keys[e] >> CSR_TGT_SHIFT), nc);
+    int64_t tp = e == 0 ? -1 : min((int64_t)(keys[e - 1] >> CSR_TGT_SHIFT), nc);
     for (int64_t c = tp + 1; c <= t; ++c) off[c] = (uint32_t)e;
     if (e == ne - 1)
         for (int64_t c = t + 1; c <= nc; ++c) off[c] = (uint32_t)ne;
@@ -539,26 +542,45 @@ __global__ void k_seg_need(const uint64_t* __restrict__ ent, int64_t ne, uint32_
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     uint64_t k = ent[e];
+    if (k == ~0ull) return;   // self entry
     int src = (int)((k >> CSR_SRC_SHIFT) & 0xFFFFFFFFull);
     int sg;
     int ax = axis_of((int)(k & 31), &sg);
     need[(int64_t)src * NAXES + ax] = 1u;
 }
 
-__global__ void k_seg_list(const uint32_t* __restrict__ need, const uint32_t* __restrict__ idx, int64_t nca,
-                           const Cell* __restrict__ cells, uint32_t* __restrict__ list,
-                           uint32_t* __restrict__ lens) {
+// Per (cell, axis) list: its length where some pair entry needs it (0
+// elsewhere), and its sort class: 65..SEG_LDS_MAX entries (one block sorts
+// it in LDS) or longer (one global radix sort over all such lists).
+__global__ void k_seg_lens(const uint32_t* __restrict__ need, int64_t nca, const Cell* __restrict__ cells,
+                           uint32_t* __restrict__ lens, uint32_t* __restrict__ mid, uint32_t* __restrict__ big) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nca || !need[q]) return;
-    uint32_t k = idx[q];
-    list[k] = (uint32_t)q;
-    lens[k] = (uint32_t)cells[q / NAXES].count;
+    if (q >= nca) return;
+    const uint32_t n = need[q] ? (uint32_t)cells[q / NAXES].count : 0u;
+    lens[q] = n;
+    mid[q] = (n > 64u && n <= (uint32_t)SEG_LDS_MAX) ? 1u : 0u;
+    big[q] = n > (uint32_t)SEG_LDS_MAX ? 1u : 0u;
 }
 
-__global__ void k_seg_table(const uint32_t* __restrict__ list, const uint32_t* __restrict__ off, int64_t ns,
-                            uint32_t* __restrict__ table) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < ns) table[list[k]] = off[k];
+// After the scans: lists nobody needs get offset ~0; the mid-size and long
+// lists are listed by (cell, axis) index.
+__global__ void k_seg_post(const uint32_t* __restrict__ need, int64_t nca, const Cell* __restrict__ cells,
+                           uint32_t* __restrict__ segoff, const uint32_t* __restrict__ mid_idx,
+                           const uint32_t* __restrict__ big_idx, uint32_t* __restrict__ mids,
+                           uint32_t* __restrict__ big, uint32_t* __restrict__ blen) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nca) return;
+    if (!need[q]) {
+        segoff[q] = 0xFFFFFFFFu;
+        return;
+    }
+    const uint32_t n = (uint32_t)cells[q / NAXES].count;
+    if (n > 64u && n <= (uint32_t)SEG_LDS_MAX) {
+        mids[mid_idx[q]] = (uint32_t)q;
+    } else if (n > (uint32_t)SEG_LDS_MAX) {
+        big[big_idx[q]] = (uint32_t)q;
+        blen[big_idx[q]] = n;
+    }
 }
 
 __device__ inline float project(const float4& p, int ax) {
@@ -654,18 +676,16 @@ __global__ __launch_bounds__(256) void k_seg_sort_cell(int64_t nc, const SetInfo
     }
 }
 
-// Segments of 65..SEG_LDS_MAX entries (listed in sel): one block each,
-// bitonic sort in LDS.
+// Segments of 65..SEG_LDS_MAX entries (their (cell, axis) indices listed in
+// sel): one block each, bitonic sort in LDS.
 __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict__ sel, int64_t nsel,
-                                                      const uint32_t* __restrict__ list,
                                                       const uint32_t* __restrict__ off, const SetInfo* sets,
                                                       const Cell* __restrict__ cells,
                                                       const float4* __restrict__ pos, const float* __restrict__ ph,
                                                       float4* __restrict__ sproj, uint32_t* __restrict__ sidx) {
     __shared__ uint64_t s[SEG_LDS_MAX];
     for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
-    const int64_t q = sel[i];
-    uint32_t ca = list[q];
+    const uint32_t ca = sel[i];
     const Cell C = cells[ca / NAXES];
     int ax = (int)(ca % NAXES);
     int n = C.count;
@@ -691,7 +711,7 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
             __syncthreads();
         }
     }
-    uint32_t o = off[q];
+    uint32_t o = off[ca];
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         uint64_t k = s[e];
         uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
@@ -702,39 +722,13 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
     }
 }
 
-__global__ void k_big_flag(const uint32_t* __restrict__ lens, int64_t ns, uint32_t* __restrict__ flag) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < ns) flag[q] = lens[q] > (uint32_t)SEG_LDS_MAX ? 1u : 0u;
-}
-
-__global__ void k_mid_flag(const uint32_t* __restrict__ lens, int64_t ns, uint32_t* __restrict__ flag) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < ns) flag[q] = (lens[q] > 64u && lens[q] <= (uint32_t)SEG_LDS_MAX) ? 1u : 0u;
-}
-
-__global__ void k_compact(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx, int64_t ns,
-                          uint32_t* __restrict__ out) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < ns && flag[q]) out[idx[q]] = (uint32_t)q;
-}
-
-__global__ void k_big_list(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ idx, int64_t ns,
-                           const uint32_t* __restrict__ lens, uint32_t* __restrict__ big,
-                           uint32_t* __restrict__ blen) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= ns || !flag[q]) return;
-    big[idx[q]] = (uint32_t)q;
-    blen[idx[q]] = lens[q];
-}
-
 __global__ __launch_bounds__(256) void k_big_keys(const uint32_t* __restrict__ big,
-                                                  const uint32_t* __restrict__ boff,
-                                                  const uint32_t* __restrict__ list, const SetInfo* sets,
+                                                  const uint32_t* __restrict__ boff, const SetInfo* sets,
                                                   const Cell* __restrict__ cells, const float4* __restrict__ pos,
                                                   const float* __restrict__ ph,
                                                   uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
     uint32_t r = blockIdx.x;
-    uint32_t ca = list[big[r]];
+    uint32_t ca = big[r];
     const Cell C = cells[ca / NAXES];
     int ax = (int)(ca % NAXES);
     const float lim = small_h_limit(sets, C);
@@ -778,9 +772,13 @@ static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) 
         if (e_.st != SPH_OK) return e_;    \
     } while (0)
 
-static Err read_u32(const uint32_t* d, uint32_t* h, hipStream_t st) {
-    HIPTRY(hipMemcpyAsync(h, d, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
+// Device words read back through the context's pinned buffer: one
+// asynchronous copy, one stream synchronisation.
+static Err read_back(sph_ctx* ctx, const void* d, size_t bytes, const void** h) {
+    if (bytes > sph_ctx::PIN_BYTES) return Err{SPH_E_STATE, "internal: read-back larger than the pinned buffer"};
+    HIPTRY(hipMemcpyAsync(ctx->h_pin, d, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(hipStreamSynchronize(ctx->stream));
+    *h = ctx->h_pin;
     return Err{};
 }
 
@@ -838,10 +836,11 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         hipLaunchKernelGGL(k_set_hstats, dim3(gx, S), dim3(256), 0, st, d_sets, in->h, (int*)d_hmax, (int*)d_hmin,
                            d_bad);
         HIPTRY(hipGetLastError());
-        HIPTRY(hipMemcpyAsync(hmax.data(), d_hmax, sizeof(float) * S, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipMemcpyAsync(hmin.data(), d_hmin, sizeof(float) * S, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipMemcpyAsync(bad.data(), d_bad, sizeof(int) * S, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipStreamSynchronize(st));
+        const void* hs;
+        ERRTRY(read_back(ctx, d_hmax, 3 * sizeof(float) * S, &hs));
+        std::memcpy(hmax.data(), hs, sizeof(float) * S);
+        std::memcpy(hmin.data(), (const float*)hs + S, sizeof(float) * S);
+        std::memcpy(bad.data(), (const float*)hs + 2 * S, sizeof(int) * S);
     }
     int max_lg = 0;
     int64_t ntop = 0;
@@ -946,14 +945,20 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
                        ntop, t->key, t->hdec, prm->n_split, prm->split_frac, t->cells);
     HIPTRY(hipGetLastError());
 
-    // top-level tasks
+    // top-level tasks and the split flags of level 0: one read-back for both
     ERRTRY(t->scratch(ntop + 1));
+    ERRTRY(t->alloc(t->b_split, sizeof(uint32_t) * (ntop + 1), (void**)&t->split_idx));
 #define total (t->d_total)
     hipLaunchKernelGGL(k_top_task_count, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, S, (int)ntop, t->cells,
                        t->sc_a);
     HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ntop, t->sc_tmp, total, st));
-    uint32_t nt0 = 0;
-    ERRTRY(read_u32(total, &nt0, st));
+    hipLaunchKernelGGL(k_split_flags, dim3(nblk(ntop, 256)), dim3(256), 0, st, t->cells, (int64_t)0, ntop,
+                       t->split_idx);
+    HIPTRY(exclusive_scan(t->split_idx, t->split_idx, ntop, t->sc_tmp, total + 2, st));
+    const void* rb;
+    ERRTRY(read_back(ctx, total, 3 * sizeof(uint32_t), &rb));
+    const uint32_t nt0 = ((const uint32_t*)rb)[0];
+    uint32_t nsplit = ((const uint32_t*)rb)[2];   // split cells of the current level
     int64_t cap_tasks = std::max<int64_t>(nt0, 1);
     ERRTRY(t->alloc(t->b_taskA, sizeof(int4) * cap_tasks, (void**)&t->taskA));
     hipLaunchKernelGGL(k_top_task_emit, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, (int)ntop, t->cells,
@@ -963,16 +968,12 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     int64_t nfinal = 0;        // final tasks (in finals)
     ERRTRY(t->alloc(t->b_final, sizeof(int4) * std::max<int64_t>(nt0, 1), (void**)&t->finals));
 
+    // One read-back per level: the task counts of this level and the split
+    // count of the next, whose cells exist before this level's tasks are
+    // decided (a task splits into tasks of the children).
     int level = 0;
     for (;; ++level) {
         const int64_t c0 = t->lvl_start[level], c1 = t->lvl_start[level + 1];
-        const int64_t nlev = c1 - c0;
-        // children of split cells at this level
-        ERRTRY(t->scratch(std::max(nlev, ncur) + 1));
-        hipLaunchKernelGGL(k_split_flags, dim3(nblk(nlev, 256)), dim3(256), 0, st, t->cells, c0, c1, t->sc_a);
-        HIPTRY(exclusive_scan(t->sc_a, t->sc_b, nlev, t->sc_tmp, total, st));
-        uint32_t nsplit = 0;
-        ERRTRY(read_u32(total, &nsplit, st));
         const int64_t nnext = 8 * (int64_t)nsplit;
         if (c1 + nnext > (int64_t)1 << 27) return Err{SPH_E_CAPACITY, "too many cells (limit 2^27)"};
         if (c1 + nnext > cap_cells) {
@@ -980,28 +981,36 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
             ERRTRY(t->grow(t->b_cell, sizeof(Cell) * c1, sizeof(Cell) * nc, (void**)&t->cells));
             cap_cells = nc;
         }
+        ERRTRY(t->scratch(std::max(nnext, ncur) + 1));
         if (nsplit > 0) {
-            hipLaunchKernelGGL(k_make_children, dim3(nblk(nlev, 256)), dim3(256), 0, st, c0, c1, c1, t->sc_b,
-                               t->cells);
+            hipLaunchKernelGGL(k_make_children, dim3(nblk(c1 - c0, 256)), dim3(256), 0, st, c0, c1, c1,
+                               t->split_idx, t->cells);
             HIPTRY(hipGetLastError());
             hipLaunchKernelGGL(k_cell_stats, dim3(nblk(nnext, 4)), dim3(256), 0, st, d_sets, bmax,
                                level + 1, c1, c1 + nnext, t->key, t->hdec, prm->n_split, prm->split_frac,
                                t->cells);
             HIPTRY(hipGetLastError());
+            // the children's split flags (the buffer is free once the
+            // children exist: a reallocation waits for the device)
+            ERRTRY(t->alloc(t->b_split, sizeof(uint32_t) * (nnext + 1), (void**)&t->split_idx));
+            hipLaunchKernelGGL(k_split_flags, dim3(nblk(nnext, 256)), dim3(256), 0, st, t->cells, c1, c1 + nnext,
+                               t->split_idx);
+            HIPTRY(exclusive_scan(t->split_idx, t->split_idx, nnext, t->sc_tmp, total + 2, st));
         }
         t->lvl_start.push_back(c1 + nnext);
-        // decide this level's tasks
+        if (ncur == 0 && nsplit == 0) break;
         if (ncur > 0) {
-            ERRTRY(t->scratch(ncur + 1));
             hipLaunchKernelGGL(k_task_decide, dim3(nblk(ncur, 256)), dim3(256), 0, st, d_sets, t->taskA, ncur,
                                t->cells, t->sc_a, t->sc_c);
             HIPTRY(hipGetLastError());
             HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ncur, t->sc_tmp, total, st));
             HIPTRY(exclusive_scan(t->sc_c, t->sc_d, ncur, t->sc_tmp, total + 1, st));
-            uint32_t nfc[2] = {0, 0};
-            HIPTRY(hipMemcpyAsync(nfc, total, sizeof(nfc), hipMemcpyDeviceToHost, st));
-            HIPTRY(hipStreamSynchronize(st));
-            const uint32_t nf = nfc[0], nc = nfc[1];
+        }
+        ERRTRY(read_back(ctx, total, 3 * sizeof(uint32_t), &rb));
+        const uint32_t nf = ncur > 0 ? ((const uint32_t*)rb)[0] : 0u;
+        const uint32_t nc = ncur > 0 ? ((const uint32_t*)rb)[1] : 0u;
+        const uint32_t nsplit_next = nsplit > 0 ? ((const uint32_t*)rb)[2] : 0u;
+        if (ncur > 0) {
             if (nfinal + nf > (int64_t)0x7FFFFFFF) return Err{SPH_E_CAPACITY, "too many tasks"};
             ERRTRY(t->grow(t->b_final, sizeof(int4) * nfinal, sizeof(int4) * std::max<int64_t>(nfinal + nf, 1),
                            (void**)&t->finals));
@@ -1020,34 +1029,29 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
             // (k_task_decide only splits tasks of split cells)
             return Err{SPH_E_STATE, "internal: tasks left without split cells"};
         }
+        nsplit = nsplit_next;
     }
     t->nlevels = level + 1;
     t->ncells = t->lvl_start.back();
     t->ntasks = nfinal;
 
     // ---- leaves -> chunks; particle h bounds ------------------------------
+    // (the chunk and leaf counts are read back once, at the end)
     const int64_t nc = t->ncells;
     ERRTRY(t->scratch(std::max<int64_t>(nc, t->n) + 1));
     HIPTRY(fill_u32((uint32_t*)t->d_maxleaf, 2, 0, st));
-    hipLaunchKernelGGL(k_chunk_count, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_a, t->d_maxleaf);
+    hipLaunchKernelGGL(k_chunk_count, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->d_maxleaf);
     HIPTRY(fill_u32(t->sc_c, t->n, 0u, st));
     hipLaunchKernelGGL(k_chunk_mark, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_c);
     HIPTRY(exclusive_scan(t->sc_c, t->sc_d, t->n, t->sc_tmp, total, st));
-    uint32_t nchunks = 0;
-    int lstats[2] = {0, 0};
-    HIPTRY(hipMemcpyAsync(&nchunks, total, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipMemcpyAsync(lstats, t->d_maxleaf, sizeof(lstats), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    const int maxleaf = lstats[1];
-    t->nleaves = lstats[0];
-    ERRTRY(t->alloc(t->b_chunk, sizeof(int4) * std::max<uint32_t>(nchunks, 1), (void**)&t->chunks));
+    // a leaf of k particles gives ceil(k / CHUNK) <= k / CHUNK + 1 chunks
+    const int64_t chunk_cap = nc + t->n / CHUNK + 1;
+    ERRTRY(t->alloc(t->b_chunk, sizeof(int4) * chunk_cap, (void**)&t->chunks));
     hipLaunchKernelGGL(k_chunk_emit, dim3(nblk(nc, 256)), dim3(256), 0, st, t->cells, nc, t->sc_d, t->chunks);
     HIPTRY(hipGetLastError());
-    t->nchunks = nchunks;
-    t->max_leaf = maxleaf;
-    if (nchunks > 0) {
-        hipLaunchKernelGGL(k_particle_bound, dim3(nblk(nchunks, 4)), dim3(256), 0, st, t->chunks, (int64_t)nchunks,
-                           t->cells, t->bound);
+    if (t->n > 0) {
+        hipLaunchKernelGGL(k_particle_bound, dim3((unsigned)std::min<int64_t>(nblk(chunk_cap, 4), 8192)), dim3(256),
+                           0, st, t->chunks, total, t->cells, t->bound);
         HIPTRY(hipGetLastError());
     }
 
@@ -1056,8 +1060,6 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(t->alloc(t->b_csr, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr));
     ERRTRY(t->alloc(t->b_csr2, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr2));
     ERRTRY(t->alloc(t->b_csroff, sizeof(uint32_t) * (nc + 1), (void**)&t->csr_off));
-    // every non-empty leaf holds exactly one final self task
-    const int64_t npairs = nfinal - t->nleaves;
     if (ne > 0) {
         ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(ne), radix_tmp_words(nn)),
                         (void**)&t->rs_tmp));
@@ -1074,16 +1076,21 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
             std::swap(t->csr, t->csr2);
             std::swap(t->b_csr, t->b_csr2);
         }
-    }
-    t->npairs = npairs;
-    if (npairs > 0) {
-        hipLaunchKernelGGL(k_csr_offsets, dim3(nblk(2 * npairs, 256)), dim3(256), 0, st, t->csr, 2 * npairs, nc,
-                           t->csr_off);
+        hipLaunchKernelGGL(k_csr_offsets, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, nc, t->csr_off);
         HIPTRY(hipGetLastError());
     } else {
         HIPTRY(fill_u32(t->csr_off, nc + 1, 0u, st));
     }
-    HIPTRY(hipStreamSynchronize(st));
+    // chunk count (total[0], untouched since its scan), leaves, largest leaf
+    static_assert(sizeof(int) == sizeof(uint32_t), "layout of the count words");
+    ERRTRY(read_back(ctx, total, 18 * sizeof(uint32_t), &rb));
+    const uint32_t nchunks = ((const uint32_t*)rb)[0];
+    t->nleaves = ((const int*)rb)[16];
+    t->max_leaf = ((const int*)rb)[17];
+    t->nchunks = nchunks;
+    if ((int64_t)nchunks > chunk_cap) return Err{SPH_E_STATE, "internal: chunk count above its bound"};
+    // every non-empty leaf holds exactly one final self task
+    t->npairs = nfinal - t->nleaves;
     t->built = true;
     return Err{};
 }
@@ -1096,92 +1103,84 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     const int64_t nca = nc * NAXES;
     ERRTRY(t->alloc(t->b_segoff, sizeof(uint32_t) * std::max<int64_t>(nca, 1), (void**)&t->segoff));
     ERRTRY(t->scratch(nca + 1));
-    HIPTRY(fill_u32(t->sc_a, nca, 0, st));
-    HIPTRY(fill_u32(t->segoff, nca, 0xFFFFFFFFu, st));
-    const int64_t ne = 2 * t->npairs;
+    // which (cell, axis) lists a pair entry reads; their lengths and sort
+    // classes; offsets and class ranks by three scans over all (cell, axis)
+    // slots; one read-back of the three totals
+    uint32_t* need = t->sc_a;
+    uint32_t* mid_idx = t->sc_c;
+    uint32_t* big_idx = t->sc_d;
+    HIPTRY(fill_u32(need, nca, 0, st));
+    const int64_t ne = 2 * t->ntasks;
     if (ne > 0) {
-        hipLaunchKernelGGL(k_seg_need, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, t->sc_a);
+        hipLaunchKernelGGL(k_seg_need, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, need);
         HIPTRY(hipGetLastError());
     }
-    HIPTRY(exclusive_scan(t->sc_a, t->sc_b, nca, t->sc_tmp, total, st));
-    uint32_t ns = 0;
-    ERRTRY(read_u32(total, &ns, st));
-    t->nsegs = ns;
-    int64_t nent = 0;
-    if (ns > 0) {
-        // seglist | lengths | offsets | mid-size list | long list | long lengths
-        ERRTRY(t->alloc(t->b_seglist, sizeof(uint32_t) * ns * 6, (void**)&t->seglist));
-        uint32_t* lens = t->seglist + ns;
-        uint32_t* soff = t->seglist + 2 * (int64_t)ns;
-        uint32_t* mids = t->seglist + 3 * (int64_t)ns;
-        hipLaunchKernelGGL(k_seg_list, dim3(nblk(nca, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, nca, t->cells,
-                           t->seglist, lens);
+    if (nca > 0) {
+        hipLaunchKernelGGL(k_seg_lens, dim3(nblk(nca, 256)), dim3(256), 0, st, need, nca, t->cells, t->segoff,
+                           mid_idx, big_idx);
         HIPTRY(hipGetLastError());
-        HIPTRY(exclusive_scan(lens, soff, ns, t->sc_tmp, total, st));
-        uint32_t tot = 0;
-        ERRTRY(read_u32(total, &tot, st));
-        nent = tot;
-        hipLaunchKernelGGL(k_seg_table, dim3(nblk(ns, 256)), dim3(256), 0, st, t->seglist, soff, (int64_t)ns,
-                           t->segoff);
+    }
+    HIPTRY(exclusive_scan(t->segoff, t->segoff, nca, t->sc_tmp, total, st));
+    HIPTRY(exclusive_scan(mid_idx, mid_idx, nca, t->sc_tmp, total + 1, st));
+    HIPTRY(exclusive_scan(big_idx, big_idx, nca, t->sc_tmp, total + 2, st));
+    const void* rb;
+    ERRTRY(read_back(ctx, total, 3 * sizeof(uint32_t), &rb));
+    const uint32_t tot = ((const uint32_t*)rb)[0], nmid = ((const uint32_t*)rb)[1],
+                   nbig = ((const uint32_t*)rb)[2];
+    const int64_t nent = tot;
+    t->nsegent = nent;
+    // mid-size list | long list | long lengths
+    ERRTRY(t->alloc(t->b_seglist, sizeof(uint32_t) * ((int64_t)nmid + 2 * (int64_t)nbig + 1), (void**)&t->seglist));
+    uint32_t* mids = t->seglist;
+    uint32_t* big = t->seglist + nmid;
+    uint32_t* blen = big + nbig;
+    ERRTRY(t->alloc(t->b_segproj, sizeof(float4) * std::max<int64_t>(nent, 1), (void**)&t->segpos));
+    ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
+    if (nca > 0) {
+        hipLaunchKernelGGL(k_seg_post, dim3(nblk(nca, 256)), dim3(256), 0, st, need, nca, t->cells, t->segoff,
+                           mid_idx, big_idx, mids, big, blen);
         HIPTRY(hipGetLastError());
-        ERRTRY(t->alloc(t->b_segproj, sizeof(float4) * std::max<int64_t>(nent, 1), (void**)&t->segpos));
-        ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
+    }
+    if (nent > 0) {
         hipLaunchKernelGGL(k_cell_nsmall, dim3(nblk(nc, 4)), dim3(256), 0, st, t->d_sets, t->cells, nc, t->ph);
         hipLaunchKernelGGL(k_seg_sort_cell, dim3((unsigned)std::min<int64_t>((nc + 3) / 4, 16384)), dim3(256), 0,
                            st, nc, t->d_sets, t->cells, t->segoff, t->pos, t->ph, t->segpos, t->segidx);
         HIPTRY(hipGetLastError());
-        ERRTRY(t->scratch(std::max<int64_t>(nca, ns) + 1));
-        // segments of 65..SEG_LDS_MAX entries (LDS sort) and longer ones (one
-        // global radix sort over all of them): both classes counted at once
-        hipLaunchKernelGGL(k_mid_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_a);
-        hipLaunchKernelGGL(k_big_flag, dim3(nblk(ns, 256)), dim3(256), 0, st, lens, (int64_t)ns, t->sc_c);
-        HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ns, t->sc_tmp, total, st));
-        HIPTRY(exclusive_scan(t->sc_c, t->sc_d, ns, t->sc_tmp, total + 1, st));
-        uint32_t ncls[2] = {0, 0};
-        HIPTRY(hipMemcpyAsync(ncls, total, sizeof(ncls), hipMemcpyDeviceToHost, st));
-        HIPTRY(hipStreamSynchronize(st));
-        const uint32_t nmid = ncls[0], nbig = ncls[1];
-        if (nmid > 0) {
-            hipLaunchKernelGGL(k_compact, dim3(nblk(ns, 256)), dim3(256), 0, st, t->sc_a, t->sc_b, (int64_t)ns,
-                               mids);
-            hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)std::min<uint32_t>(nmid, 65535)), dim3(256), 0, st,
-                               mids, (int64_t)nmid, t->seglist, soff, t->d_sets, t->cells, t->pos, t->ph,
-                               t->segpos, t->segidx);
-            HIPTRY(hipGetLastError());
-        }
-        if (nbig > 0) {
-            uint32_t* big = t->seglist + 4 * (int64_t)ns;
-            uint32_t* blen = t->seglist + 5 * (int64_t)ns;
-            hipLaunchKernelGGL(k_big_list, dim3(nblk(ns, 256)), dim3(256), 0, st, t->sc_c, t->sc_d, (int64_t)ns,
-                               lens, big, blen);
-            HIPTRY(hipGetLastError());
-            uint32_t* boff = t->sc_a;   // the mid-size flags are consumed (stream order)
-            HIPTRY(exclusive_scan(blen, boff, nbig, t->sc_tmp, total, st));
-            uint32_t nbe = 0;
-            ERRTRY(read_u32(total, &nbe, st));
-            uint64_t *bk, *bk2;
-            uint32_t *bv, *bv2;
-            ERRTRY(t->alloc(t->b_bigk, sizeof(uint64_t) * nbe * 2, (void**)&bk));
-            ERRTRY(t->alloc(t->b_bigv, sizeof(uint32_t) * nbe * 2, (void**)&bv));
-            bk2 = bk + nbe;
-            bv2 = bv + nbe;
-            ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(nbe), radix_tmp_words(t->n)),
-                            (void**)&t->rs_tmp));
-            hipLaunchKernelGGL(k_big_keys, dim3(nbig), dim3(256), 0, st, big, boff, t->seglist, t->d_sets, t->cells,
-                               t->pos, t->ph, bk, bv);
-            HIPTRY(hipGetLastError());
-            int rb = 0;
-            while ((1u << rb) < nbig) ++rb;
-            bool alt = false;
-            HIPTRY(radix_sort(bk, bv, bk2, bv2, nbe, 33 + rb, t->rs_tmp, st, &alt));
-            if (alt) { bk = bk2; bv = bv2; }
-            hipLaunchKernelGGL(k_big_write, dim3(nblk(nbe, 256)), dim3(256), 0, st, bk, bv, (int64_t)nbe, boff, big,
-                               soff, t->pos, t->segpos, t->segidx);
-            HIPTRY(hipGetLastError());
-        }
     }
-    t->nsegent = nent;
-    HIPTRY(hipStreamSynchronize(st));
+    if (nmid > 0) {
+        hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)std::min<uint32_t>(nmid, 65535)), dim3(256), 0, st, mids,
+                           (int64_t)nmid, t->segoff, t->d_sets, t->cells, t->pos, t->ph, t->segpos, t->segidx);
+        HIPTRY(hipGetLastError());
+    }
+    if (nbig > 0) {
+        // lists longer than SEG_LDS_MAX: one radix sort over all of them
+        // (a second read-back, for their total length)
+        ERRTRY(t->scratch(std::max<int64_t>(nca, nbig) + 1));
+        uint32_t* boff = t->sc_b;
+        HIPTRY(exclusive_scan(blen, boff, nbig, t->sc_tmp, total, st));
+        ERRTRY(read_back(ctx, total, sizeof(uint32_t), &rb));
+        const uint32_t nbe = ((const uint32_t*)rb)[0];
+        uint64_t *bk, *bk2;
+        uint32_t *bv, *bv2;
+        ERRTRY(t->alloc(t->b_bigk, sizeof(uint64_t) * nbe * 2, (void**)&bk));
+        ERRTRY(t->alloc(t->b_bigv, sizeof(uint32_t) * nbe * 2, (void**)&bv));
+        bk2 = bk + nbe;
+        bv2 = bv + nbe;
+        ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(nbe), radix_tmp_words(t->n)),
+                        (void**)&t->rs_tmp));
+        hipLaunchKernelGGL(k_big_keys, dim3(nbig), dim3(256), 0, st, big, boff, t->d_sets, t->cells, t->pos, t->ph,
+                           bk, bv);
+        HIPTRY(hipGetLastError());
+        int rb_bits = 0;
+        while ((1u << rb_bits) < nbig) ++rb_bits;
+        bool alt = false;
+        HIPTRY(radix_sort(bk, bv, bk2, bv2, nbe, 33 + rb_bits, t->rs_tmp, st, &alt));
+        if (alt) { bk = bk2; bv = bv2; }
+        hipLaunchKernelGGL(k_big_write, dim3(nblk(nbe, 256)), dim3(256), 0, st, bk, bv, (int64_t)nbe, boff, big,
+                           t->segoff, t->pos, t->segpos, t->segidx);
+        HIPTRY(hipGetLastError());
+    }
+    HIPTRY(hipGetLastError());
     t->sorted = true;
     return Err{};
 }

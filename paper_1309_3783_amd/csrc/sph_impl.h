@@ -24,6 +24,10 @@ struct sph_ctx {
     size_t nev = 0;
     std::vector<std::pair<const char*, double>> last_ms;
     int32_t* d_counter = nullptr;   // persistent-kernel work counters
+    // pinned host memory that device counts are read back into: one
+    // asynchronous copy per read, then one stream synchronisation
+    static constexpr size_t PIN_BYTES = 65536;
+    void* h_pin = nullptr;
     hipStream_t cap_stream = nullptr; // private stream used only to capture graphs
 };
 
@@ -41,10 +45,10 @@ struct sph_tree {
     sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_pv, b_ph, b_hdec, b_pu,
         b_bound, b_mix, b_rs, b_cell, b_taskA, b_taskB, b_final, b_chunk, b_csr, b_csr2, b_csroff,
         b_segoff, b_seglist, b_segproj, b_segidx, b_bigk, b_bigv, b_sc, b_dens, b_force, b_solve,
-        b_red, b_misc, b_saved;
+        b_red, b_misc, b_saved, b_split;
 
     // ---- sizes (host) --------------------------------------------------
-    int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nsegs = 0, nchunks = 0, max_leaf = 0;
+    int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nchunks = 0, max_leaf = 0;
     int64_t nleaves = 0;
     std::vector<int64_t> lvl_start;
     int64_t sc_cap = 0;
@@ -62,6 +66,7 @@ struct sph_tree {
     uint32_t *csr_off = nullptr, *segoff = nullptr, *seglist = nullptr, *segidx = nullptr;
     float4* segpos = nullptr;   // sorted lists: the particle records (x, y, z, m) in list order
     uint32_t *sc_a = nullptr, *sc_b = nullptr, *sc_c = nullptr, *sc_d = nullptr, *sc_tmp = nullptr;
+    uint32_t* split_idx = nullptr;   // split flags of one level, scanned in place
     uint32_t* d_total = nullptr;
     int* d_maxleaf = nullptr;
     int* d_npairs = nullptr;
@@ -108,7 +113,7 @@ struct sph_tree {
         return {&b_sets, &b_small, &b_key, &b_key2, &b_val, &b_val2, &b_perm, &b_pos, &b_pv, &b_ph, &b_hdec,
                 &b_pu, &b_bound, &b_mix, &b_rs, &b_cell, &b_taskA, &b_taskB, &b_final, &b_chunk, &b_csr,
                 &b_csr2, &b_csroff, &b_segoff, &b_seglist, &b_segproj, &b_segidx, &b_bigk, &b_bigv, &b_sc,
-                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved};
+                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split};
     }
 
     void release() {
