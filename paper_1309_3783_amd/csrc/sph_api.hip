@@ -114,8 +114,6 @@ sph_status sph_tree_bytes(const sph_tree* t, size_t* bytes) {
 sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* p) {
     if (!ctx || !t) return SPH_E_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return SPH_E_HIP;
-    t->red_chunks.clear();
-    t->nred = 0;
     return fail(ctx, sph::build_tree(ctx, t, in, p));
 }
 

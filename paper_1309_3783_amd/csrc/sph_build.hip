@@ -807,6 +807,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     t->built = t->sorted = t->have_density = false;
     t->hash = (prm->flags & SPH_FLAG_PAIR_HASH) != 0;
     t->invalidate_graph();
+    ev_mark(ctx, "start");
 
     // ---- per-set h statistics -> top grids ------------------------------
     const int S = in->nsets;
@@ -1092,6 +1093,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     // every non-empty leaf holds exactly one final self task
     t->npairs = nfinal - t->nleaves;
     t->built = true;
+    ev_mark(ctx, "build");
     return Err{};
 }
 
@@ -1099,6 +1101,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     hipStream_t st = ctx->stream;
     if (!t->built) return Err{SPH_E_STATE, "sort_pairs before build_cells"};
     t->invalidate_graph();
+    ev_mark(ctx, "start");
     const int64_t nc = t->ncells;
     const int64_t nca = nc * NAXES;
     ERRTRY(t->alloc(t->b_segoff, sizeof(uint32_t) * std::max<int64_t>(nca, 1), (void**)&t->segoff));
@@ -1182,6 +1185,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     }
     HIPTRY(hipGetLastError());
     t->sorted = true;
+    ev_mark(ctx, "sort");
     return Err{};
 }
 #undef total

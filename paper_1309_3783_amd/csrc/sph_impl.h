@@ -53,6 +53,7 @@ struct sph_tree {
     std::vector<int64_t> lvl_start;
     int64_t sc_cap = 0;
     std::vector<int4> red_chunks;   // (set, first, count, 0) reduction chunks
+    std::vector<int64_t> red_off;   // the set offsets red_chunks was made for
     int64_t nred = 0;
 
     // ---- device views --------------------------------------------------
@@ -118,6 +119,7 @@ struct sph_tree {
 
     void release() {
         invalidate_graph();
+        red_off.clear();
         for (const sph::DevBuf* d : bufs()) {
             sph::DevBuf* m = const_cast<sph::DevBuf*>(d);
             if (m->p) (void)hipFree(m->p);
@@ -214,6 +216,22 @@ struct sph_tree {
 };
 
 namespace sph {
+// Stage events: ev_mark records the end of a stage (a call's first mark,
+// "start", opens it); nothing is synchronised here, the intervals are
+// computed when the timings are read.
+inline void ev_mark(sph_ctx* ctx, const char* name) {
+    if (!ctx->timing) return;
+    if (ctx->nev == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        ctx->ev_pool.push_back(e);
+        ctx->ev_name.push_back(name);
+    }
+    ctx->ev_name[ctx->nev] = name;
+    (void)hipEventRecord(ctx->ev_pool[ctx->nev], ctx->stream);
+    ++ctx->nev;
+}
+
 Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* prm);
 Err sort_pairs(sph_ctx* ctx, sph_tree* t);
 Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out);

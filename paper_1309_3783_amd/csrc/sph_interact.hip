@@ -299,33 +299,41 @@ __device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, i
 // interaction-list entries of one cell at a time, built with one entry per
 // lane (all the loads and the geometry of the batch in one round instead of
 // a chain of dependent loads and uniform float arithmetic per entry), two
-// descriptors per entry (small-h and large-h part of the partner's list):
-//   q: first list position, length, sweep direction (+1/-1), offset code;
-//   f: shift S added to the partner's positions, and the sweep limit -- the
-//      largest o.y that a point y within the cutoff of a particle of the
-//      chunk can have, o the offset direction of the pair (a record is a
-//      candidate while o.(p + S) stays below it).
+// per entry (small-h and large-h part of the partner's list).  The sweep of
+// a part covers the records whose o.(p + S) stays below the sweep limit --
+// the largest o.y that a point y within the cutoff of a particle of the
+// chunk can have, o the offset direction of the pair, S the shift into the
+// target's frame.  The list is sorted along o, so these records form a
+// prefix of the part in sweep order; its length is found by bisection, one
+// part per lane.  Only parts with records keep a descriptor:
+//   q: first list position, part length, sweep direction (+1/-1), 0;
+//   f: the shift S;
+//   o: number of records of the parts before (o[nd] = all of them),
+// so that the records of all parts of the batch form one sequence that
+// the walk stages a tile at a time.
 constexpr int DBATCH = 32;
 struct SweepTab {
     int4 q[2 * DBATCH];
     float4 f[2 * DBATCH];
+    int o[2 * DBATCH + 1];
 };
 
-// Builds the descriptors of entries [e0, e0 + n) of cell cA (n <= DBATCH)
-// and returns their number (parts without records get none; the others keep
-// the entry order, part 0 first).  box: largest o_k x_k over the chunk's
-// particles per axis and sign (bx[0..2] = max x, bx[3..5] = -min x); hmax:
-// largest h of the chunk.
+// Builds the descriptors of entries [e0, e0 + n) of cell cA (n <= DBATCH);
+// returns their number, *total the number of records they cover.  bx:
+// largest o_k x_k over the chunk's particles per axis and sign (bx[0..2] =
+// max x, bx[3..5] = -min x); hmax: largest h of the chunk.
 template <class P>
 __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cell& cA, float L0, uint32_t e0, int n,
-                                            const float (&bx)[6], float hmax, SweepTab& T) {
+                                            const float (&bx)[6], float hmax, SweepTab& T, int* total) {
     const int lane = threadIdx.x & 63;
     int4 q0 = make_int4(0, 0, 0, 0), q1 = q0;
-    float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0;
+    float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float lim0 = 0.f, lim1 = 0.f;
+    int code = 13;
     if (lane < n) {
         const uint64_t key = a.csr[e0 + lane];
         const int B = (int)((key >> 5) & 0xFFFFFFFFull);
-        const int code = (int)(key & 31);
+        code = (int)(key & 31);
         const PairGeo g = pair_geo(cA, code, L0);
         const Cell cB = a.cells[B];
         const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
@@ -335,33 +343,65 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
         const float tb = (ox > 0 ? bx[0] : (ox < 0 ? bx[3] : 0.f)) + (oy > 0 ? bx[1] : (oy < 0 ? bx[4] : 0.f)) +
                          (oz > 0 ? bx[2] : (oz < 0 ? bx[5] : 0.f));
         const float tiny = 1e-5f * L0;
-        q0 = make_int4((int)so, cB.nsmall, g.sign, code);
-        q1 = make_int4((int)so + cB.nsmall, cB.count - cB.nsmall, g.sign, code);
-        f0 = make_float4(g.Sx, g.Sy, g.Sz, tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny));
-        f1 = make_float4(g.Sx, g.Sy, g.Sz, tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny));
+        q0 = make_int4((int)so, cB.nsmall, g.sign, 0);
+        q1 = make_int4((int)so + cB.nsmall, cB.count - cB.nsmall, g.sign, 0);
+        f0 = make_float4(g.Sx, g.Sy, g.Sz, 0.f);
+        lim0 = tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny);
+        lim1 = tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny);
     }
-    const bool ne0 = q0.y > 0, ne1 = q1.y > 0;
+    // the swept prefix of each part: the first record (in sweep order)
+    // beyond the limit, by bisection
+    const float fox = (float)ocx(code), foy = (float)ocy(code), foz = (float)ocz(code);
+    auto prefix = [&](const int4& q, float lim) {
+        int lo = 0, hi = q.y;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const float4 p = a.segpos[(uint32_t)q.x + (uint32_t)(q.z > 0 ? mid : q.y - 1 - mid)];
+            const float t = fmaf(fox, p.x + f0.x, fmaf(foy, p.y + f0.y, foz * (p.z + f0.z)));
+            if (t <= lim) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    const int c0 = prefix(q0, lim0), c1 = prefix(q1, lim1);
+    const bool ne0 = c0 > 0, ne1 = c1 > 0;
     const uint64_t b0 = __ballot(ne0), b1 = __ballot(ne1);
     const uint64_t below = (1ull << lane) - 1ull;
     const int pos = __popcll(b0 & below) + __popcll(b1 & below);
+    // records of the parts before this lane's: inclusive scan of c0 + c1
+    int cs = c0 + c1;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(cs, d, 64);
+        if (lane >= d) cs += v;
+    }
+    const int before = cs - c0 - c1;
     if (ne0) {
         T.q[pos] = q0;
         T.f[pos] = f0;
+        T.o[pos] = before;
     }
     if (ne1) {
-        T.q[pos + (ne0 ? 1 : 0)] = q1;
-        T.f[pos + (ne0 ? 1 : 0)] = f1;
+        const int p1 = pos + (ne0 ? 1 : 0);
+        T.q[p1] = q1;
+        T.f[p1] = f0;
+        T.o[p1] = before + c0;
     }
+    const int nd = __popcll(b0) + __popcll(b1);
+    const int all = __shfl(cs, 63, 64);
+    if (lane == 0) T.o[nd] = all;
     wave_lds_sync();
-    return __popcll(b0) + __popcll(b1);
+    *total = all;
+    return nd;
 }
 
 // The walk of one chunk: the leaf's self task, then the pair tasks of the
 // leaf and of its ancestors; each pair task sweeps the partner's sorted
 // list (small-h part, then large-h part) up to the largest reach of the
 // chunk along the pair axis, bounded by the bounding box of its particles
-// plus the largest cutoff.  Written as one loop over blocks of up to 64
-// records, so that the tile processing is inlined once.
+// plus the largest cutoff.  The swept records of a batch of pair tasks are
+// staged in sequence, each step filling the current tile; written as one
+// loop so that the tile processing is inlined once.
 template <class P>
 __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds& S, SweepTab& T,
                                      const typename P::Lane& L, typename P::Acc& acc, int leaf, int R, int rep,
@@ -384,108 +424,75 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
     Cell cA = C;
     float L0 = (float)a.sets[C.set].L0;
     uint32_t e = a.csr_off[A], e1 = a.csr_off[A + 1];
-    int nd = 0, di = 0, base = 0;        // descriptors loaded, current one, position in it
+    int nd = 0, tot = 0, g0 = 0;     // descriptors of the batch, their records, records staged
     int fill = 0;
     bool tself = false;   // the current tile holds a self-task block
-    // the records of the next block are loaded one block ahead (pdi, pbase:
-    // its descriptor and position; pdi < 0: none in flight)
-    int pdi = -1, pbase = 0;
-    float4 ppj = make_float4(0.f, 0.f, 0.f, 0.f);
-    uint32_t pqq = 0;
-    auto load_block = [&](int d, int b, float4& pj, uint32_t& qq) {
-        const int4 dq = T.q[d];
-        const int qs = uni(dq.x), len = uni(dq.y), dir = uni(dq.z);
-        if (lane < min(64, len - b)) {
-            const uint32_t q = (uint32_t)qs + (uint32_t)(dir > 0 ? b + lane : len - 1 - b - lane);
-            pj = a.segpos[q];
-            qq = a.segidx[q];
-        }
-    };
     for (;;) {
         bool done = false, self = false;
         int nuse = 0;
-        uint32_t qq = 0;
+        uint32_t j = 0;                     // the lane's record: particle, position, shift
         float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
         float Sx = 0.f, Sy = 0.f, Sz = 0.f;
         if (sbase < cend) {
+            // a block of the self task (a tile holds whole self blocks)
             nuse = min(64, cend - sbase);
-            qq = (uint32_t)(sbase + lane);
-            if (lane < nuse) pj = a.pos[qq];
+            j = (uint32_t)(sbase + lane);
+            if (lane < nuse) pj = a.pos[j];
             self = true;
             sbase += nuse;
         } else {
-            if (di >= nd) {
-                // next batch of entries: of this cell, or of its ancestors
-                // (a batch may have no records at all)
-                while (di >= nd) {
-                    while (e >= e1 && A >= 0) {
-                        A = cA.parent;
-                        if (A >= 0) {
-                            cA = a.cells[A];
-                            L0 = (float)a.sets[cA.set].L0;
-                            e = a.csr_off[A];
-                            e1 = a.csr_off[A + 1];
-                        }
+            // next batch of entries: of this cell, or of its ancestors
+            // (a batch may sweep no records at all)
+            while (g0 >= tot) {
+                while (e >= e1 && A >= 0) {
+                    A = cA.parent;
+                    if (A >= 0) {
+                        cA = a.cells[A];
+                        L0 = (float)a.sets[cA.set].L0;
+                        e = a.csr_off[A];
+                        e1 = a.csr_off[A + 1];
                     }
-                    if (A < 0) {
-                        done = true;
-                        break;
-                    }
-                    const int n = (int)min(e1 - e, (uint32_t)DBATCH);
-                    nd = build_sweeps<P>(a, cA, L0, e, n, bx, hmax, T);
-                    e += n;
-                    di = 0;
-                    base = 0;
-                    pdi = -1;
                 }
+                if (A < 0) {
+                    done = true;
+                    break;
+                }
+                const int n = (int)min(e1 - e, (uint32_t)DBATCH);
+                nd = build_sweeps<P>(a, cA, L0, e, n, bx, hmax, T, &tot);
+                e += n;
+                g0 = 0;
             }
-            if (!done) {
-                const int4 dq = T.q[di];
-                const int len = uni(dq.y), code = uni(dq.w);
-                const float4 df = T.f[di];
-                Sx = unif(df.x);
-                Sy = unif(df.y);
-                Sz = unif(df.z);
-                const float tlim = unif(df.w);
-                const int nsrc = min(64, len - base);
-                if (pdi == di && pbase == base) {
-                    pj = ppj;
-                    qq = pqq;
-                } else {
-                    load_block(di, base, pj, qq);
+            // the next records of the batch's sequence, up to a full tile
+            // (the next one if this one is full: it is processed first)
+            if (!done) nuse = min(fill == TCAP ? TCAP : TCAP - fill, tot - g0);
+            if (lane < nuse) {
+                const int g = g0 + lane;
+                int lo = 0, hi = nd - 1;   // the last part starting at or before g
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (T.o[mid] <= g) lo = mid;
+                    else hi = mid - 1;
                 }
-                // the next block: further along this list, or the next list
-                pdi = di;
-                pbase = base + 64;
-                if (pbase >= len) {
-                    pdi = di + 1;
-                    pbase = 0;
-                }
-                if (pdi < nd) load_block(pdi, pbase, ppj, pqq);
-                else pdi = -1;
-                const float fox = (float)ocx(code), foy = (float)ocy(code), foz = (float)ocz(code);
-                bool ok = false;
-                if (lane < nsrc) {
-                    const float t = fmaf(fox, pj.x + Sx, fmaf(foy, pj.y + Sy, foz * (pj.z + Sz)));
-                    ok = t <= tlim;
-                }
-                const uint64_t okm = __ballot(ok);
-                // the prefix in sweep order is staged; the sweep ends at its end
-                nuse = okm == ~0ull ? 64 : __builtin_ctzll(~okm);
-                base = nuse < nsrc ? len : base + 64;
-                if (base >= len) {
-                    ++di;
-                    base = 0;
-                }
+                const int4 dq = T.q[lo];
+                const float4 df = T.f[lo];
+                const int k = g - T.o[lo];
+                const uint32_t q = (uint32_t)dq.x + (uint32_t)(dq.z > 0 ? k : dq.y - 1 - k);
+                pj = a.segpos[q];
+                j = a.segidx[q];
+                Sx = df.x;
+                Sy = df.y;
+                Sz = df.z;
             }
+            g0 += nuse;
         }
+        // the records just loaded are in flight while a full tile is processed
         if (done || fill + nuse > TCAP) {
             if (fill > 0) process_tile<P>(S, fill, R, rep, L, acc, tself);
             fill = 0;
             tself = false;
         }
         if (done) break;
-        if (lane < nuse) P::stage(S, fill + lane, qq, pj, Sx, Sy, Sz, a);
+        if (lane < nuse) P::stage(S, fill + lane, j, pj, Sx, Sy, Sz, a);
         tself = tself || self;
         fill += nuse;
     }
@@ -691,7 +698,7 @@ struct ForceP {
 };
 
 template <bool HASH>
-__global__ __launch_bounds__(BLK) void k_force(ForceArgs a) {
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k_force(ForceArgs a) {
     using P = ForceP<HASH>;
     __shared__ typename P::Lds s_l[BLK / 64];
     __shared__ SweepTab s_t[BLK / 64];
@@ -1113,7 +1120,8 @@ static Err ensure_state(sph_tree* t) {
     t->fS = t->fvs + n;
     t->fn = (int32_t*)(t->fS + n);
     // reduction chunks: RED_CHUNK particles of one set each
-    if (t->red_chunks.empty()) {
+    if (t->red_off != t->off) {
+        t->red_chunks.clear();
         for (int s = 0; s < t->nsets; ++s) {
             int64_t a = t->off[s], b = t->off[s + 1];
             if (a == b) t->red_chunks.push_back(make_int4(s, (int)a, 0, 0));
@@ -1128,25 +1136,11 @@ static Err ensure_state(sph_tree* t) {
         t->d_red = (int4*)(t->sums_int + (int64_t)t->nsets * NRED);
         t->part_cnt = (int32_t*)(t->d_red + t->nred);
         HIPTRY(hipMemcpy(t->d_red, t->red_chunks.data(), sizeof(int4) * t->nred, hipMemcpyHostToDevice));
+        t->red_off = t->off;
     }
     return Err{};
 }
 
-// Stage events: ev_mark records the end of a stage (a call's first mark,
-// "start", opens it); nothing is synchronised here, the intervals are
-// computed when the timings are read.
-static void ev_mark(sph_ctx* ctx, const char* name) {
-    if (!ctx->timing) return;
-    if (ctx->nev == ctx->ev_pool.size()) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        ctx->ev_pool.push_back(e);
-        ctx->ev_name.push_back(name);
-    }
-    ctx->ev_name[ctx->nev] = name;
-    (void)hipEventRecord(ctx->ev_pool[ctx->nev], ctx->stream);
-    ++ctx->nev;
-}
 
 static int rmax_of(const sph_tree* t) {
     int r = t->prm.max_replicas;
