@@ -210,7 +210,8 @@ void sph_enable_timing(sph_ctx* ctx, int32_t on);
 
 /* Tree statistics (host): [0] particles, [1] cells, [2] leaves, [3] tasks
  * (self + pair), [4] pair tasks, [5] sorted entries, [6] work chunks,
- * [7] levels, [8] top cells per side of set 0, [9] max leaf size. */
+ * [7] levels, [8] top cells per side of set 0, [9] max leaf size.  May
+ * synchronise the device (a count the sort kept on the device). */
 sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap);
 
 #ifdef __cplusplus

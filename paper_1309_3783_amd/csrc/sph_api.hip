@@ -174,6 +174,14 @@ void sph_enable_timing(sph_ctx* ctx, int32_t on) {
 
 sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap) {
     if (!t || !stats) return SPH_E_ARG;
+    if (t->nsegent < 0 && t->d_counts) {
+        // the sort kept its entry count on the device
+        uint32_t v = 0;
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemcpy(&v, t->d_counts, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+            return SPH_E_HIP;
+        const_cast<sph_tree*>(t)->nsegent = v;
+    }
     int64_t v[10] = {t->n,
                      t->ncells,
                      t->nleaves,

@@ -558,8 +558,14 @@ __global__ void k_seg_lens(const uint32_t* __restrict__ need, int64_t nca, const
     if (q >= nca) return;
     const uint32_t n = need[q] ? (uint32_t)cells[q / NAXES].count : 0u;
     lens[q] = n;
-    mid[q] = (n > 64u && n <= (uint32_t)SEG_LDS_MAX) ? 1u : 0u;
-    big[q] = n > (uint32_t)SEG_LDS_MAX ? 1u : 0u;
+    if (mid) {   // null when no list can exceed 64 entries
+        mid[q] = (n > 64u && n <= (uint32_t)SEG_LDS_MAX) ? 1u : 0u;
+        big[q] = n > (uint32_t)SEG_LDS_MAX ? 1u : 0u;
+    }
+}
+
+__global__ void k_copy_u32(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int n) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
 }
 
 // After the scans: lists nobody needs get offset ~0; the mid-size and long
@@ -574,6 +580,7 @@ __global__ void k_seg_post(const uint32_t* __restrict__ need, int64_t nca, const
         segoff[q] = 0xFFFFFFFFu;
         return;
     }
+    if (!mids) return;   // no list exceeds 64 entries
     const uint32_t n = (uint32_t)cells[q / NAXES].count;
     if (n > 64u && n <= (uint32_t)SEG_LDS_MAX) {
         mids[mid_idx[q]] = (uint32_t)q;
@@ -816,6 +823,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     int* d_bad;
     SetInfo* d_sets;
     ERRTRY(t->alloc(t->b_sets, sizeof(SetInfo) * S, (void**)&d_sets));
+    ERRTRY(t->alloc(t->b_counts, 64 * sizeof(uint32_t), (void**)&t->d_counts));
     ERRTRY(t->alloc(t->b_small, 2 * sizeof(float) * S + sizeof(int) * S + 64, (void**)&d_hmax));
     d_hmin = d_hmax + S;
     d_bad = (int*)(d_hmin + S);
@@ -833,7 +841,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         HIPTRY(fill_u32((uint32_t*)d_hmin, S, 0x7F800000u, st));   // +inf
         int64_t maxc = 0;
         for (int s = 0; s < S; ++s) maxc = std::max<int64_t>(maxc, sets[s].count);
-        unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((maxc + 8191) / 8192, 1), 256);
+        unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((maxc + 1023) / 1024, 1), 1024);
         hipLaunchKernelGGL(k_set_hstats, dim3(gx, S), dim3(256), 0, st, d_sets, in->h, (int*)d_hmax, (int*)d_hmin,
                            d_bad);
         HIPTRY(hipGetLastError());
@@ -971,7 +979,8 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
 
     // One read-back per level: the task counts of this level and the split
     // count of the next, whose cells exist before this level's tasks are
-    // decided (a task splits into tasks of the children).
+    // decided (a task splits into tasks of the children).  A level without
+    // split cells ends the loop: its tasks are all final.
     int level = 0;
     for (;; ++level) {
         const int64_t c0 = t->lvl_start[level], c1 = t->lvl_start[level + 1];
@@ -1000,6 +1009,23 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         }
         t->lvl_start.push_back(c1 + nnext);
         if (ncur == 0 && nsplit == 0) break;
+        if (nsplit == 0) {
+            // no cell of this level splits: every task of the level is final
+            // (only tasks of split cells are replaced), in task order
+            if (nfinal == 0) {
+                std::swap(t->finals, t->taskA);
+                std::swap(t->b_final, t->b_taskA);
+            } else {
+                ERRTRY(t->grow(t->b_final, sizeof(int4) * nfinal, sizeof(int4) * (nfinal + ncur),
+                               (void**)&t->finals));
+                HIPTRY(hipMemcpyAsync(t->finals + nfinal, t->taskA, sizeof(int4) * ncur, hipMemcpyDeviceToDevice,
+                                      st));
+            }
+            if (nfinal + ncur > (int64_t)0x7FFFFFFF) return Err{SPH_E_CAPACITY, "too many tasks"};
+            nfinal += ncur;
+            ncur = 0;
+            break;
+        }
         if (ncur > 0) {
             hipLaunchKernelGGL(k_task_decide, dim3(nblk(ncur, 256)), dim3(256), 0, st, d_sets, t->taskA, ncur,
                                t->cells, t->sc_a, t->sc_c);
@@ -1010,7 +1036,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         ERRTRY(read_back(ctx, total, 3 * sizeof(uint32_t), &rb));
         const uint32_t nf = ncur > 0 ? ((const uint32_t*)rb)[0] : 0u;
         const uint32_t nc = ncur > 0 ? ((const uint32_t*)rb)[1] : 0u;
-        const uint32_t nsplit_next = nsplit > 0 ? ((const uint32_t*)rb)[2] : 0u;
+        const uint32_t nsplit_next = ((const uint32_t*)rb)[2];
         if (ncur > 0) {
             if (nfinal + nf > (int64_t)0x7FFFFFFF) return Err{SPH_E_CAPACITY, "too many tasks"};
             ERRTRY(t->grow(t->b_final, sizeof(int4) * nfinal, sizeof(int4) * std::max<int64_t>(nfinal + nf, 1),
@@ -1023,12 +1049,6 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
             std::swap(t->taskA, t->taskB);
             std::swap(t->b_taskA, t->b_taskB);
             ncur = nc;
-        }
-        if (nsplit == 0 && ncur == 0) break;
-        if (nsplit == 0 && ncur > 0) {
-            // no deeper cells: remaining tasks cannot split further
-            // (k_task_decide only splits tasks of split cells)
-            return Err{SPH_E_STATE, "internal: tasks left without split cells"};
         }
         nsplit = nsplit_next;
     }
@@ -1107,8 +1127,13 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     ERRTRY(t->alloc(t->b_segoff, sizeof(uint32_t) * std::max<int64_t>(nca, 1), (void**)&t->segoff));
     ERRTRY(t->scratch(nca + 1));
     // which (cell, axis) lists a pair entry reads; their lengths and sort
-    // classes; offsets and class ranks by three scans over all (cell, axis)
-    // slots; one read-back of the three totals
+    // classes; offsets and class ranks by scans over all (cell, axis)
+    // slots.  A tree of one level whose leaves hold at most 64 particles
+    // has no list longer than 64 and at most 13 n entries: its lists are
+    // placed without reading anything back (the exact entry count is kept
+    // on the device for the statistics).  Otherwise one read-back of the
+    // entry count and of the two class counts.
+    const bool flat = t->nlevels == 1 && t->max_leaf <= 64;
     uint32_t* need = t->sc_a;
     uint32_t* mid_idx = t->sc_c;
     uint32_t* big_idx = t->sc_d;
@@ -1120,18 +1145,27 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     }
     if (nca > 0) {
         hipLaunchKernelGGL(k_seg_lens, dim3(nblk(nca, 256)), dim3(256), 0, st, need, nca, t->cells, t->segoff,
-                           mid_idx, big_idx);
+                           flat ? nullptr : mid_idx, flat ? nullptr : big_idx);
         HIPTRY(hipGetLastError());
     }
     HIPTRY(exclusive_scan(t->segoff, t->segoff, nca, t->sc_tmp, total, st));
-    HIPTRY(exclusive_scan(mid_idx, mid_idx, nca, t->sc_tmp, total + 1, st));
-    HIPTRY(exclusive_scan(big_idx, big_idx, nca, t->sc_tmp, total + 2, st));
-    const void* rb;
-    ERRTRY(read_back(ctx, total, 3 * sizeof(uint32_t), &rb));
-    const uint32_t tot = ((const uint32_t*)rb)[0], nmid = ((const uint32_t*)rb)[1],
-                   nbig = ((const uint32_t*)rb)[2];
-    const int64_t nent = tot;
-    t->nsegent = nent;
+    uint32_t nmid = 0, nbig = 0;
+    int64_t nent = 0;
+    if (flat) {
+        hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, st, total, t->d_counts, 1);
+        HIPTRY(hipGetLastError());
+        nent = NAXES * t->n;   // bound
+        t->nsegent = -1;       // exact count on the device
+    } else {
+        HIPTRY(exclusive_scan(mid_idx, mid_idx, nca, t->sc_tmp, total + 1, st));
+        HIPTRY(exclusive_scan(big_idx, big_idx, nca, t->sc_tmp, total + 2, st));
+        const void* rb;
+        ERRTRY(read_back(ctx, total, 3 * sizeof(uint32_t), &rb));
+        nent = ((const uint32_t*)rb)[0];
+        nmid = ((const uint32_t*)rb)[1];
+        nbig = ((const uint32_t*)rb)[2];
+        t->nsegent = nent;
+    }
     // mid-size list | long list | long lengths
     ERRTRY(t->alloc(t->b_seglist, sizeof(uint32_t) * ((int64_t)nmid + 2 * (int64_t)nbig + 1), (void**)&t->seglist));
     uint32_t* mids = t->seglist;
@@ -1141,7 +1175,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     ERRTRY(t->alloc(t->b_segidx, sizeof(uint32_t) * std::max<int64_t>(nent, 1), (void**)&t->segidx));
     if (nca > 0) {
         hipLaunchKernelGGL(k_seg_post, dim3(nblk(nca, 256)), dim3(256), 0, st, need, nca, t->cells, t->segoff,
-                           mid_idx, big_idx, mids, big, blen);
+                           mid_idx, big_idx, flat ? nullptr : mids, big, blen);
         HIPTRY(hipGetLastError());
     }
     if (nent > 0) {
@@ -1158,6 +1192,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     if (nbig > 0) {
         // lists longer than SEG_LDS_MAX: one radix sort over all of them
         // (a second read-back, for their total length)
+        const void* rb;
         ERRTRY(t->scratch(std::max<int64_t>(nca, nbig) + 1));
         uint32_t* boff = t->sc_b;
         HIPTRY(exclusive_scan(blen, boff, nbig, t->sc_tmp, total, st));

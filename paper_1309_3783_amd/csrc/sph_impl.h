@@ -45,7 +45,7 @@ struct sph_tree {
     sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_pv, b_ph, b_hdec, b_pu,
         b_bound, b_mix, b_rs, b_cell, b_taskA, b_taskB, b_final, b_chunk, b_csr, b_csr2, b_csroff,
         b_segoff, b_seglist, b_segproj, b_segidx, b_bigk, b_bigv, b_sc, b_dens, b_force, b_solve,
-        b_red, b_misc, b_saved, b_split;
+        b_red, b_misc, b_saved, b_split, b_counts;
 
     // ---- sizes (host) --------------------------------------------------
     int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nchunks = 0, max_leaf = 0;
@@ -68,6 +68,7 @@ struct sph_tree {
     float4* segpos = nullptr;   // sorted lists: the particle records (x, y, z, m) in list order
     uint32_t *sc_a = nullptr, *sc_b = nullptr, *sc_c = nullptr, *sc_d = nullptr, *sc_tmp = nullptr;
     uint32_t* split_idx = nullptr;   // split flags of one level, scanned in place
+    uint32_t* d_counts = nullptr;    // [0] sorted-list entries when not read back (nsegent < 0)
     uint32_t* d_total = nullptr;
     int* d_maxleaf = nullptr;
     int* d_npairs = nullptr;
@@ -114,7 +115,7 @@ struct sph_tree {
         return {&b_sets, &b_small, &b_key, &b_key2, &b_val, &b_val2, &b_perm, &b_pos, &b_pv, &b_ph, &b_hdec,
                 &b_pu, &b_bound, &b_mix, &b_rs, &b_cell, &b_taskA, &b_taskB, &b_final, &b_chunk, &b_csr,
                 &b_csr2, &b_csroff, &b_segoff, &b_seglist, &b_segproj, &b_segidx, &b_bigk, &b_bigv, &b_sc,
-                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split};
+                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts};
     }
 
     void release() {
