@@ -639,11 +639,11 @@ __global__ __launch_bounds__(256) void k_seg_sort_cell(int64_t nc, const SetInfo
                                                        const uint32_t* __restrict__ segoff,
                                                        const float4* __restrict__ pos, const float* __restrict__ ph,
                                                        float4* __restrict__ sproj, uint32_t* __restrict__ sidx) {
-    __shared__ uint64_t s_key[4][64];
+    __shared__ __align__(16) uint64_t s_key[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int64_t c = (int64_t)blockIdx.x * 4 + w; c < nc; c += (int64_t)gridDim.x * 4) {
         const Cell C = cells[c];
-        const int n = C.count;
+        const int n = __builtin_amdgcn_readfirstlane(C.count);
         if (n == 0 || n > 64) continue;
         const uint32_t so_l = lane < NAXES ? segoff[c * NAXES + lane] : 0xFFFFFFFFu;
         uint64_t need = __ballot(so_l != 0xFFFFFFFFu);
@@ -668,9 +668,16 @@ __global__ __launch_bounds__(256) void k_seg_sort_cell(int64_t nc, const SetInfo
             const uint64_t k = act ? seg_key(project(rec, ax), cls, (uint32_t)e) : ~0ull;
             s_key[w][lane] = k;
             wave_lds_sync();
+            // rank: keys of the list below this one (two keys per LDS read,
+            // several reads in flight; the keys past n are ~0)
             const int first = upper ? 32 : 0;
+            const ulonglong2* kp = (const ulonglong2*)&s_key[w][first];
             int rank = 0;
-            for (int t = 0; t < n; ++t) rank += s_key[w][first + t] < k ? 1 : 0;
+#pragma unroll 4
+            for (int t = 0; t < (n + 1) >> 1; ++t) {
+                const ulonglong2 kk = kp[t];
+                rank += (kk.x < k ? 1 : 0) + (kk.y < k ? 1 : 0);
+            }
             const uint32_t o0 = (uint32_t)__builtin_amdgcn_readlane((int)so_l, a0);
             const uint32_t o1 = a1 >= 0 ? (uint32_t)__builtin_amdgcn_readlane((int)so_l, a1) : 0u;
             if (act) {
