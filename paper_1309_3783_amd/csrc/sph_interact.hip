@@ -307,10 +307,11 @@ __device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, i
 // prefix of the part in sweep order; its length is found by bisection, one
 // part per lane.  Only parts with records keep a descriptor:
 //   q: first list position, part length, sweep direction (+1/-1), 0;
-//   f: the shift S;
+//   f: the shift S and the square of the part's cutoff radius around the
+//      chunk's bounding box (with a rounding margin);
 //   o: number of records of the parts before (o[nd] = all of them),
 // so that the records of all parts of the batch form one sequence that
-// the walk stages a tile at a time.
+// the walk loads 64 at a time.
 constexpr int DBATCH = 32;
 struct SweepTab {
     int4 q[2 * DBATCH];
@@ -327,7 +328,7 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
                                             const float (&bx)[6], float hmax, SweepTab& T, int* total) {
     const int lane = threadIdx.x & 63;
     int4 q0 = make_int4(0, 0, 0, 0), q1 = q0;
-    float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0;
     float lim0 = 0.f, lim1 = 0.f;
     int code = 13;
     if (lane < n) {
@@ -345,7 +346,10 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
         const float tiny = 1e-5f * L0;
         q0 = make_int4((int)so, cB.nsmall, g.sign, 0);
         q1 = make_int4((int)so + cB.nsmall, cB.count - cB.nsmall, g.sign, 0);
-        f0 = make_float4(g.Sx, g.Sy, g.Sz, 0.f);
+        const float r0 = fmaf(P::cut(hmax, cB.hcur), 1.000002f, tiny);
+        const float r1 = fmaf(P::cut(hmax, cB.hcur_l), 1.000002f, tiny);
+        f0 = make_float4(g.Sx, g.Sy, g.Sz, r0 * r0);
+        f1 = make_float4(g.Sx, g.Sy, g.Sz, r1 * r1);
         lim0 = tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny);
         lim1 = tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny);
     }
@@ -384,7 +388,7 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
     if (ne1) {
         const int p1 = pos + (ne0 ? 1 : 0);
         T.q[p1] = q1;
-        T.f[p1] = f0;
+        T.f[p1] = f1;
         T.o[p1] = before + c0;
     }
     const int nd = __popcll(b0) + __popcll(b1);
@@ -424,20 +428,29 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
     Cell cA = C;
     float L0 = (float)a.sets[C.set].L0;
     uint32_t e = a.csr_off[A], e1 = a.csr_off[A + 1];
-    int nd = 0, tot = 0, g0 = 0;     // descriptors of the batch, their records, records staged
+    int nd = 0, tot = 0, g0 = 0;     // descriptors of the batch, their records, records loaded
     int fill = 0;
-    bool tself = false;   // the current tile holds a self-task block
+    bool tself = false;   // the current tile holds records of the self task
+    // a record is staged only if it lies within the cutoff of the chunk's
+    // bounding box (the sweep bounds the distance along the pair axis only)
+    const float lox = -bx[3], loy = -bx[4], loz = -bx[5];
+    const float rs = fmaf(P::cut(hmax, fmaxf(C.hcur, C.hcur_l)), 1.000002f, 1e-5f * L0);
+    const float rself2 = rs * rs;
     for (;;) {
         bool done = false, self = false;
         int nuse = 0;
-        uint32_t j = 0;                     // the lane's record: particle, position, shift
+        uint32_t j = 0;                     // the lane's record: particle, position, shift, radius^2
         float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
-        float Sx = 0.f, Sy = 0.f, Sz = 0.f;
+        float Sx = 0.f, Sy = 0.f, Sz = 0.f, rad2 = 0.f;
+        uint32_t q = 0;                     // where it was read: list position (or particle) and part
+        int dl = -1;
         if (sbase < cend) {
-            // a block of the self task (a tile holds whole self blocks)
+            // a block of the self task
             nuse = min(64, cend - sbase);
             j = (uint32_t)(sbase + lane);
+            q = j;
             if (lane < nuse) pj = a.pos[j];
+            rad2 = rself2;
             self = true;
             sbase += nuse;
         } else {
@@ -462,9 +475,8 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
                 e += n;
                 g0 = 0;
             }
-            // the next records of the batch's sequence, up to a full tile
-            // (the next one if this one is full: it is processed first)
-            if (!done) nuse = min(fill == TCAP ? TCAP : TCAP - fill, tot - g0);
+            // the next 64 records of the batch's sequence
+            if (!done) nuse = min(64, tot - g0);
             if (lane < nuse) {
                 const int g = g0 + lane;
                 int lo = 0, hi = nd - 1;   // the last part starting at or before g
@@ -476,25 +488,52 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
                 const int4 dq = T.q[lo];
                 const float4 df = T.f[lo];
                 const int k = g - T.o[lo];
-                const uint32_t q = (uint32_t)dq.x + (uint32_t)(dq.z > 0 ? k : dq.y - 1 - k);
+                q = (uint32_t)dq.x + (uint32_t)(dq.z > 0 ? k : dq.y - 1 - k);
+                dl = lo;
                 pj = a.segpos[q];
                 j = a.segidx[q];
                 Sx = df.x;
                 Sy = df.y;
                 Sz = df.z;
+                rad2 = df.w;
             }
             g0 += nuse;
         }
-        // the records just loaded are in flight while a full tile is processed
-        if (done || fill + nuse > TCAP) {
+        // the records within reach, packed: the first ones complete the
+        // current tile, the others start the next
+        bool ok = false;
+        if (lane < nuse) {
+            const float px = pj.x + Sx, py = pj.y + Sy, pz = pj.z + Sz;
+            const float ex = fmaxf(fmaxf(lox - px, px - bx[0]), 0.f);
+            const float ey = fmaxf(fmaxf(loy - py, py - bx[1]), 0.f);
+            const float ez = fmaxf(fmaxf(loz - pz, pz - bx[2]), 0.f);
+            ok = fmaf(ex, ex, fmaf(ey, ey, ez * ez)) <= rad2;
+        }
+        const uint64_t okm = __ballot(ok);
+        const int m = __popcll(okm);
+        const int slot = __popcll(okm & ((1ull << lane) - 1ull));
+        const int room = TCAP - fill;
+        if (ok && slot < room) P::stage(S, fill + slot, j, pj, Sx, Sy, Sz, a);
+        const int first = min(m, room);
+        fill += first;
+        tself = tself || (self && first > 0);
+        if (done || fill == TCAP) {
             if (fill > 0) process_tile<P>(S, fill, R, rep, L, acc, tself);
             fill = 0;
             tself = false;
         }
         if (done) break;
-        if (lane < nuse) P::stage(S, fill + lane, j, pj, Sx, Sy, Sz, a);
-        tself = tself || self;
-        fill += nuse;
+        if (ok && slot >= room) {
+            // read again rather than kept through the tile's evaluation
+            if (dl < 0) {
+                P::stage(S, slot - room, q, a.pos[q], 0.f, 0.f, 0.f, a);
+            } else {
+                const float4 df = T.f[dl];
+                P::stage(S, slot - room, a.segidx[q], a.segpos[q], df.x, df.y, df.z, a);
+            }
+        }
+        fill += m - first;
+        tself = tself || (self && m > first);
     }
 }
 
