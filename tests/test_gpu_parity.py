@@ -299,3 +299,34 @@ def test_bad_arguments(sph, ctx):
     batch = sph.batch_from_sets([ps], h=[np.full(100, np.nan)])
     with pytest.raises(sph.SphError):
         tree.build_cells(batch, sph.params())
+
+
+def _errors(ps, h, g, rd, rf):
+    """Largest errors of one case against the oracle, in the metrics of the bar."""
+    vmax = max(np.abs(ps.vx).max(), np.abs(ps.vy).max(), np.abs(ps.vz).max(), 1e-30)
+    S = np.maximum(rf["S"], 1e-300)
+    return {
+        "rho": float((np.abs(g[0]["rho"] - rd["rho"]) / rd["rho"]).max()),
+        "N_w": float((np.abs(g[0]["nw"] - rd["nw"]) / rd["nw"]).max()),
+        "drho/dh": float((np.abs(g[0]["drho_dh"] - rd["drho_dh"]) / (3 * rd["rho"] / h)).max()),
+        "a/S": float(max((np.abs(g[1][k] - rf[k]) / S).max() for k in ("ax", "ay", "az"))),
+        "du/dt": float((np.abs(g[1]["dudt"] - rf["dudt"]) / (S * 2 * np.sqrt(3) * vmax)).max()),
+    }
+
+
+def test_error_report(sph, ctx):
+    """Prints the largest error of every result against the FP64 oracle on
+    three cases (run with -s to see the table) and checks the bar."""
+    cases = [("uniform 4096", *I.cfg_small_uniform(velocity=True))]
+    ps = sphinputs.lattice(24, 0.1, 2, velocity=True)
+    cases.append(("jittered lattice 24^3", *I.fixed_h_case(ps)))
+    ps = sphinputs.plummer_mixture(20000, 3, velocity=True)
+    cases.append(("plummer mixture 20000", *I.fixed_h_case(ps)))
+    print()
+    for name, ps, h in cases:
+        (g,), _ = run_fixed(sph, ctx, [ps], [h])
+        rd, rf = I.oracle_reference(ps, h)
+        e = _errors(ps, h, g, rd, rf)
+        print(f"[errors] {name:24s} " + "  ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+        assert e["rho"] <= RHO_TOL and e["N_w"] <= RHO_TOL and e["drho/dh"] <= RHO_TOL
+        assert e["a/S"] <= FORCE_TOL and e["du/dt"] <= FORCE_TOL
