@@ -207,42 +207,80 @@ __global__ __launch_bounds__(RS_BS) void k_rs_hist(const uint64_t* __restrict__ 
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// One pass: the tile of RS_TILE elements of this block is first placed in
+// LDS in digit order (stable: within a digit, input order), then written
+// out, so that runs of one digit go to consecutive addresses.  offs is the
+// scanned histogram: offs[d * nb + b] = first output position of digit d of
+// block b; the next entry bounds it, so the block's own digit counts (and
+// their local starts) follow from offs alone.
 template <bool VALS>
 __global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                       const uint32_t* __restrict__ vin,
                                                       uint64_t* __restrict__ kout,
                                                       uint32_t* __restrict__ vout, int64_t n, int shift,
                                                       const uint32_t* __restrict__ offs, int64_t nb) {
+    __shared__ uint64_t s_k[RS_TILE];
+    __shared__ uint32_t s_v[VALS ? RS_TILE : 1];
     __shared__ uint32_t g_off[256];
+    __shared__ uint32_t l_off[256];
     __shared__ uint32_t d_base[256];
     __shared__ uint32_t w_cnt[RS_BS / 64][256];
+    __shared__ uint32_t w_sum[RS_BS / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    g_off[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    const int64_t b = blockIdx.x;
+    const int64_t base = b * RS_TILE;
+    const int tile_n = (int)min((int64_t)RS_TILE, n - base);
+    // this block's digit counts and their local starts (exclusive scan)
+    const int64_t oi = (int64_t)tid * nb + b;
+    const uint32_t go = offs[oi];
+    const uint32_t gnext = oi + 1 < 256 * nb ? offs[oi + 1] : (uint32_t)n;
+    const uint32_t cnt = gnext - go;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += v;
+    }
+    if (lane == 63) w_sum[w] = inc;
+    g_off[tid] = go;
     d_base[tid] = 0;
     for (int k = 0; k < RS_BS / 64; ++k) w_cnt[k][tid] = 0;
     __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += w_sum[k];
+    l_off[tid] = before + inc - cnt;
+    __syncthreads();
+    // the whole tile is loaded at once (all loads in flight together)
+    uint64_t kr[RS_ROUNDS];
+    uint32_t vr[RS_ROUNDS];
+#pragma unroll
     for (int r = 0; r < RS_ROUNDS; ++r) {
-        int64_t i = base + (int64_t)r * RS_BS + tid;
-        bool valid = i < n;
-        uint64_t k = valid ? kin[i] : 0;
-        uint32_t v = (VALS && valid) ? vin[i] : 0;
-        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const int li = r * RS_BS + tid;
+        kr[r] = li < tile_n ? kin[base + li] : 0;
+        vr[r] = (VALS && li < tile_n) ? vin[base + li] : 0;
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const int li = r * RS_BS + tid;
+        const bool valid = li < tile_n;
+        const uint64_t k = kr[r];
+        const uint32_t v = vr[r];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
         uint64_t match = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot(valid && ((d >> b) & 1u));
-            match &= ((d >> b) & 1u) ? bal : ~bal;
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bal = __ballot(valid && ((d >> bit) & 1u));
+            match &= ((d >> bit) & 1u) ? bal : ~bal;
         }
-        uint32_t rank = __popcll(match & lt);
-        bool leader = valid && ((match & lt) == 0);
+        const uint32_t rank = __popcll(match & lt);
+        const bool leader = valid && ((match & lt) == 0);
         if (leader) w_cnt[w][d] = (uint32_t)__popcll(match);
         __syncthreads();
         {
             uint32_t run = d_base[tid];
             for (int q = 0; q < RS_BS / 64; ++q) {
-                uint32_t c = w_cnt[q][tid];
+                const uint32_t c = w_cnt[q][tid];
                 w_cnt[q][tid] = run;
                 run += c;
             }
@@ -250,13 +288,22 @@ __global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint64_t* __restrict
         }
         __syncthreads();
         if (valid) {
-            uint32_t pos = g_off[d] + w_cnt[w][d] + rank;
-            kout[pos] = k;
-            if (VALS) vout[pos] = v;
+            const uint32_t pos = l_off[d] + w_cnt[w][d] + rank;
+            s_k[pos] = k;
+            if (VALS) s_v[pos] = v;
         }
         __syncthreads();
         for (int q = 0; q < RS_BS / 64; ++q) w_cnt[q][tid] = 0;
         __syncthreads();
+    }
+    // write out in digit order: consecutive threads, consecutive addresses
+    // within a digit's run
+    for (int i = tid; i < tile_n; i += RS_BS) {
+        const uint64_t k = s_k[i];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = g_off[d] + (uint32_t)i - l_off[d];
+        kout[pos] = k;
+        if (VALS) vout[pos] = s_v[i];
     }
 }
 
