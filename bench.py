@@ -35,7 +35,7 @@ HBM_PEAK = 8.0e12
 OPS_DENSITY = 52.0
 OPS_FORCE = 118.0
 # Newton passes captured in the batched/served graphs
-K_ITER = 12
+K_ITER = 24
 
 
 def log(*a):

@@ -49,7 +49,7 @@ def save_table(tab: dict) -> None:
     os.replace(tmp, TABLE)
 
 
-def tune(ctx: B.Context, batch: B.Batch, base: dict | None = None, k_iter: int = 12, reps: int = 2,
+def tune(ctx: B.Context, batch: B.Batch, base: dict | None = None, k_iter: int = 24, reps: int = 2,
          grid: dict | None = None, label: str = "", use_cache: bool = True, log=None) -> dict:
     import torch
     sig = signature(batch, label)

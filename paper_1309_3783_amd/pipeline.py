@@ -116,7 +116,7 @@ def finish_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int, m
     return reruns
 
 
-def run_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int = 12):
+def run_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int = 24):
     import torch
     launch_graph(tree, batch, prm, out, k_iter)
     tree.ctx.stream.synchronize() if hasattr(tree.ctx.stream, "synchronize") else torch.cuda.synchronize()

@@ -118,7 +118,7 @@ class Scheduler:
 class GpuExecutor:
     """Lanes = HIP streams with their own context, tree and buffers."""
 
-    def __init__(self, prm=None, k_iter: int = 12, lanes: int = 2, keep_results: bool = False, device=0):
+    def __init__(self, prm=None, k_iter: int = 24, lanes: int = 2, keep_results: bool = False, device=0):
         import torch
         from . import binding as B
         from . import pipeline as P
