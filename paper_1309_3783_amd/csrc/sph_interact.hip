@@ -434,7 +434,10 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
     // a record is staged only if it lies within the cutoff of the chunk's
     // bounding box (the sweep bounds the distance along the pair axis only)
     const float lox = -bx[3], loy = -bx[4], loz = -bx[5];
-    const float rs = fmaf(P::cut(hmax, fmaxf(C.hcur, C.hcur_l)), 1.000002f, 1e-5f * L0);
+    const float tiny = 1e-5f * L0;
+    const float rw = 1.2f * fmaf(hmax, 1.000002f, tiny);
+    const float rwide2 = rw * rw;
+    const float rs = fmaf(P::cut(hmax, fmaxf(C.hcur, C.hcur_l)), 1.000002f, tiny);
     const float rself2 = rs * rs;
     for (;;) {
         bool done = false, self = false;
@@ -444,6 +447,7 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
         float Sx = 0.f, Sy = 0.f, Sz = 0.f, rad2 = 0.f;
         uint32_t q = 0;                     // where it was read: list position (or particle) and part
         int dl = -1;
+        typename P::Pre pre{};
         if (sbase < cend) {
             // a block of the self task
             nuse = min(64, cend - sbase);
@@ -499,10 +503,15 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
             }
             g0 += nuse;
         }
+        // the records' own data bound their reach only where some part
+        // reaches more than 20% beyond the chunk's cutoff (wave-uniform)
+        const bool early = P::kPre && __ballot(lane < nuse && rad2 > rwide2) != 0ull;
+        if (early) pre = P::pre(a, j, lane < nuse);
         // the records within reach, packed: the first ones complete the
         // current tile, the others start the next
         bool ok = false;
         if (lane < nuse) {
+            if (early) rad2 = P::rad2(rad2, pre, hmax, tiny);
             const float px = pj.x + Sx, py = pj.y + Sy, pz = pj.z + Sz;
             const float ex = fmaxf(fmaxf(lox - px, px - bx[0]), 0.f);
             const float ey = fmaxf(fmaxf(loy - py, py - bx[1]), 0.f);
@@ -513,7 +522,7 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
         const int m = __popcll(okm);
         const int slot = __popcll(okm & ((1ull << lane) - 1ull));
         const int room = TCAP - fill;
-        if (ok && slot < room) P::stage(S, fill + slot, j, pj, Sx, Sy, Sz, a);
+        if (ok && slot < room) P::stage(S, fill + slot, j, pj, Sx, Sy, Sz, a, pre, early);
         const int first = min(m, room);
         fill += first;
         tself = tself || (self && first > 0);
@@ -526,10 +535,11 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
         if (ok && slot >= room) {
             // read again rather than kept through the tile's evaluation
             if (dl < 0) {
-                P::stage(S, slot - room, q, a.pos[q], 0.f, 0.f, 0.f, a);
+                P::stage(S, slot - room, q, a.pos[q], 0.f, 0.f, 0.f, a, pre, false);
             } else {
                 const float4 df = T.f[dl];
-                P::stage(S, slot - room, a.segidx[q], a.segpos[q], df.x, df.y, df.z, a);
+                const uint32_t jj = a.segidx[q];
+                P::stage(S, slot - room, jj, a.segpos[q], df.x, df.y, df.z, a, pre, false);
             }
         }
         fill += m - first;
@@ -558,8 +568,14 @@ struct DensP {
     };
     static __device__ __forceinline__ float cut(float hmax, float) { return hmax; }
     static __device__ __forceinline__ bool in_range(float r2, float hi2, float) { return r2 < hi2; }
+    // data of a record read before it is filtered (none: the cutoff is the
+    // target's h)
+    struct Pre {};
+    static constexpr bool kPre = false;
+    static __device__ __forceinline__ Pre pre(const Args&, uint32_t, bool) { return Pre{}; }
+    static __device__ __forceinline__ float rad2(float part2, const Pre&, float, float) { return part2; }
     static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
-                                                 float Sz, const Args& a) {
+                                                 float Sz, const Args& a, const Pre&, bool) {
         S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, pj.w);
         if (HASH) S.m[slot] = a.mix[j];
     }
@@ -696,9 +712,25 @@ struct ForceP {
     static __device__ __forceinline__ bool in_range(float r2, float hi2, float hj) {
         return r2 < fmaxf(hi2, hj * hj);
     }
+    // where a part's largest h reaches well beyond the chunk's own cutoff,
+    // the partner's force record is read before the record is filtered: its
+    // own h bounds its reach (the cutoff is max(h_i, h_j))
+    struct Pre {
+        float4 f;
+    };
+    static constexpr bool kPre = true;
+    static __device__ __forceinline__ Pre pre(const Args& a, uint32_t j, bool valid) {
+        Pre p;
+        p.f = valid ? a.frec[j] : make_float4(1.f, 0.f, 0.f, 0.f);
+        return p;
+    }
+    static __device__ __forceinline__ float rad2(float part2, const Pre& p, float hmax, float tiny) {
+        const float r = fmaf(fmaxf(hmax, p.f.x), 1.000002f, tiny);
+        return fminf(part2, r * r);
+    }
     static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
-                                                 float Sz, const Args& a) {
-        const float4 fj = a.frec[j];
+                                                 float Sz, const Args& a, const Pre& pr, bool loaded) {
+        const float4 fj = loaded ? pr.f : a.frec[j];
         S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, fj.x);
         S.h[slot] = make_float4(pj.w, frcp(fj.x), fj.w, fj.y);
         S.v[slot] = a.pv[j];
