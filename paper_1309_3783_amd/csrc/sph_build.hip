@@ -691,48 +691,94 @@ __global__ __launch_bounds__(256) void k_seg_sort_cell(int64_t nc, const SetInfo
 }
 
 // Segments of 65..SEG_LDS_MAX entries (their (cell, axis) indices listed in
-// sel): one block each, bitonic sort in LDS.
+// sel), bitonic sort in LDS.  A block takes four lists at a time: each list
+// of at most WAVE_SORT_MAX entries is sorted by one wavefront on its own
+// (wave-level synchronisation only), the longer ones by the whole block.
+constexpr int WAVE_SORT_MAX = 256;
+static_assert(4 * WAVE_SORT_MAX <= SEG_LDS_MAX, "wave sorts share the block's array");
+
+template <int NT>
+__device__ __forceinline__ void bitonic_lds(uint64_t* s, int P, int t) {
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = t; e < P / 2; e += NT) {
+                const int i = 2 * e - (e & (stride - 1));
+                const int j = i + stride;
+                const bool up = ((i & size) == 0);
+                const uint64_t a = s[i], b = s[j];
+                if ((a > b) == up) {
+                    s[i] = b;
+                    s[j] = a;
+                }
+            }
+            if (NT == 64) wave_lds_sync();
+            else __syncthreads();
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict__ sel, int64_t nsel,
                                                       const uint32_t* __restrict__ off, const SetInfo* sets,
                                                       const Cell* __restrict__ cells,
                                                       const float4* __restrict__ pos, const float* __restrict__ ph,
                                                       float4* __restrict__ sproj, uint32_t* __restrict__ sidx) {
     __shared__ uint64_t s[SEG_LDS_MAX];
-    for (int64_t i = blockIdx.x; i < nsel; i += gridDim.x) {
-    const uint32_t ca = sel[i];
-    const Cell C = cells[ca / NAXES];
-    int ax = (int)(ca % NAXES);
-    int n = C.count;
-    if (n <= 64 || n > SEG_LDS_MAX) continue;
-    int P = 1;
-    while (P < n) P <<= 1;
-    const float lim = small_h_limit(sets, C);
-    for (int e = threadIdx.x; e < P; e += blockDim.x) {
-        uint64_t k = ~0ull;
-        if (e < n) k = seg_key(project(pos[C.first + e], ax), ph[C.first + e] > lim ? 1 : 0, (uint32_t)e);
-        s[e] = k;
-    }
-    __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int e = threadIdx.x; e < P / 2; e += blockDim.x) {
-                int i = 2 * e - (e & (stride - 1));
-                int j = i + stride;
-                bool up = ((i & size) == 0);
-                uint64_t a = s[i], b = s[j];
-                if ((a > b) == up) { s[i] = b; s[j] = a; }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t g0 = (int64_t)blockIdx.x * 4; g0 < nsel; g0 += (int64_t)gridDim.x * 4) {
+        // short lists: one per wave
+        if (g0 + w < nsel) {
+            const uint32_t ca = sel[g0 + w];
+            const Cell C = cells[ca / NAXES];
+            const int ax = (int)(ca % NAXES);
+            const int n = __builtin_amdgcn_readfirstlane(C.count);
+            if (n > 64 && n <= WAVE_SORT_MAX) {
+                uint64_t* sw = s + w * WAVE_SORT_MAX;
+                int P = 1;
+                while (P < n) P <<= 1;
+                const float lim = small_h_limit(sets, C);
+                for (int e = lane; e < P; e += 64) {
+                    uint64_t k = ~0ull;
+                    if (e < n) k = seg_key(project(pos[C.first + e], ax), ph[C.first + e] > lim ? 1 : 0, (uint32_t)e);
+                    sw[e] = k;
+                }
+                wave_lds_sync();
+                bitonic_lds<64>(sw, P, lane);
+                const uint32_t o = off[ca];
+                for (int e = lane; e < n; e += 64) {
+                    const uint64_t k = sw[e];
+                    const uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+                    sproj[o + e] = pos[j];
+                    sidx[o + e] = j;
+                }
+            }
+        }
+        __syncthreads();
+        // longer lists: the whole block, one after the other
+        for (int k4 = 0; k4 < 4 && g0 + k4 < nsel; ++k4) {
+            const uint32_t ca = sel[g0 + k4];
+            const Cell C = cells[ca / NAXES];
+            const int ax = (int)(ca % NAXES);
+            const int n = C.count;
+            if (n <= WAVE_SORT_MAX || n > SEG_LDS_MAX) continue;
+            int P = 1;
+            while (P < n) P <<= 1;
+            const float lim = small_h_limit(sets, C);
+            for (int e = threadIdx.x; e < P; e += blockDim.x) {
+                uint64_t k = ~0ull;
+                if (e < n) k = seg_key(project(pos[C.first + e], ax), ph[C.first + e] > lim ? 1 : 0, (uint32_t)e);
+                s[e] = k;
+            }
+            __syncthreads();
+            bitonic_lds<256>(s, P, threadIdx.x);
+            const uint32_t o = off[ca];
+            for (int e = threadIdx.x; e < n; e += blockDim.x) {
+                const uint64_t k = s[e];
+                const uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+                sproj[o + e] = pos[j];
+                sidx[o + e] = j;
             }
             __syncthreads();
         }
-    }
-    uint32_t o = off[ca];
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        uint64_t k = s[e];
-        uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
-        sproj[o + e] = pos[j];
-        sidx[o + e] = j;
-    }
-    __syncthreads();
     }
 }
 
@@ -1192,7 +1238,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
         HIPTRY(hipGetLastError());
     }
     if (nmid > 0) {
-        hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)std::min<uint32_t>(nmid, 65535)), dim3(256), 0, st, mids,
+        hipLaunchKernelGGL(k_seg_sort_lds, dim3((unsigned)std::min<uint32_t>((nmid + 3) / 4, 65535)), dim3(256), 0, st, mids,
                            (int64_t)nmid, t->segoff, t->d_sets, t->cells, t->pos, t->ph, t->segpos, t->segidx);
         HIPTRY(hipGetLastError());
     }
