@@ -152,7 +152,7 @@ __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
                          const float* __restrict__ vx, const float* __restrict__ vy,
                          const float* __restrict__ vz, float slack, float4* __restrict__ pos,
                          float* __restrict__ ph, float* __restrict__ hdec, float* __restrict__ pu,
-                         float4* __restrict__ pv, uint32_t* __restrict__ perm,
+                         float4* __restrict__ pv, uint32_t* __restrict__ perm, uint32_t* __restrict__ iperm,
                          uint64_t* __restrict__ mix) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -174,6 +174,7 @@ __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
     pu[p] = u[i];
     pv[p] = make_float4(vx[i], vy[i], vz[i], 0.f);
     perm[p] = i;
+    iperm[i] = (uint32_t)p;
     mix[p] = splitmix64((uint64_t)((int64_t)i - S.first));
 }
 
@@ -241,6 +242,7 @@ __global__ __launch_bounds__(256) void k_cell_stats(const SetInfo* sets, int bma
     const float half = (float)(0.5 * S.L0 / (double)(1 << level));
     float hm = 0.f;
     int nsmall = 0;
+#pragma unroll 8
     for (int64_t p = C.first + lane; p < (int64_t)C.first + C.count; p += 64) {
         float hh = hdec[p];
         hm = fmaxf(hm, hh);
@@ -619,6 +621,7 @@ __global__ __launch_bounds__(256) void k_cell_nsmall(const SetInfo* sets, Cell* 
     const Cell C = cells[c];
     const float lim = small_h_limit(sets, C);
     int k = 0;
+#pragma unroll 8
     for (int p = C.first + lane; p < C.first + C.count; p += 64) k += ph[p] <= lim ? 1 : 0;
     k = wave_sum_i(k);
     if (lane == 0) cells[c].nsmall = k;
@@ -967,6 +970,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(t->alloc(t->b_val, sizeof(uint32_t) * nn, (void**)&t->val));
     ERRTRY(t->alloc(t->b_val2, sizeof(uint32_t) * nn, (void**)&t->val2));
     ERRTRY(t->alloc(t->b_perm, sizeof(uint32_t) * nn, (void**)&t->perm));
+    ERRTRY(t->alloc(t->b_iperm, sizeof(uint32_t) * nn, (void**)&t->iperm));
     ERRTRY(t->alloc(t->b_pos, sizeof(float4) * nn, (void**)&t->pos));
     ERRTRY(t->alloc(t->b_pv, sizeof(float4) * nn, (void**)&t->pv));
     ERRTRY(t->alloc(t->b_ph, sizeof(float) * nn, (void**)&t->ph));
@@ -990,7 +994,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         }
         hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, bmax, t->key,
                            t->val, in->x, in->y, in->z, in->h, in->m, in->u, in->vx, in->vy, in->vz,
-                           prm->h_slack, t->pos, t->ph, t->hdec, t->pu, t->pv, t->perm, t->mix);
+                           prm->h_slack, t->pos, t->ph, t->hdec, t->pu, t->pv, t->perm, t->iperm, t->mix);
         HIPTRY(hipGetLastError());
     }
 

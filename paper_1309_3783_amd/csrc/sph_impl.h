@@ -45,7 +45,7 @@ struct sph_tree {
     sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_pv, b_ph, b_hdec, b_pu,
         b_bound, b_mix, b_rs, b_cell, b_taskA, b_taskB, b_final, b_chunk, b_csr, b_csr2, b_csroff,
         b_segoff, b_seglist, b_segproj, b_segidx, b_bigk, b_bigv, b_sc, b_dens, b_force, b_solve,
-        b_red, b_misc, b_saved, b_split, b_counts;
+        b_red, b_misc, b_saved, b_split, b_counts, b_iperm;
 
     // ---- sizes (host) --------------------------------------------------
     int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nchunks = 0, max_leaf = 0;
@@ -60,6 +60,7 @@ struct sph_tree {
     sph::SetInfo* d_sets = nullptr;
     uint64_t *key = nullptr, *key2 = nullptr, *mix = nullptr, *csr = nullptr, *csr2 = nullptr;
     uint32_t *val = nullptr, *val2 = nullptr, *perm = nullptr, *rs_tmp = nullptr;
+    uint32_t* iperm = nullptr;   // caller order -> cell order
     float4 *pos = nullptr, *pv = nullptr;
     float *ph = nullptr, *hdec = nullptr, *pu = nullptr, *bound = nullptr;
     sph::Cell* cells = nullptr;
@@ -115,7 +116,7 @@ struct sph_tree {
         return {&b_sets, &b_small, &b_key, &b_key2, &b_val, &b_val2, &b_perm, &b_pos, &b_pv, &b_ph, &b_hdec,
                 &b_pu, &b_bound, &b_mix, &b_rs, &b_cell, &b_taskA, &b_taskB, &b_final, &b_chunk, &b_csr,
                 &b_csr2, &b_csroff, &b_segoff, &b_seglist, &b_segproj, &b_segidx, &b_bigk, &b_bigv, &b_sc,
-                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts};
+                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts, &b_iperm};
     }
 
     void release() {

@@ -956,13 +956,15 @@ __global__ __launch_bounds__(256) void k_count_final(const int4* __restrict__ re
     }
 }
 
-__global__ void k_save_state(int64_t n, const uint32_t* __restrict__ perm, const uint8_t* active, const float* lo,
+// Outputs in caller order are written in that order (coalesced), each read
+// from its cell-order slot through the inverse permutation.
+__global__ void k_save_state(int64_t n, const uint32_t* __restrict__ iperm, const uint8_t* active, const float* lo,
                              const float* hi, const float* dstep, const float* rho, const float* drho,
                              const float* nw, const float* dnw, const int32_t* nngb, const uint64_t* hash,
                              SolveState sv) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    uint32_t i = perm[p];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = iperm[i];
     sv.active[i] = active[p];
     sv.lo[i] = lo[p];
     sv.hi[i] = hi[p];
@@ -1029,10 +1031,12 @@ __global__ __launch_bounds__(256) void k_cell_hcur(Cell* __restrict__ cells, int
     for (int k = 0; k < NAXES && so == 0xFFFFFFFFu; ++k) so = segoff[c * NAXES + k];
     float ms = 0.f, ml = 0.f;
     if (so == 0xFFFFFFFFu) {
+#pragma unroll 8
         for (int p = first + lane; p < first + count; p += 64) ms = fmaxf(ms, ph[p]);
         ms = wmax(ms);
         ml = ms;
     } else {
+#pragma unroll 8
         for (int q = lane; q < count; q += 64) {
             float hv = ph[segidx[so + q]];
             if (q < ns) ms = fmaxf(ms, hv); else ml = fmaxf(ml, hv);
@@ -1046,12 +1050,12 @@ __global__ __launch_bounds__(256) void k_cell_hcur(Cell* __restrict__ cells, int
     }
 }
 
-__global__ void k_scatter_density(int64_t n, const uint32_t* __restrict__ perm, const float* rho,
+__global__ void k_scatter_density(int64_t n, const uint32_t* __restrict__ iperm, const float* rho,
                                   const float* drho, const float* nw, const float* dnw, const int32_t* nngb,
                                   const uint64_t* hash, const float* ph, sph_density_out o) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    uint32_t i = perm[p];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = iperm[i];
     if (o.rho) o.rho[i] = rho[p];
     if (o.drho_dh) o.drho_dh[i] = drho[p];
     if (o.nw) o.nw[i] = nw[p];
@@ -1061,12 +1065,12 @@ __global__ void k_scatter_density(int64_t n, const uint32_t* __restrict__ perm, 
     if (o.h) o.h[i] = ph[p];
 }
 
-__global__ void k_scatter_force(int64_t n, const uint32_t* __restrict__ perm, const float* ax, const float* ay,
+__global__ void k_scatter_force(int64_t n, const uint32_t* __restrict__ iperm, const float* ax, const float* ay,
                                 const float* az, const float* du, const float* vs, const float* S,
                                 const int32_t* nf, const uint64_t* hash, sph_force_out o) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    uint32_t i = perm[p];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = iperm[i];
     if (o.ax) o.ax[i] = ax[p];
     if (o.ay) o.ay[i] = ay[p];
     if (o.az) o.az[i] = az[p];
@@ -1325,13 +1329,13 @@ static void launch_reduce(sph_ctx* ctx, sph_tree* t, double* sums_out) {
 
 static void launch_scatter_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* o) {
     if (!o || t->n == 0) return;
-    hipLaunchKernelGGL(k_scatter_density, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->perm, t->rho,
+    hipLaunchKernelGGL(k_scatter_density, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->iperm, t->rho,
                        t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr, t->ph, *o);
 }
 
 static void launch_scatter_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* o) {
     if (!o || t->n == 0) return;
-    hipLaunchKernelGGL(k_scatter_force, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->perm, t->fax,
+    hipLaunchKernelGGL(k_scatter_force, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->iperm, t->fax,
                        t->fay, t->faz, t->fdu, t->fvs, t->fS, t->fn, t->hash ? t->hashf : nullptr, *o);
 }
 
@@ -1400,7 +1404,7 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     launch_scatter_density(ctx, t, out);
     if (rebuild) {
         ERRTRY(t->ensure_saved());
-        hipLaunchKernelGGL(k_save_state, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->perm, t->active, t->lo, t->hi,
+        hipLaunchKernelGGL(k_save_state, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->iperm, t->active, t->lo, t->hi,
                            t->dstep, t->rho, t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr,
                            t->saved_state());
         t->saved = true;
