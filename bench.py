@@ -63,9 +63,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current kernel sources and on this workload; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -74,7 +74,7 @@ def measured_traffic(kernel):
     except Exception:
         return None
     e = d.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash() or d.get("workload") != workload:
         return None
     return e.get("bytes_per_launch")
 
@@ -172,7 +172,7 @@ def run(args):
 
     ach = P * OPS_FORCE / (force_ms / 1e3)
     roof = {"kernel": "k_force", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "Tlane-op/s", "frac": ach / VALU_PEAK, "traffic": measured_traffic("k_force"),
+            "unit": "Tlane-op/s", "frac": ach / VALU_PEAK, "traffic": measured_traffic("k_force", cfg["workload"]),
             "launch_ms": force_ms, "ops_per_pair": OPS_FORCE, "pairs_per_launch": P}
     out = {"metric": "pair interactions/sec (density+force), batched vs plain; p50/p99 latency",
            "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps,
