@@ -334,6 +334,64 @@ __global__ void k_top_task_emit(const SetInfo* sets, int ntop, const Cell* __res
     }
 }
 
+// Interaction-list keys: target << 37 | source << 5 | offset code.
+constexpr int CSR_SRC_SHIFT = 5;
+constexpr int CSR_TGT_SHIFT = 37;
+
+// Interaction lists of a tree of one level, straight from the top grid: the
+// entries of cell c are the pair tasks (c, B, o) it emits (one per non-empty
+// neighbour in the 13 positive directions) and the tasks (A', c, o) of its
+// non-empty neighbours A' in the 13 negative directions, in the order a
+// stable sort of the task list by target gives: by emitting cell, then by
+// axis (tasks are emitted per cell in cell order, each cell's in axis
+// order).  COUNT: only the number of entries per cell.
+template <bool COUNT>
+__global__ void k_top_csr(const SetInfo* sets, int ntop, const Cell* __restrict__ cells,
+                          const uint32_t* __restrict__ off, uint32_t* __restrict__ cnt,
+                          uint64_t* __restrict__ csr) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ntop) return;
+    const Cell A = cells[c];
+    if (A.count == 0) {
+        if (COUNT) cnt[c] = 0;
+        return;
+    }
+    const SetInfo S = sets[A.set];
+    int src[26];
+    bool ok[26];
+    int64_t key[26];
+#pragma unroll
+    for (int a = 0; a < 13; ++a) {
+        const int code = axis_code(a);
+        const int ox = ocx(code), oy = ocy(code), oz = ocz(code);
+        const int B = top_neighbour(S, A, ox, oy, oz);
+        const int Ap = top_neighbour(S, A, -ox, -oy, -oz);
+        src[a] = B;
+        ok[a] = cells[B].count > 0;
+        key[a] = ((int64_t)c << 5) | a;
+        src[13 + a] = Ap;
+        ok[13 + a] = cells[Ap].count > 0;
+        key[13 + a] = ((int64_t)Ap << 5) | a;
+    }
+    if (COUNT) {
+        uint32_t k = 0;
+#pragma unroll
+        for (int i = 0; i < 26; ++i) k += ok[i] ? 1u : 0u;
+        cnt[c] = k;
+        return;
+    }
+    const uint32_t o = off[c];
+#pragma unroll
+    for (int i = 0; i < 26; ++i) {
+        if (!ok[i]) continue;
+        uint32_t pos = 0;
+#pragma unroll
+        for (int j = 0; j < 26; ++j) pos += (ok[j] && key[j] < key[i]) ? 1u : 0u;
+        const int code = i < 13 ? axis_code(i) : 26 - axis_code(i - 13);
+        csr[o + pos] = ((uint64_t)c << CSR_TGT_SHIFT) | ((uint64_t)src[i] << CSR_SRC_SHIFT) | (uint64_t)code;
+    }
+}
+
 __device__ inline uint32_t nonempty_children(const Cell* cells, const Cell& A) {
     uint32_t m = 0;
     for (int o = 0; o < 8; ++o)
@@ -507,8 +565,6 @@ __global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__
 // Per-cell interaction lists: each pair task (A,B,o) gives A the source
 // (B, o) and B the source (A, -o).  Keys sort by (target, source, code).
 // ---------------------------------------------------------------------------
-constexpr int CSR_SRC_SHIFT = 5;
-constexpr int CSR_TGT_SHIFT = 37;
 
 __global__ void k_csr_keys(const int4* __restrict__ tasks, int64_t nt, uint64_t* __restrict__ keys) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -540,9 +596,10 @@ __global__ void k_csr_offsets(const uint64_t* __restrict__ keys, int64_t ne, int
 // ---------------------------------------------------------------------------
 // Sorted lists per (cell, axis).
 // ---------------------------------------------------------------------------
-__global__ void k_seg_need(const uint64_t* __restrict__ ent, int64_t ne, uint32_t* __restrict__ need) {
+__global__ void k_seg_need(const uint64_t* __restrict__ ent, int64_t ne, const uint32_t* __restrict__ ne_dev,
+                           uint32_t* __restrict__ need) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ne) return;
+    if (e >= ne || (ne_dev && e >= (int64_t)*ne_dev)) return;
     uint64_t k = ent[e];
     if (k == ~0ull) return;   // self entry
     int src = (int)((k >> CSR_SRC_SHIFT) & 0xFFFFFFFFull);
@@ -1025,21 +1082,29 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(read_back(ctx, total, 3 * sizeof(uint32_t), &rb));
     const uint32_t nt0 = ((const uint32_t*)rb)[0];
     uint32_t nsplit = ((const uint32_t*)rb)[2];   // split cells of the current level
-    int64_t cap_tasks = std::max<int64_t>(nt0, 1);
-    ERRTRY(t->alloc(t->b_taskA, sizeof(int4) * cap_tasks, (void**)&t->taskA));
-    hipLaunchKernelGGL(k_top_task_emit, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, (int)ntop, t->cells,
-                       t->sc_b, t->taskA);
-    HIPTRY(hipGetLastError());
+    // no top cell splits: one level, whose interaction lists come straight
+    // from the top grid (no task list is made)
+    const bool flat = nsplit == 0;
     int64_t ncur = nt0;        // tasks of the current level (in taskA)
     int64_t nfinal = 0;        // final tasks (in finals)
-    ERRTRY(t->alloc(t->b_final, sizeof(int4) * std::max<int64_t>(nt0, 1), (void**)&t->finals));
+    if (!flat) {
+        ERRTRY(t->alloc(t->b_taskA, sizeof(int4) * std::max<int64_t>(nt0, 1), (void**)&t->taskA));
+        hipLaunchKernelGGL(k_top_task_emit, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, (int)ntop, t->cells,
+                           t->sc_b, t->taskA);
+        HIPTRY(hipGetLastError());
+        ERRTRY(t->alloc(t->b_final, sizeof(int4) * std::max<int64_t>(nt0, 1), (void**)&t->finals));
+    }
 
     // One read-back per level: the task counts of this level and the split
     // count of the next, whose cells exist before this level's tasks are
     // decided (a task splits into tasks of the children).  A level without
     // split cells ends the loop: its tasks are all final.
     int level = 0;
-    for (;; ++level) {
+    if (flat) {
+        t->lvl_start.push_back(ntop);
+        nfinal = nt0;
+    }
+    for (; !flat; ++level) {
         const int64_t c0 = t->lvl_start[level], c1 = t->lvl_start[level + 1];
         const int64_t nnext = 8 * (int64_t)nsplit;
         if (c1 + nnext > (int64_t)1 << 27) return Err{SPH_E_CAPACITY, "too many cells (limit 2^27)"};
@@ -1134,30 +1199,47 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     }
 
     // ---- per-cell interaction lists (CSR) --------------------------------
-    const int64_t ne = 2 * nfinal;
-    ERRTRY(t->alloc(t->b_csr, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr));
-    ERRTRY(t->alloc(t->b_csr2, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr2));
     ERRTRY(t->alloc(t->b_csroff, sizeof(uint32_t) * (nc + 1), (void**)&t->csr_off));
-    if (ne > 0) {
-        ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(ne), radix_tmp_words(nn)),
-                        (void**)&t->rs_tmp));
-        hipLaunchKernelGGL(k_csr_keys, dim3(nblk(nfinal, 256)), dim3(256), 0, st, t->finals, nfinal, t->csr);
+    if (flat) {
+        // at most 26 entries per top cell; the count stays on the device
+        const int64_t ecap = 26 * ntop;
+        ERRTRY(t->alloc(t->b_csr, sizeof(uint64_t) * std::max<int64_t>(ecap, 1), (void**)&t->csr));
+        hipLaunchKernelGGL(k_top_csr<true>, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, (int)ntop, t->cells,
+                           nullptr, t->sc_a, nullptr);
         HIPTRY(hipGetLastError());
-        bool alt = false;
-        // stable sort on the target field only: a target's entries keep the
-        // order of the task list, which the tree fixes; self tasks (all
-        // ones) sort last
-        int tbits = 1;
-        while (((int64_t)1 << tbits) <= nc) ++tbits;
-        HIPTRY(radix_sort(t->csr, nullptr, t->csr2, nullptr, ne, tbits, t->rs_tmp, st, &alt, CSR_TGT_SHIFT));
-        if (alt) {
-            std::swap(t->csr, t->csr2);
-            std::swap(t->b_csr, t->b_csr2);
-        }
-        hipLaunchKernelGGL(k_csr_offsets, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, nc, t->csr_off);
+        HIPTRY(exclusive_scan(t->sc_a, t->csr_off, ntop, t->sc_tmp, t->csr_off + ntop, st));
+        hipLaunchKernelGGL(k_top_csr<false>, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, (int)ntop, t->cells,
+                           t->csr_off, nullptr, t->csr);
         HIPTRY(hipGetLastError());
+        t->ncsr = ecap;
+        t->ncsr_dev = t->csr_off + ntop;
     } else {
-        HIPTRY(fill_u32(t->csr_off, nc + 1, 0u, st));
+        const int64_t ne = 2 * nfinal;
+        ERRTRY(t->alloc(t->b_csr, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr));
+        ERRTRY(t->alloc(t->b_csr2, sizeof(uint64_t) * std::max<int64_t>(ne, 1), (void**)&t->csr2));
+        if (ne > 0) {
+            ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(ne), radix_tmp_words(nn)),
+                            (void**)&t->rs_tmp));
+            hipLaunchKernelGGL(k_csr_keys, dim3(nblk(nfinal, 256)), dim3(256), 0, st, t->finals, nfinal, t->csr);
+            HIPTRY(hipGetLastError());
+            bool alt = false;
+            // stable sort on the target field only: a target's entries keep
+            // the order of the task list, which the tree fixes; self tasks
+            // (all ones) sort last
+            int tbits = 1;
+            while (((int64_t)1 << tbits) <= nc) ++tbits;
+            HIPTRY(radix_sort(t->csr, nullptr, t->csr2, nullptr, ne, tbits, t->rs_tmp, st, &alt, CSR_TGT_SHIFT));
+            if (alt) {
+                std::swap(t->csr, t->csr2);
+                std::swap(t->b_csr, t->b_csr2);
+            }
+            hipLaunchKernelGGL(k_csr_offsets, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, nc, t->csr_off);
+            HIPTRY(hipGetLastError());
+        } else {
+            HIPTRY(fill_u32(t->csr_off, nc + 1, 0u, st));
+        }
+        t->ncsr = ne;
+        t->ncsr_dev = nullptr;
     }
     // chunk count (total[0], untouched since its scan), leaves, largest leaf
     static_assert(sizeof(int) == sizeof(uint32_t), "layout of the count words");
@@ -1195,9 +1277,9 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     uint32_t* mid_idx = t->sc_c;
     uint32_t* big_idx = t->sc_d;
     HIPTRY(fill_u32(need, nca, 0, st));
-    const int64_t ne = 2 * t->ntasks;
+    const int64_t ne = t->ncsr;
     if (ne > 0) {
-        hipLaunchKernelGGL(k_seg_need, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, need);
+        hipLaunchKernelGGL(k_seg_need, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, t->ncsr_dev, need);
         HIPTRY(hipGetLastError());
     }
     if (nca > 0) {

@@ -50,6 +50,8 @@ struct sph_tree {
     // ---- sizes (host) --------------------------------------------------
     int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nchunks = 0, max_leaf = 0;
     int64_t nleaves = 0;
+    int64_t ncsr = 0;                   // interaction-list entries (a bound when ncsr_dev is set)
+    const uint32_t* ncsr_dev = nullptr; // their exact count on the device
     std::vector<int64_t> lvl_start;
     int64_t sc_cap = 0;
     std::vector<int4> red_chunks;   // (set, first, count, 0) reduction chunks
