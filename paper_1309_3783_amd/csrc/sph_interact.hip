@@ -864,54 +864,68 @@ __device__ __forceinline__ int set_of(const SetInfo* sets, int nsets, int64_t p)
 // particle whose root lies beyond the largest h its cells support is parked
 // (state 2, no more density passes) and raises the rebuild flag of its set;
 // the other particles go on converging.
+// Newton (or bracketing) step of particle p; returns whether it stays
+// active.  hcap: half the box (the minimum-image convention needs h < box/2).
+__device__ __forceinline__ bool newton_step(int64_t p, uint8_t* __restrict__ active, const float* __restrict__ nw,
+                                            const float* __restrict__ dnw, float* __restrict__ ph,
+                                            const float* __restrict__ bound, float* __restrict__ lo,
+                                            float* __restrict__ hi, float* __restrict__ dstep, double target,
+                                            double tol, double hcap, bool& rebuild_any) {
+    if (active[p] != 1) return false;
+    const double err = (double)nw[p] - target;
+    if (fabs(err) <= tol) {
+        active[p] = 0;
+        return false;
+    }
+    const double h = ph[p];
+    double l = lo[p], u = hi[p];
+    if (err < 0) l = h; else u = h;
+    const double d = dnw[p];
+    const double Nw = (double)nw[p];
+    const bool slope_ok = d > 0 && Nw > 0;
+    const double dl = slope_ok ? -log(Nw / target) / (d * h / Nw) : 0.0;
+    double hn = h * exp(dl);
+    const bool newton = slope_ok && hn > l && hn < u && fabs(dl) <= M_LN2 && fabs(dl) < 0.5 * (double)dstep[p];
+    if (!newton) hn = isinf(u) ? 2.0 * h : (l > 0 ? sqrt(l * u) : 0.5 * h);
+    if (hn >= hcap) hn = 0.5 * (h + hcap);
+    float hf = (float)hn;
+    if (hf == (float)h) hf = err < 0 ? nextafterf((float)h, INFINITY) : nextafterf((float)h, 0.f);
+    if (!((double)hf < hcap)) hf = nextafterf((float)hcap, 0.f);
+    // a step past the largest h the cells support first probes just below
+    // it; only if the root still lies beyond is a rebuild needed, and the
+    // particle then keeps the step it would take, so that the rebuilt cells
+    // are sized for it
+    bool rebuild = false;
+    const float hb = nextafterf(bound[p], 0.f);
+    if (!(hf < bound[p])) {
+        if ((float)h == hb && err < 0) rebuild = true;
+        else hf = hb;
+    }
+    lo[p] = (float)l;
+    hi[p] = (float)u;
+    dstep[p] = (float)fabs(log((double)hf / h));
+    ph[p] = hf;
+    if (rebuild) {
+        // parked: no density passes until the tree is rebuilt for it
+        active[p] = 2;
+        rebuild_any = true;
+        return false;
+    }
+    return true;
+}
+
+// The step of every active particle (one thread each); the rare rebuild
+// flags.  The particles still active are counted afterwards (k_count_active).
 __global__ void k_newton(int64_t n, const SetInfo* __restrict__ sets, int nsets, uint8_t* __restrict__ active,
                          const float* __restrict__ nw, const float* __restrict__ dnw, float* __restrict__ ph,
                          const float* __restrict__ bound, float* __restrict__ lo, float* __restrict__ hi,
                          float* __restrict__ dstep, double target, double tol, int32_t* __restrict__ status) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || active[p] != 1) return;
+    const int s = set_of(sets, nsets, p);
     bool rebuild = false;
-    if (p < n && active[p] == 1) {
-        const double err = (double)nw[p] - target;
-        if (fabs(err) <= tol) {
-            active[p] = 0;
-        } else {
-            const double h = ph[p];
-            double l = lo[p], u = hi[p];
-            if (err < 0) l = h; else u = h;
-            const double d = dnw[p];
-            const double Nw = (double)nw[p];
-            const bool slope_ok = d > 0 && Nw > 0;
-            const double dl = slope_ok ? -log(Nw / target) / (d * h / Nw) : 0.0;
-            double hn = h * exp(dl);
-            const bool newton = slope_ok && hn > l && hn < u && fabs(dl) <= M_LN2 && fabs(dl) < 0.5 * (double)dstep[p];
-            if (!newton) hn = isinf(u) ? 2.0 * h : (l > 0 ? sqrt(l * u) : 0.5 * h);
-            // the minimum-image convention needs h < box/2
-            const double hcap = 0.5 * sets[set_of(sets, nsets, p)].box;
-            if (hn >= hcap) hn = 0.5 * (h + hcap);
-            float hf = (float)hn;
-            if (hf == (float)h) hf = err < 0 ? nextafterf((float)h, INFINITY) : nextafterf((float)h, 0.f);
-            if (!((double)hf < hcap)) hf = nextafterf((float)hcap, 0.f);
-            // a step past the largest h the cells support first probes just
-            // below it; only if the root still lies beyond is a rebuild
-            // needed, and the particle then keeps the step it would take, so
-            // that the rebuilt cells are sized for it
-            const float hb = nextafterf(bound[p], 0.f);
-            if (!(hf < bound[p])) {
-                if ((float)h == hb && err < 0) rebuild = true;
-                else hf = hb;
-            }
-            lo[p] = (float)l;
-            hi[p] = (float)u;
-            dstep[p] = (float)fabs(log((double)hf / h));
-            ph[p] = hf;
-            // parked: no density passes until the tree is rebuilt for it
-            if (rebuild) active[p] = 2;
-        }
-    }
-    // still-active particles are counted afterwards (k_count_active); only
-    // the rare rebuild flag is raised here
+    (void)newton_step(p, active, nw, dnw, ph, bound, lo, hi, dstep, target, tol, 0.5 * sets[s].box, rebuild);
     if (rebuild) {
-        const int s = set_of(sets, nsets, p);
         atomicExch(&status[0], 1);
         atomicExch(&status[2 + 2 * s], 1);
     }
@@ -940,19 +954,30 @@ __device__ __forceinline__ int first_red_chunk(const int4* __restrict__ red, int
     return lo;
 }
 
-// ... then per set and in total: one wavefront per set, lanes striding over
-// the set's chunks, combined in a fixed butterfly.
-__global__ __launch_bounds__(256) void k_count_final(const int4* __restrict__ red, int nred,
-                                                     const int32_t* __restrict__ part, int nsets,
-                                                     int32_t* __restrict__ status) {
-    const int s = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (s >= nsets) return;
-    int c = 0;
-    for (int r = first_red_chunk(red, nred, s) + lane; r < nred && red[r].x == s; r += 64) c += part[r];
-    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
-    if (lane == 0) {
-        status[3 + 2 * s] = c;
-        if (c) atomicAdd(&status[1], c);
+// ... then per set (status[3 + 2s]) and in total (status[1]): one block, one wavefront per set in turn, lanes
+// striding over the set's chunks; integer sums, written (not accumulated).
+constexpr int COUNT_BS = 1024;
+__global__ __launch_bounds__(COUNT_BS) void k_count_final(const int4* __restrict__ red, int nred,
+                                                          const int32_t* __restrict__ part, int nsets,
+                                                          int32_t* __restrict__ status) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int tot = 0;
+    for (int s = w; s < nsets; s += COUNT_BS / 64) {
+        int c = 0;
+        const int r0 = first_red_chunk(red, nred, s);
+#pragma unroll 8
+        for (int r = r0 + lane; r < nred && red[r].x == s; r += 64) c += part[r];
+        for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+        if (lane == 0) status[3 + 2 * s] = c;
+        tot += c;
+    }
+    __shared__ int s_t[COUNT_BS / 64];
+    if (lane == 0) s_t[w] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int k = 0; k < COUNT_BS / 64; ++k) t += s_t[k];
+        status[1] = t;
     }
 }
 
@@ -995,12 +1020,6 @@ __global__ void k_load_state(int64_t n, const uint32_t* __restrict__ perm, uint8
     if (hash) hash[p] = sv.hash[i];
 }
 
-// zero the counts of still-active particles (total and per set)
-__global__ void k_zero_unconv(int32_t* status, int nsets) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) status[1] = 0;
-    if (i < nsets) status[3 + 2 * i] = 0;
-}
 
 __global__ void k_ghost(int64_t n, const float* __restrict__ ph, const float* __restrict__ rho,
                         const float* __restrict__ drho, const float* __restrict__ u, float gamma,
@@ -1309,12 +1328,19 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     else hipLaunchKernelGGL((k_force<false>), g, b, 0, st, a);
 }
 
-// status[1] and status[3+2s] = particles still active after a Newton step
+// A Newton step of every active particle.
+static void launch_newton(sph_ctx* ctx, sph_tree* t) {
+    hipLaunchKernelGGL(k_newton, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->d_sets, t->nsets,
+                       t->active, t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi, t->dstep, (double)t->prm.n_target,
+                       (double)t->prm.h_tol, t->status);
+}
+
+// status[1] and status[3+2s] = particles still active after the last Newton
+// step (written, not accumulated: nothing to clear first)
 static void launch_count(sph_ctx* ctx, sph_tree* t) {
-    hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_zero_unconv, dim3(nblk(t->nsets, 256)), dim3(256), 0, st, t->status, t->nsets);
-    hipLaunchKernelGGL(k_count_active, dim3((unsigned)t->nred), dim3(256), 0, st, t->d_red, t->active, t->part_cnt);
-    hipLaunchKernelGGL(k_count_final, dim3(nblk(t->nsets, 4)), dim3(256), 0, st, t->d_red, (int)t->nred, t->part_cnt,
+    hipLaunchKernelGGL(k_count_active, dim3((unsigned)t->nred), dim3(256), 0, ctx->stream, t->d_red, t->active,
+                       t->part_cnt);
+    hipLaunchKernelGGL(k_count_final, dim3(1), dim3(COUNT_BS), 0, ctx->stream, t->d_red, (int)t->nred, t->part_cnt,
                        t->nsets, t->status);
 }
 
@@ -1385,9 +1411,7 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     bool rebuild = false;
     for (; it < t->prm.max_iter; ++it) {
         launch_density(ctx, t, true, ctx->d_counter);
-        hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->d_sets, t->nsets, t->active,
-                           t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi, t->dstep, (double)t->prm.n_target,
-                           (double)t->prm.h_tol, t->status);
+        launch_newton(ctx, t);
         launch_count(ctx, t);
         HIPTRY(hipGetLastError());
         HIPTRY(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
@@ -1493,11 +1517,10 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
             hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
             for (int it = 0; it < k_iter; ++it) {
                 launch_density(ctx, t, true, ctx->d_counter);
-                hipLaunchKernelGGL(k_newton, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->d_sets, t->nsets,
-                                   t->active, t->nw, t->dnw, t->ph, t->bound, t->lo, t->hi, t->dstep,
-                                   (double)t->prm.n_target, (double)t->prm.h_tol, t->status);
-                launch_count(ctx, t);
+                launch_newton(ctx, t);
             }
+            // only the state after the last step is reported
+            launch_count(ctx, t);
             launch_density(ctx, t, true, ctx->d_counter);
             launch_force(ctx, t, ctx->d_counter + NGRP * CSTRIDE);
             launch_reduce(ctx, t, fout ? fout->sums : nullptr);
