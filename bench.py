@@ -171,9 +171,18 @@ def run(args):
     log(f"[bench] newton iterations {it} (incl. rebuilds)")
 
     ach = P * OPS_FORCE / (force_ms / 1e3)
+    traffic = measured_traffic("k_force", cfg["workload"])
     roof = {"kernel": "k_force", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "Tlane-op/s", "frac": ach / VALU_PEAK, "traffic": measured_traffic("k_force", cfg["workload"]),
+            "unit": "Tlane-op/s", "frac": ach / VALU_PEAK, "traffic": traffic,
             "launch_ms": force_ms, "ops_per_pair": OPS_FORCE, "pairs_per_launch": P}
+    # the HBM side: the kernel's measured bytes per launch against the peak
+    # and against what a plain device copy reaches on this GPU
+    copy_tbs = copy_bandwidth()
+    roof["hbm"] = {"copy_TBps": copy_tbs, "peak_TBps": HBM_PEAK / 1e12,
+                   "k_force_TBps": traffic / (force_ms / 1e3) / 1e12 if traffic else None}
+    if traffic:
+        roof["hbm"]["frac_of_peak"] = roof["hbm"]["k_force_TBps"] * 1e12 / HBM_PEAK
+        roof["hbm"]["frac_of_copy"] = roof["hbm"]["k_force_TBps"] / copy_tbs
     out = {"metric": "pair interactions/sec (density+force), batched vs plain; p50/p99 latency",
            "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -280,6 +289,23 @@ def bench_served(sph, n_req=400, pool_size=24, load=0.7):
     summ.update({"saturation_requests_per_s": sat, "arrival_rate_per_s": rate, "load": load,
                  "n_range": [10000, 2000000], "pool_sets": pool_size, "budget_bytes": budget})
     return summ
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Bytes read + written per second by a plain 1 GiB device copy (TB/s)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2 * nbytes / t / 1e12
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):
