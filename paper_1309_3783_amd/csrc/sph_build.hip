@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256) void k_set_hstats(const SetInfo* sets, const f
     const SetInfo S = sets[blockIdx.y];
     float m = 0.f, mn = INFINITY;
     int bad = 0;
+#pragma unroll 8
     for (int64_t i = S.first + (int64_t)blockIdx.x * 256 + threadIdx.x; i < S.first + S.count;
          i += (int64_t)gridDim.x * 256) {
         float v = h[i];
@@ -954,7 +955,8 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         HIPTRY(fill_u32((uint32_t*)d_hmin, S, 0x7F800000u, st));   // +inf
         int64_t maxc = 0;
         for (int s = 0; s < S; ++s) maxc = std::max<int64_t>(maxc, sets[s].count);
-        unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((maxc + 1023) / 1024, 1), 1024);
+        // a few hundred blocks per set at most: their atomics on one word serialise
+        unsigned gx = (unsigned)std::min<int64_t>(std::max<int64_t>((maxc + 4095) / 4096, 1), 256);
         hipLaunchKernelGGL(k_set_hstats, dim3(gx, S), dim3(256), 0, st, d_sets, in->h, (int*)d_hmax, (int*)d_hmin,
                            d_bad);
         HIPTRY(hipGetLastError());
