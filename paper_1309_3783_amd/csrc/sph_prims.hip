@@ -99,12 +99,16 @@ __global__ __launch_bounds__(SCAN_BS) void k_scan_apply(const uint32_t* __restri
 // Inputs up to SCAN_SMALL elements: one block stages them in LDS with
 // coalesced loads, each thread scans a contiguous run of SCAN_SMALL / 1024,
 // and the results go back coalesced (one launch instead of three).
-constexpr int64_t SCAN_SMALL = 8192;
+constexpr int64_t SCAN_SMALL = 32768;
+// (element i sits at i + i/32 in LDS: a thread's run of consecutive
+// elements then spreads over all banks)
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
 __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_t* out, int64_t n,
                                                      uint32_t* __restrict__ total) {
-    __shared__ uint32_t s_v[SCAN_SMALL];
+    __shared__ uint32_t s_v[SCAN_SMALL + SCAN_SMALL / 32];
     __shared__ uint32_t s_w[16];
-    for (int64_t i = threadIdx.x; i < n; i += 1024) s_v[i] = in[i];
+#pragma unroll 8
+    for (int i = threadIdx.x; i < (int)n; i += 1024) s_v[scan_pad(i)] = in[i];
     __syncthreads();
     constexpr int PER = (int)(SCAN_SMALL / 1024);
     const int base = (int)threadIdx.x * PER;
@@ -112,18 +116,19 @@ __global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in, uint32_
     uint32_t acc = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        v[k] = base + k < n ? s_v[base + k] : 0u;
+        v[k] = base + k < n ? s_v[scan_pad(base + k)] : 0u;
         acc += v[k];
     }
     uint32_t tot;
     uint32_t ex = block_excl_scan(acc, s_w, tot);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        if (base + k < n) s_v[base + k] = ex;
+        if (base + k < n) s_v[scan_pad(base + k)] = ex;
         ex += v[k];
     }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += 1024) out[i] = s_v[i];
+#pragma unroll 8
+    for (int i = threadIdx.x; i < (int)n; i += 1024) out[i] = s_v[scan_pad(i)];
     if (threadIdx.x == 0 && total) *total = tot;
 }
 
