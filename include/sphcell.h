@@ -66,7 +66,7 @@ typedef struct sph_tree sph_tree;
 typedef struct {
     int32_t n_split;     /* split a cell only if it holds more than this many particles (400) */
     float split_frac;    /* ... and more than this fraction has h < edge/2 (0.875) */
-    float h_slack;       /* decisions use h*(1+h_slack) to leave room for h to grow (0.1) */
+    float h_slack;       /* decisions use h*(1+h_slack) to leave room for h to grow (0.2) */
     int32_t max_depth;   /* levels below the top grid (12) */
     int32_t top_grid;    /* top cells per side (power of two), 0 = largest allowed */
     float n_target;      /* target N_w for the h solve (48) */

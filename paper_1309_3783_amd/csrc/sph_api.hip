@@ -35,7 +35,7 @@ void sph_params_default(sph_params* p) {
     std::memset(p, 0, sizeof(*p));
     p->n_split = 400;
     p->split_frac = 0.875f;
-    p->h_slack = 0.1f;
+    p->h_slack = 0.2f;
     p->max_depth = 12;
     p->top_grid = 0;
     p->n_target = 48.f;
