@@ -330,3 +330,22 @@ def test_error_report(sph, ctx):
         print(f"[errors] {name:24s} " + "  ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
         assert e["rho"] <= RHO_TOL and e["N_w"] <= RHO_TOL and e["drho/dh"] <= RHO_TOL
         assert e["a/S"] <= FORCE_TOL and e["du/dt"] <= FORCE_TOL
+
+
+def test_one_level_lists_match_general_path(sph, ctx):
+    """A set whose tree has one level gets its interaction lists straight
+    from the top grid; inside a batch whose tree is deeper the same set goes
+    through the task list and its sort.  Both orders must agree, so the
+    results are bitwise the same."""
+    u = sphinputs.uniform(3000, 71, velocity=True)
+    u, hu = I.fixed_h_case(u)
+    p = sphinputs.plummer_mixture(12000, 72, velocity=True)
+    p, hp = I.fixed_h_case(p)
+    (alone,), t1 = run_fixed(sph, ctx, [u], [hu])
+    assert t1.stats()["levels"] == 1
+    res, t2 = run_fixed(sph, ctx, [u, p], [hu, hp])
+    assert t2.stats()["levels"] > 1
+    for k in ("rho", "nw", "drho_dh", "nngb", "hash"):
+        assert np.array_equal(alone[0][k], res[0][0][k]), k
+    for k in ("ax", "ay", "az", "dudt", "S", "nforce", "hash"):
+        assert np.array_equal(alone[1][k], res[0][1][k]), k
