@@ -217,57 +217,67 @@ __global__ __launch_bounds__(RS_BS) void k_rs_hist(const uint64_t* __restrict__ 
 // out, so that runs of one digit go to consecutive addresses.  offs is the
 // scanned histogram: offs[d * nb + b] = first output position of digit d of
 // block b; the next entry bounds it, so the block's own digit counts (and
-// their local starts) follow from offs alone.
+// their local starts) follow from offs alone.  RS_SBS threads take the tile
+// in RS_TILE / RS_SBS rounds (the histogram kernel's tiling is the same).
+constexpr int RS_SBS = 1024;
+constexpr int RS_SROUNDS = RS_TILE / RS_SBS;
+constexpr int RS_SW = RS_SBS / 64;
 template <bool VALS>
-__global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                      const uint32_t* __restrict__ vin,
-                                                      uint64_t* __restrict__ kout,
-                                                      uint32_t* __restrict__ vout, int64_t n, int shift,
-                                                      const uint32_t* __restrict__ offs, int64_t nb) {
+__global__ __launch_bounds__(RS_SBS) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                       const uint32_t* __restrict__ vin,
+                                                       uint64_t* __restrict__ kout,
+                                                       uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                       const uint32_t* __restrict__ offs, int64_t nb) {
     __shared__ uint64_t s_k[RS_TILE];
     __shared__ uint32_t s_v[VALS ? RS_TILE : 1];
     __shared__ uint32_t g_off[256];
     __shared__ uint32_t l_off[256];
     __shared__ uint32_t d_base[256];
-    __shared__ uint32_t w_cnt[RS_BS / 64][256];
-    __shared__ uint32_t w_sum[RS_BS / 64];
+    __shared__ uint32_t w_cnt[RS_SW][256];
+    __shared__ uint32_t w_sum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t b = blockIdx.x;
     const int64_t base = b * RS_TILE;
     const int tile_n = (int)min((int64_t)RS_TILE, n - base);
-    // this block's digit counts and their local starts (exclusive scan)
-    const int64_t oi = (int64_t)tid * nb + b;
-    const uint32_t go = offs[oi];
-    const uint32_t gnext = oi + 1 < 256 * nb ? offs[oi + 1] : (uint32_t)n;
-    const uint32_t cnt = gnext - go;
-    uint32_t inc = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t v = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += v;
-    }
-    if (lane == 63) w_sum[w] = inc;
-    g_off[tid] = go;
-    d_base[tid] = 0;
-    for (int k = 0; k < RS_BS / 64; ++k) w_cnt[k][tid] = 0;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int k = 0; k < w; ++k) before += w_sum[k];
-    l_off[tid] = before + inc - cnt;
-    __syncthreads();
     // the whole tile is loaded at once (all loads in flight together)
-    uint64_t kr[RS_ROUNDS];
-    uint32_t vr[RS_ROUNDS];
+    uint64_t kr[RS_SROUNDS];
+    uint32_t vr[RS_SROUNDS];
 #pragma unroll
-    for (int r = 0; r < RS_ROUNDS; ++r) {
-        const int li = r * RS_BS + tid;
+    for (int r = 0; r < RS_SROUNDS; ++r) {
+        const int li = r * RS_SBS + tid;
         kr[r] = li < tile_n ? kin[base + li] : 0;
         vr[r] = (VALS && li < tile_n) ? vin[base + li] : 0;
     }
+    // this block's digit counts and their local starts (exclusive scan);
+    // threads 0..255 stand for the digits
+    uint32_t cnt = 0, inc = 0;
+    if (tid < 256) {
+        const int64_t oi = (int64_t)tid * nb + b;
+        const uint32_t go = offs[oi];
+        const uint32_t gnext = oi + 1 < 256 * nb ? offs[oi + 1] : (uint32_t)n;
+        cnt = gnext - go;
+        inc = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += v;
+        }
+        if (lane == 63) w_sum[w] = inc;
+        g_off[tid] = go;
+        d_base[tid] = 0;
+    }
+    for (int i = tid; i < RS_SW * 256; i += RS_SBS) (&w_cnt[0][0])[i] = 0;
+    __syncthreads();
+    if (tid < 256) {
+        uint32_t before = 0;
+        for (int k = 0; k < w; ++k) before += w_sum[k];
+        l_off[tid] = before + inc - cnt;
+    }
+    __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int r = 0; r < RS_ROUNDS; ++r) {
-        const int li = r * RS_BS + tid;
+    for (int r = 0; r < RS_SROUNDS; ++r) {
+        const int li = r * RS_SBS + tid;
         const bool valid = li < tile_n;
         const uint64_t k = kr[r];
         const uint32_t v = vr[r];
@@ -282,9 +292,9 @@ __global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint64_t* __restrict
         const bool leader = valid && ((match & lt) == 0);
         if (leader) w_cnt[w][d] = (uint32_t)__popcll(match);
         __syncthreads();
-        {
+        if (tid < 256) {
             uint32_t run = d_base[tid];
-            for (int q = 0; q < RS_BS / 64; ++q) {
+            for (int q = 0; q < RS_SW; ++q) {
                 const uint32_t c = w_cnt[q][tid];
                 w_cnt[q][tid] = run;
                 run += c;
@@ -298,12 +308,12 @@ __global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint64_t* __restrict
             if (VALS) s_v[pos] = v;
         }
         __syncthreads();
-        for (int q = 0; q < RS_BS / 64; ++q) w_cnt[q][tid] = 0;
+        for (int i = tid; i < RS_SW * 256; i += RS_SBS) (&w_cnt[0][0])[i] = 0;
         __syncthreads();
     }
     // write out in digit order: consecutive threads, consecutive addresses
     // within a digit's run
-    for (int i = tid; i < tile_n; i += RS_BS) {
+    for (int i = tid; i < tile_n; i += RS_SBS) {
         const uint64_t k = s_k[i];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         const uint32_t pos = g_off[d] + (uint32_t)i - l_off[d];
@@ -332,10 +342,10 @@ hipError_t radix_sort(uint64_t* key, uint32_t* val, uint64_t* key_alt, uint32_t*
         hipError_t e = exclusive_scan(hist, hist, 256 * nb, stmp, nullptr, st);
         if (e != hipSuccess) return e;
         if (val)
-            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nb), dim3(RS_BS), 0, st, ka, va, kb, vb,
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nb), dim3(RS_SBS), 0, st, ka, va, kb, vb,
                                n, shift, hist, nb);
         else
-            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)nb), dim3(RS_BS), 0, st, ka, va, kb,
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)nb), dim3(RS_SBS), 0, st, ka, va, kb,
                                vb, n, shift, hist, nb);
         std::swap(ka, kb);
         std::swap(va, vb);
