@@ -198,18 +198,24 @@ constexpr int RS_BS = 256;
 constexpr int RS_ROUNDS = 16;
 constexpr int RS_TILE = RS_BS * RS_ROUNDS;
 
-__global__ __launch_bounds__(RS_BS) void k_rs_hist(const uint64_t* __restrict__ key, int64_t n, int shift,
-                                                   uint32_t* __restrict__ hist, int64_t nb) {
+__global__ __launch_bounds__(1024) void k_rs_hist(const uint64_t* __restrict__ key, int64_t n, int shift,
+                                                 uint32_t* __restrict__ hist, int64_t nb) {
+    // the block's tile of RS_TILE elements, 1024 threads, all loads in flight
     __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int r = 0; r < RS_ROUNDS; ++r) {
-        int64_t i = base + (int64_t)r * RS_BS + threadIdx.x;
-        if (i < n) atomicAdd(&h[(uint32_t)(key[i] >> shift) & 255u], 1u);
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    uint32_t d[RS_TILE / 1024];
+#pragma unroll
+    for (int r = 0; r < RS_TILE / 1024; ++r) {
+        const int64_t i = base + (int64_t)r * 1024 + threadIdx.x;
+        d[r] = i < n ? (uint32_t)(key[i] >> shift) & 255u : 256u;
     }
+#pragma unroll
+    for (int r = 0; r < RS_TILE / 1024; ++r)
+        if (d[r] < 256u) atomicAdd(&h[d[r]], 1u);
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
 // One pass: the tile of RS_TILE elements of this block is first placed in
@@ -338,7 +344,7 @@ hipError_t radix_sort(uint64_t* key, uint32_t* val, uint64_t* key_alt, uint32_t*
     uint64_t *ka = key, *kb = key_alt;
     uint32_t *va = val, *vb = val_alt;
     for (int shift = lo_bit; shift < lo_bit + nbits; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(RS_BS), 0, st, ka, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(1024), 0, st, ka, n, shift, hist, nb);
         hipError_t e = exclusive_scan(hist, hist, 256 * nb, stmp, nullptr, st);
         if (e != hipSuccess) return e;
         if (val)
