@@ -303,8 +303,7 @@ __device__ inline int top_neighbour(const SetInfo& S, const Cell& A, int ox, int
     return S.top_base + (int)morton3((uint64_t)bx, (uint64_t)by, (uint64_t)bz);
 }
 
-__global__ void k_top_task_count(const SetInfo* sets, int nsets, int ntop, const Cell* __restrict__ cells,
-                                 uint32_t* cnt) {
+__global__ void k_top_task_count(const SetInfo* sets, int ntop, const Cell* __restrict__ cells, uint32_t* cnt) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ntop) return;
     const Cell A = cells[c];
@@ -1074,7 +1073,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(t->scratch(ntop + 1));
     ERRTRY(t->alloc(t->b_split, sizeof(uint32_t) * (ntop + 1), (void**)&t->split_idx));
 #define total (t->d_total)
-    hipLaunchKernelGGL(k_top_task_count, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, S, (int)ntop, t->cells,
+    hipLaunchKernelGGL(k_top_task_count, dim3(nblk(ntop, 256)), dim3(256), 0, st, d_sets, (int)ntop, t->cells,
                        t->sc_a);
     HIPTRY(exclusive_scan(t->sc_a, t->sc_b, ntop, t->sc_tmp, total, st));
     hipLaunchKernelGGL(k_split_flags, dim3(nblk(ntop, 256)), dim3(256), 0, st, t->cells, (int64_t)0, ntop,
