@@ -33,6 +33,7 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // are far inside the stated tolerances.
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Work distribution of the persistent interaction kernels.  The chunk list
 // runs through space in Morton order; it is cut into NGRP contiguous ranges,
@@ -743,8 +744,11 @@ struct ForceP {
         const float4 sv = S.v[j];
         const float cj = S.c[j];
         const float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
-        const float r = fsqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        const float rinv = frcp(r);
+        // 1/r from one reciprocal square root, r = r^2 / r (r > 0: positions
+        // in a set are distinct)
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        const float rinv = frsq(r2);
+        const float r = r2 * rinv;
         const float ki = L.K * gradF(r * L.hinv, L.h, rinv);
         const float kj = sh.z * gradF(r * sh.y, q.w, rinv);
         const float vdx = L.v.x - sv.x, vdy = L.v.y - sv.y, vdz = L.v.z - sv.z;
