@@ -81,6 +81,7 @@ struct sph_tree {
     uint64_t* hashd = nullptr;
     // solve state
     uint8_t* active = nullptr;
+    uint32_t* alist = nullptr;   // chunks with active particles, per work range
     float *lo = nullptr, *hi = nullptr, *dstep = nullptr;
     int32_t* status = nullptr;   // [0] rebuild flag, [1] unconverged count
     // ghost + force state (cell order)

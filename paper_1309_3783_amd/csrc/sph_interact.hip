@@ -41,24 +41,86 @@ __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x)
 // the XCDs in turn), so the chunks one XCD works on at a time are neighbours
 // and share partner data in that XCD's L2; a wave whose range is exhausted
 // moves on to the following ranges.  ctr holds NGRP counters (CSTRIDE
-// words apart), zero at launch.  Which wave takes which chunk changes no result.
+// words apart), zero at launch.  In a Newton pass after the first, the
+// ranges hold only the chunks that still have active particles: lcount[g *
+// CSTRIDE] of them, listed from the start of range g in list (made by
+// k_chunk_list), so that a pass in which few particles are left costs a
+// few atomics rather than one per chunk.  A wave looking past its own range
+// first reads the counter and skips a range already handed out, without an
+// atomic.  Which wave takes which chunk changes no result.
 constexpr int NGRP = 8;
 // the counters sit 128 bytes apart: atomics on one cache line from all XCDs
 // serialise
 constexpr int CSTRIDE = 32;
-__device__ __forceinline__ int next_chunk(int* __restrict__ ctr, int nchunks, int home, int& k) {
+__device__ __forceinline__ int next_chunk(int* __restrict__ ctr, int nchunks, const uint32_t* __restrict__ list,
+                                          const int* __restrict__ lcount, int home, int& k) {
     const int lane = threadIdx.x & 63;
     while (k < NGRP) {
         const int g = (home + k) & (NGRP - 1);
         const int lo = (int)((int64_t)nchunks * g / NGRP);
         const int hi = (int)((int64_t)nchunks * (g + 1) / NGRP);
-        int item = 0;
-        if (lane == 0) item = atomicAdd(&ctr[g * CSTRIDE], 1);
-        item = uni(__shfl(item, 0, 64));
-        if (lo + item < hi) return lo + item;
+        const int cnt = list ? uni(lcount[g * CSTRIDE]) : hi - lo;
+        const bool open =
+            cnt > 0 && (k == 0 || __hip_atomic_load(&ctr[g * CSTRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < cnt);
+        if (open) {
+            int item = 0;
+            if (lane == 0) item = atomicAdd(&ctr[g * CSTRIDE], 1);
+            item = uni(__shfl(item, 0, 64));
+            if (item < cnt) return list ? (int)list[lo + item] : lo + item;
+        }
         ++k;
     }
     return -1;
+}
+
+// The chunks that still hold particles in Newton state 1 (active), listed
+// per work range for the next density pass: one thread per chunk, blocks
+// within one range, one atomic per block.  lcount must be zero on entry; the
+// order inside a range follows the blocks' atomics and changes no result.
+// active is read as 8-byte words: its buffer is 8-byte aligned and padded
+// past the last particle.
+constexpr int LIST_BS = 256;
+__global__ __launch_bounds__(LIST_BS) void k_chunk_list(const int4* __restrict__ chunks, int nchunks, int bpg,
+                                                        const uint8_t* __restrict__ active, uint32_t* __restrict__ list,
+                                                        int* __restrict__ lcount) {
+    const int g = blockIdx.x / bpg, part = blockIdx.x - g * bpg;
+    const int lo = (int)((int64_t)nchunks * g / NGRP);
+    const int hi = (int)((int64_t)nchunks * (g + 1) / NGRP);
+    const int c = lo + part * LIST_BS + (int)threadIdx.x;
+    bool on = false;
+    if (c < hi) {
+        const int4 ch = chunks[c];
+        const int64_t a = ch.y, b = (int64_t)ch.y + ch.z;   // particles [a, b)
+        const uint64_t* w = reinterpret_cast<const uint64_t*>(active);
+        uint64_t any = 0;
+        for (int64_t q = a >> 3; q < (b + 7) >> 3; ++q) {
+            uint64_t v = w[q];
+            // bytes equal to 1 (states are 0, 1, 2)
+            v = v & ~(v >> 1) & 0x0101010101010101ull;
+            const int64_t first = q << 3;
+            if (first < a) v &= ~0ull << (8 * (a - first));
+            if (first + 8 > b) v &= ~0ull >> (8 * (first + 8 - b));
+            any |= v;
+        }
+        on = any != 0;
+    }
+    __shared__ int s_n[LIST_BS / 64];
+    __shared__ int s_base;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t bal = __ballot(on);
+    if (lane == 0) s_n[wv] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int i = 0; i < LIST_BS / 64; ++i) {
+            const int v = s_n[i];
+            s_n[i] = tot;
+            tot += v;
+        }
+        s_base = tot ? atomicAdd(&lcount[g * CSTRIDE], tot) : 0;
+    }
+    __syncthreads();
+    if (on) list[lo + s_base + s_n[wv] + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)c;
 }
 
 // Staged tiles hold TILE_PAD extra slots of far-away points, so that every
@@ -183,6 +245,8 @@ struct DensArgs {
     const float* ph;
     const uint64_t* mix;
     const uint8_t* active;
+    const uint32_t* list;   // chunks with active particles (null: all chunks)
+    const int* lcount;
     const uint64_t* csr;
     const uint32_t* csr_off;
     const uint32_t* segoff;
@@ -611,7 +675,7 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
     const int home = blockIdx.x & (NGRP - 1);
     int grp = 0;
     for (;;) {
-        const int item = next_chunk(a.counter, a.nchunks, home, grp);
+        const int item = next_chunk(a.counter, a.nchunks, a.list, a.lcount, home, grp);
         if (item < 0) break;
         const int4 ch = a.chunks[item];
         const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
@@ -782,7 +846,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int home = blockIdx.x & (NGRP - 1);
     int grp = 0;
     for (;;) {
-        const int item = next_chunk(a.counter, a.nchunks, home, grp);
+        const int item = next_chunk(a.counter, a.nchunks, nullptr, nullptr, home, grp);
         if (item < 0) break;
         const int4 ch = a.chunks[item];
         const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
@@ -1197,14 +1261,19 @@ static Err ensure_state(sph_tree* t) {
     t->nw = t->drho + n;
     t->dnw = t->nw + n;
     t->nngb = (int32_t*)(t->dnw + n);
-    // solve: lo, hi, dstep, status (2 + 2 per set), active
+    // solve: lo, hi, dstep (float), status (2 + 2 per set), active (one byte
+    // per particle; 256-byte aligned and padded, k_chunk_list reads it as
+    // 8-byte words), the chunk list of the listed density passes
     const int64_t nst = 2 + 2 * (int64_t)t->nsets;
-    ERRTRY(t->alloc(t->b_solve, n * (3 * sizeof(float) + 1) + sizeof(int32_t) * (nst + 64) + 256, &p));
+    const size_t act_off = (3 * n * sizeof(float) + sizeof(int32_t) * ((nst + 63) / 64) * 64 + 255) & ~(size_t)255;
+    const size_t list_off = (act_off + n + 8 + 255) & ~(size_t)255;
+    ERRTRY(t->alloc(t->b_solve, list_off + sizeof(uint32_t) * std::max<int64_t>(t->nchunks, 1), &p));
     t->lo = (float*)p;
     t->hi = t->lo + n;
     t->dstep = t->hi + n;
     t->status = (int32_t*)(t->dstep + n);
-    t->active = (uint8_t*)(t->status + ((nst + 63) / 64) * 64);
+    t->active = (uint8_t*)p + act_off;
+    t->alist = (uint32_t*)((uint8_t*)p + list_off);
     // force: frec (float4), ax, ay, az, du, vs, S (float), nf (int), hash (u64)
     ERRTRY(t->alloc(t->b_force, n * (sizeof(float4) + 6 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 64,
                     &p));
@@ -1252,7 +1321,7 @@ static int persistent_blocks(sph_ctx* ctx, const sph_tree* t, int64_t items) {
     return (int)std::max<int64_t>(1, std::min(want, cap));
 }
 
-static DensArgs dens_args(sph_tree* t, int* counter) {
+static DensArgs dens_args(sph_tree* t, int* counter, const int* lcount) {
     DensArgs a;
     a.cells = t->cells;
     a.sets = t->d_sets;
@@ -1263,6 +1332,8 @@ static DensArgs dens_args(sph_tree* t, int* counter) {
     a.ph = t->ph;
     a.mix = t->mix;
     a.active = t->active;
+    a.list = lcount ? t->alist : nullptr;
+    a.lcount = lcount;
     a.csr = t->csr;
     a.csr_off = t->csr_off;
     a.segoff = t->segoff;
@@ -1279,10 +1350,22 @@ static DensArgs dens_args(sph_tree* t, int* counter) {
     return a;
 }
 
-static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, int* counter) {
+// listed: a Newton pass after the first, over the chunks that still hold
+// active particles (k_chunk_list; its counts sit in the context's counter
+// block after the force counters, zeroed here with the density counters)
+static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, bool listed, int* counter) {
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
-    DensArgs a = dens_args(t, counter);
+    int* lcount = nullptr;
+    if (listed) {
+        lcount = counter + 2 * NGRP * CSTRIDE;
+        hipLaunchKernelGGL(k_zero_i32, dim3(3), dim3(256), 0, st, counter, 3 * NGRP * CSTRIDE);
+        const int bpg = (int)((t->nchunks / NGRP + LIST_BS) / LIST_BS);
+        hipLaunchKernelGGL(k_chunk_list, dim3(NGRP * bpg), dim3(LIST_BS), 0, st, t->chunks, (int)t->nchunks, bpg,
+                           t->active, t->alist, lcount);
+    } else {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
+    }
+    DensArgs a = dens_args(t, counter, lcount);
     dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
     if (solve) {
         if (t->hash) hipLaunchKernelGGL((k_density<true, true>), g, b, 0, st, a);
@@ -1376,7 +1459,7 @@ Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out) {
     ERRTRY(ensure_state(t));
     if (t->n == 0) return Err{};
     ev_mark(ctx, "start");
-    launch_density(ctx, t, false, ctx->d_counter);
+    launch_density(ctx, t, false, false, ctx->d_counter);
     ev_mark(ctx, "density");
     launch_scatter_density(ctx, t, out);
     HIPTRY(hipGetLastError());
@@ -1414,7 +1497,7 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     int it = 0;
     bool rebuild = false;
     for (; it < t->prm.max_iter; ++it) {
-        launch_density(ctx, t, true, ctx->d_counter);
+        launch_density(ctx, t, true, it > 0, ctx->d_counter);
         launch_newton(ctx, t);
         launch_count(ctx, t);
         HIPTRY(hipGetLastError());
@@ -1426,7 +1509,7 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     if (!rebuild && hstat[1] > 0) {
         // unconverged particles moved h after their last density: recompute
         // their density at the h they hold now
-        launch_density(ctx, t, true, ctx->d_counter);
+        launch_density(ctx, t, true, true, ctx->d_counter);
     }
     ev_mark(ctx, "solve");
     launch_scatter_density(ctx, t, out);
@@ -1520,12 +1603,12 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
             const int nst = 2 + 2 * t->nsets;
             hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
             for (int it = 0; it < k_iter; ++it) {
-                launch_density(ctx, t, true, ctx->d_counter);
+                launch_density(ctx, t, true, it > 0, ctx->d_counter);
                 launch_newton(ctx, t);
             }
             // only the state after the last step is reported
             launch_count(ctx, t);
-            launch_density(ctx, t, true, ctx->d_counter);
+            launch_density(ctx, t, true, k_iter > 0, ctx->d_counter);
             launch_force(ctx, t, ctx->d_counter + NGRP * CSTRIDE);
             launch_reduce(ctx, t, fout ? fout->sums : nullptr);
             launch_scatter_density(ctx, t, dout);
