@@ -751,11 +751,24 @@ __global__ __launch_bounds__(256) void k_seg_sort_cell(int64_t nc, const SetInfo
 }
 
 // Segments of 65..SEG_LDS_MAX entries (their (cell, axis) indices listed in
-// sel), bitonic sort in LDS.  A block takes four lists at a time: each list
-// of at most WAVE_SORT_MAX entries is sorted by one wavefront on its own
+// sel), sorted in LDS.  A block takes four lists at a time: each list of at
+// most WAVE_SORT_MAX entries is sorted by one wavefront on its own
 // (wave-level synchronisation only), the longer ones by the whole block.
-constexpr int WAVE_SORT_MAX = 256;
+// Lists of up to BITONIC_MAX entries take a bitonic network in LDS; longer
+// ones a merge sort (runs of 16 sorted in registers, then merged pairwise
+// through LDS), which moves each key through LDS once per doubling instead
+// of once per bitonic stage.
+constexpr int WAVE_SORT_MAX = 1024;
+constexpr int BITONIC_MAX = 256;
+constexpr int MS_RUN = 16;
 static_assert(4 * WAVE_SORT_MAX <= SEG_LDS_MAX, "wave sorts share the block's array");
+static_assert(SEG_LDS_MAX <= 256 * MS_RUN, "the block's threads hold the whole list in runs");
+
+template <int NT>
+__device__ __forceinline__ void group_sync() {
+    if (NT == 64) wave_lds_sync();
+    else __syncthreads();
+}
 
 template <int NT>
 __device__ __forceinline__ void bitonic_lds(uint64_t* s, int P, int t) {
@@ -771,9 +784,87 @@ __device__ __forceinline__ void bitonic_lds(uint64_t* s, int P, int t) {
                     s[j] = a;
                 }
             }
-            if (NT == 64) wave_lds_sync();
-            else __syncthreads();
+            group_sync<NT>();
         }
+    }
+}
+
+__device__ __forceinline__ void cmp_swap(uint64_t& x, uint64_t& y) {
+    const uint64_t a = x, b = y;
+    const bool sw = b < a;
+    x = sw ? b : a;
+    y = sw ? a : b;
+}
+
+// ascending sort of 16 keys held in registers (bitonic network, fixed indices)
+__device__ __forceinline__ void sort_run(uint64_t (&r)[MS_RUN]) {
+#pragma unroll
+    for (int lg = 1; lg <= 4; ++lg) {
+#pragma unroll
+        for (int ls = lg - 1; ls >= 0; --ls) {
+#pragma unroll
+            for (int i = 0; i < MS_RUN; ++i) {
+                const int j = i ^ (1 << ls);
+                if (j > i) {
+                    if ((i & (1 << lg)) == 0) cmp_swap(r[i], r[j]);
+                    else cmp_swap(r[j], r[i]);
+                }
+            }
+        }
+    }
+}
+
+// Merge sort of the P keys in s (P a power of two, 2 * MS_RUN <= P <=
+// NT * MS_RUN) by the NT threads of a wave (NT = 64) or block (NT = 256);
+// thread t owns output positions [16 t, 16 t + 16).  Each round merges
+// pairs of sorted runs of length L: a thread finds where its 16 outputs
+// start on the merge path of its pair (binary search), merges them into
+// registers, and all write back after a barrier.  Keys are compared as
+// unsigned integers; equal keys (the padding) take the first run first.
+template <int NT>
+__device__ __forceinline__ void merge_sort_lds(uint64_t* s, int P, int t) {
+    const bool on = t * MS_RUN < P;
+    uint64_t r[MS_RUN];
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < MS_RUN; ++k) r[k] = s[t * MS_RUN + k];
+        sort_run(r);
+#pragma unroll
+        for (int k = 0; k < MS_RUN; ++k) s[t * MS_RUN + k] = r[k];
+    }
+    group_sync<NT>();
+    for (int L = MS_RUN; L < P; L <<= 1) {
+        if (on) {
+            const int d = (t * MS_RUN) & (2 * L - 1);   // position in the merged pair
+            const uint64_t* A = s + (t * MS_RUN - d);
+            const uint64_t* B = A + L;
+            int lo = d > L ? d - L : 0, hi = d < L ? d : L;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (!(B[d - 1 - mid] < A[mid])) lo = mid + 1;
+                else hi = mid;
+            }
+            int i = lo, j = d - lo;
+            uint64_t a = i < L ? A[i] : 0ull, b = j < L ? B[j] : 0ull;
+            // one LDS read per output: the successor of the key taken
+#pragma unroll
+            for (int k = 0; k < MS_RUN; ++k) {
+                const bool ta = i < L && (j >= L || !(b < a));
+                r[k] = ta ? a : b;
+                i += ta ? 1 : 0;
+                j += ta ? 0 : 1;
+                const int q = ta ? i : j;
+                const uint64_t v = q < L ? (ta ? A : B)[q] : 0ull;
+                a = ta ? v : a;
+                b = ta ? b : v;
+            }
+        }
+        group_sync<NT>();
+        if (on) {
+#pragma unroll
+            for (int k = 0; k < MS_RUN; ++k) s[t * MS_RUN + k] = r[k];
+        }
+        group_sync<NT>();
     }
 }
 
@@ -802,7 +893,8 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
                     sw[e] = k;
                 }
                 wave_lds_sync();
-                bitonic_lds<64>(sw, P, lane);
+                if (P <= BITONIC_MAX) bitonic_lds<64>(sw, P, lane);
+                else merge_sort_lds<64>(sw, P, lane);
                 const uint32_t o = off[ca];
                 for (int e = lane; e < n; e += 64) {
                     const uint64_t k = sw[e];
@@ -829,7 +921,7 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
                 s[e] = k;
             }
             __syncthreads();
-            bitonic_lds<256>(s, P, threadIdx.x);
+            merge_sort_lds<256>(s, P, threadIdx.x);
             const uint32_t o = off[ca];
             for (int e = threadIdx.x; e < n; e += blockDim.x) {
                 const uint64_t k = s[e];

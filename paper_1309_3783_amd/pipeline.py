@@ -89,11 +89,21 @@ def finish_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int, m
     if not bad:
         return 0
     reruns = 0
-    aux = B.Tree(tree.ctx)
+    # one auxiliary tree per main tree, and the outputs of each round, are
+    # kept from call to call: a batch that needs the same re-run every step
+    # allocates once
+    aux = getattr(tree, "_aux", None)
+    if aux is None:
+        aux = tree._aux = B.Tree(tree.ctx)
+    cache = tree.__dict__.setdefault("_aux_out", {})
+    hashed = out.d.hash is not None
     cur_batch, cur_out, ids = batch, out, list(range(batch.nsets))
-    for _ in range(max_rounds):
+    for r in range(max_rounds):
         sub = sub_batch(cur_batch, bad, cur_out.d.h)
-        sub_out = Outputs(sub.n, sub.nsets, hash=out.d.hash is not None)
+        key = (sub.n, sub.nsets, hashed)
+        if r not in cache or cache[r][0] != key:
+            cache[r] = (key, Outputs(sub.n, sub.nsets, hash=hashed))
+        sub_out = cache[r][1]
         launch_graph(aux, sub, prm, sub_out, k_iter)
         aux.ctx.stream.synchronize()
         reruns += len(bad)
