@@ -338,7 +338,13 @@ __device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, i
                                              typename P::Acc& acc, bool self) {
     const int lane = threadIdx.x & 63;
     // far-away padding: every share has the same length (R * share - n < 16)
-    if (lane < TILE - TCAP) S.p[n + lane] = make_float4(FAR, FAR, FAR, 0.f);
+    if (lane < TILE - TCAP) {
+        // the constant is made here, not kept live across the walk (the
+        // compiler would otherwise hold it in four registers or spill it)
+        float far = FAR;
+        asm volatile("" : "+v"(far));
+        S.p[n + lane] = make_float4(far, far, far, 0.f);
+    }
     wave_lds_sync();
     const int share = (n + R - 1) >> (31 - __builtin_clz(R));
     const int j0 = rep * share;
