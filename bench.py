@@ -11,7 +11,9 @@ U(+-0.1) spacings (seed 2), h solved by Newton to 48 +- 0.5.
 The same line carries the batched comparison (256 uneven sets in one build
 and one HIP graph, autotuned, vs the plain one-set-at-a-time loop) and the
 served Poisson stream (p50/p99 latency).  --config multires times the 8M
-clumpy set instead.  Prints ONE JSON line.
+clumpy set instead; --config sod times leapfrog time steps of the paper's
+shock tube (each step: two kicks, a drift, build, sort, h solve, force, the
+Courant step).  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -319,12 +321,49 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
+def bench_sod(args):
+    """Time steps of the shock tube (780,448 + 197,173 particles standing in
+    for the paper's 800,000 + 200,000): W untimed steps, then K timed ones,
+    each at the Courant step of the current forces."""
+    import torch
+    import paper_1309_3783_amd as sph
+    from paper_1309_3783_amd import integrate
+    import sphinputs
+    ps = sphinputs.sod()
+    ctx = sph.Context(0)
+    batch = sph.batch_from_sets([ps])
+    lf = integrate.Leapfrog(ctx, batch)
+    for _ in range(args.warmup):
+        lf.step(lf.cfl_dt())
+    torch.cuda.synchronize()
+    t0, e0 = lf.t, lf.energy()
+    pairs = 0.0
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        lf.step(lf.cfl_dt())
+        pairs += float(lf.f.sums[6].item()) / 2.0
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    e1 = lf.energy()
+    ms = el * 1e3 / args.steps
+    log(f"[bench] sod: {args.steps} steps in {el:.3f} s ({ms:.2f} ms/step), t {t0:.4f} -> {lf.t:.4f}, "
+        f"dE/E {(e1 - e0) / e0:.2e}")
+    return {"metric": "pair interactions/sec (density+force) within leapfrog time steps", "value": 2 * pairs / el,
+            "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "sod_shock_tube_1M", "n": ps.n, "n_left": ps.meta["n_left"],
+                       "n_right": ps.meta["n_right"], "rho": [1.0, ps.meta["rho_right"]], "P": [1.0, 0.1795],
+                       "step": "kick-drift-kick, Courant 0.3", "h": "Newton to N_w = 48 +- 0.5"},
+            "sim_time": [t0, lf.t], "energy_drift": (e1 - e0) / e0, "cpu_baseline": None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="plain", choices=["plain", "multires"])
+    ap.add_argument("--config", default="plain", choices=["plain", "multires", "sod"])
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only (no batched/served)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -338,7 +377,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    out = run(args)
+    out = bench_sod(args) if args.config == "sod" else run(args)
     print(json.dumps(out))
 
 

@@ -199,6 +199,32 @@ sph_status sph_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out);
 sph_status sph_run_graph(sph_ctx* ctx, sph_tree* t, int32_t k_iter, const sph_density_out* dout,
                          const sph_force_out* fout, int32_t* n_unconverged_dev);
 
+/* Time integration (Section III-A: the test runs advance all particles with
+ * one fixed time step and recompute every force each step), as the pieces
+ * of a kick-drift-kick leapfrog over caller-order arrays.  One step of size
+ * dt: sph_kick(dt/2) with the forces a_n, sph_drift(dt), a second
+ * sph_kick(dt/2) from the half-step velocities into separate arrays (the
+ * velocities and energies predicted for the end of the step, which the
+ * viscosity and pressure terms of the new forces use), build / solve_h /
+ * force at the new positions, then sph_kick(dt/2) with a_{n+1}.
+ *
+ * sph_kick: v_out = v + dt a and u_out = u + dt du/dt, element-wise for n
+ * particles ([device] arrays; the outputs may alias the inputs).
+ * sph_drift: x += dt v (FP64 positions, FP32 velocities) for the particles
+ * of every set, each wrapped into [0, box[s]) ([host] offsets, box as in
+ * sph_input).
+ * sph_cfl_dt: *dt [host] = c_cfl min_i h_i / vsig_i over the particles with
+ * vsig_i > 0 (h from the density outputs, vsig from the force outputs;
+ * +inf if there are none); synchronises the stream.
+ * Errors: SPH_E_ARG (null pointers, bad sizes or a non-finite dt),
+ * SPH_E_HIP. */
+sph_status sph_kick(sph_ctx* ctx, int64_t n, float dt, const float* vx, const float* vy, const float* vz,
+                    const float* u, const float* ax, const float* ay, const float* az, const float* dudt,
+                    float* vx_out, float* vy_out, float* vz_out, float* u_out);
+sph_status sph_drift(sph_ctx* ctx, int32_t nsets, const int64_t* offsets, const double* box, double dt, double* x,
+                     double* y, double* z, const float* vx, const float* vy, const float* vz);
+sph_status sph_cfl_dt(sph_ctx* ctx, int64_t n, const float* h, const float* vsig, float c_cfl, double* dt);
+
 /* Per-stage timing (milliseconds, from HIP events recorded on the context's
  * stream while timing is enabled) of every call since the timings were last
  * read, in call order: names[i] = stage name, ms[i] = time.  Reading

@@ -3,8 +3,8 @@ cell-pair sweeps (arXiv:1309.3783, Section II).
 
 The compute runs in libsphcell.so (HIP, built by ``build.py``); this package
 only marshals arguments (``binding``) and drives batches and request streams
-(``serve``).
+(``pipeline``, ``serve``) and time stepping (``integrate``).
 """
 from .binding import (Batch, Context, DensityOut, ForceOut, SphError, Tree, batch_from_sets,  # noqa: F401
                       footprint, lib, params, solve_with_rebuild, SPH_FLAG_PAIR_HASH, SPH_OK,
-                      SPH_E_REBUILD, SPH_E_NOCONV)
+                      SPH_E_REBUILD, SPH_E_NOCONV, kick, drift, cfl_dt)

@@ -24,7 +24,7 @@ SPH_FLAG_RESUME = 2
 EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
            "sph_last_error", "sph_footprint", "sph_tree_create", "sph_tree_destroy", "sph_tree_bytes",
            "sph_build_cells", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
-           "sph_last_timings", "sph_enable_timing", "sph_tree_stats"]
+           "sph_last_timings", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
 
 
 class sph_params(C.Structure):
@@ -93,9 +93,12 @@ def lib():
         L.sph_enable_timing.argtypes = [vp, C.c_int32]
         L.sph_enable_timing.restype = None
         L.sph_tree_stats.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32]
+        L.sph_kick.argtypes = [vp, C.c_int64, C.c_float] + [vp] * 12
+        L.sph_drift.argtypes = [vp, C.c_int32, vp, vp, C.c_double] + [vp] * 6
+        L.sph_cfl_dt.argtypes = [vp, C.c_int64, vp, vp, C.c_float, C.POINTER(C.c_double)]
         for name in ("sph_ctx_create", "sph_footprint", "sph_tree_create", "sph_tree_bytes", "sph_build_cells",
                      "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
-                     "sph_tree_stats"):
+                     "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -341,3 +344,30 @@ def solve_with_rebuild(tree: Tree, batch: Batch, prm: sph_params, dout: DensityO
             continue
         return st, nu, total_it
     return SPH_E_REBUILD, -1, total_it
+
+
+def kick(ctx: Context, dt: float, v, u, a, dudt, v_out=None, u_out=None):
+    """v_out = v + dt a, u_out = u + dt du/dt (v, a, v_out: triples of device
+    tensors); in place when the outputs are omitted."""
+    v_out = v if v_out is None else v_out
+    u_out = u if u_out is None else u_out
+    n = int(u.numel())
+    ctx.check(lib().sph_kick(ctx.h, n, float(dt), *(_ptr(t) for t in v), _ptr(u), *(_ptr(t) for t in a),
+                             _ptr(dudt), *(_ptr(t) for t in v_out), _ptr(u_out)), "sph_kick")
+
+
+def drift(ctx: Context, batch: Batch, dt: float, v=None):
+    """x += dt v for every set of the batch, wrapped into its box (v defaults
+    to the batch velocities)."""
+    vx, vy, vz = (batch.vx, batch.vy, batch.vz) if v is None else v
+    off = np.ascontiguousarray(batch.offsets, dtype=np.int64)
+    box = np.ascontiguousarray(batch.box, dtype=np.float64)
+    ctx.check(lib().sph_drift(ctx.h, batch.nsets, off.ctypes.data_as(C.c_void_p), box.ctypes.data_as(C.c_void_p),
+                              float(dt), _ptr(batch.x), _ptr(batch.y), _ptr(batch.z), _ptr(vx), _ptr(vy), _ptr(vz)),
+              "sph_drift")
+
+
+def cfl_dt(ctx: Context, h, vsig, c_cfl: float = 0.3) -> float:
+    dt = C.c_double(0.0)
+    ctx.check(lib().sph_cfl_dt(ctx.h, int(h.numel()), _ptr(h), _ptr(vsig), float(c_cfl), C.byref(dt)), "sph_cfl_dt")
+    return float(dt.value)

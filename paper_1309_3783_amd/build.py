@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsphcell.so")
-SOURCES = ["sph_prims.hip", "sph_build.hip", "sph_interact.hip", "sph_api.hip"]
+SOURCES = ["sph_prims.hip", "sph_build.hip", "sph_interact.hip", "sph_integrate.hip", "sph_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

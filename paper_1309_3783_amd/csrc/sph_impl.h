@@ -23,7 +23,10 @@ struct sph_ctx {
     std::vector<const char*> ev_name;
     size_t nev = 0;
     std::vector<std::pair<const char*, double>> last_ms;
-    int32_t* d_counter = nullptr;   // persistent-kernel work counters
+    // device words (1024): [0, 256) density work counters, [256, 512) force
+    // work counters, [512, 768) chunk-list counts, [CTR_CFL] Courant minimum
+    int32_t* d_counter = nullptr;
+    static constexpr int CTR_CFL = 768;
     // pinned host memory that device counts are read back into: one
     // asynchronous copy per read, then one stream synchronisation
     static constexpr size_t PIN_BYTES = 65536;

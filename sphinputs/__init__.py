@@ -17,6 +17,13 @@ Recipes (all periodic unit box, equal masses m = FP32(1/N), u = 1.5):
 * ``lattice``   -- simple-cubic lattice of n^3 points, spacing 1/n, each
                    coordinate jittered by U(-j, +j) spacings (j = 0: perfect).
                    Stands in for the Sedov-blast lattice of Section III-B.
+* ``sod``       -- the shock tube of the paper's validation runs (Section
+                   III-A): a dense half x < 1/2 (density 1, pressure 1) and a
+                   light half (density ~1/4, pressure 0.1795) of equal-mass
+                   particles on two simple-cubic lattices, at rest; u from the
+                   ideal-gas law (gamma = 5/3).  Its default sizes (780,448 +
+                   197,173 particles) stand in for the paper's 800,000 +
+                   200,000.
 * ``plummer_mixture`` -- 64 Plummer spheres (scale radius a = 10^U(-3,-1),
                    truncated at min(20a, 0.45)) holding 80% of the particles
                    plus a 20% uniform background.  Stands in for the
@@ -135,6 +142,41 @@ def lattice(n_side: int, jitter: float, seed: int, velocity: bool = False) -> Pa
     pos = _snap_unique(pos, redraw, rng)
     return _finish(pos, n, rng, np.full(n, h_for_density(float(n))), velocity,
                    {"recipe": "lattice", "n_side": n_side, "jitter": jitter, "seed": seed})
+
+
+def sod(n_left: int = 116, n_right: int = 73, nx_right: int = 37, p_left: float = 1.0, p_right: float = 0.1795,
+        gamma: float = 5.0 / 3.0) -> ParticleSet:
+    """Shock tube in the periodic unit cube: x < 1/2 holds an n_left/2 x
+    n_left x n_left lattice (spacing 1/n_left, density 1), x >= 1/2 an
+    nx_right x n_right x n_right lattice (spacings 1/(2 nx_right) along x,
+    1/n_right across).  Equal masses; both halves at rest with the given
+    pressures, u = P / ((gamma - 1) rho) from the lattice densities.  The
+    tube has two interfaces (x = 0 and x = 1/2, periodic): the waves of the
+    one at 1/2 stay inside [1/4, 3/4] until t ~ 0.15."""
+    if n_left % 2:
+        raise ValueError("n_left must be even")
+    gl = (np.arange(n_left) + 0.5) / n_left
+    X, Y, Z = np.meshgrid(gl[: n_left // 2], gl, gl, indexing="ij")
+    left = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    gx = 0.5 + (np.arange(nx_right) + 0.5) * (0.5 / nx_right)
+    gr = (np.arange(n_right) + 0.5) / n_right
+    X, Y, Z = np.meshgrid(gx, gr, gr, indexing="ij")
+    right = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    pos = np.concatenate([left, right])
+    rng = _rng(0)
+    pos = _snap_unique(pos, lambda idx, r: pos[idx], rng)
+    nl, nr = left.shape[0], right.shape[0]
+    m = float(np.float32(0.5 / nl))                  # density 1 on the left
+    rho_l, rho_r = m * nl / 0.5, m * nr / 0.5
+    u = np.concatenate([np.full(nl, p_left / ((gamma - 1.0) * rho_l)),
+                        np.full(nr, p_right / ((gamma - 1.0) * rho_r))])
+    h0 = np.concatenate([np.full(nl, h_for_density(nl / 0.5)), np.full(nr, h_for_density(nr / 0.5))])
+    n = nl + nr
+    z = np.zeros(n)
+    return ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.full(n, m), _f32(u),
+                       z.copy(), z.copy(), z.copy(), _f32(h0), 1.0,
+                       {"recipe": "sod", "n_left": nl, "n_right": nr, "rho_left": rho_l, "rho_right": rho_r,
+                        "p_left": p_left, "p_right": p_right, "gamma": gamma})
 
 
 def _plummer_radius(rng, a, rmax, size):
