@@ -11,9 +11,9 @@ U(+-0.1) spacings (seed 2), h solved by Newton to 48 +- 0.5.
 The same line carries the batched comparison (256 uneven sets in one build
 and one HIP graph, autotuned, vs the plain one-set-at-a-time loop) and the
 served Poisson stream (p50/p99 latency).  --config multires times the 8M
-clumpy set instead; --config sod times leapfrog time steps of the paper's
-shock tube (each step: two kicks, a drift, build, sort, h solve, force, the
-Courant step).  Prints ONE JSON line.
+clumpy set instead; --config sod / sedov time leapfrog time steps of the
+paper's shock tube / blast (each step: three kicks, a drift, build, sort, h
+solve, force, the Courant step).  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -321,15 +321,16 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
-def bench_sod(args):
-    """Time steps of the shock tube (780,448 + 197,173 particles standing in
-    for the paper's 800,000 + 200,000): W untimed steps, then K timed ones,
-    each at the Courant step of the current forces."""
+def bench_steps(args):
+    """Time steps of the paper's validation set-ups: the shock tube (780,448 +
+    197,173 particles standing in for 800,000 + 200,000) or the blast on the
+    101^3 lattice.  W untimed steps, then K timed ones, each at the Courant
+    step of the current forces."""
     import torch
     import paper_1309_3783_amd as sph
     from paper_1309_3783_amd import integrate
     import sphinputs
-    ps = sphinputs.sod()
+    ps = sphinputs.sod() if args.config == "sod" else sphinputs.sedov(101)
     ctx = sph.Context(0)
     batch = sph.batch_from_sets([ps])
     lf = integrate.Leapfrog(ctx, batch)
@@ -346,15 +347,18 @@ def bench_sod(args):
     el = time.perf_counter() - t
     e1 = lf.energy()
     ms = el * 1e3 / args.steps
-    log(f"[bench] sod: {args.steps} steps in {el:.3f} s ({ms:.2f} ms/step), t {t0:.4f} -> {lf.t:.4f}, "
+    log(f"[bench] {args.config}: {args.steps} steps in {el:.3f} s ({ms:.2f} ms/step), t {t0:.4g} -> {lf.t:.4g}, "
         f"dE/E {(e1 - e0) / e0:.2e}")
+    if args.config == "sod":
+        cfg = {"workload": "sod_shock_tube_1M", "n": ps.n, "n_left": ps.meta["n_left"],
+               "n_right": ps.meta["n_right"], "rho": [1.0, ps.meta["rho_right"]], "P": [1.0, 0.1795]}
+    else:
+        cfg = {"workload": "sedov_blast_101^3", "n": ps.n, "E": 100.0, "hot_particles": 33, "P0": 1e-5}
+    cfg.update({"step": "kick-drift-kick, Courant 0.3", "h": "Newton to N_w = 48 +- 0.5"})
     return {"metric": "pair interactions/sec (density+force) within leapfrog time steps", "value": 2 * pairs / el,
             "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-            "data": "synthetic",
-            "config": {"workload": "sod_shock_tube_1M", "n": ps.n, "n_left": ps.meta["n_left"],
-                       "n_right": ps.meta["n_right"], "rho": [1.0, ps.meta["rho_right"]], "P": [1.0, 0.1795],
-                       "step": "kick-drift-kick, Courant 0.3", "h": "Newton to N_w = 48 +- 0.5"},
+            "data": "synthetic", "config": cfg,
             "sim_time": [t0, lf.t], "energy_drift": (e1 - e0) / e0, "cpu_baseline": None}
 
 
@@ -363,7 +367,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="plain", choices=["plain", "multires", "sod"])
+    ap.add_argument("--config", default="plain", choices=["plain", "multires", "sod", "sedov"])
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only (no batched/served)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -377,7 +381,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    out = bench_sod(args) if args.config == "sod" else run(args)
+    out = bench_steps(args) if args.config in ("sod", "sedov") else run(args)
     print(json.dumps(out))
 
 

@@ -24,6 +24,10 @@ Recipes (all periodic unit box, equal masses m = FP32(1/N), u = 1.5):
                    ideal-gas law (gamma = 5/3).  Its default sizes (780,448 +
                    197,173 particles) stand in for the paper's 800,000 +
                    200,000.
+* ``sedov``     -- the blast of the paper's validation runs (Section III-A):
+                   a simple-cubic lattice at rest with density 1 and pressure
+                   1e-5, the energy E = 100 given to the 33 particles nearest
+                   the centre (u = E / 33 / m each).
 * ``plummer_mixture`` -- 64 Plummer spheres (scale radius a = 10^U(-3,-1),
                    truncated at min(20a, 0.45)) holding 80% of the particles
                    plus a 20% uniform background.  Stands in for the
@@ -177,6 +181,32 @@ def sod(n_left: int = 116, n_right: int = 73, nx_right: int = 37, p_left: float 
                        z.copy(), z.copy(), z.copy(), _f32(h0), 1.0,
                        {"recipe": "sod", "n_left": nl, "n_right": nr, "rho_left": rho_l, "rho_right": rho_r,
                         "p_left": p_left, "p_right": p_right, "gamma": gamma})
+
+
+def sedov(n_side: int = 101, e_total: float = 100.0, n_hot: int = 33, p0: float = 1e-5,
+          gamma: float = 5.0 / 3.0) -> ParticleSet:
+    """n_side^3 lattice (spacing 1/n_side, density 1) in the periodic unit
+    cube, at rest with pressure p0; the n_hot particles nearest the centre
+    (ties of distance broken by index) share e_total equally as internal
+    energy.  With an odd n_side a lattice point sits at the centre and the
+    33 nearest are the centre, its 6 face, 12 edge and 8 corner neighbours
+    and the 6 points two spacings out along the axes."""
+    d = 1.0 / n_side
+    g = (np.arange(n_side) + 0.5) * d
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    pos = _snap_unique(pos, lambda idx, r: pos[idx], _rng(0))
+    n = pos.shape[0]
+    m = float(np.float32(1.0 / n))
+    r2 = np.sum((pos - 0.5) ** 2, axis=1)
+    hot = np.argsort(r2, kind="stable")[:n_hot]
+    u = np.full(n, p0 / ((gamma - 1.0) * 1.0))
+    u[hot] = e_total / n_hot / m
+    z = np.zeros(n)
+    return ParticleSet(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.full(n, m), _f32(u),
+                       z.copy(), z.copy(), z.copy(), _f32(np.full(n, h_for_density(float(n)))), 1.0,
+                       {"recipe": "sedov", "n_side": n_side, "e_total": e_total, "n_hot": n_hot, "p0": p0,
+                        "gamma": gamma, "hot": hot})
 
 
 def _plummer_radius(rng, a, rmax, size):
