@@ -127,7 +127,8 @@ const char* sph_status_str(sph_status st);
 void sph_params_default(sph_params* p);
 
 /* Create a context bound to device `device` and HIP stream `stream` (a
- * hipStream_t, NULL = the default stream).  *out receives the context. */
+ * hipStream_t, NULL = the default stream).  *out receives the context.  On
+ * failure sph_last_error(NULL) says why (per thread). */
 sph_status sph_ctx_create(sph_ctx** out, int device, void* stream);
 void sph_ctx_destroy(sph_ctx* ctx);
 const char* sph_last_error(const sph_ctx* ctx);

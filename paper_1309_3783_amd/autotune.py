@@ -24,7 +24,7 @@ from . import pipeline as P
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuned.json")
 
-GRID = {"n_split": [200, 400, 800], "blocks_per_cu": [4, 8, 16], "max_replicas": [4, 16], "h_slack": [0.1, 0.2]}
+GRID = {"n_split": [200, 400, 800], "blocks_per_cu": [4, 8, 16], "max_replicas": [4, 16], "h_slack": [0.2, 0.3]}
 
 
 def signature(batch: B.Batch, label: str = "") -> str:

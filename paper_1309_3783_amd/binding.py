@@ -142,7 +142,7 @@ class Context:
         h = C.c_void_p()
         st = lib().sph_ctx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
         if st:
-            raise SphError(st, "sph_ctx_create")
+            raise SphError(st, "sph_ctx_create: " + lib().sph_last_error(None).decode(errors="replace"))
         self.h = h
 
     def check(self, st, what):

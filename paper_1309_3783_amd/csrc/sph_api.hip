@@ -12,6 +12,10 @@ static sph_status fail(sph_ctx* ctx, const Err& e) {
     return e.st;
 }
 
+// why the last sph_ctx_create on this thread failed (read through
+// sph_last_error(NULL))
+static thread_local std::string g_create_error;
+
 extern "C" {
 
 const char* sph_version(void) { return "sphcell 0.1 (gfx950)"; }
@@ -50,9 +54,20 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
     if (!out) return SPH_E_ARG;
     *out = nullptr;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SPH_E_HIP;
-    if (device < 0 || device >= ndev) return SPH_E_ARG;
-    if (hipSetDevice(device) != hipSuccess) return SPH_E_HIP;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        g_create_error = std::string("hipGetDeviceCount: ") + (e != hipSuccess ? hipGetErrorString(e) : "no device");
+        return SPH_E_HIP;
+    }
+    if (device < 0 || device >= ndev) {
+        g_create_error = "device index out of range";
+        return SPH_E_ARG;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return SPH_E_HIP;
+    }
     sph_ctx* c = new sph_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -81,7 +96,7 @@ void sph_ctx_destroy(sph_ctx* ctx) {
     delete ctx;
 }
 
-const char* sph_last_error(const sph_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+const char* sph_last_error(const sph_ctx* ctx) { return ctx ? ctx->last_error.c_str() : g_create_error.c_str(); }
 
 sph_status sph_footprint(int64_t n, const sph_params* p, size_t* bytes) {
     if (!bytes || n < 0) return SPH_E_ARG;
