@@ -57,10 +57,17 @@ def make_workload(name):
     raise SystemExit(f"unknown config {name}")
 
 
+# the translation unit of k_density / k_force: its source and every header it
+# includes (the counters in profiles/traffic.json hold for these bytes only)
+KERNEL_SOURCES = ["paper_1309_3783_amd/csrc/sph_interact.hip", "paper_1309_3783_amd/csrc/sph_impl.h",
+                  "paper_1309_3783_amd/csrc/sph_internal.h", "paper_1309_3783_amd/csrc/sph_prims.h",
+                  "include/sphcell.h", "paper_1309_3783_amd/build.py"]
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1309_3783_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1309_3783_amd", "csrc", f), "rb") as fh:
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

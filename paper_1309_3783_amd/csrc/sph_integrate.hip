@@ -10,7 +10,7 @@
 
 #include "sph_impl.h"
 
-namespace {
+namespace sph {
 
 constexpr int BS = 256;
 
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(BS) void k_kick(int64_t n, float dt, const float* v
     ou[i] = fmaf(dt, d, u[i]);
 }
 
-__device__ __forceinline__ double wrap(double x, double box) {
+__device__ __forceinline__ double wrap_box(double x, double box) {
     x -= box * floor(x / box);
     return x >= box ? x - box : x;   // a value just below zero rounds up to box
 }
@@ -40,12 +40,12 @@ __global__ __launch_bounds__(BS) void k_drift(int64_t p0, int64_t p1, double box
                                               const float* __restrict__ vz) {
     const int64_t i = p0 + (int64_t)blockIdx.x * BS + threadIdx.x;
     if (i >= p1) return;
-    x[i] = wrap(fma(dt, (double)vx[i], x[i]), box);
-    y[i] = wrap(fma(dt, (double)vy[i], y[i]), box);
-    z[i] = wrap(fma(dt, (double)vz[i], z[i]), box);
+    x[i] = wrap_box(fma(dt, (double)vx[i], x[i]), box);
+    y[i] = wrap_box(fma(dt, (double)vy[i], y[i]), box);
+    z[i] = wrap_box(fma(dt, (double)vz[i], z[i]), box);
 }
 
-__global__ void k_fill_i32(int32_t* p, int32_t v) { *p = v; }
+__global__ void k_cfl_init(int32_t* p, int32_t v) { *p = v; }
 
 // min over particles of c h_i / vsig_i into *slot (a positive float's bits
 // order like the float, so the minimum is an integer atomicMin); a particle
@@ -66,6 +66,12 @@ __global__ __launch_bounds__(BS) void k_cfl(int64_t n, const float* __restrict__
         atomicMin(slot, __float_as_int(m));
     }
 }
+
+}  // namespace sph
+
+namespace {
+
+using sph::BS;
 
 unsigned nblk(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
 
@@ -92,7 +98,7 @@ sph_status sph_kick(sph_ctx* ctx, int64_t n, float dt, const float* vx, const fl
     if (n == 0) return SPH_OK;
     if (!vx || !vy || !vz || !u || !ax || !ay || !az || !dudt || !vx_out || !vy_out || !vz_out || !u_out)
         return fail(ctx, SPH_E_ARG, "sph_kick: null pointer");
-    hipLaunchKernelGGL(k_kick, dim3(nblk(n)), dim3(BS), 0, ctx->stream, n, dt, vx, vy, vz, u, ax, ay, az, dudt,
+    hipLaunchKernelGGL(sph::k_kick, dim3(nblk(n)), dim3(BS), 0, ctx->stream, n, dt, vx, vy, vz, u, ax, ay, az, dudt,
                        vx_out, vy_out, vz_out, u_out);
     return check_launch(ctx, "sph_kick");
 }
@@ -111,7 +117,7 @@ sph_status sph_drift(sph_ctx* ctx, int32_t nsets, const int64_t* offsets, const 
     for (int s = 0; s < nsets; ++s) {
         const int64_t a = offsets[s], b = offsets[s + 1];
         if (a == b) continue;
-        hipLaunchKernelGGL(k_drift, dim3(nblk(b - a)), dim3(BS), 0, ctx->stream, a, b, box[s], dt, x, y, z, vx, vy,
+        hipLaunchKernelGGL(sph::k_drift, dim3(nblk(b - a)), dim3(BS), 0, ctx->stream, a, b, box[s], dt, x, y, z, vx, vy,
                            vz);
     }
     return check_launch(ctx, "sph_drift");
@@ -124,9 +130,11 @@ sph_status sph_cfl_dt(sph_ctx* ctx, int64_t n, const float* h, const float* vsig
     if (n == 0) return SPH_OK;
     if (!h || !vsig) return fail(ctx, SPH_E_ARG, "sph_cfl_dt: null pointer");
     int32_t* slot = ctx->d_counter + sph_ctx::CTR_CFL;
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, ctx->stream, slot, (int32_t)0x7f800000);   // +inf
-    const unsigned g = std::min<unsigned>(nblk(n), 2048u);
-    hipLaunchKernelGGL(k_cfl, dim3(g), dim3(BS), 0, ctx->stream, n, h, vsig, c_cfl, slot);
+    hipLaunchKernelGGL(sph::k_cfl_init, dim3(1), dim3(1), 0, ctx->stream, slot, (int32_t)0x7f800000);   // +inf
+    // a few hundred blocks: one same-address atomic per block, and those
+    // serialise (~25 ns each)
+    const unsigned g = std::min<unsigned>(nblk(n), 256u);
+    hipLaunchKernelGGL(sph::k_cfl, dim3(g), dim3(BS), 0, ctx->stream, n, h, vsig, c_cfl, slot);
     sph_status st = check_launch(ctx, "sph_cfl_dt");
     if (st != SPH_OK) return st;
     hipError_t e = hipMemcpyAsync(ctx->h_pin, slot, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream);
