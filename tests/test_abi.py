@@ -53,3 +53,24 @@ def test_null_arguments_are_rejected():
     assert L.sph_force(None, None, None) == binding.SPH_E_ARG
     assert L.sph_run_graph(None, None, 1, None, None, None) == binding.SPH_E_ARG
     L.sph_ctx_destroy(None)
+
+
+def test_integration_calls_reject_bad_arguments():
+    import ctypes as C
+    L = sph.lib()
+    assert L.sph_kick(None, 0, 0.1, *([None] * 12)) == binding.SPH_E_ARG
+    assert L.sph_drift(None, 1, None, None, 0.1, *([None] * 6)) == binding.SPH_E_ARG
+    dt = C.c_double(0.0)
+    assert L.sph_cfl_dt(None, 0, None, None, 0.3, C.byref(dt)) == binding.SPH_E_ARG
+
+
+def test_context_creation_failure_is_explained():
+    import ctypes as C
+    L = sph.lib()
+    h = C.c_void_p()
+    st = L.sph_ctx_create(C.byref(h), 1 << 20, None)
+    msg = L.sph_last_error(None).decode()
+    # no GPU here: the device count fails; with one: the index is out of range
+    assert (st == binding.SPH_E_HIP and msg.startswith("hipGetDeviceCount")) or \
+        (st == binding.SPH_E_ARG and "out of range" in msg)
+    assert not h.value
