@@ -608,9 +608,14 @@ __global__ void k_seg_need(const uint64_t* __restrict__ ent, int64_t ne, const u
     need[(int64_t)src * NAXES + ax] = 1u;
 }
 
+// Long lists up to this length are sorted in LDS by one block each; longer
+// ones by the global radix sort.
+constexpr int SEG_LARGE_MAX = 16384;
+
 // Per (cell, axis) list: its length where some pair entry needs it (0
-// elsewhere), and its sort class: 65..SEG_LDS_MAX entries (one block sorts
-// it in LDS) or longer (one global radix sort over all such lists).
+// elsewhere), and its sort class: 65..SEG_LDS_MAX entries (a wave or a block
+// sorts it in LDS) or longer (the long class: in LDS up to SEG_LARGE_MAX,
+// else one global radix sort over all such lists).
 __global__ void k_seg_lens(const uint32_t* __restrict__ need, int64_t nca, const Cell* __restrict__ cells,
                            uint32_t* __restrict__ lens, uint32_t* __restrict__ mid, uint32_t* __restrict__ big) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -645,7 +650,7 @@ __global__ void k_seg_post(const uint32_t* __restrict__ need, int64_t nca, const
         mids[mid_idx[q]] = (uint32_t)q;
     } else if (n > (uint32_t)SEG_LDS_MAX) {
         big[big_idx[q]] = (uint32_t)q;
-        blen[big_idx[q]] = n;
+        blen[big_idx[q]] = n > (uint32_t)SEG_LARGE_MAX ? n : 0u;   // entries of the radix sort
     }
 }
 
@@ -934,6 +939,42 @@ __global__ __launch_bounds__(256) void k_seg_sort_lds(const uint32_t* __restrict
     }
 }
 
+// Lists of SEG_LDS_MAX+1 .. SEG_LARGE_MAX entries (the long class, listed in
+// big): one block of LARGE_BS threads per list, the merge sort in 128 KB of
+// LDS.  Longer lists are left to the global radix sort.
+constexpr int LARGE_BS = 1024;
+static_assert(SEG_LARGE_MAX <= LARGE_BS * MS_RUN, "the block's threads hold the whole list in runs");
+__global__ __launch_bounds__(LARGE_BS) void k_seg_sort_large(const uint32_t* __restrict__ big,
+                                                             const uint32_t* __restrict__ off, const SetInfo* sets,
+                                                             const Cell* __restrict__ cells,
+                                                             const float4* __restrict__ pos,
+                                                             const float* __restrict__ ph,
+                                                             float4* __restrict__ sproj, uint32_t* __restrict__ sidx) {
+    __shared__ uint64_t s[SEG_LARGE_MAX];
+    const uint32_t ca = big[blockIdx.x];
+    const Cell C = cells[ca / NAXES];
+    const int n = C.count;
+    if (n <= SEG_LDS_MAX || n > SEG_LARGE_MAX) return;
+    const int ax = (int)(ca % NAXES);
+    int P = 1;
+    while (P < n) P <<= 1;
+    const float lim = small_h_limit(sets, C);
+    for (int e = threadIdx.x; e < P; e += LARGE_BS) {
+        uint64_t k = ~0ull;
+        if (e < n) k = seg_key(project(pos[C.first + e], ax), ph[C.first + e] > lim ? 1 : 0, (uint32_t)e);
+        s[e] = k;
+    }
+    __syncthreads();
+    merge_sort_lds<LARGE_BS>(s, P, threadIdx.x);
+    const uint32_t o = off[ca];
+    for (int e = threadIdx.x; e < n; e += LARGE_BS) {
+        const uint64_t k = s[e];
+        const uint32_t j = (uint32_t)C.first + (uint32_t)(k & 0xFFFFFFFFu);
+        sproj[o + e] = pos[j];
+        sidx[o + e] = j;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_big_keys(const uint32_t* __restrict__ big,
                                                   const uint32_t* __restrict__ boff, const SetInfo* sets,
                                                   const Cell* __restrict__ cells, const float4* __restrict__ pos,
@@ -942,6 +983,7 @@ __global__ __launch_bounds__(256) void k_big_keys(const uint32_t* __restrict__ b
     uint32_t r = blockIdx.x;
     uint32_t ca = big[r];
     const Cell C = cells[ca / NAXES];
+    if (C.count <= SEG_LARGE_MAX) return;   // sorted in LDS (k_seg_sort_large)
     int ax = (int)(ca % NAXES);
     const float lim = small_h_limit(sets, C);
     uint32_t o = boff[r];
@@ -1422,14 +1464,23 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
         HIPTRY(hipGetLastError());
     }
     if (nbig > 0) {
-        // lists longer than SEG_LDS_MAX: one radix sort over all of them
+        // lists longer than SEG_LDS_MAX: up to SEG_LARGE_MAX entries one
+        // block each in LDS, the longer ones one radix sort over all of them
         // (a second read-back, for their total length)
+        hipLaunchKernelGGL(k_seg_sort_large, dim3(nbig), dim3(LARGE_BS), 0, st, big, t->segoff, t->d_sets, t->cells,
+                           t->pos, t->ph, t->segpos, t->segidx);
+        HIPTRY(hipGetLastError());
         const void* rb;
         ERRTRY(t->scratch(std::max<int64_t>(nca, nbig) + 1));
         uint32_t* boff = t->sc_b;
         HIPTRY(exclusive_scan(blen, boff, nbig, t->sc_tmp, total, st));
         ERRTRY(read_back(ctx, total, sizeof(uint32_t), &rb));
         const uint32_t nbe = ((const uint32_t*)rb)[0];
+        if (nbe == 0) {
+            t->sorted = true;
+            ev_mark(ctx, "sort");
+            return Err{};
+        }
         uint64_t *bk, *bk2;
         uint32_t *bv, *bv2;
         ERRTRY(t->alloc(t->b_bigk, sizeof(uint64_t) * nbe * 2, (void**)&bk));

@@ -164,15 +164,25 @@ def test_deep_refinement(sph, ctx):
     assert st["levels"] >= 4, st
 
 
-def test_large_cells_use_global_sort(sph, ctx):
+def test_large_cells_use_long_list_sorts(sph, ctx):
     # two top cells per side, no refinement: (cell, axis) lists of ~5000
-    # particles exceed the LDS sort and go through the radix sort
-    ps = sphinputs.uniform(40000, 8, velocity=True)
-    h0 = I.f32(np.full(ps.n, sphinputs.h_for_density(float(ps.n))))
-    ps = I.redraw_ties_uniform(ps, h0, seed=108)
-    g, rd, rf, tree = full_check(sph, ctx, ps, h0, top_grid=2, n_split=1 << 30)
+    # particles (set 0: one block each, sorted in LDS) and of ~20000 (set 1:
+    # past the LDS sorts, through the global radix sort), in one batch
+    sets, hs = [], []
+    for n, seed in ((40000, 8), (160000, 9)):
+        ps = sphinputs.uniform(n, seed, velocity=True)
+        h0 = I.f32(np.full(ps.n, sphinputs.h_for_density(float(ps.n))))
+        ps = I.redraw_ties_uniform(ps, h0, seed=100 + seed)
+        sets.append(ps)
+        hs.append(h0)
+    res, tree = run_fixed(sph, ctx, sets, hs, top_grid=2, n_split=1 << 30)
     st = tree.stats()
-    assert st["top_grid"] == 2 and st["max_leaf"] > 4096, st
+    assert st["top_grid"] == 2 and st["max_leaf"] > 16384, st
+    for ps, h, (g, gf) in zip(sets, hs, res):
+        assert ps.n / 8 > 4096
+        rd, rf = I.oracle_reference(ps, h)
+        check_density(ps, h, g, rd)
+        check_force(ps, gf, rf)
 
 
 def test_two_cells_per_side_periodic_images(sph, ctx):
