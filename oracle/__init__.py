@@ -10,9 +10,11 @@ function follows.
 Pinned by ``tests/test_oracle_pins.py`` (kernel normalisation and shape,
 finite-difference derivatives, Lagrangian force and adiabatic du/dt,
 conservation, lattice symmetry and counts, the paper's printed candidate
-fractions, brute force vs grid vs an independent k-d tree).  The viscosity
-magnitude is only partially pinned (sign, dissipation, conservation and
-linearity in alpha): there is no closed form for it.
+fractions, brute force vs grid vs an independent k-d tree, and the viscosity,
+sound speed and signal velocity of an isolated approaching / receding pair,
+also across a periodic face, written out from their definitions with the
+kernel derivatives taken by finite differences of scipy's B-spline and the
+sound speed from dP/drho along the adiabat).
 """
 from __future__ import annotations
 

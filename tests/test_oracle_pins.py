@@ -11,8 +11,11 @@ operand anywhere in it fails at least one of them:
 * force           -- the pressure force is minus the gradient of the
                      thermal energy with h re-solved (grad-h Lagrangian);
 * du/dt           -- the adiabatic rate (P/rho^2) drho/dt along the flow;
-* viscosity       -- conservation, non-negative dissipation, linear in alpha
-                     (its magnitude has no closed form: partially pinned);
+* viscosity       -- conservation, non-negative dissipation, linear in alpha,
+                     and its magnitude, the sound speed and the signal
+                     velocity on an isolated pair (plus a spectator), written
+                     out with kernel derivatives by finite differences of the
+                     B-spline and c^2 = dP/drho along the adiabat;
 * neighbour sets  -- an independent scipy k-d tree, an independent
                      splitmix64, brute force vs the grid search;
 * lattice         -- 56 neighbours inside h at N_w = 48 and zero force by
@@ -396,3 +399,130 @@ def test_face_pair_in_range_fraction(paper):
     only = oracle.density(a[:, 0], a[:, 1], a[:, 2], hh[:n], m[:n])["nngb"].sum()
     frac = (both - only) / float(n * n)
     assert abs(frac - paper["face_in_range"]) < 0.004
+
+
+# --------------------------------------------------------------------------
+# viscosity, sound speed and signal velocity: two particles in closed form
+# --------------------------------------------------------------------------
+_BS = interpolate.BSpline.basis_element([-2, -1, 0, 1, 2], extrapolate=False)
+_BS0 = float(_BS(0.0))
+
+
+def _W_bspline(r, h):
+    """Cubic-spline kernel from scipy's de Boor basis (support radius h, unit
+    volume: the normalisation 8/(pi h^3) of f(0) = 1 is the quadrature pin
+    above), independent of the oracle's polynomial pieces."""
+    q = r / h
+    f = float(np.nan_to_num(_BS(2.0 * q))) / _BS0 if q < 1.0 else 0.0
+    return 8.0 / (math.pi * h ** 3) * f
+
+
+def _dWdr(r, h):
+    e = 1e-5 * h
+    return (_W_bspline(r + e, h) - _W_bspline(r - e, h)) / (2 * e)
+
+
+def _sound_speed(rho, u, gamma):
+    """Adiabatic sound speed sqrt(dP/drho at constant entropy) of the ideal
+    gas P = (gamma-1) rho u, by a central difference along the adiabat
+    u(rho') = u (rho'/rho)^(gamma-1)."""
+    def P(r):
+        return (gamma - 1.0) * r * u * (r / rho) ** (gamma - 1.0)
+    e = 1e-5 * rho
+    return math.sqrt((P(rho + e) - P(rho - e)) / (2 * e))
+
+
+def _two_particle_reference(r, h, m, u, v, gamma, alpha, spec, mutate=None):
+    """Density and force of particle 0 of a pair on the x axis (particle 1 at
+    +r), written out from the definitions: density sums over j within h_i
+    (self included), grad-h factor from a finite difference of rho(h),
+    ideal-gas pressure, the signal-velocity viscosity of the chosen reading,
+    and the force/energy sums over j within max(h_i, h_j).  A spectator
+    particle 2 at rest sits a distance s from particle 0 along y: it adds to
+    the densities (so that no particle is alone in its own h, where the
+    grad-h factor is singular) but not to the x force or du/dt of particle 0
+    (its pair with 0 is perpendicular to x and to the velocities).
+    mutate names a plausible mistake to apply (the test shows each one moves
+    the result far outside the tolerance)."""
+    s, m2, u2 = spec
+    d = [[0.0, r, s], [r, 0.0, math.hypot(r, s)]]   # distances of 0 and 1 to 0, 1, 2
+    mm = [m[0], m[1], m2]
+
+    def rho_of(i, hh):
+        return sum(mm[j] * _W_bspline(d[i][j], hh) for j in range(3) if d[i][j] < hh or j == i)
+
+    rho = [rho_of(0, h[0]), rho_of(1, h[1])]
+    drho = [(rho_of(i, h[i] * (1 + 1e-6)) - rho_of(i, h[i] * (1 - 1e-6))) / (2e-6 * h[i]) for i in (0, 1)]
+    fgr = [1.0 / (1.0 + h[i] / (3.0 * rho[i]) * drho[i]) for i in (0, 1)]
+    Pr = [(gamma - 1.0) * rho[i] * u[i] for i in (0, 1)]
+    if mutate == "c_sqrt_gamma_u":
+        c = [math.sqrt(gamma * uu) for uu in (u[0], u[1], u2)]
+    else:
+        c = [_sound_speed(rho[i], u[i], gamma) for i in (0, 1)] + [_sound_speed(1.0, u2, gamma)]
+    A = [fgr[i] * Pr[i] / rho[i] ** 2 for i in (0, 1)]
+    out = {"rho": rho[0], "c": c[0], "A": A[0]}
+    # x_01 = x_0 - x_1 = -r along x; grad_0 W(r, h) = dW/dr * x_01 / r
+    xij = -r
+    vij = v[0] - v[1]
+    w = vij * xij / r
+    Gi = (_dWdr(r, h[0]) if r < h[0] else 0.0) * xij / r
+    Gj = (_dWdr(r, h[1]) if r < h[1] else 0.0) * xij / r
+    Gbar = 0.5 * (Gi + Gj)
+    a_eff = 0.25 * alpha if mutate == "alpha_half" else 0.5 * alpha
+    rhobar = (rho[0] + rho[1]) if mutate == "rho_sum" else 0.5 * (rho[0] + rho[1])
+    beta = 0.0 if mutate == "no_minus_3w" else 3.0
+    Pi = -a_eff * (c[0] + c[1] - beta * w) * w / rhobar if w < 0 else 0.0
+    out["ax"] = -m[1] * (A[0] * Gi + A[1] * Gj + Pi * Gbar)
+    out["dudt"] = m[1] * (A[0] * vij * Gi + 0.5 * Pi * vij * Gbar)
+    # the spectator is at rest and met perpendicular to the flow: w = 0
+    out["vsig"] = max(c[0] + c[1] - beta * min(w, 0.0), c[0] + c[2])
+    return out
+
+
+_PAIR_CASES = {
+    # approaching, both within each other's h
+    "approaching": dict(x0=0.40, r=0.05, h=(0.08, 0.12), v=(0.7, -0.4)),
+    # receding: no viscosity, v_sig is the sum of the sound speeds
+    "receding": dict(x0=0.40, r=0.05, h=(0.08, 0.12), v=(-0.3, 0.5)),
+    # r between the two h: only particle 1 sees particle 0 in its density
+    "one_sided": dict(x0=0.30, r=0.10, h=(0.08, 0.12), v=(0.9, -0.2)),
+    # the same approaching pair across the periodic face x = 0 = 1
+    "periodic": dict(x0=0.98, r=0.05, h=(0.08, 0.12), v=(0.7, -0.4)),
+}
+
+
+@pytest.mark.parametrize("name", list(_PAIR_CASES))
+def test_two_particle_viscosity_closed_form(name):
+    cs = _PAIR_CASES[name]
+    r, h, v = cs["r"], cs["h"], cs["v"]
+    m, u, gamma, alpha = (1.0, 2.0), (1.0, 3.0), 5.0 / 3.0, 2.0
+    spec = (0.5 * h[0], 1.5, 0.2)
+    x = np.array([cs["x0"], math.fmod(cs["x0"] + r, 1.0), cs["x0"]])
+    y = np.array([0.5, 0.5, 0.5 + spec[0]])
+    z = np.array([0.5, 0.5, 0.5])
+    hh = np.array([h[0], h[1], 0.05])
+    mm = np.array([m[0], m[1], spec[1]])
+    uu = np.array([u[0], u[1], spec[2]])
+    d = oracle.density(x, y, z, hh, mm, brute=True)
+    g = oracle.ghost(hh, d["rho"], d["drho_dh"], uu, gamma)
+    vx = np.array([v[0], v[1], 0.0])
+    zero = np.zeros(3)
+    f = oracle.force(x, y, z, hh, mm, vx, zero, zero, uu, d["rho"], d["drho_dh"],
+                     gamma=gamma, alpha=alpha, brute=True)
+    ref = _two_particle_reference(r, h, m, u, v, gamma, alpha, spec)
+    # finite differences of the kernel and of the adiabat carry ~1e-9
+    assert d["rho"][0] == pytest.approx(ref["rho"], rel=1e-9)
+    assert g["c"][0] == pytest.approx(ref["c"], rel=1e-8)
+    assert g["A"][0] == pytest.approx(ref["A"], rel=1e-7)
+    assert f["ax"][0] == pytest.approx(ref["ax"], rel=1e-6)
+    assert f["dudt"][0] == pytest.approx(ref["dudt"], rel=1e-6, abs=1e-12)
+    assert f["vsig"][0] == pytest.approx(ref["vsig"], rel=1e-8)
+    assert f["az"][0] == 0.0
+    # each plausible misreading moves some result far outside those bars
+    # (the receding pair has no viscosity, so only the sound speed shows)
+    mutations = ["c_sqrt_gamma_u"] if name == "receding" else \
+        ["alpha_half", "rho_sum", "no_minus_3w", "c_sqrt_gamma_u"]
+    for mu in mutations:
+        bad = _two_particle_reference(r, h, m, u, v, gamma, alpha, spec, mutate=mu)
+        moved = max(abs(bad[k] / ref[k] - 1.0) for k in ("ax", "dudt", "vsig", "c") if ref[k] != 0.0)
+        assert moved > 1e-3, mu
