@@ -152,7 +152,7 @@ __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
                          const float* __restrict__ m, const float* __restrict__ u,
                          const float* __restrict__ vx, const float* __restrict__ vy,
                          const float* __restrict__ vz, float slack, float4* __restrict__ pos,
-                         float* __restrict__ ph, float* __restrict__ hdec, float* __restrict__ pu,
+                         float4* __restrict__ plo, float* __restrict__ ph, float* __restrict__ hdec, float* __restrict__ pu,
                          float4* __restrict__ pv, uint32_t* __restrict__ perm, uint32_t* __restrict__ iperm,
                          uint64_t* __restrict__ mix) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,13 +162,19 @@ __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
     const SetInfo S = sets[s];
     int64_t R = (int64_t)1 << (S.lgG + S.depth);
     double xs[3] = {x[i], y[i], z[i]};
-    float o[3];
+    float o[3], lo[3];
     for (int d = 0; d < 3; ++d) {
         double w = xs[d] - S.box * floor(xs[d] / S.box);
         int64_t top = fine_coord(xs[d], S.box, R) >> S.depth;
-        o[d] = (float)(w - (double)top * S.L0);
+        // offset from the top cell origin: exact in FP64 (w and top L0 are
+        // within a factor two of each other, or top = 0), then split into
+        // its FP32 rounding and the FP32 rounding of the remainder
+        const double off = w - (double)top * S.L0;
+        o[d] = (float)off;
+        lo[d] = (float)(off - (double)o[d]);
     }
     pos[p] = make_float4(o[0], o[1], o[2], m[i]);
+    plo[p] = make_float4(lo[0], lo[1], lo[2], 0.f);
     float hh = h[i];
     ph[p] = hh;
     hdec[p] = hh * (1.0f + slack);
@@ -616,15 +622,31 @@ constexpr int SEG_LARGE_MAX = 16384;
 // elsewhere), and its sort class: 65..SEG_LDS_MAX entries (a wave or a block
 // sorts it in LDS) or longer (the long class: in LDS up to SEG_LARGE_MAX,
 // else one global radix sort over all such lists).
-__global__ void k_seg_lens(const uint32_t* __restrict__ need, int64_t nca, const Cell* __restrict__ cells,
-                           uint32_t* __restrict__ lens, uint32_t* __restrict__ mid, uint32_t* __restrict__ big) {
+// The total length is also summed in 64 bits (total64, zero on entry; one
+// atomic per block): list positions are 32-bit, so the host refuses a tree
+// whose lists hold 2^32 entries or more.
+__global__ __launch_bounds__(256) void k_seg_lens(const uint32_t* __restrict__ need, int64_t nca,
+                                                  const Cell* __restrict__ cells, uint32_t* __restrict__ lens,
+                                                  uint32_t* __restrict__ mid, uint32_t* __restrict__ big,
+                                                  unsigned long long* __restrict__ total64) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nca) return;
-    const uint32_t n = need[q] ? (uint32_t)cells[q / NAXES].count : 0u;
-    lens[q] = n;
-    if (mid) {   // null when no list can exceed 64 entries
-        mid[q] = (n > 64u && n <= (uint32_t)SEG_LDS_MAX) ? 1u : 0u;
-        big[q] = n > (uint32_t)SEG_LDS_MAX ? 1u : 0u;
+    uint32_t n = 0;
+    if (q < nca) {
+        n = need[q] ? (uint32_t)cells[q / NAXES].count : 0u;
+        lens[q] = n;
+        if (mid) {   // null when no list can exceed 64 entries
+            mid[q] = (n > 64u && n <= (uint32_t)SEG_LDS_MAX) ? 1u : 0u;
+            big[q] = n > (uint32_t)SEG_LDS_MAX ? 1u : 0u;
+        }
+    }
+    unsigned long long v = n;
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    __shared__ unsigned long long s_v[4];
+    if ((threadIdx.x & 63) == 0) s_v[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        v = s_v[0] + s_v[1] + s_v[2] + s_v[3];
+        if (v) atomicAdd(total64, v);
     }
 }
 
@@ -1164,6 +1186,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(t->alloc(t->b_perm, sizeof(uint32_t) * nn, (void**)&t->perm));
     ERRTRY(t->alloc(t->b_iperm, sizeof(uint32_t) * nn, (void**)&t->iperm));
     ERRTRY(t->alloc(t->b_pos, sizeof(float4) * nn, (void**)&t->pos));
+    ERRTRY(t->alloc(t->b_plo, sizeof(float4) * nn, (void**)&t->plo));
     ERRTRY(t->alloc(t->b_pv, sizeof(float4) * nn, (void**)&t->pv));
     ERRTRY(t->alloc(t->b_ph, sizeof(float) * nn, (void**)&t->ph));
     ERRTRY(t->alloc(t->b_hdec, sizeof(float) * nn, (void**)&t->hdec));
@@ -1186,7 +1209,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         }
         hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, bmax, t->key,
                            t->val, in->x, in->y, in->z, in->h, in->m, in->u, in->vx, in->vy, in->vz,
-                           prm->h_slack, t->pos, t->ph, t->hdec, t->pu, t->pv, t->perm, t->iperm, t->mix);
+                           prm->h_slack, t->pos, t->plo, t->ph, t->hdec, t->pu, t->pv, t->perm, t->iperm, t->mix);
         HIPTRY(hipGetLastError());
     }
 
@@ -1407,11 +1430,15 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     // placed without reading anything back (the exact entry count is kept
     // on the device for the statistics).  Otherwise one read-back of the
     // entry count and of the two class counts.
-    const bool flat = t->nlevels == 1 && t->max_leaf <= 64;
+    // (and whose 13 n entries cannot reach 2^32: past that the total is read
+    // back to be checked)
+    const bool flat = t->nlevels == 1 && t->max_leaf <= 64 && (int64_t)NAXES * t->n < ((int64_t)1 << 32);
     uint32_t* need = t->sc_a;
     uint32_t* mid_idx = t->sc_c;
     uint32_t* big_idx = t->sc_d;
     HIPTRY(fill_u32(need, nca, 0, st));
+    unsigned long long* total64 = (unsigned long long*)(t->d_counts + 8);   // 8-byte aligned
+    HIPTRY(fill_u32(t->d_counts + 8, 2, 0u, st));
     const int64_t ne = t->ncsr;
     if (ne > 0) {
         hipLaunchKernelGGL(k_seg_need, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, t->ncsr_dev, need);
@@ -1419,7 +1446,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     }
     if (nca > 0) {
         hipLaunchKernelGGL(k_seg_lens, dim3(nblk(nca, 256)), dim3(256), 0, st, need, nca, t->cells, t->segoff,
-                           flat ? nullptr : mid_idx, flat ? nullptr : big_idx);
+                           flat ? nullptr : mid_idx, flat ? nullptr : big_idx, total64);
         HIPTRY(hipGetLastError());
     }
     HIPTRY(exclusive_scan(t->segoff, t->segoff, nca, t->sc_tmp, total, st));
@@ -1433,11 +1460,17 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     } else {
         HIPTRY(exclusive_scan(mid_idx, mid_idx, nca, t->sc_tmp, total + 1, st));
         HIPTRY(exclusive_scan(big_idx, big_idx, nca, t->sc_tmp, total + 2, st));
+        HIPTRY(hipMemcpyAsync(total + 4, total64, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
         const void* rb;
-        ERRTRY(read_back(ctx, total, 3 * sizeof(uint32_t), &rb));
-        nent = ((const uint32_t*)rb)[0];
+        ERRTRY(read_back(ctx, total, 6 * sizeof(uint32_t), &rb));
         nmid = ((const uint32_t*)rb)[1];
         nbig = ((const uint32_t*)rb)[2];
+        uint64_t n64;
+        std::memcpy(&n64, (const uint32_t*)rb + 4, sizeof(n64));
+        if (n64 >= ((uint64_t)1 << 32))
+            return Err{SPH_E_CAPACITY, "sorted lists hold " + std::to_string(n64) +
+                                           " entries (32-bit list positions: limit 2^32 - 1)"};
+        nent = (int64_t)n64;
         t->nsegent = nent;
     }
     // mid-size list | long list | long lengths

@@ -45,7 +45,7 @@ struct sph_tree {
     bool built = false, sorted = false, have_density = false, have_ghost = false, hash = false;
 
     // ---- device buffers ------------------------------------------------
-    sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_pv, b_ph, b_hdec, b_pu,
+    sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_plo, b_pv, b_ph, b_hdec, b_pu,
         b_bound, b_mix, b_rs, b_cell, b_taskA, b_taskB, b_final, b_chunk, b_csr, b_csr2, b_csroff,
         b_segoff, b_seglist, b_segproj, b_segidx, b_bigk, b_bigv, b_sc, b_dens, b_force, b_solve,
         b_red, b_misc, b_saved, b_split, b_counts, b_iperm;
@@ -67,6 +67,7 @@ struct sph_tree {
     uint32_t *val = nullptr, *val2 = nullptr, *perm = nullptr, *rs_tmp = nullptr;
     uint32_t* iperm = nullptr;   // caller order -> cell order
     float4 *pos = nullptr, *pv = nullptr;
+    float4* plo = nullptr;   // FP32 remainders of the positions: pos.xyz + plo.xyz = offset to ~2^-48
     float *ph = nullptr, *hdec = nullptr, *pu = nullptr, *bound = nullptr;
     sph::Cell* cells = nullptr;
     int4 *taskA = nullptr, *taskB = nullptr, *finals = nullptr, *chunks = nullptr;
@@ -119,7 +120,7 @@ struct sph_tree {
     }
 
     std::vector<const sph::DevBuf*> bufs() const {
-        return {&b_sets, &b_small, &b_key, &b_key2, &b_val, &b_val2, &b_perm, &b_pos, &b_pv, &b_ph, &b_hdec,
+        return {&b_sets, &b_small, &b_key, &b_key2, &b_val, &b_val2, &b_perm, &b_pos, &b_plo, &b_pv, &b_ph, &b_hdec,
                 &b_pu, &b_bound, &b_mix, &b_rs, &b_cell, &b_taskA, &b_taskB, &b_final, &b_chunk, &b_csr,
                 &b_csr2, &b_csroff, &b_segoff, &b_seglist, &b_segproj, &b_segidx, &b_bigk, &b_bigv, &b_sc,
                 &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts, &b_iperm};

@@ -13,11 +13,30 @@
 // The records met are staged in LDS tiles, tested, and the in-range ones
 // evaluated (see the walk below).  Every particle therefore meets each
 // in-range partner exactly once per stage, and sums in an order fixed by the
-// tree alone.  Positions are FP32 offsets from the top cell origin; a task
-// adds the exact top-cell shift of its partner (a multiple of the top cell
-// edge), so on inputs of the 2^-24 grid every coordinate difference is exact.
-// Sums are plain FP32 sums over at most a few hundred terms per particle,
-// whose rounding stays far inside the stated tolerances.
+// tree alone.
+//
+// Precision.  A position is kept as two FP32 numbers, its offset from the
+// origin of its top cell rounded to FP32 (pos) and the FP32 rounding of the
+// remainder (plo).  A wave evaluates its chunk in one or more frames: a
+// frame's origin o lies on a grid of pitch L0 / 2^20 (L0 the top cell edge)
+// at the particle with the smallest h still to do, and takes the particles
+// within FRAME_K of their own h of o (the smallest-h one always; usually all
+// of the chunk).  Lane coordinates and staged partner records are formed as
+// (offset + exact shift) + remainder, the shift -- the partner's top cell
+// shift minus o -- being a multiple of the grid pitch and exact in FP32.  A
+// coordinate therefore carries about one rounding of its own size, and a
+// partner within the cutoff of a lane sits within (FRAME_K + 1) cutoffs of
+// o: a distance carries ~(1.5 FRAME_K + 1) roundings of the cutoff whatever
+// the input positions and however large the leaf (a leaf of a few hundred
+// particles may hold a compact clump of particles with h hundreds of times
+// below its edge).  The density sums and the
+// acceleration are summed in FP32 within one staged tile (at most 64 terms
+// per lane) and accumulated across tiles in FP64 (blocked compensated
+// summation), so their rounding stays below ~65 units in the last place of
+// the sum of magnitudes for any number of neighbours.  du/dt and the error
+// scale S are plain FP32 sums (registers: carrying them in FP64 too would
+// cost the force kernel a wave per SIMD); the recursive-sum bound keeps them
+// within their bars up to ~1600 neighbours.
 #include <cmath>
 
 #include "sph_impl.h"
@@ -28,6 +47,11 @@ constexpr float C8PI = 2.5464790894703255f;   // 8/pi: cubic-spline normalisatio
 constexpr int BLK = 256;                      // 4 wavefronts per block, each independent
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Number of set bits of m in the lanes below this one (two mbcnt
+// instructions; no 64-bit lane mask in registers).
+__device__ __forceinline__ int bits_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
 // Hardware square root and reciprocal (1 ulp): the arguments here are
 // normal numbers (r^2 >= 2^-48 for distinct particles), and 1-ulp results
 // are far inside the stated tolerances.
@@ -120,7 +144,7 @@ __global__ __launch_bounds__(LIST_BS) void k_chunk_list(const int4* __restrict__
         s_base = tot ? atomicAdd(&lcount[g * CSTRIDE], tot) : 0;
     }
     __syncthreads();
-    if (on) list[lo + s_base + s_n[wv] + __popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)c;
+    if (on) list[lo + s_base + s_n[wv] + bits_below(bal)] = (uint32_t)c;
 }
 
 // Staged tiles hold TILE_PAD extra slots of far-away points, so that every
@@ -228,6 +252,51 @@ __device__ __forceinline__ PairGeo pair_geo(const Cell& cA, int code, float L0) 
     return g;
 }
 
+// Frames of a chunk (see the header).  A frame takes the particles whose
+// coordinates stay within FRAME_K of their own h of its origin; origins lie
+// on a grid of pitch L0 / 2^FRAME_LG inside the top cell, so that a top-cell
+// shift minus an origin is exact in FP32.
+constexpr float FRAME_K = 4.f;
+constexpr int FRAME_LG = 20;
+
+// A frame origin: grid indices (wave-uniform integers, kept in scalar
+// registers through the walk) and the grid pitch; the origin is k * pitch.
+struct Frame {
+    int kx, ky, kz;
+    float g;
+    // the positions' FP32 remainders are added only where the top cell edge
+    // exceeds twice the frame's smallest h: elsewhere leaving them out moves
+    // a distance by at most 2^-24 sqrt(3) L0 < 2.1e-7 of the cutoff
+    bool lo;
+    __device__ __forceinline__ float3 o() const { return make_float3((float)kx * g, (float)ky * g, (float)kz * g); }
+};
+
+// Coordinates of a particle in the frame with origin o (relative to the top
+// cell): one rounding of their own size, then the remainder.
+__device__ __forceinline__ float4 in_frame(const float4& x, const float4& lo, const float3& o) {
+    return make_float4((x.x - o.x) + lo.x, (x.y - o.y) + lo.y, (x.z - o.z) + lo.z, x.w);
+}
+
+// The next frame of a chunk: pend holds the lanes (lane = particle of the
+// chunk) still to do, x / lo / h this lane's particle.  Returns the lanes it
+// takes (the smallest-h pending one always) and its origin in *f.
+__device__ __forceinline__ uint64_t next_frame(uint64_t pend, const float4& x, const float4& lo, float h, float L0,
+                                               Frame* f) {
+    const int lane = threadIdx.x & 63;
+    const bool pd = (pend >> lane) & 1ull;
+    const float hm = -wave_max_dpp(pd ? -h : -INFINITY);
+    const int lm = __builtin_ctzll(__ballot(pd && h == hm));
+    f->g = L0 * (1.f / (float)(1 << FRAME_LG));   // exact: a power-of-two scale
+    const float gi = (float)(1 << FRAME_LG) / L0;
+    f->kx = __builtin_amdgcn_readlane((int)floorf(x.x * gi), lm);
+    f->ky = __builtin_amdgcn_readlane((int)floorf(x.y * gi), lm);
+    f->kz = __builtin_amdgcn_readlane((int)floorf(x.z * gi), lm);
+    f->lo = L0 > 2.f * hm;
+    const float4 c = in_frame(x, lo, f->o());
+    const bool ok = pd && fmaxf(fabsf(c.x), fmaxf(fabsf(c.y), fabsf(c.z))) <= FRAME_K * h;
+    return (__ballot(ok) | (1ull << lm)) & pend;
+}
+
 __device__ __forceinline__ float proj3(float dx, float dy, float dz, float x, float y, float z) {
     float r = dx * x;
     r = r + dy * y;
@@ -242,6 +311,7 @@ struct DensArgs {
     int nchunks;
     int* counter;
     const float4* pos;
+    const float4* plo;
     const float* ph;
     const uint64_t* mix;
     const uint8_t* active;
@@ -274,6 +344,10 @@ __device__ __forceinline__ int replicas_lg(int cnt, int rmax) {
 // Butterfly over the replica bits (32, 16, ... down to T): a fixed pairing,
 // so the result is the same on every replica and from run to run.
 __device__ __forceinline__ float comb_f(float v, int R) {
+    for (int d = 32, r = R; r > 1; d >>= 1, r >>= 1) v = v + __shfl_xor(v, d, 64);
+    return v;
+}
+__device__ __forceinline__ double comb_d(double v, int R) {
     for (int d = 32, r = R; r > 1; d >>= 1, r >>= 1) v = v + __shfl_xor(v, d, 64);
     return v;
 }
@@ -349,8 +423,10 @@ __device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, i
     const int share = (n + R - 1) >> (31 - __builtin_clz(R));
     const int j0 = rep * share;
     uint32_t m[NWORD];
-    if (self) tile_test<P, true>(S.p, j0, share, L.x, L.hi2, m);
-    else tile_test<P, false>(S.p, j0, share, L.x, L.hi2, m);
+    // (an idle lane sits at -FAR: no record is ever within its h)
+    const float hi2 = L.h * L.h;
+    if (self) tile_test<P, true>(S.p, j0, share, L.x, hi2, m);
+    else tile_test<P, false>(S.p, j0, share, L.x, hi2, m);
     // set bits in increasing record order, 64 at a time
 #pragma unroll
     for (int w = 0; w < NWORD; ++w) acc.nn += __popc(m[w]);
@@ -363,6 +439,7 @@ __device__ __forceinline__ void process_tile(typename P::Lds& S, int n, int R, i
             P::pair(acc, S, j0 + 32 * w + k, L);
         }
     }
+    P::fold(acc);
     wave_lds_sync();   // the tile is overwritten next
 }
 
@@ -395,8 +472,9 @@ struct SweepTab {
 // largest o_k x_k over the chunk's particles per axis and sign (bx[0..2] =
 // max x, bx[3..5] = -min x); hmax: largest h of the chunk.
 template <class P>
-__device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cell& cA, float L0, uint32_t e0, int n,
-                                            const float (&bx)[6], float hmax, SweepTab& T, int* total) {
+__device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cell& cA, float L0, const Frame& fr,
+                                            uint32_t e0, int n, const float (&bx)[6], float hmax, SweepTab& T,
+                                            int* total) {
     const int lane = threadIdx.x & 63;
     int4 q0 = make_int4(0, 0, 0, 0), q1 = q0;
     float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0;
@@ -419,8 +497,12 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
         q1 = make_int4((int)so + cB.nsmall, cB.count - cB.nsmall, g.sign, 0);
         const float r0 = fmaf(P::cut(hmax, cB.hcur), 1.000002f, tiny);
         const float r1 = fmaf(P::cut(hmax, cB.hcur_l), 1.000002f, tiny);
-        f0 = make_float4(g.Sx, g.Sy, g.Sz, r0 * r0);
-        f1 = make_float4(g.Sx, g.Sy, g.Sz, r1 * r1);
+        // shift into the frame: top cell shift minus the frame origin (both
+        // multiples of the frame grid pitch: exact)
+        const float3 oA = fr.o();
+        const float Dx = g.Sx - oA.x, Dy = g.Sy - oA.y, Dz = g.Sz - oA.z;
+        f0 = make_float4(Dx, Dy, Dz, r0 * r0);
+        f1 = make_float4(Dx, Dy, Dz, r1 * r1);
         lim0 = tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny);
         lim1 = tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny);
     }
@@ -441,8 +523,7 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
     const int c0 = prefix(q0, lim0), c1 = prefix(q1, lim1);
     const bool ne0 = c0 > 0, ne1 = c1 > 0;
     const uint64_t b0 = __ballot(ne0), b1 = __ballot(ne1);
-    const uint64_t below = (1ull << lane) - 1ull;
-    const int pos = __popcll(b0 & below) + __popcll(b1 & below);
+    const int pos = bits_below(b0) + bits_below(b1);
     // records of the parts before this lane's: inclusive scan of c0 + c1
     int cs = c0 + c1;
 #pragma unroll
@@ -470,8 +551,9 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
     return nd;
 }
 
-// The walk of one chunk: the leaf's self task, then the pair tasks of the
-// leaf and of its ancestors; each pair task sweeps the partner's sorted
+// The walk of one chunk, in one frame (origin oA relative to the leaf's top
+// cell; the lanes' coordinates are in that frame): the leaf's self task, then
+// the pair tasks of the leaf and of its ancestors; each pair task sweeps the partner's sorted
 // list (small-h part, then large-h part) up to the largest reach of the
 // chunk along the pair axis, bounded by the bounding box of its particles
 // plus the largest cutoff.  The swept records of a batch of pair tasks are
@@ -479,8 +561,8 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
 // loop so that the tile processing is inlined once.
 template <class P>
 __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds& S, SweepTab& T,
-                                     const typename P::Lane& L, typename P::Acc& acc, int leaf, int R, int rep,
-                                     bool act) {
+                                     const typename P::Lane& L, typename P::Acc& acc, int leaf, const Frame& fr,
+                                     int R, int rep, bool act) {
     const int lane = threadIdx.x & 63;
     const Cell C = a.cells[leaf];
     int sbase = C.first;                 // next record of the self task
@@ -525,6 +607,10 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
             j = (uint32_t)(sbase + lane);
             q = j;
             if (lane < nuse) pj = a.pos[j];
+            const float3 oA = fr.o();
+            Sx = -oA.x;
+            Sy = -oA.y;
+            Sz = -oA.z;
             rad2 = rself2;
             self = true;
             sbase += nuse;
@@ -546,7 +632,7 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
                     break;
                 }
                 const int n = (int)min(e1 - e, (uint32_t)DBATCH);
-                nd = build_sweeps<P>(a, cA, L0, e, n, bx, hmax, T, &tot);
+                nd = build_sweeps<P>(a, cA, L0, fr, e, n, bx, hmax, T, &tot);
                 e += n;
                 g0 = 0;
             }
@@ -591,9 +677,9 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
         }
         const uint64_t okm = __ballot(ok);
         const int m = __popcll(okm);
-        const int slot = __popcll(okm & ((1ull << lane) - 1ull));
+        const int slot = bits_below(okm);
         const int room = TCAP - fill;
-        if (ok && slot < room) P::stage(S, fill + slot, j, pj, Sx, Sy, Sz, a, pre, early);
+        if (ok && slot < room) P::stage(S, fill + slot, j, pj, Sx, Sy, Sz, a, pre, early, fr.lo);
         const int first = min(m, room);
         fill += first;
         tself = tself || (self && first > 0);
@@ -606,11 +692,12 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
         if (ok && slot >= room) {
             // read again rather than kept through the tile's evaluation
             if (dl < 0) {
-                P::stage(S, slot - room, q, a.pos[q], 0.f, 0.f, 0.f, a, pre, false);
+                const float3 oA = fr.o();
+                P::stage(S, slot - room, q, a.pos[q], -oA.x, -oA.y, -oA.z, a, pre, false, fr.lo);
             } else {
                 const float4 df = T.f[dl];
                 const uint32_t jj = a.segidx[q];
-                P::stage(S, slot - room, jj, a.segpos[q], df.x, df.y, df.z, a, pre, false);
+                P::stage(S, slot - room, jj, a.segpos[q], df.x, df.y, df.z, a, pre, false, fr.lo);
             }
         }
         fill += m - first;
@@ -626,13 +713,22 @@ struct DensP {
     using Args = DensArgs;
     struct Lane {
         float4 x;   // position, mass
-        float h, hinv, hi2;
+        float h, hinv;
     };
     struct Acc {
-        float sf = 0, sg = 0, sw = 0, sq = 0;   // sums of m f, m (3f + q f'), f, q f'
+        float sf = 0, sg = 0, sw = 0, sq = 0;   // sums of m f, m (3f + q f'), f, q f' over one tile
+        double tf = 0, tg = 0, tw = 0, tq = 0;  // the same over the tiles done
         int nn = 0;
         uint64_t hs = 0;
     };
+    // a tile's partial sums (at most 64 terms per lane) into the FP64 totals
+    static __device__ __forceinline__ void fold(Acc& A) {
+        A.tf += (double)A.sf;
+        A.tg += (double)A.sg;
+        A.tw += (double)A.sw;
+        A.tq += (double)A.sq;
+        A.sf = A.sg = A.sw = A.sq = 0.f;
+    }
     struct Lds {
         float4 p[TILE];     // x, y, z (shifted into the target's frame), m
         uint64_t m[TILE];   // pair-hash terms
@@ -646,8 +742,9 @@ struct DensP {
     static __device__ __forceinline__ Pre pre(const Args&, uint32_t, bool) { return Pre{}; }
     static __device__ __forceinline__ float rad2(float part2, const Pre&, float, float) { return part2; }
     static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
-                                                 float Sz, const Args& a, const Pre&, bool) {
-        S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, pj.w);
+                                                 float Sz, const Args& a, const Pre&, bool, bool uselo) {
+        const float4 lo = uselo ? a.plo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        S.p[slot] = make_float4((pj.x + Sx) + lo.x, (pj.y + Sy) + lo.y, (pj.z + Sz) + lo.z, pj.w);
         if (HASH) S.m[slot] = a.mix[j];
     }
     static __device__ __forceinline__ void pair(Acc& A, const Lds& S, int j, const Lane& L) {
@@ -671,7 +768,7 @@ struct DensP {
 };
 
 template <bool SOLVE, bool HASH>
-__global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k_density(DensArgs a) {
     using P = DensP<HASH>;
     __shared__ typename P::Lds s_l[BLK / 64];
     __shared__ SweepTab s_t[BLK / 64];
@@ -680,47 +777,66 @@ __global__ __launch_bounds__(BLK) void k_density(DensArgs a) {
     typename P::Lds& S = s_l[w];
     const int home = blockIdx.x & (NGRP - 1);
     int grp = 0;
+    // one step per frame of a chunk: the particles of the chunk that take
+    // part -- all, or the still active ones of a Newton pass (state 1; 2 =
+    // parked until a rebuild) -- are done frame by frame (pend: those left),
+    // each frame's packed into the first slots
+    int leaf = 0, p0 = 0, cnt = 0;
+    uint64_t pend = 0;
     for (;;) {
-        const int item = next_chunk(a.counter, a.nchunks, a.list, a.lcount, home, grp);
-        if (item < 0) break;
-        const int4 ch = a.chunks[item];
-        const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
-        // particles of the chunk that take part: all, or the still active
-        // ones of a Newton pass (state 1; 2 = parked until a rebuild),
-        // packed into the first slots
-        uint64_t amask = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
-        if (SOLVE) amask = __ballot(lane < cnt && a.active[p0 + lane] == 1);
-        if (amask == 0) continue;
+        if (pend == 0) {
+            const int item = next_chunk(a.counter, a.nchunks, a.list, a.lcount, home, grp);
+            if (item < 0) break;
+            const int4 ch = a.chunks[item];
+            leaf = uni(ch.x);
+            p0 = uni(ch.y);
+            cnt = uni(ch.z);
+            pend = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+            if (SOLVE) pend = __ballot(lane < cnt && a.active[p0 + lane] == 1);
+            if (pend == 0) continue;
+        }
+        const float L0 = (float)a.sets[a.cells[leaf].set].L0;
+        Frame fr;
+        uint64_t amask;
+        {
+            // the lane's particle, read again for every frame rather than
+            // kept in registers through the walk
+            int q = p0 + (lane < cnt ? lane : 0);
+            asm volatile("" : "+v"(q));
+            amask = next_frame(pend, a.pos[q], a.plo[q], a.ph[q], L0, &fr);
+        }
+        pend &= ~amask;
         const int nact = __popcll(amask);
         const int lgR = replicas_lg(nact, a.rmax), R = 1 << lgR, T = 64 >> lgR;
         const int slot = lane & (T - 1), rep = lane >> (6 - lgR);
         // slot -> particle: the slot-th set bit of amask
-        if ((amask >> lane) & 1ull) s_pick[w][__popcll(amask & ((1ull << lane) - 1ull))] = lane;
+        if ((amask >> lane) & 1ull) s_pick[w][bits_below(amask)] = lane;
         wave_lds_sync();
         const int pick = slot < nact ? s_pick[w][slot] : 0;
         wave_lds_sync();
         const int p = p0 + pick;
         const bool act = slot < nact;
         typename P::Lane L;
-        L.x = act ? a.pos[p] : make_float4(-FAR, -FAR, -FAR, 0.f);
+        // an idle lane sits far away so no record is ever in its range
+        L.x = act ? in_frame(a.pos[p], fr.lo ? a.plo[p] : make_float4(0.f, 0.f, 0.f, 0.f), fr.o())
+                  : make_float4(-FAR, -FAR, -FAR, 0.f);
         L.h = act ? a.ph[p] : 1.f;
         L.hinv = 1.f / L.h;
-        L.hi2 = act ? L.h * L.h : -1.f;
         typename P::Acc acc;
-        walk<P>(a, S, s_t[w], L, acc, leaf, R, rep, act);
+        walk<P>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act);
 
-        const float sf = comb_f(acc.sf, R), sg = comb_f(acc.sg, R);
-        const float sw = comb_f(acc.sw, R), sq = comb_f(acc.sq, R);
+        const double sf = comb_d(acc.tf, R), sg = comb_d(acc.tg, R);
+        const double sw = comb_d(acc.tw, R), sq = comb_d(acc.tq, R);
         const int nn = comb_i(acc.nn, R);
         const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
         if (act && rep == 0) {
             const float hi = L.h, hinv = L.hinv;
             const float h3 = hi * hi * hi;
             const float mi = L.x.w;
-            a.rho[p] = C8PI / h3 * (mi + sf);
-            a.drho[p] = -C8PI / (h3 * hi) * (3.f * mi + sg);
-            a.nw[p] = (32.f / 3.f) * (1.f + sw);
-            a.dnw[p] = -(32.f / 3.f) * hinv * sq;
+            a.rho[p] = C8PI / h3 * (float)((double)mi + sf);
+            a.drho[p] = -C8PI / (h3 * hi) * (float)(3.0 * (double)mi + sg);
+            a.nw[p] = (32.f / 3.f) * (float)(1.0 + sw);
+            a.dnw[p] = -(32.f / 3.f) * hinv * (float)sq;
             a.nngb[p] = nn;
             if (HASH) a.hash[p] = hs;
         }
@@ -737,6 +853,7 @@ struct ForceArgs {
     int nchunks;
     int* counter;
     const float4* pos;
+    const float4* plo;
     const float4* pv;
     const float4* frec;   // h, A, sound speed, K = 8/(pi h^5); pv.w holds rho
     const uint64_t* mix;
@@ -765,13 +882,20 @@ struct ForceP {
     struct Lane {
         float4 x;   // position, mass
         float4 v;   // velocity, rho
-        float h, hinv, K, A, c, hi2, alpha;
+        float h, hinv, K, A, c, alpha;
     };
     struct Acc {
-        float ax = 0, ay = 0, az = 0, du = 0, vs = 0, S = 0;
+        float ax = 0, ay = 0, az = 0, du = 0, vs = 0, S = 0;   // a: over one tile; du, vs, S: over all
+        double tx = 0, ty = 0, tz = 0;                         // a over the tiles done
         int nn = 0;
         uint64_t hs = 0;
     };
+    static __device__ __forceinline__ void fold(Acc& A) {
+        A.tx += (double)A.ax;
+        A.ty += (double)A.ay;
+        A.tz += (double)A.az;
+        A.ax = A.ay = A.az = 0.f;
+    }
     struct Lds {
         float4 p[TILE];    // x, y, z (shifted into the target's frame), h
         float4 h[TILE];    // m, 1/h, K = 8/(pi h^5), A
@@ -800,9 +924,10 @@ struct ForceP {
         return fminf(part2, r * r);
     }
     static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
-                                                 float Sz, const Args& a, const Pre& pr, bool loaded) {
+                                                 float Sz, const Args& a, const Pre& pr, bool loaded, bool uselo) {
         const float4 fj = loaded ? pr.f : a.frec[j];
-        S.p[slot] = make_float4(pj.x + Sx, pj.y + Sy, pj.z + Sz, fj.x);
+        const float4 lo = uselo ? a.plo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        S.p[slot] = make_float4((pj.x + Sx) + lo.x, (pj.y + Sy) + lo.y, (pj.z + Sz) + lo.z, fj.x);
         S.h[slot] = make_float4(pj.w, frcp(fj.x), fj.w, fj.y);
         S.v[slot] = a.pv[j];
         S.c[slot] = fj.z;
@@ -814,10 +939,11 @@ struct ForceP {
         const float4 sv = S.v[j];
         const float cj = S.c[j];
         const float dx = L.x.x - q.x, dy = L.x.y - q.y, dz = L.x.z - q.z;
-        // 1/r from one reciprocal square root, r = r^2 / r (r > 0: positions
-        // in a set are distinct)
+        // 1/r from one reciprocal square root, r = r^2 / r; two distinct
+        // particles at one FP32 point (closer than a rounding of their
+        // frame) give r = 0 and no vector term instead of a NaN
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        const float rinv = frsq(r2);
+        const float rinv = r2 > 0.f ? frsq(r2) : 0.f;
         const float r = r2 * rinv;
         const float ki = L.K * gradF(r * L.hinv, L.h, rinv);
         const float kj = sh.z * gradF(r * sh.y, q.w, rinv);
@@ -847,22 +973,49 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
     using P = ForceP<HASH>;
     __shared__ typename P::Lds s_l[BLK / 64];
     __shared__ SweepTab s_t[BLK / 64];
+    __shared__ int s_pick[BLK / 64][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     typename P::Lds& S = s_l[w];
     const int home = blockIdx.x & (NGRP - 1);
     int grp = 0;
+    // one step per frame of a chunk (pend: the chunk's particles left, each
+    // frame's packed into the first slots)
+    int leaf = 0, p0 = 0, cnt = 0;
+    uint64_t pend = 0;
     for (;;) {
-        const int item = next_chunk(a.counter, a.nchunks, nullptr, nullptr, home, grp);
-        if (item < 0) break;
-        const int4 ch = a.chunks[item];
-        const int leaf = uni(ch.x), p0 = uni(ch.y), cnt = uni(ch.z);
-        const int lgR = replicas_lg(cnt, a.rmax), R = 1 << lgR, T = 64 >> lgR;
+        if (pend == 0) {
+            const int item = next_chunk(a.counter, a.nchunks, nullptr, nullptr, home, grp);
+            if (item < 0) break;
+            const int4 ch = a.chunks[item];
+            leaf = uni(ch.x);
+            p0 = uni(ch.y);
+            cnt = uni(ch.z);
+            pend = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+        }
+        const float L0 = (float)a.sets[a.cells[leaf].set].L0;
+        Frame fr;
+        uint64_t amask;
+        {
+            // the lane's particle, read again for every frame rather than
+            // kept in registers through the walk
+            int q = p0 + (lane < cnt ? lane : 0);
+            asm volatile("" : "+v"(q));
+            amask = next_frame(pend, a.pos[q], a.plo[q], a.frec[q].x, L0, &fr);
+        }
+        pend &= ~amask;
+        const int nact = __popcll(amask);
+        const int lgR = replicas_lg(nact, a.rmax), R = 1 << lgR, T = 64 >> lgR;
         const int slot = lane & (T - 1), rep = lane >> (6 - lgR);
-        const int p = p0 + slot;
-        const bool act = slot < cnt;
+        if ((amask >> lane) & 1ull) s_pick[w][bits_below(amask)] = lane;
+        wave_lds_sync();
+        const int pick = slot < nact ? s_pick[w][slot] : 0;
+        wave_lds_sync();
+        const int p = p0 + pick;
+        const bool act = slot < nact;
         typename P::Lane L;
         // an idle lane sits far away so no record is ever in its range
-        L.x = act ? a.pos[p] : make_float4(-FAR, -FAR, -FAR, 0.f);
+        L.x = act ? in_frame(a.pos[p], fr.lo ? a.plo[p] : make_float4(0.f, 0.f, 0.f, 0.f), fr.o())
+                  : make_float4(-FAR, -FAR, -FAR, 0.f);
         // the same records as the staged partners: the two sides of a pair
         // see identical values
         const float4 fi = act ? a.frec[p] : make_float4(1.f, 0.f, 0.f, 0.f);
@@ -872,13 +1025,12 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
         L.v = act ? a.pv[p] : make_float4(0.f, 0.f, 0.f, 1.f);
         L.A = fi.y;
         L.c = fi.z;
-        L.hi2 = act ? L.h * L.h : -1.f;
         L.alpha = a.alpha;
         typename P::Acc acc;
-        walk<P>(a, S, s_t[w], L, acc, leaf, R, rep, act);
+        walk<P>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act);
 
-        const float ax = comb_f(acc.ax, R), ay = comb_f(acc.ay, R);
-        const float az = comb_f(acc.az, R), du = comb_f(acc.du, R);
+        const float ax = (float)comb_d(acc.tx, R), ay = (float)comb_d(acc.ty, R);
+        const float az = (float)comb_d(acc.tz, R), du = comb_f(acc.du, R);
         const float vs = comb_max(acc.vs, R), Ss = comb_f(acc.S, R);
         const int nn = comb_i(acc.nn, R);
         const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
@@ -1335,6 +1487,7 @@ static DensArgs dens_args(sph_tree* t, int* counter, const int* lcount) {
     a.nchunks = (int)t->nchunks;
     a.counter = counter;
     a.pos = t->pos;
+    a.plo = t->plo;
     a.ph = t->ph;
     a.mix = t->mix;
     a.active = t->active;
@@ -1398,6 +1551,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.nchunks = (int)t->nchunks;
     a.counter = counter;
     a.pos = t->pos;
+    a.plo = t->plo;
     a.pv = t->pv;
     a.frec = t->frec;
     a.mix = t->mix;

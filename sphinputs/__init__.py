@@ -7,9 +7,11 @@ SPH arithmetic (no kernel, no neighbour sums) so that both the FP64 oracle
 and the GPU path can take their inputs from here without sharing method
 code.
 
-Every position is snapped to the 2^-24 grid of the periodic unit cube and
-exact duplicates are redrawn, so that any coordinate difference between two
-particles of one top-level cell is exactly representable in FP32.
+By default every position is snapped to the 2^-24 grid of the periodic unit
+cube and exact duplicates are redrawn, so that any coordinate difference
+between two particles of one top-level cell is exactly representable in
+FP32.  With ``snap=False`` the positions keep all their FP64 bits (wrapped
+into [0, 1)): the off-grid inputs a caller or a time step produces.
 
 Recipes (all periodic unit box, equal masses m = FP32(1/N), u = 1.5):
 
@@ -78,13 +80,16 @@ def _f32(a) -> np.ndarray:
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-def _snap_unique(pos: np.ndarray, redraw, rng: np.random.Generator) -> np.ndarray:
-    """Snap positions to the 2^-24 grid (mod 1) and redraw exact duplicates."""
+def _snap_unique(pos: np.ndarray, redraw, rng: np.random.Generator, snap: bool = True) -> np.ndarray:
+    """Snap positions to the 2^-24 grid (mod 1) and redraw exact duplicates;
+    snap=False: wrap into [0, 1) only, redrawing positions whose 2^-24 cell
+    is taken (distinct particles stay at least ~2^-24 apart either way)."""
     for _ in range(64):
-        k = np.floor(np.mod(pos, 1.0) * GRID).astype(np.int64) % int(GRID)
+        w = np.mod(pos, 1.0)
+        k = np.floor(w * GRID).astype(np.int64) % int(GRID)
         dup = _duplicates(k)
         if not dup.any():
-            return k.astype(np.float64) / GRID
+            return k.astype(np.float64) / GRID if snap else w
         idx = np.nonzero(dup)[0]
         pos = pos.copy()
         pos[idx] = redraw(idx, rng)
@@ -119,16 +124,16 @@ def h_for_density(n_density, n_ngb: float = N_NGB) -> np.ndarray:
     return np.cbrt(3.0 * n_ngb / (4.0 * math.pi * np.asarray(n_density, dtype=np.float64)))
 
 
-def uniform(n: int, seed: int, velocity: bool = False) -> ParticleSet:
+def uniform(n: int, seed: int, velocity: bool = False, snap: bool = True) -> ParticleSet:
     rng = _rng(seed)
     pos = rng.random((n, 3))
-    pos = _snap_unique(pos, lambda idx, r: r.random((idx.size, 3)), rng)
+    pos = _snap_unique(pos, lambda idx, r: r.random((idx.size, 3)), rng, snap)
     h = h_for_density(float(n))
     return _finish(pos, n, rng, np.full(n, h), velocity,
-                   {"recipe": "uniform", "seed": seed})
+                   {"recipe": "uniform", "seed": seed, "snap": snap})
 
 
-def lattice(n_side: int, jitter: float, seed: int, velocity: bool = False) -> ParticleSet:
+def lattice(n_side: int, jitter: float, seed: int, velocity: bool = False, snap: bool = True) -> ParticleSet:
     rng = _rng(seed)
     d = 1.0 / n_side
     g = (np.arange(n_side) + 0.5) * d
@@ -143,9 +148,9 @@ def lattice(n_side: int, jitter: float, seed: int, velocity: bool = False) -> Pa
     def redraw(idx, r):
         return base[idx] + r.uniform(-jitter, jitter, size=(idx.size, 3)) * d
 
-    pos = _snap_unique(pos, redraw, rng)
+    pos = _snap_unique(pos, redraw, rng, snap)
     return _finish(pos, n, rng, np.full(n, h_for_density(float(n))), velocity,
-                   {"recipe": "lattice", "n_side": n_side, "jitter": jitter, "seed": seed})
+                   {"recipe": "lattice", "n_side": n_side, "jitter": jitter, "seed": seed, "snap": snap})
 
 
 def sod(n_left: int = 116, n_right: int = 73, nx_right: int = 37, p_left: float = 1.0, p_right: float = 0.1795,
@@ -222,7 +227,7 @@ def _iso(rng, size):
 
 
 def plummer_mixture(n: int, seed: int, n_clumps: int = 64, bg_frac: float = 0.2,
-                    velocity: bool = False) -> ParticleSet:
+                    velocity: bool = False, snap: bool = True) -> ParticleSet:
     rng = _rng(seed)
     n_bg = int(round(bg_frac * n))
     n_cl = n - n_bg
@@ -251,12 +256,12 @@ def plummer_mixture(n: int, seed: int, n_clumps: int = 64, bg_frac: float = 0.2,
                 out[k] = centre[c] + rr[:, None] * _iso(r, 1)
         return out
 
-    pos = _snap_unique(pos, redraw, rng)
+    pos = _snap_unique(pos, redraw, rng, snap)
     dens = plummer_number_density(pos, n_bg, per, a, rmax, centre)
     h0 = h_for_density(dens)
     return _finish(pos, n, rng, h0, velocity,
                    {"recipe": "plummer_mixture", "seed": seed, "n_clumps": n_clumps,
-                    "bg_frac": bg_frac, "a": a.tolist(), "centre": centre.tolist()})
+                    "bg_frac": bg_frac, "a": a.tolist(), "centre": centre.tolist(), "snap": snap})
 
 
 def plummer_number_density(pos, n_bg, per, a, rmax, centre):

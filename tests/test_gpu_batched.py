@@ -129,6 +129,29 @@ def test_batched_sets_equal_alone(sph, ctx):
         assert np.abs(nw - 48.0).max() <= 0.5 + 1e-4
 
 
+def test_batched_at_gpu_h(sph, ctx):
+    """A batch of uneven clumpy sets through the graph pipeline (24 Newton
+    passes in the graph, re-runs for sets that need them): every set's
+    density and force compared element by element with the oracle at the h
+    the GPU solved, which the oracle accepts (N_w within 48 +- 0.5 in FP64)."""
+    from _checks import at_gpu_h
+    from paper_1309_3783_amd import pipeline as P
+    sizes = [2100, 9000, 33000, 4100, 61000, 2600, 17000, 5200, 12000]
+    sets = [sphinputs.plummer_mixture(n, 1300 + k, velocity=True, snap=(k % 2 == 0)) for k, n in enumerate(sizes)]
+    batch = sph.batch_from_sets(sets)
+    out = P.Outputs(batch.n, batch.nsets)
+    P.run_graph(sph.Tree(ctx), batch, sph.params(), out, 24)
+    torch.cuda.synchronize()
+    excl = 0
+    for s, ps in enumerate(sets):
+        r = grab(out, batch, s)
+        print(f"\n[batched at gpu h] set {s}: n {ps.n} snapped {ps.meta['snap']}", flush=True)
+        k, e = at_gpu_h(ps, r, r)
+        excl += e
+        assert k + e == ps.n
+    print(f"\n[batched at gpu h] {len(sets)} sets, {batch.n} particles, excluded near a cutoff {excl}", flush=True)
+
+
 def test_served_mix_equals_alone(sph):
     from paper_1309_3783_amd import serve as S
     rng = np.random.default_rng(5)
@@ -149,14 +172,21 @@ def test_served_mix_equals_alone(sph):
         S.Scheduler(alone_ex, budget_bytes=2 << 30, footprint=lambda x: 1, max_batch=1).run([q])
         same(r.result, q.result)
         assert q.batch_size == 1
-    # the solved h against the oracle's own FP64 root on a sample of the
+    # every request against the oracle at the h the GPU solved (the oracle
+    # accepts that h: N_w within 48 +- 0.5 in FP64), density and force
+    # element by element
+    from _checks import at_gpu_h
+    for r in reqs:
+        k, e = at_gpu_h(r.ps, r.result, r.result)
+        assert k + e == r.ps.n
+        assert np.abs(r.result["nw"] - 48.0).max() <= 0.5 + 1e-4
+    # and the solved h against the oracle's own FP64 root on a sample of the
     # smallest requests (|N_w - 48| <= 0.5 bounds h to well under 1.5%)
     for r in sorted(reqs, key=lambda x: x.n)[:3]:
         ps = r.ps
         t = np.arange(0, ps.n, max(1, ps.n // 300))
         h_ref, _ = oracle.solve_h(ps.x, ps.y, ps.z, ps.m, ps.h0, targets=t, tol=1e-9)
         assert np.abs(np.asarray(r.result["h"], dtype=np.float64)[t] / h_ref[t] - 1.0).max() < 1.5e-2
-        assert np.abs(r.result["nw"] - 48.0).max() <= 0.5 + 1e-4
 
 
 def test_autotune_picks_a_candidate(sph, ctx):
