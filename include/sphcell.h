@@ -14,9 +14,16 @@
  *
  * Conventions
  *  - Every pointer marked [device] is a device pointer owned by the caller;
- *    pointers marked [host] are host memory.  The library owns only the
- *    device memory of a tree (sph_tree), which it allocates at build time and
- *    frees in sph_tree_destroy.
+ *    pointers marked [host] are host memory.
+ *  - Device memory of a tree: a caller-provided workspace (the intended use:
+ *    sph_workspace_size, sph_tree_set_workspace), carved into the tree's
+ *    buffers by the library with no allocation, free or device-wide
+ *    synchronisation inside any call; SPH_E_WORKSPACE when it is too small
+ *    (sph_tree_workspace_needed says how much to offer, then build again).
+ *    Without a workspace the library allocates the tree's buffers itself
+ *    (hipMalloc, grow-only; a growth frees the old buffer, which waits for
+ *    the device) and frees them in sph_tree_destroy.  A context allocates a
+ *    4 KiB device counter block and 64 KiB of pinned host memory once.
  *  - One context per HIP stream.  Every call enqueues work on the context's
  *    stream; outputs are valid once that stream has been synchronised, except
  *    where a host output is documented (those calls synchronise).
@@ -133,15 +140,44 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream);
 void sph_ctx_destroy(sph_ctx* ctx);
 const char* sph_last_error(const sph_ctx* ctx);
 
-/* Device bytes a tree for n particles is expected to need (admission
- * control); an estimate from the cell/task statistics of clustered sets. */
+/* Workspace for a tree of n particles in nsets sets (contract of Section II:
+ * the two stages' inputs and outputs plus the decomposition of Section II-B
+ * and the sorted lists of Section II-C): an estimate for sets like uniform,
+ * lattice and clumpy mixtures with up to ~3 decades of h (per particle:
+ * ~275 B of particle state, ~520 B of sorted lists, ~120 B of cells, tasks
+ * and interaction lists; plus 4 KiB per set and 24 MiB).  The need depends
+ * on the data; a build that finds the workspace too small fails with
+ * SPH_E_WORKSPACE and reports what it needs (sph_tree_workspace_needed).
+ * sph_footprint(n, p) = sph_workspace_size(n, 1, p): the size admission
+ * control charges per request.  Errors: SPH_E_ARG. */
+sph_status sph_workspace_size(int64_t n, int32_t nsets, const sph_params* p, size_t* bytes);
 sph_status sph_footprint(int64_t n, const sph_params* p, size_t* bytes);
 
 /* Create an empty tree object (no device memory yet). */
 sph_status sph_tree_create(sph_ctx* ctx, sph_tree** out);
 void sph_tree_destroy(sph_ctx* ctx, sph_tree* t);
-/* Device bytes currently held by the tree. */
+/* Device bytes currently held by the tree's buffers. */
 sph_status sph_tree_bytes(const sph_tree* t, size_t* bytes);
+
+/* Give the tree a workspace: ws [device] is a caller-owned region of ws_bytes
+ * (at least 1 MiB) that every buffer of the tree is carved from from now on
+ * (first fit, 256-byte granules; blocks are freed and reused in the order of
+ * the context's stream, so no call allocates, frees or synchronises the
+ * device).  ws = NULL returns the tree to library-owned buffers.  The tree's
+ * previous buffers are dropped -- build again before the next density or
+ * force call -- except the Newton state that a solve saved for a rebuild
+ * (SPH_FLAG_RESUME), which is copied into the new memory on the stream: the
+ * previous workspace must stay valid until the stream has run past this
+ * call.  The workspace must outlive the tree's use of it and must not be
+ * shared with another tree.  Errors: SPH_E_ARG, SPH_E_WORKSPACE (the saved
+ * state does not fit), SPH_E_HIP. */
+sph_status sph_tree_set_workspace(sph_ctx* ctx, sph_tree* t, void* ws, size_t ws_bytes);
+
+/* Bytes a workspace must offer: after a call failed with SPH_E_WORKSPACE, at
+ * least what it needed (the blocks in use plus the request, with an eighth of
+ * the old size to spare; offer it and repeat the build); otherwise the peak
+ * the tree's buffers have used in the current workspace. */
+sph_status sph_tree_workspace_needed(const sph_tree* t, size_t* bytes);
 
 /* Section II-B (spatial decomposition): for every set, a top grid of cells of
  * edge >= max h (a power of two per side, at least 2), Morton ordering of the

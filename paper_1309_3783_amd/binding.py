@@ -22,8 +22,9 @@ SPH_FLAG_RESUME = 2
 
 # every function the header declares
 EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
-           "sph_last_error", "sph_footprint", "sph_tree_create", "sph_tree_destroy", "sph_tree_bytes",
-           "sph_build_cells", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
+           "sph_last_error", "sph_workspace_size", "sph_footprint", "sph_tree_create", "sph_tree_destroy",
+           "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
+           "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
            "sph_last_timings", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
 
 
@@ -76,6 +77,9 @@ def lib():
         L.sph_last_error.argtypes = [vp]
         L.sph_last_error.restype = C.c_char_p
         L.sph_footprint.argtypes = [C.c_int64, C.POINTER(sph_params), C.POINTER(C.c_size_t)]
+        L.sph_workspace_size.argtypes = [C.c_int64, C.c_int32, C.POINTER(sph_params), C.POINTER(C.c_size_t)]
+        L.sph_tree_set_workspace.argtypes = [vp, vp, vp, C.c_size_t]
+        L.sph_tree_workspace_needed.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.sph_tree_create.argtypes = [vp, C.POINTER(vp)]
         L.sph_tree_destroy.argtypes = [vp, vp]
         L.sph_tree_destroy.restype = None
@@ -96,9 +100,10 @@ def lib():
         L.sph_kick.argtypes = [vp, C.c_int64, C.c_float] + [vp] * 12
         L.sph_drift.argtypes = [vp, C.c_int32, vp, vp, C.c_double] + [vp] * 6
         L.sph_cfl_dt.argtypes = [vp, C.c_int64, vp, vp, C.c_float, C.POINTER(C.c_double)]
-        for name in ("sph_ctx_create", "sph_footprint", "sph_tree_create", "sph_tree_bytes", "sph_build_cells",
-                     "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
-                     "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"):
+        for name in ("sph_ctx_create", "sph_footprint", "sph_workspace_size", "sph_tree_create", "sph_tree_bytes",
+                     "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
+                     "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force",
+                     "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -123,6 +128,14 @@ def footprint(n: int, prm: sph_params | None = None) -> int:
     st = lib().sph_footprint(int(n), C.byref(prm or params()), C.byref(b))
     if st:
         raise SphError(st, "sph_footprint")
+    return int(b.value)
+
+
+def workspace_size(n: int, nsets: int = 1, prm: sph_params | None = None) -> int:
+    b = C.c_size_t(0)
+    st = lib().sph_workspace_size(int(n), int(nsets), C.byref(prm or params()), C.byref(b))
+    if st:
+        raise SphError(st, "sph_workspace_size")
     return int(b.value)
 
 
@@ -259,15 +272,44 @@ class ForceOut:
 
 
 class Tree:
-    """A device-resident cell tree for one Batch (kept across density -> force)."""
+    """A device-resident cell tree for one Batch (kept across density -> force).
 
-    def __init__(self, ctx: Context):
+    workspace=True (default): the tree's device memory is one torch uint8
+    tensor handed to the library (sph_tree_set_workspace), sized by
+    sph_workspace_size and grown (doubled, at least to what the library
+    reports it needs) when a build fails with SPH_E_WORKSPACE; the library
+    then never allocates inside a call.  workspace=False: the library owns
+    the buffers."""
+
+    def __init__(self, ctx: Context, workspace: bool = True):
         self.ctx = ctx
         h = C.c_void_p()
         ctx.check(lib().sph_tree_create(ctx.h, C.byref(h)), "sph_tree_create")
         self.h = h
         self.batch = None
         self.prm = None
+        self.use_ws = workspace
+        self.ws = None          # the workspace tensor
+        self._old_ws = []       # previous workspaces, kept until the stream has passed their last use
+
+    def set_workspace(self, nbytes: int):
+        """Attach a fresh workspace of nbytes (the tree must be built again)."""
+        import torch
+        ws = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        if self.ws is not None:
+            self._old_ws.append(self.ws)
+        self.ctx.check(lib().sph_tree_set_workspace(self.ctx.h, self.h, _ptr(ws), int(nbytes)),
+                       "sph_tree_set_workspace")
+        self.ws = ws
+        if self._old_ws:
+            # the saved Newton state (if any) is copied out of the old one
+            self.ctx.stream.synchronize()
+            self._old_ws.clear()
+
+    def workspace_needed(self) -> int:
+        b = C.c_size_t(0)
+        self.ctx.check(lib().sph_tree_workspace_needed(self.h, C.byref(b)), "sph_tree_workspace_needed")
+        return int(b.value)
 
     def close(self):
         if getattr(self, "h", None):
@@ -284,33 +326,65 @@ class Tree:
         self.batch = batch
         self.prm = prm or params()
         self._in = batch.as_input(h)
-        self.ctx.check(lib().sph_build_cells(self.ctx.h, self.h, C.byref(self._in), C.byref(self.prm)),
-                       "sph_build_cells")
+        self._sorted = False
+        if self.use_ws:
+            want = workspace_size(batch.n, batch.nsets, self.prm)
+            if self.ws is None or self.ws.numel() < want:
+                self.set_workspace(max(want, 0 if self.ws is None else 2 * self.ws.numel()))
+        self._call(lambda: lib().sph_build_cells(self.ctx.h, self.h, C.byref(self._in), C.byref(self.prm)),
+                   "sph_build_cells")
+
+    def _call(self, fn, what, ok=(SPH_OK,)):
+        """Run a library call; with a workspace, a call that ran out of it is
+        repeated on a larger one (twice the size, at least what the library
+        says it needs), after building -- and sorting -- the tree again."""
+        st = fn()
+        for _ in range(8):
+            if st != SPH_E_WORKSPACE or not self.use_ws:
+                break
+            self.set_workspace(max(2 * self.ws.numel(), self.workspace_needed()))
+            if fn is not self._rebuild:
+                rs = self._rebuild()
+                if rs != SPH_OK:
+                    st = rs
+                    continue
+            st = fn()
+        if st not in ok:
+            self.ctx.check(st, what)
+        return st
+
+    def _rebuild(self):
+        st = lib().sph_build_cells(self.ctx.h, self.h, C.byref(self._in), C.byref(self.prm))
+        if st == SPH_OK and self._sorted:
+            st = lib().sph_sort_pairs(self.ctx.h, self.h)
+        return st
 
     def sort_pairs(self):
-        self.ctx.check(lib().sph_sort_pairs(self.ctx.h, self.h), "sph_sort_pairs")
+        self._sorted = False
+        self._call(lambda: lib().sph_sort_pairs(self.ctx.h, self.h), "sph_sort_pairs")
+        self._sorted = True
 
     def density(self, out: DensityOut):
         self._dout = out.c()
-        self.ctx.check(lib().sph_density(self.ctx.h, self.h, C.byref(self._dout)), "sph_density")
+        self._call(lambda: lib().sph_density(self.ctx.h, self.h, C.byref(self._dout)), "sph_density")
 
     def solve_h(self, out: DensityOut):
         """Returns (status, n_unconverged, iterations); REBUILD/NOCONV are returned, not raised."""
         self._dout = out.c()
         nu, it = C.c_int32(0), C.c_int32(0)
-        st = lib().sph_solve_h(self.ctx.h, self.h, C.byref(self._dout), C.byref(nu), C.byref(it))
-        if st not in (SPH_OK, SPH_E_REBUILD, SPH_E_NOCONV):
-            self.ctx.check(st, "sph_solve_h")
+        st = self._call(lambda: lib().sph_solve_h(self.ctx.h, self.h, C.byref(self._dout), C.byref(nu),
+                                                  C.byref(it)),
+                        "sph_solve_h", ok=(SPH_OK, SPH_E_REBUILD, SPH_E_NOCONV))
         return st, int(nu.value), int(it.value)
 
     def force(self, out: ForceOut):
         self._fout = out.c()
-        self.ctx.check(lib().sph_force(self.ctx.h, self.h, C.byref(self._fout)), "sph_force")
+        self._call(lambda: lib().sph_force(self.ctx.h, self.h, C.byref(self._fout)), "sph_force")
 
     def run_graph(self, k_iter: int, dout: DensityOut, fout: ForceOut, unconv):
         self._gd, self._gf = dout.c(), fout.c()
-        self.ctx.check(lib().sph_run_graph(self.ctx.h, self.h, int(k_iter), C.byref(self._gd), C.byref(self._gf),
-                                           _ptr(unconv)), "sph_run_graph")
+        self._call(lambda: lib().sph_run_graph(self.ctx.h, self.h, int(k_iter), C.byref(self._gd),
+                                               C.byref(self._gf), _ptr(unconv)), "sph_run_graph")
 
     def stats(self) -> dict:
         v = (C.c_int64 * 10)()

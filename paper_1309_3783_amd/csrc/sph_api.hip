@@ -16,6 +16,12 @@ static sph_status fail(sph_ctx* ctx, const Err& e) {
 // sph_last_error(NULL))
 static thread_local std::string g_create_error;
 
+// Bind a tree to the stream of the call's context.
+static sph_status check_tree(sph_ctx* ctx, sph_tree* t) {
+    t->stream = ctx->stream;
+    return SPH_OK;
+}
+
 extern "C" {
 
 const char* sph_version(void) { return "sphcell 0.1 (gfx950)"; }
@@ -98,16 +104,22 @@ void sph_ctx_destroy(sph_ctx* ctx) {
 
 const char* sph_last_error(const sph_ctx* ctx) { return ctx ? ctx->last_error.c_str() : g_create_error.c_str(); }
 
-sph_status sph_footprint(int64_t n, const sph_params* p, size_t* bytes) {
-    if (!bytes || n < 0) return SPH_E_ARG;
+sph_status sph_workspace_size(int64_t n, int32_t nsets, const sph_params* p, size_t* bytes) {
+    if (!bytes || n < 0 || nsets < 1) return SPH_E_ARG;
     (void)p;
-    // particles: keys x2, vals x2, perm, pos, pv, h, hdec, u, bound, mix,
-    // density (28 B), solve (9 B), force (44 B): ~180 B; sorted lists ~13
-    // entries of 8 B; cells and tasks ~60 B per particle on clustered sets.
-    const double per = 180.0 + 13.0 * 8.0 + 60.0;
-    *bytes = (size_t)(per * (double)n) + ((size_t)64 << 20);
+    // Per particle: 124 B of cell-ordered state (keys and values twice,
+    // permutations, position and remainder, velocity, h, u, bounds, pair-hash
+    // terms), 28 B density, 13 B solve, 52 B force, 41 B saved Newton state,
+    // 16 B of radix and scan scratch: ~275 B.  Sorted lists: 20 B per entry,
+    // 13 entries per particle and tree level that holds pair tasks (~2 levels
+    // of them on clustered sets: 520 B).  Cells, tasks and interaction lists:
+    // ~120 B.  Plus the set tables and a fixed reserve.
+    const double per = 275.0 + 520.0 + 120.0;
+    *bytes = (size_t)(per * (double)n) + (size_t)nsets * 4096 + ((size_t)24 << 20);
     return SPH_OK;
 }
+
+sph_status sph_footprint(int64_t n, const sph_params* p, size_t* bytes) { return sph_workspace_size(n, 1, p, bytes); }
 
 sph_status sph_tree_create(sph_ctx* ctx, sph_tree** out) {
     if (!ctx || !out) return SPH_E_ARG;
@@ -116,7 +128,7 @@ sph_status sph_tree_create(sph_ctx* ctx, sph_tree** out) {
 }
 
 void sph_tree_destroy(sph_ctx* ctx, sph_tree* t) {
-    (void)ctx;
+    if (t && ctx) t->stream = ctx->stream;
     delete t;
 }
 
@@ -126,36 +138,55 @@ sph_status sph_tree_bytes(const sph_tree* t, size_t* bytes) {
     return SPH_OK;
 }
 
+sph_status sph_tree_set_workspace(sph_ctx* ctx, sph_tree* t, void* ws, size_t ws_bytes) {
+    if (!ctx || !t) return SPH_E_ARG;
+    if (ws && ws_bytes < ((size_t)1 << 20)) return fail(ctx, Err{SPH_E_ARG, "a workspace needs at least 1 MiB"});
+    t->stream = ctx->stream;
+    return fail(ctx, t->set_workspace(ws, ws_bytes));
+}
+
+sph_status sph_tree_workspace_needed(const sph_tree* t, size_t* bytes) {
+    if (!t || !bytes) return SPH_E_ARG;
+    *bytes = std::max(t->ws_needed, t->ar.high);
+    return SPH_OK;
+}
+
 sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* p) {
     if (!ctx || !t) return SPH_E_ARG;
+    if (sph_status s = check_tree(ctx, t)) return s;
     if (hipSetDevice(ctx->device) != hipSuccess) return SPH_E_HIP;
     return fail(ctx, sph::build_tree(ctx, t, in, p));
 }
 
 sph_status sph_sort_pairs(sph_ctx* ctx, sph_tree* t) {
     if (!ctx || !t) return SPH_E_ARG;
+    if (sph_status s = check_tree(ctx, t)) return s;
     return fail(ctx, sph::sort_pairs(ctx, t));
 }
 
 sph_status sph_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out) {
     if (!ctx || !t) return SPH_E_ARG;
+    if (sph_status s = check_tree(ctx, t)) return s;
     return fail(ctx, sph::run_density(ctx, t, out));
 }
 
 sph_status sph_solve_h(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_unconverged,
                        int32_t* iterations) {
     if (!ctx || !t) return SPH_E_ARG;
+    if (sph_status s = check_tree(ctx, t)) return s;
     return fail(ctx, sph::run_solve(ctx, t, out, n_unconverged, iterations));
 }
 
 sph_status sph_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
     if (!ctx || !t) return SPH_E_ARG;
+    if (sph_status s = check_tree(ctx, t)) return s;
     return fail(ctx, sph::run_force(ctx, t, out));
 }
 
 sph_status sph_run_graph(sph_ctx* ctx, sph_tree* t, int32_t k_iter, const sph_density_out* dout,
                          const sph_force_out* fout, int32_t* n_unconverged_dev) {
     if (!ctx || !t || k_iter < 1) return SPH_E_ARG;
+    if (sph_status s = check_tree(ctx, t)) return s;
     return fail(ctx, sph::run_graph(ctx, t, k_iter, dout, fout, n_unconverged_dev));
 }
 
@@ -190,10 +221,11 @@ void sph_enable_timing(sph_ctx* ctx, int32_t on) {
 sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap) {
     if (!t || !stats) return SPH_E_ARG;
     if (t->nsegent < 0 && t->d_counts) {
-        // the sort kept its entry count on the device
+        // the sort kept its entry count on the device: read it on the
+        // tree's stream (no device-wide synchronisation)
         uint32_t v = 0;
-        if (hipDeviceSynchronize() != hipSuccess ||
-            hipMemcpy(&v, t->d_counts, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpyAsync(&v, t->d_counts, sizeof(v), hipMemcpyDeviceToHost, t->stream) != hipSuccess ||
+            hipStreamSynchronize(t->stream) != hipSuccess)
             return SPH_E_HIP;
         const_cast<sph_tree*>(t)->nsegent = v;
     }

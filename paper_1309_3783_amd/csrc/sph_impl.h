@@ -3,6 +3,7 @@
 #pragma once
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -34,7 +35,84 @@ struct sph_ctx {
     hipStream_t cap_stream = nullptr; // private stream used only to capture graphs
 };
 
+namespace sph {
+// Sub-allocator over one device region that the caller provides (a tree's
+// workspace): first fit over a free list of 256-byte granules, neighbouring
+// free blocks merged.  Blocks are given back and handed out again in stream
+// order: every call on a tree enqueues its work on the one stream of its
+// context, so a block freed by a call and reused by a later allocation is
+// written only after every earlier use of it has run -- no synchronisation,
+// no hipMalloc, no hipFree.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    std::map<size_t, size_t> free_;   // offset -> size
+    size_t in_use = 0, high = 0;
+
+    static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
+
+    void reset(void* p, size_t bytes) {
+        const size_t a = ((uintptr_t)p + 255) & ~(uintptr_t)255;   // aligned start
+        const size_t skip = a - (uintptr_t)p;
+        base = (char*)a;
+        cap = bytes > skip ? (bytes - skip) & ~(size_t)255 : 0;
+        free_.clear();
+        if (cap) free_[0] = cap;
+        in_use = high = 0;
+    }
+
+    bool take(size_t bytes, size_t* off) {
+        bytes = round(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            in_use += bytes;
+            high = std::max(high, in_use);
+            return true;
+        }
+        return false;
+    }
+
+    void give(size_t off, size_t bytes) {
+        bytes = round(bytes);
+        in_use -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+    size_t largest_free() const {
+        size_t m = 0;
+        for (const auto& f : free_) m = std::max(m, f.second);
+        return m;
+    }
+};
+}  // namespace sph
+
 struct sph_tree {
+    // ---- device memory ---------------------------------------------------
+    // Either a workspace the caller attached (sph_tree_set_workspace: every
+    // buffer is a block of it) or, with none attached, one hipMalloc per
+    // buffer.  stream: the stream of the context of the current call.
+    sph::Arena ar;
+    bool ws = false;
+    size_t ws_needed = 0;        // after SPH_E_WORKSPACE: bytes a larger workspace must offer at least
+    hipStream_t stream = nullptr;
+
     // ---- configuration -------------------------------------------------
     sph_params prm{};
     int nsets = 0;
@@ -126,14 +204,60 @@ struct sph_tree {
                 &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts, &b_iperm};
     }
 
+    // Drop every buffer (the tree must be built again).  Library-owned
+    // buffers are freed once the stream has finished with them.
     void release() {
         invalidate_graph();
         red_off.clear();
+        if (!ws && stream) (void)hipStreamSynchronize(stream);
         for (const sph::DevBuf* d : bufs()) {
             sph::DevBuf* m = const_cast<sph::DevBuf*>(d);
-            if (m->p) (void)hipFree(m->p);
+            if (m->p && !ws) (void)hipFree(m->p);
             m->p = nullptr;
             m->cap = 0;
+        }
+        if (ws) ar.reset(ar.base, ar.cap);
+        built = sorted = have_density = have_ghost = false;
+        saved = false;
+        nsegent = 0;
+    }
+
+    // A new block of at least `bytes` (want: the preferred, larger size).
+    sph::Err take(size_t bytes, size_t want, void** p, size_t* got) {
+        if (ws) {
+            size_t off;
+            if (ar.take(want, &off)) {
+                *got = sph::Arena::round(want);
+            } else if (ar.take(bytes, &off)) {
+                *got = sph::Arena::round(bytes);
+            } else {
+                // what a workspace would need: the blocks in use plus this one
+                ws_needed = std::max(ws_needed, ar.in_use + sph::Arena::round(bytes) + (ar.cap >> 3));
+                return sph::Err{SPH_E_WORKSPACE, "workspace of " + std::to_string(ar.cap) + " bytes exhausted (" +
+                                                     std::to_string(ar.in_use) + " in use, " +
+                                                     std::to_string(bytes) + " more requested)"};
+            }
+            *p = ar.base + off;
+            return sph::Err{};
+        }
+        hipError_t e = hipMalloc(p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return sph::Err{SPH_E_WORKSPACE, "hipMalloc of " + std::to_string(want) + " bytes failed"};
+        }
+        *got = want;
+        return sph::Err{};
+    }
+
+    // Give a block back (stream-ordered reuse in a workspace; a library-owned
+    // one is freed after the stream has finished with it).
+    void give(void* p, size_t cap) {
+        if (!p) return;
+        if (ws) {
+            ar.give((size_t)((char*)p - ar.base), cap);
+        } else {
+            if (stream) (void)hipStreamSynchronize(stream);
+            (void)hipFree(p);
         }
     }
 
@@ -141,53 +265,55 @@ struct sph_tree {
     sph::Err alloc(sph::DevBuf& b, size_t bytes, void** out) {
         bytes = std::max<size_t>(bytes, 256);
         if (b.cap < bytes) {
-            if (b.p) {
-                (void)hipDeviceSynchronize();
-                (void)hipFree(b.p);
-                b.p = nullptr;
-                b.cap = 0;
-            }
-            size_t want = bytes + bytes / 8;
-            hipError_t e = hipMalloc(&b.p, want);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return sph::Err{SPH_E_WORKSPACE, "hipMalloc of " + std::to_string(want) + " bytes failed"};
-            }
-            b.cap = want;
+            give(b.p, b.cap);
+            b.p = nullptr;
+            b.cap = 0;
+            size_t got = 0;
+            sph::Err e = take(bytes, bytes + bytes / 8, &b.p, &got);
+            if (e.st) return e;
+            b.cap = got;
         }
         *out = b.p;
         return sph::Err{};
     }
 
-    // grow keeping the first `keep` bytes
+    // grow keeping the first `keep` bytes (copied on the stream)
     sph::Err grow(sph::DevBuf& b, size_t keep, size_t bytes, void** out) {
         if (b.cap >= bytes) { *out = b.p; return sph::Err{}; }
         void* np = nullptr;
-        size_t want = bytes + bytes / 4;
-        hipError_t e = hipMalloc(&np, want);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return sph::Err{SPH_E_WORKSPACE, "hipMalloc of " + std::to_string(want) + " bytes failed"};
-        }
-        (void)hipDeviceSynchronize();
+        size_t got = 0;
+        sph::Err er = take(bytes, bytes + bytes / 4, &np, &got);
+        if (er.st) return er;
         if (keep && b.p) {
-            e = hipMemcpy(np, b.p, keep, hipMemcpyDeviceToDevice);
-            if (e != hipSuccess) { (void)hipFree(np); return sph::Err{SPH_E_HIP, "grow copy failed"}; }
+            hipError_t e = hipMemcpyAsync(np, b.p, keep, hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) {
+                give(np, got);
+                return sph::Err{SPH_E_HIP, "grow copy failed"};
+            }
         }
-        if (b.p) (void)hipFree(b.p);
+        give(b.p, b.cap);
         b.p = np;
-        b.cap = want;
+        b.cap = got;
         *out = np;
         return sph::Err{};
     }
 
     sph::SolveState saved_state() const { return sv; }
 
+    static size_t saved_bytes(int64_t m) {
+        return (size_t)m * (1 + 7 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 256;
+    }
+
     sph::Err ensure_saved() {
         const int64_t m = std::max<int64_t>(n, 1);
         void* p;
-        sph::Err e = alloc(b_saved, (size_t)m * (1 + 7 * sizeof(float) + sizeof(int32_t) + sizeof(uint64_t)) + 256, &p);
+        sph::Err e = alloc(b_saved, saved_bytes(m), &p);
         if (e.st) return e;
+        layout_saved(p, m);
+        return sph::Err{};
+    }
+
+    void layout_saved(void* p, int64_t m) {
         sv.hash = (uint64_t*)p;
         sv.lo = (float*)(sv.hash + m);
         sv.hi = sv.lo + m;
@@ -198,7 +324,42 @@ struct sph_tree {
         sv.dnw = sv.nw + m;
         sv.nngb = (int32_t*)(sv.dnw + m);
         sv.active = (uint8_t*)(sv.nngb + m);
-        return sph::Err{};
+    }
+
+    // Attach a caller-provided workspace (null: go back to one hipMalloc per
+    // buffer).  Every buffer is dropped -- the tree must be built again --
+    // except the Newton state a solve saved for a rebuild, which is copied
+    // into the new memory on the stream (the old memory must stay valid
+    // until the stream has run the copy).
+    sph::Err set_workspace(void* p, size_t bytes) {
+        sph::DevBuf keep = b_saved;
+        const bool had = saved;
+        const int64_t sn = saved_n;
+        const bool old_ws = ws;
+        b_saved = sph::DevBuf{};
+        release();
+        ws = p != nullptr;
+        if (ws) ar.reset(p, bytes);
+        else ar = sph::Arena{};
+        ws_needed = 0;
+        sph::Err e{};
+        if (had && keep.p) {
+            const int64_t m = std::max<int64_t>(sn, 1);
+            void* np = nullptr;
+            e = alloc(b_saved, saved_bytes(m), &np);
+            if (!e.st) {
+                if (hipMemcpyAsync(np, keep.p, saved_bytes(m), hipMemcpyDeviceToDevice, stream) != hipSuccess)
+                    e = sph::Err{SPH_E_HIP, "copy of the saved Newton state failed"};
+                layout_saved(np, m);
+                saved = e.st == SPH_OK;
+                saved_n = sn;
+            }
+        }
+        if (!old_ws && keep.p) {
+            if (stream) (void)hipStreamSynchronize(stream);
+            (void)hipFree(keep.p);
+        }
+        return e;
     }
 
     // four uint32 scratch arrays of n entries plus scan scratch and counters

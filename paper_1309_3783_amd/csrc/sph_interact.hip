@@ -185,34 +185,6 @@ __device__ __forceinline__ float wave_max_dpp(float v) {
     return __int_as_float(m ^ ((m >> 31) & 0x7FFFFFFF));
 }
 
-// Offset code tables: axis index and sign of each of the 27 offset codes,
-// and the components of the 13 canonical directions.
-struct AxisTab {
-    int8_t axis[27], sign[27];
-    int8_t dx[13], dy[13], dz[13];
-    float norm[13];
-};
-
-__constant__ AxisTab c_ax;
-
-static AxisTab make_axis_table() {
-    AxisTab t{};
-    for (int c = 0; c < 27; ++c) {
-        int sg = 1;
-        int k = axis_of(c, &sg);
-        t.axis[c] = (int8_t)k;
-        t.sign[c] = (int8_t)sg;
-    }
-    for (int k = 0; k < 13; ++k) {
-        int c = axis_code(k);
-        t.dx[k] = (int8_t)ocx(c);
-        t.dy[k] = (int8_t)ocy(c);
-        t.dz[k] = (int8_t)ocz(c);
-        t.norm[k] = sqrtf((float)(abs(ocx(c)) + abs(ocy(c)) + abs(ocz(c))));
-    }
-    return t;
-}
-
 // Geometry of one pair entry seen from target cell A: shift S added to the
 // partner's stored positions, axis, sign, and the partner's projection offset.
 struct PairGeo {
@@ -1398,16 +1370,6 @@ static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) 
         if (e_.st != SPH_OK) return e_; \
     } while (0)
 
-static bool g_axis_ready[64] = {false};
-
-static Err ensure_axis_table(sph_ctx* ctx) {
-    if (ctx->device >= 0 && ctx->device < 64 && g_axis_ready[ctx->device]) return Err{};
-    AxisTab t = make_axis_table();
-    HIPTRY(hipMemcpyToSymbol(HIP_SYMBOL(c_ax), &t, sizeof(t)));
-    if (ctx->device >= 0 && ctx->device < 64) g_axis_ready[ctx->device] = true;
-    return Err{};
-}
-
 static Err ensure_state(sph_tree* t) {
     const int64_t n = std::max<int64_t>(t->n, 1);
     void* p;
@@ -1460,7 +1422,8 @@ static Err ensure_state(sph_tree* t) {
         t->sums_int = t->partial + t->nred * NRED;
         t->d_red = (int4*)(t->sums_int + (int64_t)t->nsets * NRED);
         t->part_cnt = (int32_t*)(t->d_red + t->nred);
-        HIPTRY(hipMemcpy(t->d_red, t->red_chunks.data(), sizeof(int4) * t->nred, hipMemcpyHostToDevice));
+        HIPTRY(hipMemcpyAsync(t->d_red, t->red_chunks.data(), sizeof(int4) * t->nred, hipMemcpyHostToDevice,
+                              t->stream));
         t->red_off = t->off;
     }
     return Err{};
@@ -1615,7 +1578,6 @@ static void launch_scatter_force(sph_ctx* ctx, sph_tree* t, const sph_force_out*
 Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out) {
     if (!t->built || !t->sorted) return Err{SPH_E_STATE, "density before build_cells/sort_pairs"};
     if (out && out->hash && !t->hash) return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
-    ERRTRY(ensure_axis_table(ctx));
     ERRTRY(ensure_state(t));
     if (t->n == 0) return Err{};
     ev_mark(ctx, "start");
@@ -1633,7 +1595,6 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     if (out && out->hash && !t->hash) return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
     if (t->prm.max_iter < 1 || !(t->prm.h_tol > 0.f) || !(t->prm.n_target > 0.f))
         return Err{SPH_E_ARG, "bad solve parameters"};
-    ERRTRY(ensure_axis_table(ctx));
     ERRTRY(ensure_state(t));
     hipStream_t st = ctx->stream;
     const int64_t n = t->n;
@@ -1695,7 +1656,6 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
 Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
     if (!t->have_density) return Err{SPH_E_STATE, "force before a density pass at the current h"};
     if (out && out->hash && !t->hash) return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
-    ERRTRY(ensure_axis_table(ctx));
     ERRTRY(ensure_state(t));
     if (t->n == 0) return Err{};
     ev_mark(ctx, "start");
@@ -1733,7 +1693,6 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
     if (!n_unconv_dev) return Err{SPH_E_ARG, "null n_unconverged_dev"};
     if (((dout && dout->hash) || (fout && fout->hash)) && !t->hash)
         return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
-    ERRTRY(ensure_axis_table(ctx));
     ERRTRY(ensure_state(t));
     if (t->n == 0) return Err{};
     std::vector<const void*> key;

@@ -74,3 +74,17 @@ def test_context_creation_failure_is_explained():
     assert (st == binding.SPH_E_HIP and msg.startswith("hipGetDeviceCount")) or \
         (st == binding.SPH_E_ARG and "out of range" in msg)
     assert not h.value
+
+
+def test_workspace_size_host_only():
+    L = sph.lib()
+    b1 = sph.workspace_size(1_000_000, 1)
+    b8 = sph.workspace_size(8_000_000, 1)
+    assert b8 > 7 * (b1 - (32 << 20))          # grows with n
+    assert sph.workspace_size(1000, 256) > sph.workspace_size(1000, 1)   # and with the set count
+    assert sph.footprint(12345) == sph.workspace_size(12345, 1)
+    out = C.c_size_t(0)
+    assert L.sph_workspace_size(-1, 1, None, C.byref(out)) == binding.SPH_E_ARG
+    assert L.sph_workspace_size(10, 0, None, C.byref(out)) == binding.SPH_E_ARG
+    assert L.sph_tree_set_workspace(None, None, None, 0) == binding.SPH_E_ARG
+    assert L.sph_tree_workspace_needed(None, C.byref(out)) == binding.SPH_E_ARG
