@@ -194,6 +194,22 @@ sph_status sph_tree_workspace_needed(const sph_tree* t, size_t* bytes);
  * SPH_E_CAPACITY (key layout or table limits), SPH_E_WORKSPACE, SPH_E_HIP. */
 sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* p);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): sph_build_cells
+ * with the library's static scratch as the tree's workspace -- a file-scope
+ * device array of 128 MiB per GPU, held until the process ends -- so that
+ * neither this call nor the later calls on the tree (sort, density, solve,
+ * force) allocate.  Sets needing more than the scratch holds
+ * (sph_workspace_size above 128 MiB, roughly 140 000 particles) are refused
+ * with SPH_E_CAPACITY; a build that still runs out fails with
+ * SPH_E_WORKSPACE.  One tree per GPU can hold the scratch: the calls of a
+ * tree that held it before another tree took it fail with SPH_E_STATE (build
+ * it again), and calls on two such trees, or on one from two streams, that
+ * overlap on the device race.  A repeated call on the tree that holds the
+ * scratch keeps its blocks.  Errors as sph_build_cells, plus SPH_E_STATE when
+ * the device has no static scratch (no context was created on it). */
+sph_status sph_build_cells_static(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* p);
+
 /* Section II-C (sorted cell pair interactions): for every cell that is the
  * source side of a pair task, the particle indices sorted by their
  * projection on the task's cell-pair axis (one of 13 directions), stored per

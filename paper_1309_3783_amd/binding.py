@@ -24,7 +24,7 @@ SPH_FLAG_RESUME = 2
 EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
            "sph_last_error", "sph_workspace_size", "sph_footprint", "sph_tree_create", "sph_tree_destroy",
            "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
-           "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
+           "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
            "sph_last_timings", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
 
 
@@ -80,6 +80,7 @@ def lib():
         L.sph_workspace_size.argtypes = [C.c_int64, C.c_int32, C.POINTER(sph_params), C.POINTER(C.c_size_t)]
         L.sph_tree_set_workspace.argtypes = [vp, vp, vp, C.c_size_t]
         L.sph_tree_workspace_needed.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.sph_build_cells_static.argtypes = [vp, vp, C.POINTER(sph_input), C.POINTER(sph_params)]
         L.sph_tree_create.argtypes = [vp, C.POINTER(vp)]
         L.sph_tree_destroy.argtypes = [vp, vp]
         L.sph_tree_destroy.restype = None
@@ -102,7 +103,7 @@ def lib():
         L.sph_cfl_dt.argtypes = [vp, C.c_int64, vp, vp, C.c_float, C.POINTER(C.c_double)]
         for name in ("sph_ctx_create", "sph_footprint", "sph_workspace_size", "sph_tree_create", "sph_tree_bytes",
                      "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
-                     "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force",
+                     "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force",
                      "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"):
             getattr(L, name).restype = st
         _lib = L
@@ -358,6 +359,15 @@ class Tree:
         if st == SPH_OK and self._sorted:
             st = lib().sph_sort_pairs(self.ctx.h, self.h)
         return st
+
+    def build_cells_static(self, batch: Batch, prm: sph_params | None = None, h=None):
+        """sph_build_cells with the library's static scratch as workspace
+        (no allocation in this or the later calls on the tree)."""
+        self.batch = batch
+        self.prm = prm or params()
+        self._in = batch.as_input(h)
+        self.ctx.check(lib().sph_build_cells_static(self.ctx.h, self.h, C.byref(self._in), C.byref(self.prm)),
+                       "sph_build_cells_static")
 
     def sort_pairs(self):
         self._sorted = False

@@ -2,6 +2,7 @@
 // error codes and the context; the work itself is in sph_build.hip and
 // sph_interact.hip.
 #include <cstring>
+#include <mutex>
 
 #include "sph_impl.h"
 
@@ -16,8 +17,33 @@ static sph_status fail(sph_ctx* ctx, const Err& e) {
 // sph_last_error(NULL))
 static thread_local std::string g_create_error;
 
-// Bind a tree to the stream of the call's context.
+// ---------------------------------------------------------------------------
+// The library's static scratch: the workspace of trees built through
+// sph_build_cells_static, for callers that cannot allocate device memory.
+// Each GPU the library runs on holds its own copy (STATIC_SCRATCH_BYTES)
+// until the process ends.  In host code `scratch` is only a stand-in for the
+// device array: its device address is taken once per device, when the first
+// context on that device is created (g_scratch_ptr), and only that address is
+// ever handed to kernels or copies.  One tree per device can use it at a
+// time: attaching it to a tree (a new generation) retires the tree that held
+// it before, whose later calls fail with SPH_E_STATE.
+// ---------------------------------------------------------------------------
+static constexpr size_t STATIC_SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+static constexpr int MAX_DEVICES = 64;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+static int g_scratch_gen[MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// Calls on a tree that held the static scratch fail once another tree took it.
 static sph_status check_tree(sph_ctx* ctx, sph_tree* t) {
+    if (t->static_gen) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (ctx->device < 0 || ctx->device >= MAX_DEVICES || g_scratch_gen[ctx->device] != t->static_gen) {
+            ctx->last_error = "this tree's static scratch was taken by a later sph_build_cells_static: build again";
+            return SPH_E_STATE;
+        }
+    }
     t->stream = ctx->stream;
     return SPH_OK;
 }
@@ -73,6 +99,20 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
     if (e != hipSuccess) {
         g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
         return SPH_E_HIP;
+    }
+    if (device < MAX_DEVICES) {
+        // the device address of this device's static scratch, once per device
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                g_create_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+                return SPH_E_HIP;
+            }
+            g_scratch_ptr[device] = p;
+        }
     }
     sph_ctx* c = new sph_ctx();
     c->device = device;
@@ -141,8 +181,8 @@ sph_status sph_tree_bytes(const sph_tree* t, size_t* bytes) {
 sph_status sph_tree_set_workspace(sph_ctx* ctx, sph_tree* t, void* ws, size_t ws_bytes) {
     if (!ctx || !t) return SPH_E_ARG;
     if (ws && ws_bytes < ((size_t)1 << 20)) return fail(ctx, Err{SPH_E_ARG, "a workspace needs at least 1 MiB"});
-    t->stream = ctx->stream;
-    return fail(ctx, t->set_workspace(ws, ws_bytes));
+    t->stream = ctx->stream;   // (a tree leaving the static scratch needs no check)
+    return fail(ctx, t->set_workspace(ws, ws_bytes, 0));
 }
 
 sph_status sph_tree_workspace_needed(const sph_tree* t, size_t* bytes) {
@@ -155,6 +195,33 @@ sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const
     if (!ctx || !t) return SPH_E_ARG;
     if (sph_status s = check_tree(ctx, t)) return s;
     if (hipSetDevice(ctx->device) != hipSuccess) return SPH_E_HIP;
+    return fail(ctx, sph::build_tree(ctx, t, in, p));
+}
+
+sph_status sph_build_cells_static(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* p) {
+    if (!ctx || !t || !in || !p || !in->offsets || in->nsets < 1) return SPH_E_ARG;
+    if (ctx->device < 0 || ctx->device >= MAX_DEVICES || !g_scratch_ptr[ctx->device])
+        return fail(ctx, Err{SPH_E_STATE, "no static scratch on this device"});
+    const int64_t n = in->offsets[in->nsets];
+    size_t need = 0;
+    if (sph_workspace_size(n, in->nsets, p, &need) != SPH_OK) return SPH_E_ARG;
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(ctx, Err{SPH_E_CAPACITY, std::to_string(n) + " particles need about " + std::to_string(need >> 20) +
+                                                 " MiB; the static scratch holds " +
+                                                 std::to_string(STATIC_SCRATCH_BYTES >> 20) + " MiB"});
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPH_E_HIP;
+    t->stream = ctx->stream;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        const int dev = ctx->device;
+        // a tree that holds the current generation keeps its blocks;
+        // otherwise the scratch is taken over (a new generation)
+        if (!(t->static_gen && t->static_gen == g_scratch_gen[dev])) {
+            const int gen = ++g_scratch_gen[dev];
+            Err e = t->set_workspace(g_scratch_ptr[dev], STATIC_SCRATCH_BYTES, gen);
+            if (e.st) return fail(ctx, e);
+        }
+    }
     return fail(ctx, sph::build_tree(ctx, t, in, p));
 }
 

@@ -110,6 +110,7 @@ struct sph_tree {
     // buffer.  stream: the stream of the context of the current call.
     sph::Arena ar;
     bool ws = false;
+    int static_gen = 0;          // > 0: the workspace is the library's static scratch (this generation)
     size_t ws_needed = 0;        // after SPH_E_WORKSPACE: bytes a larger workspace must offer at least
     hipStream_t stream = nullptr;
 
@@ -331,7 +332,7 @@ struct sph_tree {
     // except the Newton state a solve saved for a rebuild, which is copied
     // into the new memory on the stream (the old memory must stay valid
     // until the stream has run the copy).
-    sph::Err set_workspace(void* p, size_t bytes) {
+    sph::Err set_workspace(void* p, size_t bytes, int gen) {
         sph::DevBuf keep = b_saved;
         const bool had = saved;
         const int64_t sn = saved_n;
@@ -341,6 +342,7 @@ struct sph_tree {
         ws = p != nullptr;
         if (ws) ar.reset(p, bytes);
         else ar = sph::Arena{};
+        static_gen = gen;
         ws_needed = 0;
         sph::Err e{};
         if (had && keep.p) {

@@ -88,3 +88,4 @@ def test_workspace_size_host_only():
     assert L.sph_workspace_size(10, 0, None, C.byref(out)) == binding.SPH_E_ARG
     assert L.sph_tree_set_workspace(None, None, None, 0) == binding.SPH_E_ARG
     assert L.sph_tree_workspace_needed(None, C.byref(out)) == binding.SPH_E_ARG
+    assert L.sph_build_cells_static(None, None, None, None) == binding.SPH_E_ARG
