@@ -8,19 +8,30 @@ h (one density and one force interaction each).
 
 Default workload: 1,000,000 particles on a 100^3 lattice jittered by
 U(+-0.1) spacings (seed 2), h solved by Newton to 48 +- 0.5.
-The same line carries the batched comparison (256 uneven sets in one build
-and one HIP graph, autotuned, vs the plain one-set-at-a-time loop) and the
-served Poisson stream (p50/p99 latency).  --config multires times the 8M
-clumpy set instead; --config sod / sedov time leapfrog time steps of the
-paper's shock tube / blast (each step: three kicks, a drift, build, sort, h
-solve, force, the Courant step).  Prints ONE JSON line.
+The same line carries the multi-resolution workload (8,000,000 particles,
+64 Plummer clumps + 20% background, h over ~3 decades: the stand-in for the
+paper's cosmological volume), the batched comparison (256 uneven sets in one
+build and one HIP graph, autotuned, vs the plain one-set-at-a-time loop) and
+the served Poisson stream (p50/p99 latency).  --config multires times only
+the 8M clumpy set; --config sod / sedov time leapfrog time steps of the
+paper's shock tube / blast.  Prints ONE JSON line.
+
+Roofline accounting (the interaction kernels are bound by vector ALU work):
+algorithmic lane-ops per unordered pair, frozen: density 70, force 125
+(one evaluation per unordered pair with compensated accumulators; sqrt
+counted as 4), against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12
+FP32 lane-ops/s.  The pairs a launch processes are counted on the device
+(sph_last_work: the neighbour counts of the particles each pass evaluated,
+halved: an unordered pair is seen from both sides).  The decomposition and
+the sorts are priced against HBM: 250 B per particle for the build (keys,
+six radix passes, the cell-ordered gather) and 40 B per sorted-list entry
+(position and h read, a 20 B record written).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -32,12 +43,11 @@ sys.path.insert(0, ROOT)
 
 VALU_PEAK = 256 * 4 * 16 * 2.4e9     # FP32 lane-ops/s, non-packed (39.3e12)
 HBM_PEAK = 8.0e12
-# algorithmic VALU lane-ops per unordered interacting pair (both sides, one
-# distance test each, no compensation terms): see the design notes
-OPS_DENSITY = 52.0
-OPS_FORCE = 118.0
-# Newton passes captured in the batched/served graphs
-K_ITER = 24
+OPS_DENSITY = 70.0                   # lane-ops per unordered pair (frozen op table)
+OPS_FORCE = 125.0
+BUILD_BYTES_PER_PARTICLE = 250.0
+SORT_BYTES_PER_ENTRY = 40.0
+K_ITER = 24                          # Newton passes captured in the batched/served graphs
 
 
 def log(*a):
@@ -48,12 +58,12 @@ def make_workload(name):
     import sphinputs
     if name == "plain":
         ps = sphinputs.lattice(100, 0.1, 2)
-        return [ps], {"workload": "jittered_lattice_1M", "n": ps.n, "lattice": "100^3", "jitter": 0.1,
-                      "seed": 2, "h": "Newton to N_w = 48 +- 0.5", "box": "periodic unit cube"}
+        return ps, {"workload": "jittered_lattice_1M", "n": ps.n, "lattice": "100^3", "jitter": 0.1,
+                    "seed": 2, "h": "Newton to N_w = 48 +- 0.5", "box": "periodic unit cube"}
     if name == "multires":
         ps = sphinputs.plummer_mixture(8_000_000, 3)
-        return [ps], {"workload": "plummer_mixture_8M", "n": ps.n, "clumps": 64, "bg_frac": 0.2, "seed": 3,
-                      "h": "Newton to N_w = 48 +- 0.5"}
+        return ps, {"workload": "plummer_mixture_8M", "n": ps.n, "clumps": 64, "bg_frac": 0.2, "seed": 3,
+                    "h": "Newton to N_w = 48 +- 0.5", "box": "periodic unit cube"}
     raise SystemExit(f"unknown config {name}")
 
 
@@ -82,20 +92,32 @@ def measured_traffic(kernel, workload):
         d = json.load(open(p))
     except Exception:
         return None
-    e = d.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash() or d.get("workload") != workload:
+    e = d.get("workloads", {}).get(workload, {}).get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(sets, budget_s=15.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ps, gpu_h, gpu_nforce, budget_s=15.0, check_max=20000):
     """The FP64 oracle on this host, on a random sample of target particles
     of the same set: h solve, density and force for the targets (the other
     particles keep their first-guess h and the density at it, computed
     untimed beforehand).  Rate = sum over targets of their force neighbours
-    (each target's share of 2P) / timed seconds."""
+    (each target's share of 2 P) / timed seconds.  Untimed afterwards, the
+    numerator the GPU line uses is checked on a sample of targets: the
+    oracle's force-neighbour counts at the GPU's solved h against the GPU's
+    (targets with a pair within 1e-6 of a cutoff at that h left out)."""
     import oracle
-    ps = sets[0]
     rng = np.random.default_rng(0)
     ncores = oracle.num_threads()
     t_prep = time.perf_counter()
@@ -117,33 +139,36 @@ def cpu_baseline(sets, budget_s=15.0):
         if dt >= 0.5 * budget_s or k >= ps.n:
             break
         k = min(ps.n, int(k * min(16.0, max(2.0, budget_s / max(dt, 1e-3)))))
+    # the numerator: force-neighbour counts at the GPU's h, oracle vs GPU
+    hg = np.asarray(gpu_h, dtype=np.float32).astype(np.float64)
+    tc = np.sort(rng.choice(ps.n, size=min(check_max, ps.n), replace=False))
+    nc = oracle.force_neighbours(ps.x, ps.y, ps.z, hg, tc, ps.box)
+    nb = np.nonzero(nc)[0]
+    dc = oracle.density(ps.x, ps.y, ps.z, hg, ps.m, ps.box, targets=nb)
+    fc = oracle.force(ps.x, ps.y, ps.z, hg, ps.m, ps.vx, ps.vy, ps.vz, ps.u, dc["rho"], dc["drho_dh"], ps.box,
+                      targets=tc)
+    tie = oracle.near_cutoff(ps.x, ps.y, ps.z, hg, ps.box, targets=tc)[tc]
+    keep = tc[~tie]
+    equal = bool(np.array_equal(np.asarray(gpu_nforce)[keep], fc["nforce"][keep]))
     return {"value": pairs / dt, "unit": "pair interactions/s", "cores": ncores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{k} random targets of the same {ps.n}-particle set: FP64 h solve + density + force "
                       f"for the targets ({dt:.1f} s); other particles at their first-guess h with density "
-                      f"from an untimed pass ({t_prep:.1f} s)"}
+                      f"from an untimed pass ({t_prep:.1f} s)",
+            "pairs_check": {"targets": int(keep.size), "excluded_near_cutoff": int(tie.sum()),
+                            "nforce_equal_to_oracle": equal}}
 
 
-def run(args):
+def measure(sph, ps, steps, warmup, prm):
+    """K timed steps of the whole path on one set; per-step device times,
+    stage times and the work the interaction kernels did."""
     import torch
-    import paper_1309_3783_amd as sph
-
-    sets, cfg = make_workload(args.config)
-    log(f"[bench] workload {cfg}")
-    dev = "cuda"
     ctx = sph.Context(0)
-    stream = ctx.stream
-    batch = sph.batch_from_sets(sets, device=dev)
-    prm = sph.params(**({"h_slack": args.slack} if args.slack is not None else {}))
+    batch = sph.batch_from_sets([ps])
     n = batch.n
-    dout = sph.DensityOut(n, dev)
-    fout = sph.ForceOut(n, batch.nsets, dev)
+    dout = sph.DensityOut(n, "cuda")
+    fout = sph.ForceOut(n, 1, "cuda")
     tree = sph.Tree(ctx)
-
-    stage = {}
-
-    def record():
-        for name, ms in ctx.timings():
-            stage.setdefault(name, []).append(ms)
 
     def step():
         st, nu, it = sph.solve_with_rebuild(tree, batch, prm, dout)
@@ -152,66 +177,155 @@ def run(args):
         tree.force(fout)
         return it, nu
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         it, nu = step()
         torch.cuda.synchronize()
         log(f"[bench] warmup {w}: newton iterations {it}, unconverged {nu}")
     ctx.enable_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
+        ev[k][0].record(ctx.stream)
         it, nu = step()
+        ev[k][1].record(ctx.stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.enable_timing(False)
-    # stage events of the timed steps (recorded on the context stream,
-    # read once after the loop)
-    record()
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    stage = {}
+    for name, ms in ctx.timings():
+        stage.setdefault(name, []).append(ms)
+    # the work of the last step (every step repeats the same computation)
+    wd, wf = ctx.work()
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     sums = fout.sums.view(-1, 8).cpu().numpy()
-    P = float(sums[:, 6].sum()) / 2.0
-    value = 2.0 * P / (ms_step / 1e3)
-    st = tree.stats()
-    force_ms = float(np.mean(stage.get("force", [float("nan")])))
-    dens_ms = float(np.mean(stage.get("solve", [float("nan")])))
-    log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, P = {P:.4g}, stages {{"
-        + ", ".join(f"{k}: {np.mean(v):.3f}" for k, v in stage.items()) + "}")
-    log(f"[bench] tree {st}")
-    log(f"[bench] newton iterations {it} (incl. rebuilds)")
+    return {"ms_per_step": (t1 - t0) * 1e3 / steps, "step_ms": step_ms, "stage": stage,
+            "P": float(sums[:, 6].sum()) / 2.0, "work_density": wd, "work_force": wf,
+            "it": it, "nu": nu, "tree": tree.stats(), "dout": dout, "fout": fout,
+            "ws_bytes": int(tree.ws.numel()) if tree.ws is not None else None,
+            "ws_peak": tree.workspace_needed()}
 
-    ach = P * OPS_FORCE / (force_ms / 1e3)
-    traffic = measured_traffic("k_force", cfg["workload"])
-    roof = {"kernel": "k_force", "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "Tlane-op/s", "frac": ach / VALU_PEAK, "traffic": traffic,
-            "launch_ms": force_ms, "ops_per_pair": OPS_FORCE, "pairs_per_launch": P}
-    # the HBM side: the kernel's measured bytes per launch against the peak
-    # and against what a plain device copy reaches on this GPU
+
+def rooflines(m, steps, workload):
+    """VALU roofline of both interaction kernels, and the HBM fractions of the
+    build and sort stages, from one measurement."""
+    st = m["stage"]
+    dens = st.get("density_pass", [])
+    force = st.get("force", [])
+    out = {}
+    for name, times, work, ops in (("k_density", dens, m["work_density"], OPS_DENSITY),
+                                   ("k_force", force, m["work_force"], OPS_FORCE)):
+        if not times:
+            continue
+        launches = len(times) / steps
+        t_step = float(np.sum(times)) / steps            # ms of this kernel per step
+        units = work / 2.0                               # unordered-pair units per step
+        ach = units * ops / (t_step / 1e3)
+        traffic = measured_traffic(name, workload)
+        out[name] = {"kernel": name, "bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "Tlane-op/s", "frac": ach / VALU_PEAK, "traffic": traffic,
+                     "launch_ms": t_step / launches, "launches_per_step": launches, "ms_per_step": t_step,
+                     "ops_per_pair": ops, "pairs_per_launch": units / launches}
+        if traffic:
+            bps = traffic / (t_step / launches / 1e3)
+            out[name]["hbm"] = {"TBps": bps / 1e12, "frac_of_peak": bps / HBM_PEAK}
+    n = m["tree"]["particles"]
+    ent = m["tree"]["sorted_entries"]
+    stages = {}
+    for name, per in (("build", BUILD_BYTES_PER_PARTICLE * n), ("sort", SORT_BYTES_PER_ENTRY * ent)):
+        if name in st:
+            t = float(np.mean(st[name])) / 1e3
+            stages[name] = {"bound": "hbm", "algorithmic_bytes": per, "ms": t * 1e3,
+                            "achieved_TBps": per / t / 1e12, "peak_TBps": HBM_PEAK / 1e12,
+                            "frac": per / t / HBM_PEAK}
+    return out, stages
+
+
+def summarize(m, steps):
+    step_ms = m["step_ms"]
+    return {"ms_per_step": m["ms_per_step"], "step_ms_p50": float(np.percentile(step_ms, 50)),
+            "step_ms_p99": float(np.percentile(step_ms, 99)), "pairs_P": m["P"],
+            "value": 2.0 * m["P"] / (m["ms_per_step"] / 1e3),
+            "newton_iterations": m["it"], "unconverged": m["nu"],
+            "stages_ms": {k: float(np.sum(v)) / steps for k, v in m["stage"].items() if k != "start"},
+            "tree": m["tree"], "workspace_bytes": m["ws_bytes"], "workspace_peak_bytes": m["ws_peak"]}
+
+
+def run(args):
+    import paper_1309_3783_amd as sph
+
+    ps, cfg = make_workload(args.config)
+    log(f"[bench] workload {cfg}")
+    prm = sph.params(**({"h_slack": args.slack} if args.slack is not None else {}))
+    m = measure(sph, ps, args.steps, args.warmup, prm)
+    s = summarize(m, args.steps)
+    rl, stages = rooflines(m, args.steps, cfg["workload"])
+    log(f"[bench] {args.steps} steps: {s['ms_per_step']:.2f} ms/step (p50 {s['step_ms_p50']:.2f}, "
+        f"p99 {s['step_ms_p99']:.2f}), P = {s['pairs_P']:.4g}, stages "
+        + ", ".join(f"{k}: {v:.3f}" for k, v in s["stages_ms"].items()))
+    for k, r in rl.items():
+        log(f"[bench] {k}: {r['launch_ms']:.3f} ms/launch x {r['launches_per_step']:.1f}, "
+            f"{r['achieved']:.2f} Tlane-op/s = {100 * r['frac']:.1f}% of VALU peak")
+    log(f"[bench] tree {s['tree']}")
+    # the dominant interaction kernel of a step carries the roofline object
+    dom = max(rl.values(), key=lambda r: r["ms_per_step"])
+    roof = dict(dom)
     copy_tbs = copy_bandwidth()
-    roof["hbm"] = {"copy_TBps": copy_tbs, "peak_TBps": HBM_PEAK / 1e12,
-                   "k_force_TBps": traffic / (force_ms / 1e3) / 1e12 if traffic else None}
-    if traffic:
-        roof["hbm"]["frac_of_peak"] = roof["hbm"]["k_force_TBps"] * 1e12 / HBM_PEAK
-        roof["hbm"]["frac_of_copy"] = roof["hbm"]["k_force_TBps"] / copy_tbs
+    roof["hbm_copy_TBps"] = copy_tbs
     out = {"metric": "pair interactions/sec (density+force), batched vs plain; p50/p99 latency",
-           "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "value": s["value"], "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": s["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": cfg,
-           "kernel_pairs_per_s": 2.0 * P / ((force_ms + dens_ms) / 1e3),
-           "pairs_P": P, "newton_iterations": it, "unconverged": nu,
-           "stages_ms": {k: float(np.mean(v)) for k, v in stage.items()},
-           "tree": st, "roofline": roof}
-    if args.config == "plain" and not args.quick:
-        out["batched"] = bench_batched(sph)
-        log(f"[bench] batched {out['batched']['value']:.3g} pairs/s vs plain loop "
-            f"{out['batched']['plain_loop']['value']:.3g}")
-        out["served"] = bench_served(sph)
-        log(f"[bench] served p50 {out['served']['p50_ms']:.2f} ms p99 {out['served']['p99_ms']:.2f} ms")
-    if not args.skip_cpu and args.config == "plain":
+           "step_ms_p50": s["step_ms_p50"], "step_ms_p99": s["step_ms_p99"],
+           "kernel_pairs_per_s": 2.0 * s["pairs_P"] / (sum(r["ms_per_step"] for r in rl.values()) / 1e3),
+           "pairs_P": s["pairs_P"], "newton_iterations": s["newton_iterations"], "unconverged": s["unconverged"],
+           "stages_ms": s["stages_ms"], "tree": s["tree"], "workspace_bytes": s["workspace_bytes"],
+           "workspace_peak_bytes": s["workspace_peak_bytes"], "roofline": roof, "rooflines": rl,
+           "stage_hbm": stages}
+    if not args.skip_cpu:
         log("[bench] timing the FP64 oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(sets, budget_s=args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(ps, m["dout"].h.cpu().numpy(), m["fout"].nforce.cpu().numpy(),
+                                           budget_s=args.cpu_budget)
+        log(f"[bench] oracle {out['cpu_baseline']['value']:.3g} pairs/s on {out['cpu_baseline']['cores']} cores, "
+            f"pair counts equal: {out['cpu_baseline']['pairs_check']}")
     else:
         out["cpu_baseline"] = None
+    del m
+    if args.config == "plain" and not args.quick:
+        out["multires"] = bench_multires(sph, args)
+        out["batched"] = bench_batched(sph)
+        log(f"[bench] batched {out['batched']['value']:.3g} pairs/s vs plain loop "
+            f"{out['batched']['plain_loop']['value']:.3g} (tuned parameters "
+            f"{out['batched']['plain_loop_tuned']['value']:.3g})")
+        out["served"] = bench_served(sph)
+        log(f"[bench] served p50 {out['served']['p50_ms']:.2f} ms p99 {out['served']['p99_ms']:.2f} ms, "
+            f"{out['served']['pair_interactions_per_s']:.3g} pairs/s vs plain "
+            f"{out['served']['plain_same_stream']['pair_interactions_per_s']:.3g}")
     return out
+
+
+def bench_multires(sph, args, steps=3, warmup=1):
+    """The 8M clumpy mixture (h over ~3 decades), with the same accounting."""
+    import torch
+    t = time.perf_counter()
+    ps, cfg = make_workload("multires")
+    log(f"[bench] multires workload generated in {time.perf_counter() - t:.1f} s")
+    m = measure(sph, ps, steps, warmup, sph.params())
+    s = summarize(m, steps)
+    rl, stages = rooflines(m, steps, cfg["workload"])
+    log(f"[bench] multires {steps} steps: {s['ms_per_step']:.2f} ms/step, P = {s['pairs_P']:.4g}, "
+        + ", ".join(f"{k}: {v:.3f}" for k, v in s["stages_ms"].items()))
+    for k, r in rl.items():
+        log(f"[bench] multires {k}: {r['ms_per_step']:.2f} ms/step, {100 * r['frac']:.1f}% of VALU peak")
+    res = {"config": cfg, "steps": steps, "warmup": warmup, "unit": "pair interactions/s", **s,
+           "rooflines": rl, "stage_hbm": stages}
+    if not args.skip_cpu:
+        log("[bench] timing the FP64 oracle on the host (multires sample)")
+        res["cpu_baseline"] = cpu_baseline(ps, m["dout"].h.cpu().numpy(), m["fout"].nforce.cpu().numpy(),
+                                           budget_s=args.cpu_budget, check_max=5000)
+    del m
+    torch.cuda.empty_cache()
+    return res
 
 
 def plain_loop(sph, ctx, sets, prm):
@@ -236,7 +350,8 @@ def plain_loop(sph, ctx, sets, prm):
 
 
 def bench_batched(sph, n_sets=256, steps=3):
-    """Many uneven sets in one batch (one build, one graph) vs the plain loop."""
+    """Many uneven sets in one batch (one build, one graph) vs the plain loop,
+    with the default parameters and with the autotuned ones."""
     import torch
     from paper_1309_3783_amd import autotune, pipeline as P
     import sphinputs
@@ -260,14 +375,20 @@ def bench_batched(sph, n_sets=256, steps=3):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     Pp = P.pair_count(out)
     plain = plain_loop(sph, ctx, sets, sph.params())
+    plain_tuned = plain_loop(sph, ctx, sets, prm)
+    val = 2 * Pp / (ms / 1e3)
     return {"workload": "batched_256_sets", "n": batch.n, "sets": n_sets, "n_range": [2000, 200000],
-            "value": 2 * Pp / (ms / 1e3), "unit": "pair interactions/s", "ms_per_step": ms, "pairs_P": Pp,
-            "autotuned": best, "eager_fallbacks": fallbacks, "plain_loop": plain,
-            "speedup_vs_plain": (2 * Pp / (ms / 1e3)) / plain["value"]}
+            "value": val, "unit": "pair interactions/s", "ms_per_step": ms, "pairs_P": Pp,
+            "autotuned": best, "eager_fallbacks": fallbacks, "plain_loop": plain, "plain_loop_tuned": plain_tuned,
+            "speedup_vs_plain": val / plain["value"], "speedup_vs_plain_tuned": val / plain_tuned["value"]}
 
 
-def bench_served(sph, n_req=400, pool_size=24, load=0.7, h_slack=0.2):
-    """Poisson request stream, N log-uniform in [1e4, 2e6], continuous batching."""
+def bench_served(sph, n_req=1000, n_warm=50, n_plain=300, pool_size=24, load=0.7, h_slack=0.2):
+    """Poisson request stream, N log-uniform in [1e4, 2e6], continuous batching;
+    beside it the first n_plain requests of the same stream run one at a time
+    back to back (the plain path).  The served results are checked against the
+    oracle by the GPU tests (every request there), not here."""
+    import torch
     from paper_1309_3783_amd import serve as S
     import sphinputs
     rng = np.random.default_rng(5)
@@ -276,9 +397,6 @@ def bench_served(sph, n_req=400, pool_size=24, load=0.7, h_slack=0.2):
     pool = [sphinputs.plummer_mixture(int(n), 5000 + k) for k, n in enumerate(pool_n)]
     log(f"[bench] served pool: {pool_size} sets, {sum(p.n for p in pool)} particles "
         f"({time.perf_counter() - t:.1f} s to generate)")
-    # cold starts from the analytic first guess: room for h to grow (0.3
-    # measured no better: the latencies vary more between runs than between
-    # 0.2 and 0.3)
     prm = sph.params(h_slack=h_slack)
     budget = 64 << 30
     ex = S.GpuExecutor(prm, k_iter=K_ITER, lanes=2)
@@ -292,13 +410,33 @@ def bench_served(sph, n_req=400, pool_size=24, load=0.7, h_slack=0.2):
     S.Scheduler(ex, budget, fp, max_batch=16).run(burst[:8])          # warm-up
     sat = S.summary(S.Scheduler(ex, budget, fp, max_batch=16).run(burst))["requests_per_s"]
     rate = load * sat
-    gaps = rng.exponential(1.0 / rate, size=n_req)
+    total = n_warm + n_req
+    gaps = rng.exponential(1.0 / rate, size=total)
     arr = np.cumsum(gaps) - gaps[0]
-    idx = rng.integers(0, pool_size, size=n_req)
+    idx = rng.integers(0, pool_size, size=total)
     reqs = [S.Request(i, float(a), pool[k]) for i, (a, k) in enumerate(zip(arr, idx))]
-    summ = S.summary(S.Scheduler(ex, budget, fp, max_batch=16).run(reqs))
+    S.Scheduler(ex, budget, fp, max_batch=16).run(reqs)
+    summ = S.summary(reqs[n_warm:])
     summ.update({"saturation_requests_per_s": sat, "arrival_rate_per_s": rate, "load": load,
-                 "n_range": [10000, 2000000], "pool_sets": pool_size, "budget_bytes": budget})
+                 "warmup_requests": n_warm, "n_range": [10000, 2000000], "pool_sets": pool_size,
+                 "budget_bytes": budget})
+    # the plain path on the same stream: one request at a time, no batching
+    ctx = sph.Context(0)
+    tree = sph.Tree(ctx)
+    pairs = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs[n_warm:n_warm + n_plain]:
+        b = sph.batch_from_sets([r.ps])
+        d = sph.DensityOut(r.n, "cuda")
+        f = sph.ForceOut(r.n, 1, "cuda")
+        sph.solve_with_rebuild(tree, b, prm, d)
+        tree.force(f)
+        pairs += float(f.sums[6].item()) / 2.0
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    summ["plain_same_stream"] = {"requests": n_plain, "seconds": tp, "pair_interactions_per_s": 2 * pairs / tp,
+                                 "requests_per_s": n_plain / tp}
     return summ
 
 
@@ -378,7 +516,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="plain", choices=["plain", "multires", "sod", "sedov"])
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="headline workload only (no batched/served)")
+    ap.add_argument("--quick", action="store_true", help="headline workload only (no multires/batched/served)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--slack", type=float, default=None, help="h slack of the cell decisions (default: library's)")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -284,6 +284,15 @@ sph_status sph_cfl_dt(sph_ctx* ctx, int64_t n, const float* h, const float* vsig
  * synchronises with the last recorded event; recording does not.  Returns
  * the number of stages written (at most cap). */
 int32_t sph_last_timings(sph_ctx* ctx, const char** names, double* ms, int32_t cap);
+/* Pair evaluations counted on the device for the measurement of the
+ * interaction kernels against their roofline: *density_pairs [host] = the
+ * sum, over the particles each density pass evaluated, of their neighbour
+ * counts (ordered pairs i <- j with r < h_i), over all passes of the last
+ * sph_density / sph_solve_h call (or graph); *force_pairs [host] = the same
+ * for the last force pass (ordered pairs with r < max(h_i, h_j), = 2 P).
+ * Synchronises the context's stream.  Errors: SPH_E_ARG, SPH_E_HIP. */
+sph_status sph_last_work(sph_ctx* ctx, uint64_t* density_pairs, uint64_t* force_pairs);
+
 /* Enable (1) or disable (0) per-stage event timing on the context. */
 void sph_enable_timing(sph_ctx* ctx, int32_t on);
 

@@ -25,7 +25,7 @@ EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_creat
            "sph_last_error", "sph_workspace_size", "sph_footprint", "sph_tree_create", "sph_tree_destroy",
            "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
            "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
-           "sph_last_timings", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
+           "sph_last_timings", "sph_last_work", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
 
 
 class sph_params(C.Structure):
@@ -64,6 +64,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(there is no CPU fallback)")
+        # torch carries its own HIP runtime and the library links the
+        # system's: torch's must find the GPU first (loaded the other way
+        # round, the library's runtime sees no device)
+        import torch
+        torch.cuda.is_available()
         L = C.CDLL(LIB_PATH)
         vp, st = C.c_void_p, C.c_int32
         L.sph_version.restype = C.c_char_p
@@ -95,6 +100,7 @@ def lib():
                                     vp]
         L.sph_last_timings.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.c_int32]
         L.sph_last_timings.restype = C.c_int32
+        L.sph_last_work.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.sph_enable_timing.argtypes = [vp, C.c_int32]
         L.sph_enable_timing.restype = None
         L.sph_tree_stats.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32]
@@ -104,7 +110,7 @@ def lib():
         for name in ("sph_ctx_create", "sph_footprint", "sph_workspace_size", "sph_tree_create", "sph_tree_bytes",
                      "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
                      "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force",
-                     "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"):
+                     "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt", "sph_last_work"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -172,6 +178,12 @@ class Context:
         ms = (C.c_double * 4096)()
         k = lib().sph_last_timings(self.h, names, ms, 4096)
         return [(names[i].decode(), ms[i]) for i in range(k)]
+
+    def work(self):
+        """(density pair evaluations, force pair evaluations) of the last calls."""
+        d, f = C.c_uint64(0), C.c_uint64(0)
+        self.check(lib().sph_last_work(self.h, C.byref(d), C.byref(f)), "sph_last_work")
+        return int(d.value), int(f.value)
 
     def close(self):
         if getattr(self, "h", None):

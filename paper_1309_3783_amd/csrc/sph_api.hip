@@ -120,7 +120,7 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;
-    if (hipMalloc(&c->d_counter, 1024 * sizeof(int32_t)) != hipSuccess) {
+    if (hipMalloc(&c->d_counter, sph_ctx::CTR_WORDS * sizeof(int32_t)) != hipSuccess) {
         delete c;
         return SPH_E_WORKSPACE;
     }
@@ -279,6 +279,22 @@ int32_t sph_last_timings(sph_ctx* ctx, const char** names, double* ms, int32_t c
         ++k;
     }
     return k;
+}
+
+sph_status sph_last_work(sph_ctx* ctx, uint64_t* density_pairs, uint64_t* force_pairs) {
+    if (!ctx) return SPH_E_ARG;
+    // 2 x 8 counters of 64 bits, 128 bytes apart
+    const void* d = ctx->d_counter + sph_ctx::CTR_WORK;
+    if (hipMemcpyAsync(ctx->h_pin, d, 512 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return SPH_E_HIP;
+    const uint64_t* v = (const uint64_t*)ctx->h_pin;
+    uint64_t s[2] = {0, 0};
+    for (int k = 0; k < 2; ++k)
+        for (int g = 0; g < 8; ++g) s[k] += v[k * 128 + g * 16];
+    if (density_pairs) *density_pairs = s[0];
+    if (force_pairs) *force_pairs = s[1];
+    return SPH_OK;
 }
 
 void sph_enable_timing(sph_ctx* ctx, int32_t on) {

@@ -24,10 +24,14 @@ struct sph_ctx {
     std::vector<const char*> ev_name;
     size_t nev = 0;
     std::vector<std::pair<const char*, double>> last_ms;
-    // device words (1024): [0, 256) density work counters, [256, 512) force
-    // work counters, [512, 768) chunk-list counts, [CTR_CFL] Courant minimum
+    // device words (CTR_WORDS): [0, 256) density work counters, [256, 512)
+    // force work counters, [512, 768) chunk-list counts, [CTR_CFL] Courant
+    // minimum, [CTR_WORK, +512): 64-bit counts of pair evaluations, density
+    // then force, each spread over 8 counters 128 bytes apart
     int32_t* d_counter = nullptr;
     static constexpr int CTR_CFL = 768;
+    static constexpr int CTR_WORK = 1024;
+    static constexpr int CTR_WORDS = 2048;
     // pinned host memory that device counts are read back into: one
     // asynchronous copy per read, then one stream synchronisation
     static constexpr size_t PIN_BYTES = 65536;
@@ -113,6 +117,7 @@ struct sph_tree {
     int static_gen = 0;          // > 0: the workspace is the library's static scratch (this generation)
     size_t ws_needed = 0;        // after SPH_E_WORKSPACE: bytes a larger workspace must offer at least
     hipStream_t stream = nullptr;
+    int32_t* work_ctr = nullptr; // the context's pair-evaluation counters (set per call)
 
     // ---- configuration -------------------------------------------------
     sph_params prm{};

@@ -298,6 +298,7 @@ struct DensArgs {
     float *rho, *drho, *nw, *dnw;
     int32_t* nngb;
     uint64_t* hash;
+    unsigned long long* work;   // pair evaluations (sum of the counts written), for the measurement
     int rmax;
 };
 
@@ -322,6 +323,18 @@ __device__ __forceinline__ float comb_f(float v, int R) {
 __device__ __forceinline__ double comb_d(double v, int R) {
     for (int d = 32, r = R; r > 1; d >>= 1, r >>= 1) v = v + __shfl_xor(v, d, 64);
     return v;
+}
+// Pair evaluations of a wave step: the counts its lanes write, summed over
+// the wave (a wave-uniform value kept in a scalar register) ...
+__device__ __forceinline__ int wave_count(int v) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+// ... and added up once per wave when it leaves the kernel, into one of 8
+// counters 128 bytes apart (one same-address atomic per wave step from the
+// whole GPU would serialise).
+__device__ __forceinline__ void flush_work(unsigned long long* work, unsigned long long v) {
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(work + 16 * (blockIdx.x & 7), v);
 }
 __device__ __forceinline__ int comb_i(int v, int R) {
     for (int d = 32, r = R; r > 1; d >>= 1, r >>= 1) v += __shfl_xor(v, d, 64);
@@ -755,6 +768,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
     // each frame's packed into the first slots
     int leaf = 0, p0 = 0, cnt = 0;
     uint64_t pend = 0;
+    unsigned long long done_work = 0;   // pair evaluations of this wave
     for (;;) {
         if (pend == 0) {
             const int item = next_chunk(a.counter, a.nchunks, a.list, a.lcount, home, grp);
@@ -812,7 +826,9 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
             a.nngb[p] = nn;
             if (HASH) a.hash[p] = hs;
         }
+        done_work += (unsigned long long)wave_count(act && rep == 0 ? nn : 0);
     }
+    flush_work(a.work, done_work);
 }
 
 // ---------------------------------------------------------------------------
@@ -838,6 +854,7 @@ struct ForceArgs {
     float *ax, *ay, *az, *du, *vsig, *S;
     int32_t* nf;
     uint64_t* hash;
+    unsigned long long* work;
     int rmax;
 };
 
@@ -954,6 +971,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
     // frame's packed into the first slots)
     int leaf = 0, p0 = 0, cnt = 0;
     uint64_t pend = 0;
+    unsigned long long done_work = 0;   // pair evaluations of this wave
     for (;;) {
         if (pend == 0) {
             const int item = next_chunk(a.counter, a.nchunks, nullptr, nullptr, home, grp);
@@ -1016,7 +1034,9 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
             a.nf[p] = nn;
             if (HASH) a.hash[p] = hs;
         }
+        done_work += (unsigned long long)wave_count(act && rep == 0 ? nn : 0);
     }
+    flush_work(a.work, done_work);
 }
 
 // ---------------------------------------------------------------------------
@@ -1468,6 +1488,7 @@ static DensArgs dens_args(sph_tree* t, int* counter, const int* lcount) {
     a.dnw = t->dnw;
     a.nngb = t->nngb;
     a.hash = t->hashd;
+    a.work = (unsigned long long*)(t->work_ctr);
     a.rmax = rmax_of(t);
     return a;
 }
@@ -1532,6 +1553,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.S = t->fS;
     a.nf = t->fn;
     a.hash = t->hashf;
+    a.work = (unsigned long long*)(t->work_ctr + 256);
     a.rmax = rmax_of(t);
     dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
     if (t->hash) hipLaunchKernelGGL((k_force<true>), g, b, 0, st, a);
@@ -1575,12 +1597,20 @@ static void launch_scatter_force(sph_ctx* ctx, sph_tree* t, const sph_force_out*
                        t->fay, t->faz, t->fdu, t->fvs, t->fS, t->fn, t->hash ? t->hashf : nullptr, *o);
 }
 
+// The pair-evaluation counters of a stage start at zero (density: words
+// [0, 256), force: [256, 512) of the work block of the context's counters).
+static void zero_work(sph_ctx* ctx, sph_tree* t, int first, int words) {
+    t->work_ctr = ctx->d_counter + sph_ctx::CTR_WORK;
+    hipLaunchKernelGGL(k_zero_i32, dim3(2), dim3(256), 0, ctx->stream, t->work_ctr + first, words);
+}
+
 Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out) {
     if (!t->built || !t->sorted) return Err{SPH_E_STATE, "density before build_cells/sort_pairs"};
     if (out && out->hash && !t->hash) return Err{SPH_E_ARG, "pair hash requested without SPH_FLAG_PAIR_HASH"};
     ERRTRY(ensure_state(t));
     if (t->n == 0) return Err{};
     ev_mark(ctx, "start");
+    zero_work(ctx, t, 0, 256);
     launch_density(ctx, t, false, false, ctx->d_counter);
     ev_mark(ctx, "density");
     launch_scatter_density(ctx, t, out);
@@ -1614,11 +1644,14 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     t->saved = false;
     const int nst = 2 + 2 * t->nsets;
     hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
+    zero_work(ctx, t, 0, 256);
     int32_t hstat[2] = {0, 0};
     int it = 0;
     bool rebuild = false;
     for (; it < t->prm.max_iter; ++it) {
+        ev_mark(ctx, "newton");
         launch_density(ctx, t, true, it > 0, ctx->d_counter);
+        ev_mark(ctx, "density_pass");
         launch_newton(ctx, t);
         launch_count(ctx, t);
         HIPTRY(hipGetLastError());
@@ -1627,12 +1660,13 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
         if (hstat[1] == 0) { ++it; break; }
     }
     rebuild = hstat[0] != 0;
+    ev_mark(ctx, "newton");
     if (!rebuild && hstat[1] > 0) {
         // unconverged particles moved h after their last density: recompute
         // their density at the h they hold now
         launch_density(ctx, t, true, true, ctx->d_counter);
+        ev_mark(ctx, "density_pass");
     }
-    ev_mark(ctx, "solve");
     launch_scatter_density(ctx, t, out);
     if (rebuild) {
         ERRTRY(t->ensure_saved());
@@ -1659,6 +1693,7 @@ Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
     ERRTRY(ensure_state(t));
     if (t->n == 0) return Err{};
     ev_mark(ctx, "start");
+    zero_work(ctx, t, 256, 256);
     launch_force(ctx, t, ctx->d_counter + NGRP * CSTRIDE);
     ev_mark(ctx, "force");
     launch_reduce(ctx, t, out ? out->sums : nullptr);
@@ -1719,6 +1754,7 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi,
                                t->dstep);
+            zero_work(ctx, t, 0, 512);
             const int nst = 2 + 2 * t->nsets;
             hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
             for (int it = 0; it < k_iter; ++it) {
