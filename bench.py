@@ -12,8 +12,10 @@ The same line carries the multi-resolution workload (8,000,000 particles,
 64 Plummer clumps + 20% background, h over ~3 decades: the stand-in for the
 paper's cosmological volume), the batched comparison (256 uneven sets in one
 build and one HIP graph, autotuned, vs the plain one-set-at-a-time loop) and
-the served Poisson stream (p50/p99 latency).  --config multires times only
-the 8M clumpy set; --config sod / sedov time leapfrog time steps of the
+the served Poisson stream (p50/p99 latency) and one GPU's share of an
+8-GPU decomposition (1M owned particles of a 200^3 lattice plus their
+read-only halo).  --config multires times only the 8M clumpy set; --config
+share only the share; --config sod / sedov time leapfrog time steps of the
 paper's shock tube / blast.  Prints ONE JSON line.
 
 Roofline accounting (the interaction kernels are bound by vector ALU work):
@@ -293,6 +295,7 @@ def run(args):
     del m
     if args.config == "plain" and not args.quick:
         out["multires"] = bench_multires(sph, args)
+        out["share"] = bench_share(sph)
         out["batched"] = bench_batched(sph)
         log(f"[bench] batched {out['batched']['value']:.3g} pairs/s vs plain loop "
             f"{out['batched']['plain_loop']['value']:.3g} (tuned parameters "
@@ -326,6 +329,64 @@ def bench_multires(sph, args, steps=3, warmup=1):
     del m
     torch.cuda.empty_cache()
     return res
+
+
+def bench_share(sph, steps=10, warmup=2):
+    """One GPU's share of an 8-GPU decomposition at its real size: a 200^3
+    jittered lattice (8M particles, h solved whole on this GPU first, standing
+    in for the other GPUs' work) cut into 2 x 2 x 2 blocks; the share is the
+    block [0, 1/2)^3 (1M owned particles) plus the halo, one top cell of the
+    whole set around it (periodic), whose h, density and d rho/dh come from
+    the whole-set run (what a halo exchange delivers).  A step on the share:
+    build, sort, h solve of the owned particles, force of the owned ones."""
+    import torch
+    import sphinputs
+    ps = sphinputs.lattice(200, 0.1, 2)
+    ctx = sph.Context(0)
+    whole = sph.batch_from_sets([ps])
+    d = sph.DensityOut(ps.n, "cuda")
+    tree = sph.Tree(ctx)
+    st, nu, it = sph.solve_with_rebuild(tree, whole, sph.params(), d)
+    edge = 1.0 / tree.stats()["top_grid"]                # the halo: one top cell of the whole set
+    h_all, rho_all, drho_all = d.h.cpu().numpy(), d.rho.cpu().numpy(), d.drho_dh.cpu().numpy()
+    del tree, d, whole
+    torch.cuda.empty_cache()
+    pos = ps.pos()
+    dd = np.mod(pos + edge, 1.0)
+    idx = np.nonzero(np.all(dd < 0.5 + 2 * edge, axis=1))[0]
+    own = np.all((dd[idx] >= edge) & (dd[idx] < 0.5 + edge), axis=1)
+    sub = sphinputs.ParticleSet(ps.x[idx], ps.y[idx], ps.z[idx], ps.m[idx], ps.u[idx], ps.vx[idx], ps.vy[idx],
+                                ps.vz[idx], np.where(own, ps.h0[idx], h_all[idx]), ps.box)
+    batch = sph.batch_from_sets([sub])
+    owned = torch.as_tensor(own.astype(np.uint8), device="cuda")
+    rho = torch.as_tensor(rho_all[idx], device="cuda")
+    drho = torch.as_tensor(drho_all[idx], device="cuda")
+    tree = sph.Tree(ctx)
+    dout = sph.DensityOut(sub.n, "cuda")
+    fout = sph.ForceOut(sub.n, 1, "cuda")
+    prm = sph.params()
+
+    def step():
+        st, nu, it = sph.solve_with_rebuild(tree, batch, prm, dout, halo=(owned, rho, drho))
+        if st not in (sph.SPH_OK, sph.SPH_E_NOCONV):
+            raise RuntimeError(f"share solve failed: status {st}")
+        tree.force(fout)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    pairs = float(fout.sums[6].item())          # force neighbours of the owned particles (their share of 2 P)
+    log(f"[bench] share: {int(own.sum())} owned + {int((~own).sum())} halo particles, {ms:.2f} ms/step, "
+        f"{pairs / (ms / 1e3):.3g} pairs/s")
+    return {"workload": "lattice_200^3_share_1_of_8", "owned": int(own.sum()), "halo": int((~own).sum()),
+            "halo_thickness": edge, "steps": steps, "ms_per_step": ms, "unit": "pair interactions/s",
+            "value": pairs / (ms / 1e3), "owned_force_pairs": pairs,
+            "note": "pair interactions of the owned particles (each one's force neighbours) per second"}
 
 
 def plain_loop(sph, ctx, sets, prm):
@@ -514,7 +575,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="plain", choices=["plain", "multires", "sod", "sedov"])
+    ap.add_argument("--config", default="plain", choices=["plain", "multires", "share", "sod", "sedov"])
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only (no multires/batched/served)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -528,7 +589,11 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    out = bench_steps(args) if args.config in ("sod", "sedov") else run(args)
+    if args.config == "share":
+        import paper_1309_3783_amd as sph
+        out = bench_share(sph, steps=args.steps, warmup=args.warmup)
+    else:
+        out = bench_steps(args) if args.config in ("sod", "sedov") else run(args)
     print(json.dumps(out))
 
 

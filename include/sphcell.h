@@ -239,6 +239,24 @@ sph_status sph_solve_h(sph_ctx* ctx, sph_tree* t, const sph_density_out* out,
  * density pass (sph_density or sph_solve_h) at the current h. */
 sph_status sph_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out);
 
+/* One GPU's share of a set decomposed over several GPUs (Section I: each
+ * node works on its part of the data and exchanges what lies across its
+ * surface; Section IV: that exchange modelled as tasks).  After a build of
+ * the share's particles -- the ones it owns plus the halo, the layer of top
+ * cells around them whose edge is at least the largest h, so that every
+ * neighbour of an owned particle is present -- mark each particle owned (1)
+ * or read-only halo (0) and give the halo particles' density and d rho/d h
+ * as their owners computed them (what a halo exchange delivers); h of a
+ * halo particle is the one given at build.  From then on until the next
+ * build: halo particles are neighbours only -- never solved for h, never
+ * targets of the density or force stages; the ghost step takes their given
+ * density; the per-set sums cover the owned particles; the outputs of halo
+ * particles are not written.  owned, rho, drho_dh: [device] caller order, n
+ * entries (rho, drho_dh read for halo particles only).  owned = NULL: every
+ * particle owned again.  Errors: SPH_E_STATE (no build), SPH_E_ARG,
+ * SPH_E_WORKSPACE, SPH_E_HIP. */
+sph_status sph_set_halo(sph_ctx* ctx, sph_tree* t, const uint8_t* owned, const float* rho, const float* drho_dh);
+
 /* Enqueue the whole post-build pipeline -- density/Newton iterations with
  * device-side early exit (k_iter of them), ghost, force and sums -- as one
  * HIP graph on the context's stream (captured on first use, relaunched

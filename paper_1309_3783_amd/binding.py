@@ -24,8 +24,8 @@ SPH_FLAG_RESUME = 2
 EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
            "sph_last_error", "sph_workspace_size", "sph_footprint", "sph_tree_create", "sph_tree_destroy",
            "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
-           "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_run_graph",
-           "sph_last_timings", "sph_last_work", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
+           "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_set_halo",
+           "sph_run_graph", "sph_last_timings", "sph_last_work", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
 
 
 class sph_params(C.Structure):
@@ -96,6 +96,7 @@ def lib():
         L.sph_solve_h.argtypes = [vp, vp, C.POINTER(sph_density_out), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32)]
         L.sph_force.argtypes = [vp, vp, C.POINTER(sph_force_out)]
+        L.sph_set_halo.argtypes = [vp, vp, vp, vp, vp]
         L.sph_run_graph.argtypes = [vp, vp, C.c_int32, C.POINTER(sph_density_out), C.POINTER(sph_force_out),
                                     vp]
         L.sph_last_timings.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.c_int32]
@@ -110,7 +111,8 @@ def lib():
         for name in ("sph_ctx_create", "sph_footprint", "sph_workspace_size", "sph_tree_create", "sph_tree_bytes",
                      "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
                      "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force",
-                     "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt", "sph_last_work"):
+                     "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt", "sph_last_work",
+                     "sph_set_halo"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -403,6 +405,13 @@ class Tree:
         self._fout = out.c()
         self._call(lambda: lib().sph_force(self.ctx.h, self.h, C.byref(self._fout)), "sph_force")
 
+    def set_halo(self, owned, rho, drho_dh):
+        """Mark the particles owned (uint8 tensor, 1) or read-only halo (0)
+        and give the halo particles' rho and d rho/dh (caller order)."""
+        self._halo = (owned, rho, drho_dh)
+        self.ctx.check(lib().sph_set_halo(self.ctx.h, self.h, _ptr(owned), _ptr(rho), _ptr(drho_dh)),
+                       "sph_set_halo")
+
     def run_graph(self, k_iter: int, dout: DensityOut, fout: ForceOut, unconv):
         self._gd, self._gf = dout.c(), fout.c()
         self._call(lambda: lib().sph_run_graph(self.ctx.h, self.h, int(k_iter), C.byref(self._gd),
@@ -421,14 +430,18 @@ class Tree:
         return int(b.value)
 
 
-def solve_with_rebuild(tree: Tree, batch: Batch, prm: sph_params, dout: DensityOut, max_rebuilds: int = 4):
+def solve_with_rebuild(tree: Tree, batch: Batch, prm: sph_params, dout: DensityOut, max_rebuilds: int = 4,
+                       halo=None):
     """build -> sort -> solve_h, rebuilding with the current h when h outgrows
-    the cells (the library reports it; the rebuild itself runs on the GPU)."""
+    the cells (the library reports it; the rebuild itself runs on the GPU).
+    halo: (owned, rho, drho_dh) of one GPU's share, set after every build."""
     h = batch.h
     total_it = 0
     p = prm
     for _ in range(max_rebuilds + 1):
         tree.build_cells(batch, p, h=h)
+        if halo is not None:
+            tree.set_halo(*halo)
         tree.sort_pairs()
         st, nu, it = tree.solve_h(dout)
         total_it += it

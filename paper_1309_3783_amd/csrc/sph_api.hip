@@ -250,6 +250,12 @@ sph_status sph_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
     return fail(ctx, sph::run_force(ctx, t, out));
 }
 
+sph_status sph_set_halo(sph_ctx* ctx, sph_tree* t, const uint8_t* owned, const float* rho, const float* drho_dh) {
+    if (!ctx || !t) return SPH_E_ARG;
+    if (sph_status s = check_tree(ctx, t)) return s;
+    return fail(ctx, sph::set_halo(ctx, t, owned, rho, drho_dh));
+}
+
 sph_status sph_run_graph(sph_ctx* ctx, sph_tree* t, int32_t k_iter, const sph_density_out* dout,
                          const sph_force_out* fout, int32_t* n_unconverged_dev) {
     if (!ctx || !t || k_iter < 1) return SPH_E_ARG;

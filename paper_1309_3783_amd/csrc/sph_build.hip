@@ -1081,6 +1081,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     t->n = n;
     t->off.assign(in->offsets, in->offsets + in->nsets + 1);
     t->built = t->sorted = t->have_density = false;
+    t->owned = nullptr;   // a halo is set after every build
     t->hash = (prm->flags & SPH_FLAG_PAIR_HASH) != 0;
     t->invalidate_graph();
     ev_mark(ctx, "start");

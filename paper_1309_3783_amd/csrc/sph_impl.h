@@ -132,7 +132,7 @@ struct sph_tree {
     sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_plo, b_pv, b_ph, b_hdec, b_pu,
         b_bound, b_mix, b_rs, b_cell, b_taskA, b_taskB, b_final, b_chunk, b_csr, b_csr2, b_csroff,
         b_segoff, b_seglist, b_segproj, b_segidx, b_bigk, b_bigv, b_sc, b_dens, b_force, b_solve,
-        b_red, b_misc, b_saved, b_split, b_counts, b_iperm;
+        b_red, b_misc, b_saved, b_split, b_counts, b_iperm, b_owned;
 
     // ---- sizes (host) --------------------------------------------------
     int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nchunks = 0, max_leaf = 0;
@@ -150,6 +150,9 @@ struct sph_tree {
     uint64_t *key = nullptr, *key2 = nullptr, *mix = nullptr, *csr = nullptr, *csr2 = nullptr;
     uint32_t *val = nullptr, *val2 = nullptr, *perm = nullptr, *rs_tmp = nullptr;
     uint32_t* iperm = nullptr;   // caller order -> cell order
+    // one GPU's share of a decomposed set (sph_set_halo): 1 = owned, 0 = a
+    // read-only halo particle; null when every particle is owned
+    uint8_t* owned = nullptr;
     float4 *pos = nullptr, *pv = nullptr;
     float4* plo = nullptr;   // FP32 remainders of the positions: pos.xyz + plo.xyz = offset to ~2^-48
     float *ph = nullptr, *hdec = nullptr, *pu = nullptr, *bound = nullptr;
@@ -207,7 +210,7 @@ struct sph_tree {
         return {&b_sets, &b_small, &b_key, &b_key2, &b_val, &b_val2, &b_perm, &b_pos, &b_plo, &b_pv, &b_ph, &b_hdec,
                 &b_pu, &b_bound, &b_mix, &b_rs, &b_cell, &b_taskA, &b_taskB, &b_final, &b_chunk, &b_csr,
                 &b_csr2, &b_csroff, &b_segoff, &b_seglist, &b_segproj, &b_segidx, &b_bigk, &b_bigv, &b_sc,
-                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts, &b_iperm};
+                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts, &b_iperm, &b_owned};
     }
 
     // Drop every buffer (the tree must be built again).  Library-owned
@@ -414,6 +417,7 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t);
 Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out);
 Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_unconv, int32_t* iters);
 Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out);
+Err set_halo(sph_ctx* ctx, sph_tree* t, const uint8_t* owned, const float* rho, const float* drho);
 Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout, const sph_force_out* fout,
               int32_t* n_unconv_dev);
 }  // namespace sph

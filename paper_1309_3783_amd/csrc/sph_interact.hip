@@ -287,6 +287,7 @@ struct DensArgs {
     const float* ph;
     const uint64_t* mix;
     const uint8_t* active;
+    const uint8_t* owned;   // null, or 0 for read-only halo particles (never targets)
     const uint32_t* list;   // chunks with active particles (null: all chunks)
     const int* lcount;
     const uint64_t* csr;
@@ -778,7 +779,8 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
             p0 = uni(ch.y);
             cnt = uni(ch.z);
             pend = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
-            if (SOLVE) pend = __ballot(lane < cnt && a.active[p0 + lane] == 1);
+            if (SOLVE) pend = __ballot(lane < cnt && a.active[p0 + lane] == 1);   // (halo: never active)
+            else if (a.owned) pend = __ballot(lane < cnt && a.owned[p0 + lane] != 0);
             if (pend == 0) continue;
         }
         const float L0 = (float)a.sets[a.cells[leaf].set].L0;
@@ -844,6 +846,7 @@ struct ForceArgs {
     const float4* plo;
     const float4* pv;
     const float4* frec;   // h, A, sound speed, K = 8/(pi h^5); pv.w holds rho
+    const uint8_t* owned;
     const uint64_t* mix;
     const uint64_t* csr;
     const uint32_t* csr_off;
@@ -981,6 +984,8 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
             p0 = uni(ch.y);
             cnt = uni(ch.z);
             pend = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+            if (a.owned) pend = __ballot(lane < cnt && a.owned[p0 + lane] != 0);
+            if (pend == 0) continue;
         }
         const float L0 = (float)a.sets[a.cells[leaf].set].L0;
         Frame fr;
@@ -1048,10 +1053,11 @@ __global__ void k_zero_i32(int32_t* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-__global__ void k_solve_init(int64_t n, uint8_t* active, float* lo, float* hi, float* dstep) {
+__global__ void k_solve_init(int64_t n, const uint8_t* __restrict__ owned, uint8_t* active, float* lo, float* hi,
+                             float* dstep) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    active[p] = 1;
+    active[p] = (!owned || owned[p]) ? 1 : 0;   // a halo particle keeps the h it came with
     lo[p] = 0.f;
     hi[p] = INFINITY;
     dstep[p] = INFINITY;
@@ -1289,10 +1295,12 @@ __global__ __launch_bounds__(256) void k_cell_hcur(Cell* __restrict__ cells, int
 
 __global__ void k_scatter_density(int64_t n, const uint32_t* __restrict__ iperm, const float* rho,
                                   const float* drho, const float* nw, const float* dnw, const int32_t* nngb,
-                                  const uint64_t* hash, const float* ph, sph_density_out o) {
+                                  const uint64_t* hash, const float* ph, const uint8_t* __restrict__ owned,
+                                  sph_density_out o) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t p = iperm[i];
+    if (owned && !owned[p]) return;   // halo particles: the caller's entries stay as they are
     if (o.rho) o.rho[i] = rho[p];
     if (o.drho_dh) o.drho_dh[i] = drho[p];
     if (o.nw) o.nw[i] = nw[p];
@@ -1304,10 +1312,12 @@ __global__ void k_scatter_density(int64_t n, const uint32_t* __restrict__ iperm,
 
 __global__ void k_scatter_force(int64_t n, const uint32_t* __restrict__ iperm, const float* ax, const float* ay,
                                 const float* az, const float* du, const float* vs, const float* S,
-                                const int32_t* nf, const uint64_t* hash, sph_force_out o) {
+                                const int32_t* nf, const uint64_t* hash, const uint8_t* __restrict__ owned,
+                                sph_force_out o) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t p = iperm[i];
+    if (owned && !owned[p]) return;
     if (o.ax) o.ax[i] = ax[p];
     if (o.ay) o.ay[i] = ay[p];
     if (o.az) o.az[i] = az[p];
@@ -1328,11 +1338,13 @@ __global__ __launch_bounds__(256) void k_reduce_partial(const int4* __restrict__
                                                         const float* __restrict__ ay, const float* __restrict__ az,
                                                         const float* __restrict__ du, const float* __restrict__ S,
                                                         const int32_t* __restrict__ nngb,
-                                                        const int32_t* __restrict__ nf, double* __restrict__ part) {
+                                                        const int32_t* __restrict__ nf,
+                                                        const uint8_t* __restrict__ owned, double* __restrict__ part) {
     __shared__ double s[NRED][256];
     const int4 R = red[blockIdx.x];
     double acc[NRED] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int p = R.y + threadIdx.x; p < R.y + R.z; p += 256) {
+        if (owned && !owned[p]) continue;   // halo particles: no outputs of their own
         double m = pos[p].w;
         float4 v = pv[p];
         double a0 = ax[p], a1 = ay[p], a2 = az[p];
@@ -1474,6 +1486,7 @@ static DensArgs dens_args(sph_tree* t, int* counter, const int* lcount) {
     a.ph = t->ph;
     a.mix = t->mix;
     a.active = t->active;
+    a.owned = t->owned;
     a.list = lcount ? t->alist : nullptr;
     a.lcount = lcount;
     a.csr = t->csr;
@@ -1538,6 +1551,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.plo = t->plo;
     a.pv = t->pv;
     a.frec = t->frec;
+    a.owned = t->owned;
     a.mix = t->mix;
     a.csr = t->csr;
     a.csr_off = t->csr_off;
@@ -1580,7 +1594,7 @@ static void launch_reduce(sph_ctx* ctx, sph_tree* t, double* sums_out) {
     hipStream_t st = ctx->stream;
     if (t->nred == 0) return;
     hipLaunchKernelGGL(k_reduce_partial, dim3((unsigned)t->nred), dim3(256), 0, st, t->d_red, t->pos, t->pv, t->fax,
-                       t->fay, t->faz, t->fdu, t->fS, t->nngb, t->fn, t->partial);
+                       t->fay, t->faz, t->fdu, t->fS, t->nngb, t->fn, t->owned, t->partial);
     hipLaunchKernelGGL(k_reduce_final, dim3(nblk(t->nsets, 4)), dim3(256), 0, st, t->d_red, (int)t->nred, t->partial,
                        t->nsets, sums_out, t->sums_int);
 }
@@ -1588,13 +1602,13 @@ static void launch_reduce(sph_ctx* ctx, sph_tree* t, double* sums_out) {
 static void launch_scatter_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* o) {
     if (!o || t->n == 0) return;
     hipLaunchKernelGGL(k_scatter_density, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->iperm, t->rho,
-                       t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr, t->ph, *o);
+                       t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr, t->ph, t->owned, *o);
 }
 
 static void launch_scatter_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* o) {
     if (!o || t->n == 0) return;
     hipLaunchKernelGGL(k_scatter_force, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->iperm, t->fax,
-                       t->fay, t->faz, t->fdu, t->fvs, t->fS, t->fn, t->hash ? t->hashf : nullptr, *o);
+                       t->fay, t->faz, t->fdu, t->fvs, t->fS, t->fn, t->hash ? t->hashf : nullptr, t->owned, *o);
 }
 
 // The pair-evaluation counters of a stage start at zero (density: words
@@ -1638,8 +1652,8 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
                            t->dstep, t->rho, t->drho, t->nw, t->dnw, t->nngb, t->hash ? t->hashd : nullptr,
                            t->saved_state());
     } else {
-        hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi,
-                           t->dstep);
+        hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->owned, t->active, t->lo,
+                           t->hi, t->dstep);
     }
     t->saved = false;
     const int nst = 2 + 2 * t->nsets;
@@ -1703,6 +1717,45 @@ Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out) {
     return Err{};
 }
 
+// One GPU's share (Section I: a data decomposition gives each node its part
+// of the data plus the data across the surface it exchanges; Section IV:
+// that exchange becomes tasks): the ownership of every particle in cell
+// order, and the density state of the read-only halo particles as their
+// owners computed it.
+__global__ void k_set_halo(int64_t n, const uint32_t* __restrict__ perm, const uint8_t* __restrict__ owned_in,
+                           const float* __restrict__ rho_in, const float* __restrict__ drho_in,
+                           uint8_t* __restrict__ owned, float* __restrict__ rho, float* __restrict__ drho) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t i = perm[p];
+    const uint8_t o = owned_in[i] ? 1 : 0;
+    owned[p] = o;
+    if (!o) {
+        rho[p] = rho_in[i];
+        drho[p] = drho_in[i];
+    }
+}
+
+Err set_halo(sph_ctx* ctx, sph_tree* t, const uint8_t* owned, const float* rho, const float* drho) {
+    if (!t->built) return Err{SPH_E_STATE, "set_halo before build_cells"};
+    if (!owned) {
+        t->owned = nullptr;
+        t->invalidate_graph();
+        return Err{};
+    }
+    if (!rho || !drho) return Err{SPH_E_ARG, "halo densities missing"};
+    ERRTRY(ensure_state(t));
+    void* p;
+    ERRTRY(t->alloc(t->b_owned, (size_t)std::max<int64_t>(t->n, 1), &p));
+    t->owned = (uint8_t*)p;
+    t->invalidate_graph();
+    if (t->n > 0)
+        hipLaunchKernelGGL(k_set_halo, dim3(nblk(t->n, 256)), dim3(256), 0, ctx->stream, t->n, t->perm, owned, rho, drho,
+                           t->owned, t->rho, t->drho);
+    HIPTRY(hipGetLastError());
+    return Err{};
+}
+
 // caller layout: [0] unconverged total, [1] any rebuild, then per set
 // [2+2s] unconverged, [3+2s] rebuild
 __global__ void k_copy_status(const int32_t* __restrict__ status, int nsets, int32_t* __restrict__ out) {
@@ -1752,8 +1805,8 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
         const int64_t n = t->n;
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->active, t->lo, t->hi,
-                               t->dstep);
+            hipLaunchKernelGGL(k_solve_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, t->owned, t->active, t->lo,
+                               t->hi, t->dstep);
             zero_work(ctx, t, 0, 512);
             const int nst = 2 + 2 * t->nsets;
             hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
