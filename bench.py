@@ -301,9 +301,11 @@ def run(args):
             f"{out['batched']['plain_loop']['value']:.3g} (tuned parameters "
             f"{out['batched']['plain_loop_tuned']['value']:.3g})")
         out["served"] = bench_served(sph)
-        log(f"[bench] served p50 {out['served']['p50_ms']:.2f} ms p99 {out['served']['p99_ms']:.2f} ms, "
-            f"{out['served']['pair_interactions_per_s']:.3g} pairs/s vs plain "
-            f"{out['served']['plain_same_stream']['pair_interactions_per_s']:.3g}")
+        sv = out["served"]
+        log(f"[bench] served p50 {sv['p50_ms']:.2f} ms p99 {sv['p99_ms']:.2f} ms at {sv['load']:.0%} load; "
+            f"saturated {sv['saturation_pair_interactions_per_s']:.3g} pairs/s "
+            f"(mean batch {sv['saturation_mean_batch']:.1f}) vs plain one at a time "
+            f"{sv['plain_same_stream']['pair_interactions_per_s']:.3g}")
     return out
 
 
@@ -469,7 +471,8 @@ def bench_served(sph, n_req=1000, n_warm=50, n_plain=300, pool_size=24, load=0.7
     idx = rng.integers(0, pool_size, size=48)
     burst = [S.Request(i, 0.0, pool[k]) for i, k in enumerate(idx)]
     S.Scheduler(ex, budget, fp, max_batch=16).run(burst[:8])          # warm-up
-    sat = S.summary(S.Scheduler(ex, budget, fp, max_batch=16).run(burst))["requests_per_s"]
+    sat_summ = S.summary(S.Scheduler(ex, budget, fp, max_batch=16).run(burst))
+    sat = sat_summ["requests_per_s"]
     rate = load * sat
     total = n_warm + n_req
     gaps = rng.exponential(1.0 / rate, size=total)
@@ -478,7 +481,9 @@ def bench_served(sph, n_req=1000, n_warm=50, n_plain=300, pool_size=24, load=0.7
     reqs = [S.Request(i, float(a), pool[k]) for i, (a, k) in enumerate(zip(arr, idx))]
     S.Scheduler(ex, budget, fp, max_batch=16).run(reqs)
     summ = S.summary(reqs[n_warm:])
-    summ.update({"saturation_requests_per_s": sat, "arrival_rate_per_s": rate, "load": load,
+    summ.update({"saturation_requests_per_s": sat,
+                 "saturation_pair_interactions_per_s": sat_summ["pair_interactions_per_s"],
+                 "saturation_mean_batch": sat_summ["mean_batch"], "arrival_rate_per_s": rate, "load": load,
                  "warmup_requests": n_warm, "n_range": [10000, 2000000], "pool_sets": pool_size,
                  "budget_bytes": budget})
     # the plain path on the same stream: one request at a time, no batching
@@ -498,6 +503,8 @@ def bench_served(sph, n_req=1000, n_warm=50, n_plain=300, pool_size=24, load=0.7
     tp = time.perf_counter() - t0
     summ["plain_same_stream"] = {"requests": n_plain, "seconds": tp, "pair_interactions_per_s": 2 * pairs / tp,
                                  "requests_per_s": n_plain / tp}
+    summ["saturation_speedup_vs_plain"] = summ["saturation_pair_interactions_per_s"] / (2 * pairs / tp)
+    ex.close()
     return summ
 
 

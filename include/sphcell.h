@@ -259,8 +259,11 @@ sph_status sph_set_halo(sph_ctx* ctx, sph_tree* t, const uint8_t* owned, const f
 
 /* Enqueue the whole post-build pipeline -- density/Newton iterations with
  * device-side early exit (k_iter of them), ghost, force and sums -- as one
- * HIP graph on the context's stream (captured on first use, relaunched
- * afterwards while the tree and the output pointers are unchanged).  Does
+ * HIP graph on the context's stream: captured and instantiated on first use,
+ * and replayed -- also after a new build -- as long as everything it
+ * captured is unchanged (output pointers, k_iter, particle / set / chunk /
+ * cell counts, parameters and the tree's device buffers, which keep their
+ * place in a workspace that does not grow).  Does
  * not synchronise.  n_unconverged_dev [device int32[2 + 2*nsets]] receives
  * [0] the particles still unconverged after the graph, [1] 1 if some h_i
  * outgrew its cells, then per set s: [2+2s] unconverged, [3+2s] rebuild
@@ -316,8 +319,9 @@ void sph_enable_timing(sph_ctx* ctx, int32_t on);
 
 /* Tree statistics (host): [0] particles, [1] cells, [2] leaves, [3] tasks
  * (self + pair), [4] pair tasks, [5] sorted entries, [6] work chunks,
- * [7] levels, [8] top cells per side of set 0, [9] max leaf size.  May
- * synchronise the device (a count the sort kept on the device). */
+ * [7] levels, [8] top cells per side of set 0, [9] max leaf size, [10] HIP
+ * graphs captured and instantiated by sph_run_graph on this tree so far.
+ * May synchronise the tree's stream (a count the sort kept on the device). */
 sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap);
 
 #ifdef __cplusplus

@@ -418,10 +418,10 @@ class Tree:
                                                C.byref(self._gf), _ptr(unconv)), "sph_run_graph")
 
     def stats(self) -> dict:
-        v = (C.c_int64 * 10)()
-        self.ctx.check(lib().sph_tree_stats(self.h, v, 10), "sph_tree_stats")
+        v = (C.c_int64 * 11)()
+        self.ctx.check(lib().sph_tree_stats(self.h, v, 11), "sph_tree_stats")
         keys = ["particles", "cells", "leaves", "tasks", "pair_tasks", "sorted_entries", "chunks", "levels",
-                "top_grid", "max_leaf"]
+                "top_grid", "max_leaf", "graph_captures"]
         return dict(zip(keys, [int(x) for x in v]))
 
     def bytes(self) -> int:

@@ -318,7 +318,7 @@ sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap) {
             return SPH_E_HIP;
         const_cast<sph_tree*>(t)->nsegent = v;
     }
-    int64_t v[10] = {t->n,
+    int64_t v[11] = {t->n,
                      t->ncells,
                      t->nleaves,
                      t->ntasks,
@@ -327,8 +327,9 @@ sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap) {
                      t->nchunks,
                      t->nlevels,
                      t->sets.empty() ? 0 : (int64_t)1 << t->sets[0].lgG,
-                     t->max_leaf};
-    for (int i = 0; i < cap && i < 10; ++i) stats[i] = v[i];
+                     t->max_leaf,
+                     t->graph_captures};
+    for (int i = 0; i < cap && i < 11; ++i) stats[i] = v[i];
     return SPH_OK;
 }
 

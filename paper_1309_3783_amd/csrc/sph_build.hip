@@ -1083,7 +1083,6 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     t->built = t->sorted = t->have_density = false;
     t->owned = nullptr;   // a halo is set after every build
     t->hash = (prm->flags & SPH_FLAG_PAIR_HASH) != 0;
-    t->invalidate_graph();
     ev_mark(ctx, "start");
 
     // ---- per-set h statistics -> top grids ------------------------------
@@ -1418,7 +1417,6 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
 Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     hipStream_t st = ctx->stream;
     if (!t->built) return Err{SPH_E_STATE, "sort_pairs before build_cells"};
-    t->invalidate_graph();
     ev_mark(ctx, "start");
     const int64_t nc = t->ncells;
     const int64_t nca = nc * NAXES;

@@ -192,6 +192,7 @@ struct sph_tree {
     // graph
     hipGraphExec_t gexec = nullptr;
     std::vector<const void*> gkey;
+    int64_t graph_captures = 0;   // captures and instantiations so far (replays are not counted)
 
     ~sph_tree() { release(); }
 

@@ -38,6 +38,7 @@
 // cost the force kernel a wave per SIMD); the recursive-sum bound keeps them
 // within their bars up to ~1600 neighbours.
 #include <cmath>
+#include <cstring>
 
 #include "sph_impl.h"
 
@@ -1794,7 +1795,30 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
                          fout ? fout->nforce : nullptr, fout ? fout->hash : nullptr, fout ? fout->sums : nullptr};
     key.insert(key.end(), dk, dk + 7);
     key.insert(key.end(), fk, fk + 9);
+    // everything else the captured launches take: sizes, launch shapes,
+    // parameters and the device buffers.  A build that leaves all of them
+    // as they were (the same sets again, the buffers in place, as in a
+    // batched step repeated on a workspace) replays the instantiated graph;
+    // the kernels read the new data from the same buffers.
+    auto val = [&](uint64_t v) { key.push_back((const void*)(uintptr_t)v); };
+    auto fbits = [](float f) { uint32_t u; std::memcpy(&u, &f, 4); return (uint64_t)u; };
+    val((uint64_t)t->n);
+    val((uint64_t)t->nsets);
+    val((uint64_t)t->nchunks);
+    val((uint64_t)t->ncells);
+    val((uint64_t)t->nred);
+    val(t->hash ? 1 : 0);
+    val(fbits(t->prm.alpha) | (fbits(t->prm.gamma) << 32));
+    val(fbits(t->prm.n_target) | (fbits(t->prm.h_tol) << 32));
+    val((uint64_t)(uint32_t)t->prm.blocks_per_cu | ((uint64_t)(uint32_t)t->prm.max_replicas << 32));
+    val((uint64_t)ctx->n_cu);
+    const void* ptrs[] = {ctx->d_counter, t->d_sets, t->cells, t->chunks, t->csr, t->csr_off, t->segoff,
+                          t->segpos, t->segidx, t->pos, t->plo, t->pv, t->ph, t->pu, t->bound, t->mix, t->iperm,
+                          t->perm, t->owned, t->rho, t->hashd, t->lo, t->active, t->alist, t->status, t->frec,
+                          t->hashf, t->partial, t->d_red, t->sums_int, t->part_cnt};
+    key.insert(key.end(), ptrs, ptrs + sizeof(ptrs) / sizeof(ptrs[0]));
     if (!t->gexec || key != t->gkey) {
+        ++t->graph_captures;
         t->invalidate_graph();
         if (!ctx->cap_stream) HIPTRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         hipStream_t user = ctx->stream;

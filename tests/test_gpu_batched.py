@@ -110,6 +110,36 @@ def test_graph_replays_match(sph, ctx):
         del junk
 
 
+def test_graph_replayed_across_builds(sph, ctx):
+    """The batched step repeated on the same sets: every build after the
+    first leaves the graph's buffers, sizes and parameters as they were, so
+    the instantiated graph is replayed (no new capture) and gives bitwise the
+    first step's results; another batch makes a new graph."""
+    from paper_1309_3783_amd import pipeline as P
+    sets = [sphinputs.plummer_mixture(int(n), 1400 + k) for k, n in enumerate([3000, 21000, 7000, 40000])]
+    batch = sph.batch_from_sets(sets)
+    prm = sph.params()
+    tree = sph.Tree(ctx)
+    out = P.Outputs(batch.n, batch.nsets)
+    P.run_graph(tree, batch, prm, out, 16)
+    torch.cuda.synchronize()
+    first = [grab(out, batch, s) for s in range(batch.nsets)]
+    c0 = tree.stats()["graph_captures"]
+    for _ in range(3):
+        P.run_graph(tree, batch, prm, out, 16)
+        torch.cuda.synchronize()
+        for s in range(batch.nsets):
+            same(first[s], grab(out, batch, s))
+    assert tree.stats()["graph_captures"] == c0
+    other = sph.batch_from_sets(sets[:3])
+    out2 = P.Outputs(other.n, other.nsets)
+    P.run_graph(tree, other, prm, out2, 16)
+    torch.cuda.synchronize()
+    assert tree.stats()["graph_captures"] == c0 + 1
+    for s in range(other.nsets):
+        same(first[s], grab(out2, other, s))
+
+
 def test_batched_sets_equal_alone(sph, ctx):
     from paper_1309_3783_amd import pipeline as P
     sets = [sphinputs.plummer_mixture(int(n), 1000 + k) for k, n in enumerate([2000, 31000, 5000, 120000, 2600])]
@@ -172,6 +202,8 @@ def test_served_mix_equals_alone(sph):
         S.Scheduler(alone_ex, budget_bytes=2 << 30, footprint=lambda x: 1, max_batch=1).run([q])
         same(r.result, q.result)
         assert q.batch_size == 1
+    ex.close()
+    alone_ex.close()
     # every request against the oracle at the h the GPU solved (the oracle
     # accepts that h: N_w within 48 +- 0.5 in FP64), density and force
     # element by element

@@ -69,3 +69,18 @@ def test_request_larger_than_budget_is_rejected():
         assert "exceeds the whole budget" in str(e)
     else:
         raise AssertionError("expected a rejection")
+
+
+def test_retained_lane_memory_is_charged():
+    # each lane keeps 250 KB once used; with a 600 KB budget and 100 KB
+    # requests the first two batches take 4 and 2 requests; after that both
+    # lanes retain 250 KB, so a batch may take at most 600 - 250 = 350 KB of
+    # the budget (three requests) where it could take four without the charge
+    reqs = make([1000] * 12, [0.0] * 12)
+    ex = FakeExecutor(lanes=2, base=0.01, per_particle=0.0, retained=250_000)
+    sch = Scheduler(ex, budget_bytes=600_000, footprint=fp, max_batch=4)
+    sch.run(reqs)
+    assert all(r.t_done > 0 for r in reqs)
+    assert max(u for _, _, u in sch.log) <= 600_000
+    assert [n for _, n, _ in sch.log[:2]] == [4, 2]
+    assert len(sch.log) > 2 and max(n for _, n, _ in sch.log[2:]) <= 3
