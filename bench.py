@@ -292,6 +292,8 @@ def run(args):
             f"pair counts equal: {out['cpu_baseline']['pairs_check']}")
     else:
         out["cpu_baseline"] = None
+    if args.config == "plain" and not args.quick:
+        out["reuse"] = bench_reuse(sph, ps, dt=1e-3)
     del m
     if args.config == "plain" and not args.quick:
         out["multires"] = bench_multires(sph, args)
@@ -330,7 +332,73 @@ def bench_multires(sph, args, steps=3, warmup=1):
                                            budget_s=args.cpu_budget, check_max=5000)
     del m
     torch.cuda.empty_cache()
+    res["reuse"] = bench_reuse(sph, ps, dt=2e-6)
     return res
+
+
+def with_velocities(ps, seed=17, vmax=0.1):
+    """A copy of the set with velocities uniform in [-vmax, vmax] (FP32)."""
+    import sphinputs
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(-vmax, vmax, size=(ps.n, 3)).astype(np.float32).astype(np.float64)
+    return sphinputs.ParticleSet(ps.x, ps.y, ps.z, ps.m, ps.u, v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy(),
+                                 ps.h0, ps.box, dict(ps.meta))
+
+
+def bench_reuse(sph, ps, dt, steps=10):
+    """Cells and sorted lists reused over time steps (Section II-C) against a
+    build and sort every step, on the same sequence of states: the set drifts
+    by x += dt v between steps (sph_drift; velocities uniform in [-0.1, 0.1]
+    where the set has none) and each step solves h from the previous step's h
+    and computes the forces.  dt is chosen so the displacement bound stays
+    inside the cells' margin for all the steps (the refresh path would
+    otherwise fall back to a build, which it counts)."""
+    import dataclasses
+    import torch
+    if not np.any(ps.vx):
+        ps = with_velocities(ps)
+    prm = sph.params()
+    out = {"dt": dt, "steps": steps}
+    for reuse in (False, True):
+        ctx = sph.Context(0)
+        b = sph.batch_from_sets([ps])
+        d = sph.DensityOut(b.n, "cuda")
+        f = sph.ForceOut(b.n, 1, "cuda")
+        tree = sph.Tree(ctx)
+        st, _, _ = sph.solve_with_rebuild(tree, b, prm, d)
+        tree.force(f)
+        builds0 = tree.builds
+        torch.cuda.synchronize()
+        ctx.enable_timing(True)
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(steps):
+            sph.drift(ctx, b, dt)
+            b.h.copy_(d.h)
+            st, nu, it = sph.solve_with_rebuild(tree, b, prm, d, refresh=reuse)
+            if st not in (sph.SPH_OK, sph.SPH_E_NOCONV):
+                raise RuntimeError(f"solve failed: status {st}")
+            its += it
+            tree.force(f)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.enable_timing(False)
+        stage = {}
+        for name, ms in ctx.timings():
+            if name != "start":
+                stage[name] = stage.get(name, 0.0) + ms / steps
+        key = "reuse" if reuse else "rebuild"
+        out[key] = {"ms_per_step": (t1 - t0) * 1e3 / steps, "builds": tree.builds - builds0,
+                    "refreshes": getattr(tree, "refreshes", 0), "newton_passes": its / steps, "stages_ms": stage}
+        del tree, d, f, b
+        torch.cuda.empty_cache()
+    out["speedup"] = out["rebuild"]["ms_per_step"] / out["reuse"]["ms_per_step"]
+    log(f"[bench] reuse over {steps} steps of dt {dt:g}: {out['reuse']['ms_per_step']:.2f} ms/step "
+        f"({out['reuse']['refreshes']} refreshes, {out['reuse']['builds']} builds; refresh "
+        f"{out['reuse']['stages_ms'].get('refresh', 0.0):.3f} ms) vs build + sort every step "
+        f"{out['rebuild']['ms_per_step']:.2f} ms/step (build {out['rebuild']['stages_ms'].get('build', 0.0):.3f}, "
+        f"sort {out['rebuild']['stages_ms'].get('sort', 0.0):.3f} ms)")
+    return out
 
 
 def bench_share(sph, steps=10, warmup=2):

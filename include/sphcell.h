@@ -218,6 +218,26 @@ sph_status sph_build_cells_static(sph_ctx* ctx, sph_tree* t, const sph_input* in
  * sorts themselves are enqueued after that and not waited for. */
 sph_status sph_sort_pairs(sph_ctx* ctx, sph_tree* t);
 
+/* Section II-C, last paragraph (the sorted indices reused over several time
+ * steps until the decomposition must be made again): new particle data for
+ * the tree's particles -- the same sets, offsets and boxes, the same caller
+ * order as the input of the last sph_build_cells, device pointers laid out as
+ * for sph_build_cells (h is the starting h, as there) -- taken without
+ * building or sorting again.  Every particle keeps its cell, its place in
+ * cell order and its place in each sorted list; positions are stored
+ * relative to the origin of the top cell they were built in (nearest
+ * periodic image).  Each set keeps a bound d on any particle's displacement
+ * since the build (the largest displacement of every refresh, added up); the
+ * density and force sweeps then reach 2 d further along the pair axis, so the
+ * lists' build-time order still yields every pair, and the largest h the
+ * cells support shrinks by 2 d.  A halo set by sph_set_halo stays set.
+ * Synchronises the stream once (one count read back).
+ * Errors: SPH_E_STATE (no build), SPH_E_ARG (null arrays, sets, offsets or
+ * boxes unlike the build's), SPH_E_REBUILD (some particle's h is at or beyond
+ * what its cells support after the displacement: the tree is left unbuilt,
+ * call sph_build_cells), SPH_E_HIP. */
+sph_status sph_refresh_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in);
+
 /* Density stage (Section II, item 1) for every particle at its current h.
  * Requires sph_sort_pairs. */
 sph_status sph_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out);

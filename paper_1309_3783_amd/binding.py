@@ -24,7 +24,7 @@ SPH_FLAG_RESUME = 2
 EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
            "sph_last_error", "sph_workspace_size", "sph_footprint", "sph_tree_create", "sph_tree_destroy",
            "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
-           "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_set_halo",
+           "sph_build_cells_static", "sph_refresh_cells", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_set_halo",
            "sph_run_graph", "sph_last_timings", "sph_last_work", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
 
 
@@ -92,6 +92,7 @@ def lib():
         L.sph_tree_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.sph_build_cells.argtypes = [vp, vp, C.POINTER(sph_input), C.POINTER(sph_params)]
         L.sph_sort_pairs.argtypes = [vp, vp]
+        L.sph_refresh_cells.argtypes = [vp, vp, C.POINTER(sph_input)]
         L.sph_density.argtypes = [vp, vp, C.POINTER(sph_density_out)]
         L.sph_solve_h.argtypes = [vp, vp, C.POINTER(sph_density_out), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32)]
@@ -110,7 +111,8 @@ def lib():
         L.sph_cfl_dt.argtypes = [vp, C.c_int64, vp, vp, C.c_float, C.POINTER(C.c_double)]
         for name in ("sph_ctx_create", "sph_footprint", "sph_workspace_size", "sph_tree_create", "sph_tree_bytes",
                      "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
-                     "sph_build_cells_static", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force",
+                     "sph_build_cells_static", "sph_refresh_cells", "sph_sort_pairs", "sph_density", "sph_solve_h",
+                     "sph_force",
                      "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt", "sph_last_work",
                      "sph_set_halo"):
             getattr(L, name).restype = st
@@ -340,7 +342,10 @@ class Tree:
     def build_cells(self, batch: Batch, prm: sph_params | None = None, h=None):
         self.batch = batch
         self.prm = prm or params()
+        self._h_ref = h
         self._in = batch.as_input(h)
+        self.builds = getattr(self, "builds", 0) + 1
+        self._built = False
         self._sorted = False
         if self.use_ws:
             want = workspace_size(batch.n, batch.nsets, self.prm)
@@ -348,6 +353,7 @@ class Tree:
                 self.set_workspace(max(want, 0 if self.ws is None else 2 * self.ws.numel()))
         self._call(lambda: lib().sph_build_cells(self.ctx.h, self.h, C.byref(self._in), C.byref(self.prm)),
                    "sph_build_cells")
+        self._built = True
 
     def _call(self, fn, what, ok=(SPH_OK,)):
         """Run a library call; with a workspace, a call that ran out of it is
@@ -382,6 +388,29 @@ class Tree:
         self._in = batch.as_input(h)
         self.ctx.check(lib().sph_build_cells_static(self.ctx.h, self.h, C.byref(self._in), C.byref(self.prm)),
                        "sph_build_cells_static")
+
+    def refresh(self, batch: Batch, h=None) -> bool:
+        """sph_refresh_cells: the tree's particles take the batch's new data
+        (the sets and caller order of the last build) without a new build or
+        sort.  Returns False when the cells no longer support the particles'
+        h after their displacement since the build: the tree must then be
+        built again."""
+        self.batch = batch
+        self._h_ref = h
+        self._in = batch.as_input(h)
+        st = self._call(lambda: lib().sph_refresh_cells(self.ctx.h, self.h, C.byref(self._in)),
+                        "sph_refresh_cells", ok=(SPH_OK, SPH_E_REBUILD))
+        if st == SPH_OK:
+            self.refreshes = getattr(self, "refreshes", 0) + 1
+        else:
+            self._built = False      # the library left the tree unbuilt
+        return st == SPH_OK
+
+    def same_layout(self, batch: Batch) -> bool:
+        """Built, and for sets with the batch's offsets and boxes."""
+        b = self.batch
+        return (getattr(self, "_built", False) and b is not None and b.nsets == batch.nsets and np.array_equal(b.offsets, batch.offsets)
+                and np.array_equal(np.asarray(b.box, dtype=np.float64), np.asarray(batch.box, dtype=np.float64)))
 
     def sort_pairs(self):
         self._sorted = False
@@ -431,18 +460,25 @@ class Tree:
 
 
 def solve_with_rebuild(tree: Tree, batch: Batch, prm: sph_params, dout: DensityOut, max_rebuilds: int = 4,
-                       halo=None):
+                       halo=None, refresh: bool = False):
     """build -> sort -> solve_h, rebuilding with the current h when h outgrows
     the cells (the library reports it; the rebuild itself runs on the GPU).
-    halo: (owned, rho, drho_dh) of one GPU's share, set after every build."""
+    halo: (owned, rho, drho_dh) of one GPU's share, set after every build.
+    refresh: first try to keep the tree's cells and sorted lists (a tree
+    built for the same sets, whose particles moved since): the build and sort
+    run only if the refresh is refused or h then outgrows the cells."""
     h = batch.h
     total_it = 0
     p = prm
-    for _ in range(max_rebuilds + 1):
-        tree.build_cells(batch, p, h=h)
-        if halo is not None:
-            tree.set_halo(*halo)
-        tree.sort_pairs()
+    for k in range(max_rebuilds + 1):
+        if k == 0 and refresh and tree.same_layout(batch) and tree.refresh(batch, h=h):
+            if halo is not None:
+                tree.set_halo(*halo)
+        else:
+            tree.build_cells(batch, p, h=h)
+            if halo is not None:
+                tree.set_halo(*halo)
+            tree.sort_pairs()
         st, nu, it = tree.solve_h(dout)
         total_it += it
         if st == SPH_E_REBUILD:

@@ -225,6 +225,13 @@ sph_status sph_build_cells_static(sph_ctx* ctx, sph_tree* t, const sph_input* in
     return fail(ctx, sph::build_tree(ctx, t, in, p));
 }
 
+sph_status sph_refresh_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in) {
+    if (!ctx || !t) return SPH_E_ARG;
+    if (sph_status s = check_tree(ctx, t)) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPH_E_HIP;
+    return fail(ctx, sph::refresh_tree(ctx, t, in));
+}
+
 sph_status sph_sort_pairs(sph_ctx* ctx, sph_tree* t) {
     if (!ctx || !t) return SPH_E_ARG;
     if (sph_status s = check_tree(ctx, t)) return s;

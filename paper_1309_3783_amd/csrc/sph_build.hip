@@ -553,18 +553,116 @@ __global__ void k_chunk_emit(const Cell* __restrict__ cells, int64_t nc, const u
 }
 
 // One wave per chunk (the chunk count is read on the device).
+// The bound of a particle is the smallest bound of its leaf and ancestors,
+// less twice its set's accumulated displacement since the build (zero right
+// after a build): two particles that moved by at most d each and interact
+// now were within h + 2d at the build, and the cells only guarantee pairs
+// closer than their bound.  With viol given, the particles whose current h
+// is not below their bound are counted there.
 __global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__ chunks,
                                                         const uint32_t* __restrict__ nch_dev,
-                                                        const Cell* __restrict__ cells,
-                                                        float* __restrict__ bound) {
+                                                        const Cell* __restrict__ cells, const SetInfo* sets,
+                                                        const float* __restrict__ ph, float* __restrict__ bound,
+                                                        uint32_t* __restrict__ viol) {
     const int64_t nch = *nch_dev;
     const int lane = threadIdx.x & 63;
     for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nch; q += (int64_t)gridDim.x * 4) {
         const int4 ch = chunks[q];
         float b = INFINITY;
         for (int A = ch.x; A >= 0; A = cells[A].parent) b = fminf(b, cells[A].bound);
+        const float d = sets[cells[ch.x].set].drift;
+        if (d > 0.f) b -= 2.f * d;
         if (lane < ch.z) bound[ch.y + lane] = b;
+        if (viol) {
+            const bool bad = lane < ch.z && !(ph[ch.y + lane] < b);
+            const uint64_t m = __ballot(bad);
+            if (lane == 0 && m) atomicAdd(viol, (uint32_t)__popcll(m));
+        }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Reuse of a built tree over time steps (Section II-C: the sorted indices
+// are kept until the decomposition has to be made again).  The particles
+// keep their cells, their place in cell order and their place in every
+// sorted list; only their data are replaced.
+// ---------------------------------------------------------------------------
+
+// New data of every particle of a chunk (one wavefront per chunk): the
+// position as FP32 offset from the origin of the top cell it was built in
+// (nearest periodic image) plus FP32 remainder, h, m, u, v.  The largest
+// displacement against the stored position is folded into stepmax[set]
+// (non-negative floats compare like their bit patterns).
+__global__ __launch_bounds__(256) void k_refresh(const int4* __restrict__ chunks, const uint32_t* __restrict__ nch_dev,
+                                                 const Cell* __restrict__ cells, const SetInfo* sets,
+                                                 const uint32_t* __restrict__ perm, const double* __restrict__ x,
+                                                 const double* __restrict__ y, const double* __restrict__ z,
+                                                 const float* __restrict__ h, const float* __restrict__ m,
+                                                 const float* __restrict__ u, const float* __restrict__ vx,
+                                                 const float* __restrict__ vy, const float* __restrict__ vz,
+                                                 float slack, float4* __restrict__ pos, float4* __restrict__ plo,
+                                                 float* __restrict__ ph, float* __restrict__ hdec,
+                                                 float* __restrict__ pu, float4* __restrict__ pv,
+                                                 unsigned* __restrict__ stepmax) {
+    const int64_t nch = *nch_dev;
+    const int lane = threadIdx.x & 63;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nch; q += (int64_t)gridDim.x * 4) {
+        const int4 ch = chunks[q];
+        int A = ch.x;
+        while (cells[A].parent >= 0) A = cells[A].parent;
+        const Cell T = cells[A];
+        const SetInfo S = sets[T.set];
+        double d2 = 0.0;
+        if (lane < ch.z) {
+            const int64_t p = ch.y + lane;
+            const uint32_t i = perm[p];
+            const double xs[3] = {x[i], y[i], z[i]};
+            const int tc[3] = {T.ix, T.iy, T.iz};
+            const float4 o0 = pos[p], l0 = plo[p];
+            const double old[3] = {(double)o0.x + (double)l0.x, (double)o0.y + (double)l0.y,
+                                   (double)o0.z + (double)l0.z};
+            float o[3], lo[3];
+            for (int d = 0; d < 3; ++d) {
+                double off = xs[d] - S.box * floor(xs[d] / S.box) - (double)tc[d] * S.L0;
+                off -= S.box * rint(off / S.box);
+                o[d] = (float)off;
+                lo[d] = (float)(off - (double)o[d]);
+                const double dd = off - old[d];
+                d2 += dd * dd;
+            }
+            pos[p] = make_float4(o[0], o[1], o[2], m[i]);
+            plo[p] = make_float4(lo[0], lo[1], lo[2], 0.f);
+            const float hh = h[i];
+            ph[p] = hh;
+            hdec[p] = hh * (1.0f + slack);
+            pu[p] = u[i];
+            pv[p] = make_float4(vx[i], vy[i], vz[i], 0.f);
+        }
+        // rounded up so that the bound stays a bound
+        float dm = (float)sqrt(d2);
+        if ((double)dm < sqrt(d2)) dm = nextafterf(dm, INFINITY);
+        dm = wave_max_f(dm);
+        if (lane == 0 && dm > 0.f) atomicMax(&stepmax[T.set], __float_as_uint(dm));
+    }
+}
+
+__global__ void k_drift_add(SetInfo* sets, int nsets, const unsigned* __restrict__ stepmax) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsets) return;
+    // rounded up: the sum stays a bound on the displacement since the build
+    const float a = sets[s].drift, b = __uint_as_float(stepmax[s]);
+    float t = a + b;
+    if ((double)t < (double)a + (double)b) t = nextafterf(t, INFINITY);
+    sets[s].drift = t;
+}
+
+// Sorted lists: each entry's copy of its particle's record, in place (the
+// order of the list is the one of the build).
+__global__ void k_seg_refresh(const uint32_t* __restrict__ segidx, int64_t ne, const uint32_t* __restrict__ ne_dev,
+                              const float4* __restrict__ pos, float4* __restrict__ segpos) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne || (ne_dev && e >= (int64_t)*ne_dev)) return;
+    segpos[e] = pos[segidx[e]];
 }
 
 // ---------------------------------------------------------------------------
@@ -1101,6 +1199,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         sets[s].first = in->offsets[s];
         sets[s].count = in->offsets[s + 1] - in->offsets[s];
         sets[s].box = in->box[s];
+        sets[s].drift = 0.f;
     }
     HIPTRY(hipMemcpyAsync(d_sets, sets.data(), sizeof(SetInfo) * S, hipMemcpyHostToDevice, st));
     std::vector<float> hmax(S, 0.f), hmin(S, INFINITY);
@@ -1352,7 +1451,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     HIPTRY(hipGetLastError());
     if (t->n > 0) {
         hipLaunchKernelGGL(k_particle_bound, dim3((unsigned)std::min<int64_t>(nblk(chunk_cap, 4), 8192)), dim3(256),
-                           0, st, t->chunks, total, t->cells, t->bound);
+                           0, st, t->chunks, total, t->cells, d_sets, t->ph, t->bound, nullptr);
         HIPTRY(hipGetLastError());
     }
 
@@ -1411,6 +1510,64 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     t->npairs = nfinal - t->nleaves;
     t->built = true;
     ev_mark(ctx, "build");
+    return Err{};
+}
+
+Err refresh_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in) {
+    hipStream_t st = ctx->stream;
+    if (!t->built) return Err{SPH_E_STATE, "refresh before build_cells"};
+    if (!in) return Err{SPH_E_ARG, "null input"};
+    if (in->nsets != t->nsets || !in->offsets || !in->box)
+        return Err{SPH_E_ARG, "refresh: the sets differ from the build's"};
+    for (int s = 0; s <= t->nsets; ++s)
+        if (in->offsets[s] != t->off[s]) return Err{SPH_E_ARG, "refresh: set offsets differ from the build's"};
+    for (int s = 0; s < t->nsets; ++s)
+        if (in->box[s] != t->sets[s].box) return Err{SPH_E_ARG, "refresh: box differs from the build's"};
+    const int64_t n = t->n;
+    if (n > 0 && (!in->x || !in->y || !in->z || !in->h || !in->m || !in->u || !in->vx || !in->vy || !in->vz))
+        return Err{SPH_E_ARG, "null particle array"};
+    ev_mark(ctx, "start");
+    t->have_density = t->have_ghost = false;
+    if (n == 0) {
+        ev_mark(ctx, "refresh");
+        return Err{};
+    }
+    const int S = t->nsets;
+    // the small per-set buffer of the build: S step maxima, the violation
+    // count, the chunk count
+    unsigned* stepmax = (unsigned*)t->b_small.p;
+    uint32_t* viol = stepmax + S;
+    uint32_t* nchw = viol + 1;
+    HIPTRY(fill_u32(stepmax, S + 1, 0u, st));
+    HIPTRY(fill_u32(nchw, 1, (uint32_t)t->nchunks, st));
+    const unsigned gch = (unsigned)std::min<int64_t>(nblk(t->nchunks, 4), 8192);
+    hipLaunchKernelGGL(k_refresh, dim3(gch), dim3(256), 0, st, t->chunks, nchw, t->cells, t->d_sets, t->perm, in->x,
+                       in->y, in->z, in->h, in->m, in->u, in->vx, in->vy, in->vz, t->prm.h_slack, t->pos, t->plo,
+                       t->ph, t->hdec, t->pu, t->pv, stepmax);
+    HIPTRY(hipGetLastError());
+    hipLaunchKernelGGL(k_drift_add, dim3(nblk(S, 256)), dim3(256), 0, st, t->d_sets, S, stepmax);
+    HIPTRY(hipGetLastError());
+    hipLaunchKernelGGL(k_particle_bound, dim3(gch), dim3(256), 0, st, t->chunks, nchw, t->cells, t->d_sets, t->ph,
+                       t->bound, viol);
+    HIPTRY(hipGetLastError());
+    if (t->sorted) {
+        const int64_t ne = t->nsegent >= 0 ? t->nsegent : (int64_t)NAXES * n;
+        if (ne > 0) {
+            hipLaunchKernelGGL(k_seg_refresh, dim3(nblk(ne, 256)), dim3(256), 0, st, t->segidx, ne,
+                               t->nsegent >= 0 ? nullptr : t->d_counts, t->pos, t->segpos);
+            HIPTRY(hipGetLastError());
+        }
+    }
+    const void* rb;
+    ERRTRY(read_back(ctx, viol, sizeof(uint32_t), &rb));
+    const uint32_t nv = ((const uint32_t*)rb)[0];
+    if (nv > 0) {
+        // the tree no longer covers every pair: nothing may run on it
+        t->built = t->sorted = false;
+        return Err{SPH_E_REBUILD, std::to_string(nv) + " particles have h at or beyond what the cells support after "
+                                                        "the displacement since the build: build again"};
+    }
+    ev_mark(ctx, "refresh");
     return Err{};
 }
 

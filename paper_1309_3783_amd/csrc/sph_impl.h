@@ -415,6 +415,7 @@ inline void ev_mark(sph_ctx* ctx, const char* name) {
 
 Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* prm);
 Err sort_pairs(sph_ctx* ctx, sph_tree* t);
+Err refresh_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in);
 Err run_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out);
 Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_unconv, int32_t* iters);
 Err run_force(sph_ctx* ctx, sph_tree* t, const sph_force_out* out);

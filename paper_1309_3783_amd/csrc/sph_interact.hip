@@ -490,8 +490,13 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
         const float Dx = g.Sx - oA.x, Dy = g.Sy - oA.y, Dz = g.Sz - oA.z;
         f0 = make_float4(Dx, Dy, Dz, r0 * r0);
         f1 = make_float4(Dx, Dy, Dz, r1 * r1);
-        lim0 = tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny);
-        lim1 = tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny);
+        // after a refresh the partner list is in the order of the build and
+        // each entry's projection has moved by at most dn times the set's
+        // displacement bound d: every entry within lim lies in the prefix
+        // whose entries pass lim + 2 d dn, which the bisection still finds
+        const float dr = 2.f * a.sets[cA.set].drift * g.dn;
+        lim0 = tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny) + dr;
+        lim1 = tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny) + dr;
     }
     // the swept prefix of each part: the first record (in sweep order)
     // beyond the limit, by bisection

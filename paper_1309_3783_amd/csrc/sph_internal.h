@@ -94,6 +94,8 @@ struct SetInfo {
     int32_t top_base;  // id of the first top cell of this set
     int32_t key_shift; // left shift that aligns this set's Morton code in the key
     int32_t depth;     // levels below the top grid the keys resolve for this set
+    float drift;       // bound on any particle's displacement since the build (refreshes add up)
+    float pad_;
 };
 
 // One cell of the hierarchy (all levels and sets in one table).  Cells of a

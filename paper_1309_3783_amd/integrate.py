@@ -25,14 +25,19 @@ class Leapfrog:
     """State of one batch under time integration (device tensors, caller
     order).  The batch's x, y, z, vx, vy, vz, u are advanced in place."""
 
-    def __init__(self, ctx: B.Context, batch: B.Batch, prm=None, c_cfl: float = 0.3, solve_h: bool = True):
+    def __init__(self, ctx: B.Context, batch: B.Batch, prm=None, c_cfl: float = 0.3, solve_h: bool = True,
+                 reuse: bool = False):
         """solve_h False: the smoothing lengths stay at batch.h (density
-        without the Newton solve), as in a comparison at fixed h."""
+        without the Newton solve), as in a comparison at fixed h.
+        reuse: keep the cells and sorted lists from step to step while they
+        still cover the moved particles (sph_refresh_cells), building them
+        again only when the library refuses the refresh or h outgrows them."""
         import torch
         self.ctx, self.b = ctx, batch
         self.prm = prm or B.params()
         self.c_cfl = float(c_cfl)
         self.solve = solve_h
+        self.reuse = reuse
         self.tree = B.Tree(ctx)
         self.d = B.DensityOut(batch.n, batch.x.device)
         self.f = B.ForceOut(batch.n, batch.nsets, batch.x.device)
@@ -46,13 +51,14 @@ class Leapfrog:
     def _forces(self, vx, vy, vz, u, h):
         view = dataclasses.replace(self.b, vx=vx, vy=vy, vz=vz, u=u, h=h, keep=[])
         if self.solve:
-            st, nu, it = B.solve_with_rebuild(self.tree, view, self.prm, self.d)
+            st, nu, it = B.solve_with_rebuild(self.tree, view, self.prm, self.d, refresh=self.reuse)
             if st not in (B.SPH_OK, B.SPH_E_NOCONV):
                 raise B.SphError(st, "solve_h during time integration")
             self.newton_iterations += it
         else:
-            self.tree.build_cells(view, self.prm)
-            self.tree.sort_pairs()
+            if not (self.reuse and self.tree.same_layout(view) and self.tree.refresh(view)):
+                self.tree.build_cells(view, self.prm)
+                self.tree.sort_pairs()
             self.tree.density(self.d)
         self.tree.force(self.f)
 

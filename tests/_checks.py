@@ -48,9 +48,12 @@ def check_density(ps, h, g, r):
     assert rel.max() <= RHO_TOL, f"rho rel err {rel.max():.3g}"
     reln = np.abs(g["nw"] - r["nw"]) / r["nw"]
     assert reln.max() <= RHO_TOL, f"N_w rel err {reln.max():.3g}"
-    # derivatives have mixed-sign terms: scale by their natural size 3 rho / h
-    e1 = np.abs(g["drho_dh"] - r["drho_dh"]) / (3 * r["rho"] / h)
-    e2 = np.abs(g["dnw_dh"] - r["dnw_dh"]) / (3 * r["nw"] / h)
+    # derivatives: relative to their own size, floored at their natural
+    # size 3 rho / h (their terms have mixed signs, so the value can sit near
+    # zero; and where many neighbours sit close to the cutoff the value is
+    # many times the natural size)
+    e1 = np.abs(g["drho_dh"] - r["drho_dh"]) / np.maximum(3 * r["rho"] / h, np.abs(r["drho_dh"]))
+    e2 = np.abs(g["dnw_dh"] - r["dnw_dh"]) / np.maximum(3 * r["nw"] / h, np.abs(r["dnw_dh"]))
     assert e1.max() <= RHO_TOL and e2.max() <= RHO_TOL, (e1.max(), e2.max())
 
 
