@@ -548,8 +548,10 @@ __global__ void k_chunk_emit(const Cell* __restrict__ cells, int64_t nc, const u
     if (c >= nc) return;
     const Cell C = cells[c];
     if (C.split || C.count == 0) return;
+    int top = (int)c;   // the leaf's top cell
+    while (cells[top].parent >= 0) top = cells[top].parent;
     for (int s = 0; s < C.count; s += CHUNK)
-        chunks[num[C.first + s]] = make_int4((int)c, C.first + s, min(CHUNK, C.count - s), 0);
+        chunks[num[C.first + s]] = make_int4((int)c, C.first + s, min(CHUNK, C.count - s), top);
 }
 
 // One wave per chunk (the chunk count is read on the device).
@@ -588,11 +590,15 @@ __global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__
 // sorted list; only their data are replaced.
 // ---------------------------------------------------------------------------
 
-// New data of every particle of a chunk (one wavefront per chunk): the
-// position as FP32 offset from the origin of the top cell it was built in
-// (nearest periodic image) plus FP32 remainder, h, m, u, v.  The largest
-// displacement against the stored position is folded into stepmax[set]
-// (non-negative floats compare like their bit patterns).
+// New data of every particle of a chunk (one wavefront per chunk, chunks
+// strided over a bounded grid): the position as FP32 offset from the origin
+// of the top cell it was built in (nearest periodic image) plus FP32
+// remainder, h, m, u, v.  The largest displacement against the stored
+// position is folded into stepmax[set] (non-negative floats compare like
+// their bit patterns): kept per wave while its chunks stay in one set,
+// combined per block, one atomic per block and set (atomics on one word from
+// every wave would serialise).
+constexpr int REFRESH_BLOCKS = 2048;
 __global__ __launch_bounds__(256) void k_refresh(const int4* __restrict__ chunks, const uint32_t* __restrict__ nch_dev,
                                                  const Cell* __restrict__ cells, const SetInfo* sets,
                                                  const uint32_t* __restrict__ perm, const double* __restrict__ x,
@@ -605,12 +611,12 @@ __global__ __launch_bounds__(256) void k_refresh(const int4* __restrict__ chunks
                                                  float* __restrict__ pu, float4* __restrict__ pv,
                                                  unsigned* __restrict__ stepmax) {
     const int64_t nch = *nch_dev;
-    const int lane = threadIdx.x & 63;
-    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nch; q += (int64_t)gridDim.x * 4) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int cur = -1;          // set of the running maximum
+    float run = 0.f;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + w; q < nch; q += (int64_t)gridDim.x * 4) {
         const int4 ch = chunks[q];
-        int A = ch.x;
-        while (cells[A].parent >= 0) A = cells[A].parent;
-        const Cell T = cells[A];
+        const Cell T = cells[ch.w];
         const SetInfo S = sets[T.set];
         double d2 = 0.0;
         if (lane < ch.z) {
@@ -642,7 +648,31 @@ __global__ __launch_bounds__(256) void k_refresh(const int4* __restrict__ chunks
         float dm = (float)sqrt(d2);
         if ((double)dm < sqrt(d2)) dm = nextafterf(dm, INFINITY);
         dm = wave_max_f(dm);
-        if (lane == 0 && dm > 0.f) atomicMax(&stepmax[T.set], __float_as_uint(dm));
+        if (T.set != cur) {
+            if (lane == 0 && cur >= 0 && run > 0.f) atomicMax(&stepmax[cur], __float_as_uint(run));
+            cur = T.set;
+            run = 0.f;
+        }
+        run = fmaxf(run, dm);
+    }
+    __shared__ int s_set[4];
+    __shared__ float s_max[4];
+    if (lane == 0) {
+        s_set[w] = cur;
+        s_max[w] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 4; ++a) {
+            if (s_set[a] < 0) continue;
+            float v = s_max[a];
+            for (int b = a + 1; b < 4; ++b)
+                if (s_set[b] == s_set[a]) {
+                    v = fmaxf(v, s_max[b]);
+                    s_set[b] = -1;
+                }
+            if (v > 0.f) atomicMax(&stepmax[s_set[a]], __float_as_uint(v));
+        }
     }
 }
 
@@ -1541,7 +1571,7 @@ Err refresh_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in) {
     HIPTRY(fill_u32(stepmax, S + 1, 0u, st));
     HIPTRY(fill_u32(nchw, 1, (uint32_t)t->nchunks, st));
     const unsigned gch = (unsigned)std::min<int64_t>(nblk(t->nchunks, 4), 8192);
-    hipLaunchKernelGGL(k_refresh, dim3(gch), dim3(256), 0, st, t->chunks, nchw, t->cells, t->d_sets, t->perm, in->x,
+    hipLaunchKernelGGL(k_refresh, dim3((unsigned)std::min<int64_t>(gch, REFRESH_BLOCKS)), dim3(256), 0, st, t->chunks, nchw, t->cells, t->d_sets, t->perm, in->x,
                        in->y, in->z, in->h, in->m, in->u, in->vx, in->vy, in->vz, t->prm.h_slack, t->pos, t->plo,
                        t->ph, t->hdec, t->pu, t->pv, stepmax);
     HIPTRY(hipGetLastError());

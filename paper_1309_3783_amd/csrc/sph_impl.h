@@ -157,7 +157,8 @@ struct sph_tree {
     float4* plo = nullptr;   // FP32 remainders of the positions: pos.xyz + plo.xyz = offset to ~2^-48
     float *ph = nullptr, *hdec = nullptr, *pu = nullptr, *bound = nullptr;
     sph::Cell* cells = nullptr;
-    int4 *taskA = nullptr, *taskB = nullptr, *finals = nullptr, *chunks = nullptr;
+    int4 *taskA = nullptr, *taskB = nullptr, *finals = nullptr;
+    int4* chunks = nullptr;           // work chunks: (leaf, first particle, count, top cell of the leaf)
     uint32_t *csr_off = nullptr, *segoff = nullptr, *seglist = nullptr, *segidx = nullptr;
     float4* segpos = nullptr;   // sorted lists: the particle records (x, y, z, m) in list order
     uint32_t *sc_a = nullptr, *sc_b = nullptr, *sc_c = nullptr, *sc_d = nullptr, *sc_tmp = nullptr;
