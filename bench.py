@@ -514,8 +514,10 @@ def bench_batched(sph, n_sets=256, steps=3):
             "speedup_vs_plain": val / plain["value"], "speedup_vs_plain_tuned": val / plain_tuned["value"]}
 
 
-def bench_served(sph, n_req=1000, n_warm=50, n_plain=300, pool_size=24, load=0.7, h_slack=0.2):
-    """Poisson request stream, N log-uniform in [1e4, 2e6], continuous batching;
+def bench_served(sph, n_req=1000, n_warm=50, n_plain=300, pool_size=24, load=0.7, h_slack=0.2, lanes=4):
+    """Poisson request stream, N log-uniform in [1e4, 2e6], continuous batching
+    over `lanes` executor lanes (4: against 2 and 3, the highest saturation
+    rate and the lowest latency at 70% of it);
     beside it the first n_plain requests of the same stream run one at a time
     back to back (the plain path).  The served results are checked against the
     oracle by the GPU tests (every request there), not here."""
@@ -530,7 +532,7 @@ def bench_served(sph, n_req=1000, n_warm=50, n_plain=300, pool_size=24, load=0.7
         f"({time.perf_counter() - t:.1f} s to generate)")
     prm = sph.params(h_slack=h_slack)
     budget = 64 << 30
-    ex = S.GpuExecutor(prm, k_iter=K_ITER, lanes=2)
+    ex = S.GpuExecutor(prm, k_iter=K_ITER, lanes=lanes)
 
     def fp(r):
         return sph.footprint(r.n, prm)
