@@ -115,9 +115,16 @@ def test_fullsize_solve_sampled(sph, ctx, name):
     batch = sph.batch_from_sets([ps])
     dout = sph.DensityOut(ps.n, "cuda")
     tree = sph.Tree(ctx)
-    st, nu, it = sph.solve_with_rebuild(tree, batch, sph.params(), dout)
+    prm = sph.params()
+    st, nu, it = sph.solve_with_rebuild(tree, batch, prm, dout)
     assert st == sph.SPH_OK and nu == 0
+    tree.force(sph.ForceOut(ps.n, 1, "cuda"))
     torch.cuda.synchronize()
+    # the workspace estimate the served scheduler admits by covers what the
+    # build, sort, solve and force of the full-size set used
+    need, est = tree.workspace_needed(), sph.workspace_size(ps.n, 1, prm)
+    print(f"\n[fullsize] {name}: workspace used {need / ps.n:.0f} B/particle, estimate {est / ps.n:.0f}", flush=True)
+    assert need <= est
     nw = dout.nw.cpu().numpy()
     assert np.abs(nw - 48.0).max() <= 0.5 + 1e-4
     rng = np.random.default_rng(11)
