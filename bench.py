@@ -70,17 +70,30 @@ def make_workload(name):
 
 
 # the translation unit of k_density / k_force: its source and every header it
-# includes (the counters in profiles/traffic.json hold for these bytes only)
+# includes (the counters in profiles/traffic.json hold for this code only;
+# comments do not count)
 KERNEL_SOURCES = ["paper_1309_3783_amd/csrc/sph_interact.hip", "paper_1309_3783_amd/csrc/sph_impl.h",
                   "paper_1309_3783_amd/csrc/sph_internal.h", "paper_1309_3783_amd/csrc/sph_prims.h",
                   "include/sphcell.h", "paper_1309_3783_amd/build.py"]
 
 
+def _strip_comments(text: str, py: bool) -> str:
+    """The code of a source file without its comments and blank lines (the
+    hash follows code changes, not edits of the documentation)."""
+    import re
+    if py:
+        lines = [ln.split("#", 1)[0].rstrip() for ln in text.splitlines()]
+    else:
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+    return "\n".join(ln for ln in lines if ln.strip())
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(_strip_comments(fh.read(), f.endswith(".py")).encode())
     return h.hexdigest()[:16]
 
 

@@ -242,7 +242,10 @@ sph_status sph_refresh_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in);
  * Requires sph_sort_pairs. */
 sph_status sph_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out);
 
-/* Newton iteration on h_i until |N_w,i - n_target| <= h_tol (convergence
+/* Smoothing lengths: Section III-B fixes the target (48 neighbours, the
+ * weighted count N_w here); the paper does not describe how h is found.
+ * Safeguarded Newton iteration per particle on ln N_w against ln h, keeping
+ * a bracket of the root, until |N_w,i - n_target| <= h_tol (convergence
  * tested in FP64), re-running the density stage on the particles not yet
  * converged.  Writes the density outputs at the solved h.  *n_unconverged
  * [host] receives the particles left; *iterations [host] the iterations run.

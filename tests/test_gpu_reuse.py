@@ -210,3 +210,102 @@ def test_leapfrog_reuse_follows_rebuild(sph, ctx):
     for k in ("vx", "vy", "vz"):
         assert np.abs(a[k] - c[k]).max() <= 1e-5 * vs, k
     assert np.abs(a["u"] - c["u"]).max() <= 1e-5 * np.abs(a["u"]).max()
+
+
+def test_refresh_batched_graph_replayed(sph, ctx):
+    """Several uneven sets in one tree: the graph pipeline on the first
+    state, then the sets move, the tree is refreshed and the same graph is
+    replayed (no new capture); every set checked at the h the GPU solved."""
+    from paper_1309_3783_amd import pipeline as P
+    sizes = [3100, 12000, 5400, 21000, 2600]
+    sets = [sphinputs.plummer_mixture(n, 1700 + k, velocity=True, snap=False) for k, n in enumerate(sizes)]
+    prm = sph.params(h_slack=0.5)
+    tree = sph.Tree(ctx)
+    b0 = sph.batch_from_sets(sets)
+    out0 = P.Outputs(b0.n, b0.nsets)
+    P.run_graph(tree, b0, prm, out0, 24)
+    torch.cuda.synchronize()
+    caps = tree.stats()["graph_captures"]
+    h0 = [P.per_set(b0, out0.d.h, s) for s in range(len(sets))]
+    moved_sets = [moved(ps, 2e-5) for ps in sets]
+    b1 = sph.batch_from_sets(moved_sets, h=h0)
+    assert tree.refresh(b1)
+    out1 = P.Outputs(b1.n, b1.nsets)
+    tree.run_graph(24, out1.d, out1.f, out1.status)
+    torch.cuda.synchronize()
+    P.finish_graph(tree, b1, prm, out1, 24)
+    torch.cuda.synchronize()
+    assert tree.stats()["graph_captures"] == caps          # replayed, not captured again
+    excl = 0
+    for s, ps in enumerate(moved_sets):
+        r = {k: P.per_set(b1, getattr(out1.d, k), s) for k in ("rho", "h", "nngb", "nw")}
+        r.update({k: P.per_set(b1, getattr(out1.f, k), s) for k in ("ax", "ay", "az", "nforce")})
+        k, e = at_gpu_h(ps, r, r)
+        excl += e
+        assert k + e == ps.n
+    print(f"\n[reuse] refreshed batch of {len(sets)} sets through the replayed graph: {excl} near a cutoff", flush=True)
+
+
+def test_refresh_keeps_the_halo(sph, ctx):
+    """One GPU's share (owned block + halo of one top cell): built, moved,
+    refreshed, the halo's densities set again; the owned particles' density
+    and force equal the oracle's on the whole moved set."""
+    from test_gpu_share import share_of, subset
+    from _checks import RHO_TOL, FORCE_TOL
+    import oracle
+    ps0 = sphinputs.lattice(40, 0.1, 35, velocity=True, snap=False)
+    own, idx = share_of(ps0, np.array([0.0, 0.5, 0.0]), 0.5, 0.125)
+    _, h0 = I.fixed_h_case(ps0)
+    tree = sph.Tree(ctx)
+    prm = sph.params(flags=sph.SPH_FLAG_PAIR_HASH)
+    owned = torch.as_tensor(own.astype(np.uint8), device="cuda")
+    rd0, _ = I.oracle_reference(ps0, h0)
+    tree.build_cells(sph.batch_from_sets([subset(ps0, idx)], h=[h0[idx]]), prm)
+    tree.set_halo(owned, torch.as_tensor(rd0["rho"][idx].astype(np.float32), device="cuda"),
+                  torch.as_tensor(rd0["drho_dh"][idx].astype(np.float32), device="cuda"))
+    tree.sort_pairs()
+    ps = moved(ps0, 0.01)
+    _, h = I.fixed_h_case(ps, h0)
+    rd, rf = I.oracle_reference(ps, h)
+    sub = subset(ps, idx)
+    assert tree.refresh(sph.batch_from_sets([sub], h=[h[idx]]))
+    tree.set_halo(owned, torch.as_tensor(rd["rho"][idx].astype(np.float32), device="cuda"),
+                  torch.as_tensor(rd["drho_dh"][idx].astype(np.float32), device="cuda"))
+    d = sph.DensityOut(sub.n, "cuda")
+    f = sph.ForceOut(sub.n, 1, "cuda")
+    tree.density(d)
+    tree.force(f)
+    torch.cuda.synchronize()
+    o = np.nonzero(own)[0]
+    t = idx[o]
+    rel = np.abs(d.rho.cpu().numpy()[o] - rd["rho"][t]) / rd["rho"][t]
+    assert rel.max() <= RHO_TOL, rel.max()
+    assert np.array_equal(d.nngb.cpu().numpy()[o], rd["nngb"][t])
+    assert np.array_equal(f.nforce.cpu().numpy()[o], rf["nforce"][t])
+    S = rf["S"][t]
+    for k in ("ax", "ay", "az"):
+        err = np.abs(getattr(f, k).cpu().numpy()[o] - rf[k][t]) / S
+        assert err.max() <= FORCE_TOL, (k, err.max())
+    print(f"\n[reuse] refreshed share: {o.size} owned, {idx.size - o.size} halo, rho rel {rel.max():.2e}", flush=True)
+
+
+def test_refresh_on_the_static_workspace(sph, ctx):
+    """A tree on the no-allocation scratch refreshes in place and gives what
+    a tree on its own workspace gives after the same refresh, bit for bit."""
+    ps0 = sphinputs.plummer_mixture(9000, 77, velocity=True, snap=False)
+    ps = moved(ps0, 1e-4)
+    prm = sph.params(flags=sph.SPH_FLAG_PAIR_HASH, h_slack=0.5)
+    res = []
+    for static in (False, True):
+        tree = sph.Tree(ctx)
+        b0 = sph.batch_from_sets([ps0])
+        if static:
+            tree.build_cells_static(b0, prm)
+        else:
+            tree.build_cells(b0, prm)
+        tree.sort_pairs()
+        assert tree.refresh(sph.batch_from_sets([ps]))
+        res.append(results(sph, tree, ps.n))
+    for a, b in zip(res[0], res[1]):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
