@@ -226,11 +226,11 @@ def test_refresh_batched_graph_replayed(sph, ctx):
     P.run_graph(tree, b0, prm, out0, 24)
     torch.cuda.synchronize()
     caps = tree.stats()["graph_captures"]
-    h0 = [P.per_set(b0, out0.d.h, s) for s in range(len(sets))]
+    h0 = [P.per_set(b0, out0.d.h, s).copy() for s in range(len(sets))]
     moved_sets = [moved(ps, 2e-5) for ps in sets]
     b1 = sph.batch_from_sets(moved_sets, h=h0)
     assert tree.refresh(b1)
-    out1 = P.Outputs(b1.n, b1.nsets)
+    out1 = out0            # the same output buffers: the captured graph applies as it is
     tree.run_graph(24, out1.d, out1.f, out1.status)
     torch.cuda.synchronize()
     P.finish_graph(tree, b1, prm, out1, 24)
