@@ -140,6 +140,15 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream);
 void sph_ctx_destroy(sph_ctx* ctx);
 const char* sph_last_error(const sph_ctx* ctx);
 
+/* Wait for everything enqueued on the context's stream (the calls are
+ * asynchronous; outputs are valid after this, or after a stream
+ * synchronisation or event of the caller's).  Returns SPH_E_HIP, with
+ * sph_last_error saying which, when the stream reports an error of work
+ * enqueued earlier.  Conditions the kernels detect on the device (h outgrew
+ * its cells, no convergence) are not errors of the stream: sph_solve_h
+ * returns them, and sph_run_graph leaves them in its status words. */
+sph_status sph_ctx_sync(sph_ctx* ctx);
+
 /* Workspace for a tree of n particles in nsets sets (contract of Section II:
  * the two stages' inputs and outputs plus the decomposition of Section II-B
  * and the sorted lists of Section II-C): an estimate for sets like uniform,

@@ -22,7 +22,7 @@ SPH_FLAG_RESUME = 2
 
 # every function the header declares
 EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
-           "sph_last_error", "sph_workspace_size", "sph_footprint", "sph_tree_create", "sph_tree_destroy",
+           "sph_last_error", "sph_ctx_sync", "sph_workspace_size", "sph_footprint", "sph_tree_create", "sph_tree_destroy",
            "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
            "sph_build_cells_static", "sph_refresh_cells", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_set_halo",
            "sph_run_graph", "sph_last_timings", "sph_last_work", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
@@ -81,6 +81,7 @@ def lib():
         L.sph_ctx_destroy.restype = None
         L.sph_last_error.argtypes = [vp]
         L.sph_last_error.restype = C.c_char_p
+        L.sph_ctx_sync.argtypes = [vp]
         L.sph_footprint.argtypes = [C.c_int64, C.POINTER(sph_params), C.POINTER(C.c_size_t)]
         L.sph_workspace_size.argtypes = [C.c_int64, C.c_int32, C.POINTER(sph_params), C.POINTER(C.c_size_t)]
         L.sph_tree_set_workspace.argtypes = [vp, vp, vp, C.c_size_t]
@@ -109,7 +110,7 @@ def lib():
         L.sph_kick.argtypes = [vp, C.c_int64, C.c_float] + [vp] * 12
         L.sph_drift.argtypes = [vp, C.c_int32, vp, vp, C.c_double] + [vp] * 6
         L.sph_cfl_dt.argtypes = [vp, C.c_int64, vp, vp, C.c_float, C.POINTER(C.c_double)]
-        for name in ("sph_ctx_create", "sph_footprint", "sph_workspace_size", "sph_tree_create", "sph_tree_bytes",
+        for name in ("sph_ctx_create", "sph_ctx_sync", "sph_footprint", "sph_workspace_size", "sph_tree_create", "sph_tree_bytes",
                      "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
                      "sph_build_cells_static", "sph_refresh_cells", "sph_sort_pairs", "sph_density", "sph_solve_h",
                      "sph_force",
@@ -173,6 +174,10 @@ class Context:
         if st:
             msg = lib().sph_last_error(self.h).decode(errors="replace")
             raise SphError(st, f"{what}: {msg}")
+
+    def sync(self):
+        """sph_ctx_sync: wait for the context's stream; raises on a stream error."""
+        self.check(lib().sph_ctx_sync(self.h), "sph_ctx_sync")
 
     def enable_timing(self, on=True):
         lib().sph_enable_timing(self.h, 1 if on else 0)

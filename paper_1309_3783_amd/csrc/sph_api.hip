@@ -144,6 +144,16 @@ void sph_ctx_destroy(sph_ctx* ctx) {
 
 const char* sph_last_error(const sph_ctx* ctx) { return ctx ? ctx->last_error.c_str() : g_create_error.c_str(); }
 
+sph_status sph_ctx_sync(sph_ctx* ctx) {
+    if (!ctx) return SPH_E_ARG;
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        ctx->last_error = std::string("stream: ") + hipGetErrorString(e);
+        return SPH_E_HIP;
+    }
+    return SPH_OK;
+}
+
 sph_status sph_workspace_size(int64_t n, int32_t nsets, const sph_params* p, size_t* bytes) {
     if (!bytes || n < 0 || nsets < 1) return SPH_E_ARG;
     (void)p;
