@@ -127,9 +127,8 @@ def finish_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int, m
 
 
 def run_graph(tree: B.Tree, batch: B.Batch, prm, out: Outputs, k_iter: int = 24):
-    import torch
     launch_graph(tree, batch, prm, out, k_iter)
-    tree.ctx.stream.synchronize() if hasattr(tree.ctx.stream, "synchronize") else torch.cuda.synchronize()
+    tree.ctx.sync()
     return finish_graph(tree, batch, prm, out, k_iter)
 
 
