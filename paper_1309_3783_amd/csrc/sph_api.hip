@@ -137,6 +137,8 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
 void sph_ctx_destroy(sph_ctx* ctx) {
     if (!ctx) return;
     for (auto& e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto& e : ctx->solve_ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
     if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
     delete ctx;
@@ -161,10 +163,14 @@ sph_status sph_workspace_size(int64_t n, int32_t nsets, const sph_params* p, siz
     // permutations, position and remainder, velocity, h, u, bounds, pair-hash
     // terms), 28 B density, 13 B solve, 52 B force, 41 B saved Newton state,
     // 16 B of radix and scan scratch: ~275 B.  Sorted lists: 20 B per entry,
-    // 13 entries per particle and tree level that holds pair tasks (~2 levels
-    // of them on clustered sets: 520 B).  Cells, tasks and interaction lists:
-    // ~120 B.  Plus the set tables and a fixed reserve.
-    const double per = 275.0 + 520.0 + 120.0;
+    // 13 entries per particle and tree level that holds pair tasks (29 per
+    // particle on a clustered set with h over three decades: 580 B), plus
+    // 24 B of radix keys and values per entry of the lists longer than
+    // 16384 (about 10 per particle there: 240 B).  Cells, tasks and
+    // interaction lists: ~120 B.  Plus the set tables and a fixed reserve.
+    // Measured peaks: 547 B per particle on a 10^6 lattice, 1110 B on the
+    // 8*10^6 clustered mixture.
+    const double per = 275.0 + 580.0 + 240.0 + 120.0;
     *bytes = (size_t)(per * (double)n) + (size_t)nsets * 4096 + ((size_t)24 << 20);
     return SPH_OK;
 }

@@ -36,6 +36,10 @@ struct sph_ctx {
     // asynchronous copy per read, then one stream synchronisation
     static constexpr size_t PIN_BYTES = 65536;
     void* h_pin = nullptr;
+    // the Newton loop's status words, two slots at this offset of h_pin,
+    // and the events that mark their copies done
+    static constexpr size_t PIN_SOLVE = 32768;
+    hipEvent_t solve_ev[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr; // private stream used only to capture graphs
 };
 

@@ -1665,19 +1665,49 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
     const int nst = 2 + 2 * t->nsets;
     hipLaunchKernelGGL(k_zero_i32, dim3(nblk(nst, 256)), dim3(256), 0, st, t->status, nst);
     zero_work(ctx, t, 0, 256);
-    int32_t hstat[2] = {0, 0};
-    int it = 0;
-    bool rebuild = false;
-    for (; it < t->prm.max_iter; ++it) {
+    // Each pass is enqueued before the host reads the status of the one
+    // before, so the device runs pass k + 1 while the host waits for pass
+    // k's counts (no idle gap per pass).  A pass enqueued after the last
+    // one needed finds no active particle: an empty chunk list, no Newton
+    // step, no change.  The status words of pass k go to pinned slot k mod 2.
+    for (auto& e : ctx->solve_ev)
+        if (!e) HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    int32_t* slots = (int32_t*)((char*)ctx->h_pin + sph_ctx::PIN_SOLVE);
+    auto enqueue = [&](int k) -> hipError_t {
         ev_mark(ctx, "newton");
-        launch_density(ctx, t, true, it > 0, ctx->d_counter);
+        launch_density(ctx, t, true, k > 0, ctx->d_counter);
         ev_mark(ctx, "density_pass");
         launch_newton(ctx, t);
         launch_count(ctx, t);
-        HIPTRY(hipGetLastError());
-        HIPTRY(hipMemcpyAsync(hstat, t->status, sizeof(hstat), hipMemcpyDeviceToHost, st));
-        HIPTRY(hipStreamSynchronize(st));
-        if (hstat[1] == 0) { ++it; break; }
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(slots + 2 * (k & 1), t->status, 2 * sizeof(int32_t),
+                                                hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(ctx->solve_ev[k & 1], st);
+        return e;
+    };
+    int32_t hstat[2] = {0, 0};
+    int it = 0, enq = 1;
+    bool rebuild = false;
+    HIPTRY(enqueue(0));
+    for (int k = 0; k < t->prm.max_iter; ++k) {
+        if (k + 1 < t->prm.max_iter) {
+            HIPTRY(enqueue(k + 1));
+            enq = k + 2;
+        }
+        HIPTRY(hipEventSynchronize(ctx->solve_ev[k & 1]));
+        hstat[0] = slots[2 * (k & 1)];
+        hstat[1] = slots[2 * (k & 1) + 1];
+        it = k + 1;
+        if (hstat[1] == 0) break;
+    }
+    if (enq > it && ctx->timing) {
+        // the pass enqueued after the last one needed did no work: its time
+        // counts with the Newton bookkeeping, not as a density pass
+        for (size_t e = ctx->nev; e-- > 0;)
+            if (std::strcmp(ctx->ev_name[e], "density_pass") == 0) {
+                ctx->ev_name[e] = "newton";
+                break;
+            }
     }
     rebuild = hstat[0] != 0;
     ev_mark(ctx, "newton");
