@@ -261,7 +261,9 @@ sph_status sph_density(sph_ctx* ctx, sph_tree* t, const sph_density_out* out);
  * [host] receives the particles left; *iterations [host] the iterations run.
  * Returns SPH_E_REBUILD when some h_i must grow past what the tree supports
  * (out->h then holds the current h: rebuild with it and call again), and
- * SPH_E_NOCONV when max_iter is reached.  Synchronises the stream. */
+ * SPH_E_NOCONV when max_iter is reached.  The host waits for each pass's
+ * counts (the next pass is already enqueued meanwhile); the outputs are
+ * written by work still on the stream when the call returns. */
 sph_status sph_solve_h(sph_ctx* ctx, sph_tree* t, const sph_density_out* out,
                        int32_t* n_unconverged, int32_t* iterations);
 

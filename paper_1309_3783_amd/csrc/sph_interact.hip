@@ -1727,7 +1727,8 @@ Err run_solve(sph_ctx* ctx, sph_tree* t, const sph_density_out* out, int32_t* n_
         t->saved_n = n;
     }
     HIPTRY(hipGetLastError());
-    HIPTRY(hipStreamSynchronize(st));
+    // the counts are known: the scatter (and a state save) run on without
+    // the host waiting for them
     ev_mark(ctx, "scatter");
     if (iters) *iters = it;
     if (n_unconv) *n_unconv = hstat[1];
