@@ -84,7 +84,9 @@ typedef struct {
     uint32_t flags;      /* SPH_FLAG_* */
     int32_t blocks_per_cu; /* persistent interaction kernels: blocks of 4 wavefronts per CU (0 = 8) */
     int32_t max_replicas;  /* lanes per target particle for small chunks: 1, 2, 4, 8 or 16 (0 = 16) */
-    int32_t reserved[3];
+    int32_t top_coarsen;   /* with top_grid 0: this many levels coarser than the largest allowed top grid
+                              (at least 2 cells per side remain) (0) */
+    int32_t reserved[2];
 } sph_params;
 
 /* Input particle sets (see Conventions).  h is the initial smoothing length

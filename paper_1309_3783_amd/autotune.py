@@ -7,6 +7,8 @@ on the actual batch (or a sample of it) and keeps the fastest:
   * max_replicas   -- lanes per target particle for small chunks
   * h_slack        -- room left for h to grow before the cells must be
                       rebuilt (more room: fewer rebuilds, larger cells)
+  * top_coarsen    -- top grid one level coarser than the largest allowed
+                      (larger top cells, split further where dense)
 Results are cached in a JSON table keyed by a workload signature (number of
 sets and log2 of the mean set size).
 """
@@ -24,7 +26,8 @@ from . import pipeline as P
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuned.json")
 
-GRID = {"n_split": [200, 400, 800], "blocks_per_cu": [4, 8, 16], "max_replicas": [4, 16], "h_slack": [0.2, 0.3]}
+GRID = {"n_split": [200, 400, 800], "blocks_per_cu": [4, 8, 16], "max_replicas": [4, 16], "h_slack": [0.2, 0.3],
+        "top_coarsen": [0, 1]}
 
 
 def signature(batch: B.Batch, label: str = "") -> str:

@@ -33,7 +33,7 @@ class sph_params(C.Structure):
                 ("max_depth", C.c_int32), ("top_grid", C.c_int32), ("n_target", C.c_float),
                 ("h_tol", C.c_float), ("max_iter", C.c_int32), ("gamma", C.c_float), ("alpha", C.c_float),
                 ("flags", C.c_uint32), ("blocks_per_cu", C.c_int32), ("max_replicas", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("top_coarsen", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class sph_input(C.Structure):

@@ -1202,7 +1202,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     if (n > 0 && (!in->x || !in->y || !in->z || !in->h || !in->m || !in->u || !in->vx || !in->vy || !in->vz))
         return Err{SPH_E_ARG, "null particle array"};
     if (prm->n_split < 1 || !(prm->split_frac >= 0.f && prm->split_frac <= 1.f) || !(prm->h_slack >= 0.f) ||
-        prm->max_depth < 0 || prm->max_depth > 16)
+        prm->max_depth < 0 || prm->max_depth > 16 || prm->top_coarsen < 0 || prm->top_coarsen > 8)
         return Err{SPH_E_ARG, "bad decomposition parameters"};
     t->prm = *prm;
     t->nsets = in->nsets;
@@ -1271,6 +1271,7 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         } else {
             while (lg < KEY_BITS_PER_DIM && box / (double)(1 << (lg + 1)) >= hd && (1 << (3 * (lg + 1))) <= (1 << 21))
                 ++lg;
+            lg = std::max(1, lg - prm->top_coarsen);
         }
         sets[s].lgG = lg;
         sets[s].L0 = box / (double)(1 << lg);

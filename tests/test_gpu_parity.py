@@ -81,6 +81,18 @@ def test_clumpy_wide_h_range(sph, ctx, n, seed):
     assert tree.stats()["levels"] >= 2
 
 
+@pytest.mark.parametrize("name", ["lattice", "clumpy"])
+def test_coarser_top_grid(sph, ctx, name):
+    """The autotuner's top-grid knob: one level coarser than the largest
+    allowed top grid, the same pair sets and values to the full bar."""
+    ps = (sphinputs.lattice(24, 0.1, 5, velocity=True) if name == "lattice"
+          else sphinputs.plummer_mixture(12000, 47, velocity=True))
+    ps, h = I.fixed_h_case(ps)
+    g, rd, rf, tree = full_check(sph, ctx, ps, h, top_coarsen=1)
+    (g0,), tree0 = run_fixed(sph, ctx, [ps], [h])
+    assert tree.stats()["top_grid"] == max(2, tree0.stats()["top_grid"] // 2)
+
+
 def test_deep_refinement(sph, ctx):
     # a small split count forces many levels and split pair tasks
     ps = sphinputs.plummer_mixture(12000, 5, velocity=True)
