@@ -237,8 +237,8 @@ sph_status sph_sort_pairs(sph_ctx* ctx, sph_tree* t);
  * for sph_build_cells (h is the starting h, as there) -- taken without
  * building or sorting again.  Every particle keeps its cell, its place in
  * cell order and its place in each sorted list; positions are stored
- * relative to the origin of the top cell they were built in (nearest
- * periodic image).  Each set keeps a bound d on any particle's displacement
+ * relative to the origin of the top cell they were built in (the periodic
+ * image nearest the cell's centre).  Each set keeps a bound d on any particle's displacement
  * since the build (the largest displacement of every refresh, added up); the
  * density and force sweeps then reach 2 d further along the pair axis, so the
  * lists' build-time order still yields every pair, and the largest h the

@@ -592,7 +592,8 @@ __global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__
 
 // New data of every particle of a chunk (one wavefront per chunk, chunks
 // strided over a bounded grid): the position as FP32 offset from the origin
-// of the top cell it was built in (nearest periodic image) plus FP32
+// of the top cell it was built in (the periodic image nearest the cell's
+// centre) plus FP32
 // remainder, h, m, u, v.  The largest displacement against the stored
 // position is folded into stepmax[set] (non-negative floats compare like
 // their bit patterns): kept per wave while its chunks stay in one set,
@@ -629,8 +630,11 @@ __global__ __launch_bounds__(256) void k_refresh(const int4* __restrict__ chunks
                                    (double)o0.z + (double)l0.z};
             float o[3], lo[3];
             for (int d = 0; d < 3; ++d) {
+                // the periodic image nearest the top cell's centre (with two
+                // top cells per side the nearest to its origin can be the
+                // wrong one for a particle just past the far face)
                 double off = xs[d] - S.box * floor(xs[d] / S.box) - (double)tc[d] * S.L0;
-                off -= S.box * rint(off / S.box);
+                off -= S.box * rint((off - 0.5 * S.L0) / S.box);
                 o[d] = (float)off;
                 lo[d] = (float)(off - (double)o[d]);
                 const double dd = off - old[d];

@@ -309,3 +309,32 @@ def test_refresh_on_the_static_workspace(sph, ctx):
     for a, b in zip(res[0], res[1]):
         for k in a:
             assert np.array_equal(a[k], b[k]), k
+
+
+def test_refresh_two_top_cells_per_side(sph, ctx):
+    """Two top cells per side: particles that move just past the far face of
+    the top cell they were built in (and past the periodic face) keep
+    offsets from that cell's origin on the right periodic image."""
+    ps0 = sphinputs.uniform(1000, 61, velocity=True, snap=False)
+    # particles close to the faces x = 1/2 and x = 1 move out through them
+    near = (np.mod(ps0.x, 0.5) > 0.49)
+    vx = ps0.vx.copy()
+    vx[near] = 0.1
+    ps0 = sphinputs.ParticleSet(ps0.x, ps0.y, ps0.z, ps0.m, ps0.u, vx, ps0.vy, ps0.vz, ps0.h0, ps0.box,
+                                dict(ps0.meta))
+    prm = sph.params(flags=sph.SPH_FLAG_PAIR_HASH, h_slack=0.5)
+    _, h0 = I.fixed_h_case(ps0)
+    tree = sph.Tree(ctx)
+    tree.build_cells(sph.batch_from_sets([ps0], h=[h0]), prm)
+    tree.sort_pairs()
+    assert tree.stats()["top_grid"] == 2
+    ps = moved(ps0, 0.15)
+    crossed = int(np.sum(near & (np.floor(ps.x / 0.5) != np.floor(ps0.x / 0.5))))
+    assert crossed >= 5, crossed
+    _, h = I.fixed_h_case(ps, h0)
+    assert tree.refresh(sph.batch_from_sets([ps], h=[h]))
+    g_d, g_f = results(sph, tree, ps.n)
+    rd, rf = I.oracle_reference(ps, h)
+    check_density(ps, h, g_d, rd)
+    check_force(ps, g_f, rf)
+    print(f"\n[reuse] two top cells per side: {crossed} particles left their top cell", flush=True)
