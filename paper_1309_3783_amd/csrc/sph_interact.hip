@@ -379,15 +379,36 @@ __device__ __forceinline__ void tile_test(const float4* sp, int j0, int share, c
 #pragma unroll
     for (int w = 0; w < NWORD; ++w) {
         uint32_t bits = 0;
-        const int k1 = min(32, share - 32 * w);
-#pragma unroll 4
-        for (int k = 0; k < k1; ++k) {
-            const float4 q = sp[j0 + 32 * w + k];
+        // records in descending order, each result shifted in at bit 0 by an
+        // add with carry (bits + bits + [in range]: one instruction where a
+        // select of a shifted constant takes three), so record k ends at
+        // bit k.  In a block of the self task a zero distance (the particle
+        // itself) is out: for non-negative floats 0 < r2 < lim is the
+        // unsigned compare bits(r2) - 1 < bits(lim) - 1.
+        const float4* base = sp + j0 + 32 * w;
+        auto test = [&](const float4& q) {
             const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool in = P::in_range(r2, hi2, q.w) && (!SELF || r2 > 0.f);
-            bits = in ? (bits | (1u << k)) : bits;
+            const float lim = P::lim2(hi2, q.w);
+            if (SELF) {
+                const uint32_t a = __float_as_uint(r2) - 1u, b = __float_as_uint(lim) - 1u;
+                asm("v_cmp_lt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc"
+                    : "+v"(bits) : "v"(a), "v"(b) : "vcc");
+            } else {
+                asm("v_cmp_lt_f32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc"
+                    : "+v"(bits) : "v"(r2), "v"(lim) : "vcc");
+            }
+        };
+        // wave-uniform trip count, four records loaded ahead of their tests
+        int k = uni(min(32, share - 32 * w)) - 1;
+        for (; k >= 3; k -= 4) {
+            const float4 q0 = base[k], q1 = base[k - 1], q2 = base[k - 2], q3 = base[k - 3];
+            test(q0);
+            test(q1);
+            test(q2);
+            test(q3);
         }
+        for (; k >= 0; --k) test(base[k]);
         m[w] = bits;
     }
 }
@@ -726,7 +747,8 @@ struct DensP {
         uint64_t m[TILE];   // pair-hash terms
     };
     static __device__ __forceinline__ float cut(float hmax, float) { return hmax; }
-    static __device__ __forceinline__ bool in_range(float r2, float hi2, float) { return r2 < hi2; }
+    // squared cutoff of a pair: the target's h (density gathers over h_i)
+    static __device__ __forceinline__ float lim2(float hi2, float) { return hi2; }
     // data of a record read before it is filtered (none: the cutoff is the
     // target's h)
     struct Pre {};
@@ -902,9 +924,8 @@ struct ForceP {
         uint64_t m[TILE];  // pair-hash terms
     };
     static __device__ __forceinline__ float cut(float hmax, float hpart) { return fmaxf(hmax, hpart); }
-    static __device__ __forceinline__ bool in_range(float r2, float hi2, float hj) {
-        return r2 < fmaxf(hi2, hj * hj);
-    }
+    // squared cutoff of a pair: max(h_i, h_j)
+    static __device__ __forceinline__ float lim2(float hi2, float hj) { return fmaxf(hi2, hj * hj); }
     // where a part's largest h reaches well beyond the chunk's own cutoff,
     // the partner's force record is read before the record is filtered: its
     // own h bounds its reach (the cutoff is max(h_i, h_j))
