@@ -212,10 +212,12 @@ def measure(sph, ps, steps, warmup, prm):
         stage.setdefault(name, []).append(ms)
     # the work of the last step (every step repeats the same computation)
     wd, wf = ctx.work()
+    rd, rf = ctx.reads()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     sums = fout.sums.view(-1, 8).cpu().numpy()
     return {"ms_per_step": (t1 - t0) * 1e3 / steps, "step_ms": step_ms, "stage": stage,
             "P": float(sums[:, 6].sum()) / 2.0, "work_density": wd, "work_force": wf,
+            "reads_density": rd, "reads_force": rf,
             "it": it, "nu": nu, "tree": tree.stats(), "dout": dout, "fout": fout,
             "ws_bytes": int(tree.ws.numel()) if tree.ws is not None else None,
             "ws_peak": tree.workspace_needed()}

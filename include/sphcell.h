@@ -66,6 +66,12 @@ typedef struct sph_tree sph_tree;
 #define SPH_FLAG_RESUME 2u      /* sph_solve_h after this build continues the Newton state saved when
                                    the previous sph_solve_h on the same tree returned SPH_E_REBUILD
                                    (same particles); converged particles keep their density */
+#define SPH_FLAG_NO_BLOCK_SKIP 4u /* read every particle of a partner read in cell order instead of
+                                     passing over its blocks beyond a chunk's reach (bitwise the same
+                                     results, more loads; for testing) */
+#define SPH_FLAG_SORTED_ONLY 8u   /* sweep every partner through its sorted lists, also where the
+                                     swept prefix is long and reading the partner in cell order
+                                     would pass over most of it (same pairs, other summation order) */
 
 /* Parameters.  Defaults (sph_params_default) follow Section III-B: N_ngb = 48,
  * gamma = 5/3, alpha = 2.0, split if more than 400 particles and more than
@@ -86,7 +92,10 @@ typedef struct {
     int32_t max_replicas;  /* lanes per target particle for small chunks: 1, 2, 4, 8 or 16 (0 = 16) */
     int32_t top_coarsen;   /* with top_grid 0: this many levels coarser than the largest allowed top grid
                               (at least 2 cells per side remain) (0) */
-    int32_t reserved[2];
+    int32_t piece_records; /* heavy chunks: a chunk whose walk is estimated to read at least this many
+                              partner records is handed out before the others, split into 8 pieces
+                              (16 from twice as many records); 0 = 16384, -1 = off */
+    int32_t reserved[1];
 } sph_params;
 
 /* Input particle sets (see Conventions).  h is the initial smoothing length
@@ -156,8 +165,8 @@ sph_status sph_ctx_sync(sph_ctx* ctx);
  * and the sorted lists of Section II-C): an estimate for sets like uniform,
  * lattice and clumpy mixtures with up to ~3 decades of h (per particle:
  * ~275 B of particle state, ~580 B of sorted lists, ~240 B of radix scratch
- * for the longest lists, ~120 B of cells, tasks and interaction lists; plus
- * 4 KiB per set and 24 MiB).  The need depends
+ * for the longest lists, ~120 B of cells, tasks and interaction lists, ~60 B
+ * of partial sums of split heavy chunks; plus 4 KiB per set and 24 MiB).  The need depends
  * on the data; a build that finds the workspace too small fails with
  * SPH_E_WORKSPACE and reports what it needs (sph_tree_workspace_needed).
  * sph_footprint(n, p) = sph_workspace_size(n, 1, p): the size admission
@@ -212,7 +221,7 @@ sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const
  * device array of 128 MiB per GPU, held until the process ends -- so that
  * neither this call nor the later calls on the tree (sort, density, solve,
  * force) allocate.  Sets needing more than the scratch holds
- * (sph_workspace_size above 128 MiB, roughly 110 000 particles) are refused
+ * (sph_workspace_size above 128 MiB, roughly 85 000 particles) are refused
  * with SPH_E_CAPACITY; a build that still runs out fails with
  * SPH_E_WORKSPACE.  One tree per GPU can hold the scratch: the calls of a
  * tree that held it before another tree took it fail with SPH_E_STATE (build
@@ -351,13 +360,24 @@ int32_t sph_last_timings(sph_ctx* ctx, const char** names, double* ms, int32_t c
  * Synchronises the context's stream.  Errors: SPH_E_ARG, SPH_E_HIP. */
 sph_status sph_last_work(sph_ctx* ctx, uint64_t* density_pairs, uint64_t* force_pairs);
 
+/* Records the interaction walks loaded in the same passes as sph_last_work
+ * counts (self-task particles plus the swept or cell-order records of the
+ * pair tasks, each time a chunk's frame reads them): *density_records and
+ * *force_records [host].  Set beside the pair evaluations, they give the
+ * share of loaded records that fall within reach (Section II-C: the sorted
+ * sweeps bound the records read per pair task).  Synchronises the
+ * context's stream.  Errors: SPH_E_ARG, SPH_E_HIP. */
+sph_status sph_last_reads(sph_ctx* ctx, uint64_t* density_records, uint64_t* force_records);
+
 /* Enable (1) or disable (0) per-stage event timing on the context. */
 void sph_enable_timing(sph_ctx* ctx, int32_t on);
 
 /* Tree statistics (host): [0] particles, [1] cells, [2] leaves, [3] tasks
  * (self + pair), [4] pair tasks, [5] sorted entries, [6] work chunks,
  * [7] levels, [8] top cells per side of set 0, [9] max leaf size, [10] HIP
- * graphs captured and instantiated by sph_run_graph on this tree so far.
+ * graphs captured and instantiated by sph_run_graph on this tree so far,
+ * [11] heavy chunks (handed out first, see sph_params.piece_records), [12]
+ * their pieces.
  * May synchronise the tree's stream (a count the sort kept on the device). */
 sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap);
 

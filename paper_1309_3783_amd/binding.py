@@ -19,13 +19,16 @@ SPH_OK, SPH_E_ARG, SPH_E_HIP, SPH_E_WORKSPACE, SPH_E_REBUILD, SPH_E_NOCONV, SPH_
     0, -1, -2, -3, -4, -5, -6, -7
 SPH_FLAG_PAIR_HASH = 1
 SPH_FLAG_RESUME = 2
+SPH_FLAG_NO_BLOCK_SKIP = 4
+SPH_FLAG_SORTED_ONLY = 8
 
 # every function the header declares
 EXPORTS = ["sph_version", "sph_status_str", "sph_params_default", "sph_ctx_create", "sph_ctx_destroy",
-           "sph_last_error", "sph_ctx_sync", "sph_workspace_size", "sph_footprint", "sph_tree_create", "sph_tree_destroy",
-           "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
-           "sph_build_cells_static", "sph_refresh_cells", "sph_sort_pairs", "sph_density", "sph_solve_h", "sph_force", "sph_set_halo",
-           "sph_run_graph", "sph_last_timings", "sph_last_work", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
+           "sph_last_error", "sph_ctx_sync", "sph_workspace_size", "sph_footprint", "sph_tree_create",
+           "sph_tree_destroy", "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed",
+           "sph_build_cells", "sph_build_cells_static", "sph_refresh_cells", "sph_sort_pairs", "sph_density",
+           "sph_solve_h", "sph_force", "sph_set_halo", "sph_run_graph", "sph_last_timings", "sph_last_work",
+           "sph_last_reads", "sph_enable_timing", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt"]
 
 
 class sph_params(C.Structure):
@@ -33,7 +36,8 @@ class sph_params(C.Structure):
                 ("max_depth", C.c_int32), ("top_grid", C.c_int32), ("n_target", C.c_float),
                 ("h_tol", C.c_float), ("max_iter", C.c_int32), ("gamma", C.c_float), ("alpha", C.c_float),
                 ("flags", C.c_uint32), ("blocks_per_cu", C.c_int32), ("max_replicas", C.c_int32),
-                ("top_coarsen", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("top_coarsen", C.c_int32), ("piece_records", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class sph_input(C.Structure):
@@ -104,18 +108,18 @@ def lib():
         L.sph_last_timings.argtypes = [vp, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.c_int32]
         L.sph_last_timings.restype = C.c_int32
         L.sph_last_work.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.sph_last_reads.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.sph_enable_timing.argtypes = [vp, C.c_int32]
         L.sph_enable_timing.restype = None
         L.sph_tree_stats.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32]
         L.sph_kick.argtypes = [vp, C.c_int64, C.c_float] + [vp] * 12
         L.sph_drift.argtypes = [vp, C.c_int32, vp, vp, C.c_double] + [vp] * 6
         L.sph_cfl_dt.argtypes = [vp, C.c_int64, vp, vp, C.c_float, C.POINTER(C.c_double)]
-        for name in ("sph_ctx_create", "sph_ctx_sync", "sph_footprint", "sph_workspace_size", "sph_tree_create", "sph_tree_bytes",
-                     "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
+        for name in ("sph_ctx_create", "sph_ctx_sync", "sph_footprint", "sph_workspace_size", "sph_tree_create",
+                     "sph_tree_bytes", "sph_tree_set_workspace", "sph_tree_workspace_needed", "sph_build_cells",
                      "sph_build_cells_static", "sph_refresh_cells", "sph_sort_pairs", "sph_density", "sph_solve_h",
-                     "sph_force",
-                     "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt", "sph_last_work",
-                     "sph_set_halo"):
+                     "sph_force", "sph_run_graph", "sph_tree_stats", "sph_kick", "sph_drift", "sph_cfl_dt",
+                     "sph_last_work", "sph_last_reads", "sph_set_halo"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -192,6 +196,12 @@ class Context:
         """(density pair evaluations, force pair evaluations) of the last calls."""
         d, f = C.c_uint64(0), C.c_uint64(0)
         self.check(lib().sph_last_work(self.h, C.byref(d), C.byref(f)), "sph_last_work")
+        return int(d.value), int(f.value)
+
+    def reads(self):
+        """(density records loaded, force records loaded) of the same calls."""
+        d, f = C.c_uint64(0), C.c_uint64(0)
+        self.check(lib().sph_last_reads(self.h, C.byref(d), C.byref(f)), "sph_last_reads")
         return int(d.value), int(f.value)
 
     def close(self):
@@ -452,10 +462,10 @@ class Tree:
                                                C.byref(self._gf), _ptr(unconv)), "sph_run_graph")
 
     def stats(self) -> dict:
-        v = (C.c_int64 * 11)()
-        self.ctx.check(lib().sph_tree_stats(self.h, v, 11), "sph_tree_stats")
+        v = (C.c_int64 * 13)()
+        self.ctx.check(lib().sph_tree_stats(self.h, v, 13), "sph_tree_stats")
         keys = ["particles", "cells", "leaves", "tasks", "pair_tasks", "sorted_entries", "chunks", "levels",
-                "top_grid", "max_leaf", "graph_captures"]
+                "top_grid", "max_leaf", "graph_captures", "heavy_chunks", "pieces"]
         return dict(zip(keys, [int(x) for x in v]))
 
     def bytes(self) -> int:

@@ -167,10 +167,12 @@ sph_status sph_workspace_size(int64_t n, int32_t nsets, const sph_params* p, siz
     // particle on a clustered set with h over three decades: 580 B), plus
     // 24 B of radix keys and values per entry of the lists longer than
     // 16384 (about 10 per particle there: 240 B).  Cells, tasks and
-    // interaction lists: ~120 B.  Plus the set tables and a fixed reserve.
-    // Measured peaks: 547 B per particle on a 10^6 lattice, 1110 B on the
-    // 8*10^6 clustered mixture.
-    const double per = 275.0 + 580.0 + 240.0 + 120.0;
+    // interaction lists: ~120 B.  Heavy chunks: 4 KiB of partial sums per
+    // piece, ~37 B per particle on the clustered mixture (a piece per ~110
+    // particles): 60 B.  Plus the set tables and a fixed reserve.  Measured
+    // peaks: 548 B per particle on a 10^6 lattice, 1169 B on the 8*10^6
+    // clustered mixture.
+    const double per = 275.0 + 580.0 + 240.0 + 120.0 + 60.0;
     *bytes = (size_t)(per * (double)n) + (size_t)nsets * 4096 + ((size_t)24 << 20);
     return SPH_OK;
 }
@@ -326,6 +328,22 @@ sph_status sph_last_work(sph_ctx* ctx, uint64_t* density_pairs, uint64_t* force_
     return SPH_OK;
 }
 
+sph_status sph_last_reads(sph_ctx* ctx, uint64_t* density_records, uint64_t* force_records) {
+    if (!ctx) return SPH_E_ARG;
+    // the word after each pair-evaluation counter
+    const void* d = ctx->d_counter + sph_ctx::CTR_WORK;
+    if (hipMemcpyAsync(ctx->h_pin, d, 512 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return SPH_E_HIP;
+    const uint64_t* v = (const uint64_t*)ctx->h_pin;
+    uint64_t s[2] = {0, 0};
+    for (int k = 0; k < 2; ++k)
+        for (int g = 0; g < 8; ++g) s[k] += v[k * 128 + g * 16 + 1];
+    if (density_records) *density_records = s[0];
+    if (force_records) *force_records = s[1];
+    return SPH_OK;
+}
+
 void sph_enable_timing(sph_ctx* ctx, int32_t on) {
     if (ctx) ctx->timing = on != 0;
 }
@@ -341,7 +359,7 @@ sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap) {
             return SPH_E_HIP;
         const_cast<sph_tree*>(t)->nsegent = v;
     }
-    int64_t v[11] = {t->n,
+    int64_t v[13] = {t->n,
                      t->ncells,
                      t->nleaves,
                      t->ntasks,
@@ -351,8 +369,10 @@ sph_status sph_tree_stats(const sph_tree* t, int64_t* stats, int32_t cap) {
                      t->nlevels,
                      t->sets.empty() ? 0 : (int64_t)1 << t->sets[0].lgG,
                      t->max_leaf,
-                     t->graph_captures};
-    for (int i = 0; i < cap && i < 11; ++i) stats[i] = v[i];
+                     t->graph_captures,
+                     t->nheavy,
+                     t->npieces};
+    for (int i = 0; i < cap && i < 13; ++i) stats[i] = v[i];
     return SPH_OK;
 }
 

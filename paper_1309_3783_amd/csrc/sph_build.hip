@@ -554,6 +554,93 @@ __global__ void k_chunk_emit(const Cell* __restrict__ cells, int64_t nc, const u
         chunks[num[C.first + s]] = make_int4((int)c, C.first + s, min(CHUNK, C.count - s), top);
 }
 
+// Heavy chunks.  A chunk whose walk reads far more partner records than
+// most (a leaf of large h next to dense cells) would run alone at the end
+// of a pass; such chunks are handed out before the others, split into
+// pieces that each take every P-th group of the records the walk reads,
+// and the pieces' partial sums are added in piece order after the pass.
+// The records read are estimated as the sorted sweeps read them: per pair
+// entry the partner's particle count times the fraction of the partner
+// cell whose projection on the pair direction lies within the leaf's
+// largest h of the leaf cell's farthest projection (particles spread
+// evenly along the direction).  pcount: pieces per chunk (0 for the chunks handed out
+// with the others); poff: the first list slot of its pieces, reserved with
+// one atomic per heavy chunk (the slots' order changes no result: the
+// pieces of a chunk are contiguous and added in piece order); total[0]
+// counts the pieces, total[1] the heavy chunks.
+// One wave per chunk, a lane per pair entry.
+__global__ __launch_bounds__(256) void k_chunk_cost(const int4* __restrict__ chunks,
+                                                    const uint32_t* __restrict__ nch_dev, int64_t cap,
+                                                    const Cell* __restrict__ cells, const SetInfo* __restrict__ sets,
+                                                    const uint32_t* __restrict__ csr_off,
+                                                    const uint64_t* __restrict__ csr, float piece,
+                                                    uint32_t* __restrict__ pcount, uint32_t* __restrict__ poff,
+                                                    uint32_t* __restrict__ total) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= cap) return;
+    if (c >= (int64_t)*nch_dev) {
+        if (lane == 0) pcount[c] = 0;
+        return;
+    }
+    const int4 ch = chunks[c];
+    const Cell L = cells[ch.x];
+    // lengths in top-cell edges; cell corners as integer coordinates times
+    // the edge of their level (exact)
+    const float hr = (float)((double)L.hmax / sets[L.set].L0);
+    const float el = ldexpf(1.f, -L.level);
+    const float lo[3] = {(float)L.ix * el, (float)L.iy * el, (float)L.iz * el};
+    float est = 0.f;
+    for (int A = ch.x; A >= 0;) {
+        const Cell CA = cells[A];
+        const float ea = ldexpf(1.f, -CA.level);
+        const uint32_t e1 = csr_off[A + 1];
+        for (uint32_t e = csr_off[A] + lane; e < e1; e += 64) {
+            const uint64_t key = csr[e];
+            const int B = (int)((key >> CSR_SRC_SHIFT) & 0xFFFFFFFFull), code = (int)(key & 31);
+            const int o[3] = {ocx(code), ocy(code), ocz(code)};
+            const int ci[3] = {CA.ix, CA.iy, CA.iz};
+            // the leaf's farthest projection on o, the partner's range
+            float tb = 0.f, p0 = 0.f, p1 = 0.f;
+            for (int d = 0; d < 3; ++d) {
+                const float b0 = (float)(ci[d] + o[d]) * ea;
+                if (o[d] > 0) {
+                    tb += lo[d] + el;
+                    p0 += b0;
+                    p1 += b0 + ea;
+                } else if (o[d] < 0) {
+                    tb -= lo[d];
+                    p0 -= b0 + ea;
+                    p1 -= b0;
+                }
+            }
+            const int nz = abs(o[0]) + abs(o[1]) + abs(o[2]);
+            const float dn = nz == 1 ? 1.f : (nz == 2 ? 1.41421356f : 1.73205081f);
+            const float f = fminf(fmaxf((tb + hr * dn - p0) / (p1 - p0), 0.f), 1.f);
+            est += (float)cells[B].count * f;
+        }
+        A = CA.parent;
+    }
+    for (int d = 32; d >= 1; d >>= 1) est += __shfl_xor(est, d, 64);
+    if (lane != 0) return;
+    // at the threshold 8 pieces, up to PIECE_MAX for twice as many records
+    int pn = 0;
+    if (piece > 0.f && est >= piece) pn = min((int)ceilf(8.f * est / piece), PIECE_MAX);
+    pcount[c] = (uint32_t)pn;
+    if (pn > 0) {
+        poff[c] = atomicAdd(&total[0], (uint32_t)pn);
+        atomicAdd(&total[1], 1u);
+    }
+}
+
+__global__ void k_piece_emit(const uint32_t* __restrict__ nch_dev, const uint32_t* __restrict__ pcount,
+                             const uint32_t* __restrict__ poff, uint32_t* __restrict__ list) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)*nch_dev) return;
+    const uint32_t pn = pcount[c];
+    for (uint32_t k = 0; k < pn; ++k) list[poff[c] + k] = ((uint32_t)c << 5) | k;
+}
+
 // One wave per chunk (the chunk count is read on the device).
 // The bound of a particle is the smallest bound of its leaf and ancestors,
 // less twice its set's accumulated displacement since the build (zero right
@@ -688,6 +775,45 @@ __global__ void k_drift_add(SetInfo* sets, int nsets, const unsigned* __restrict
     float t = a + b;
     if ((double)t < (double)a + (double)b) t = nextafterf(t, INFINITY);
     sets[s].drift = t;
+}
+
+// Block summaries of the particle array in cell order (blocks of BLK_PART
+// particles at aligned indices): a bit per top cell's first particle, then
+// per block the bounding box of its positions.  The cells nest in this
+// order, so a block covers a small region, and a chunk reading a large cell
+// in this order can pass over the blocks that lie beyond its reach without
+// loading them.  A block that holds particles of two top cells (offsets from
+// different origins) gets the whole space as its box and is never passed
+// over.
+constexpr int BLK_PART = 64;
+__global__ void k_top_starts(const Cell* __restrict__ cells, int64_t nc, unsigned long long* __restrict__ bits) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const Cell C = cells[c];
+    if (C.parent >= 0 || C.count == 0) return;
+    atomicOr(&bits[C.first / BLK_PART], 1ull << (C.first % BLK_PART));
+}
+
+// One wavefront per block.
+__global__ __launch_bounds__(256) void k_block_box(const float4* __restrict__ pos, int64_t n,
+                                                   const unsigned long long* __restrict__ bits, int64_t nblk,
+                                                   float4* __restrict__ box) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nblk; b += (int64_t)gridDim.x * 4) {
+        const int64_t e = b * BLK_PART + lane;
+        const bool in = e < n;
+        const float4 p = in ? pos[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float v[6] = {in ? -p.x : -INFINITY, in ? -p.y : -INFINITY, in ? -p.z : -INFINITY,
+                      in ? p.x : -INFINITY, in ? p.y : -INFINITY, in ? p.z : -INFINITY};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = wave_max_f(v[k]);
+        if (lane == 0) {
+            const bool mixed = (bits[b] & ~1ull) != 0ull;
+            const float big = 3.0e38f;
+            box[2 * b] = mixed ? make_float4(-big, -big, -big, 0.f) : make_float4(-v[0], -v[1], -v[2], 0.f);
+            box[2 * b + 1] = mixed ? make_float4(big, big, big, 0.f) : make_float4(v[3], v[4], v[5], 0.f);
+        }
+    }
 }
 
 // Sorted lists: each entry's copy of its particle's record, in place (the
@@ -1190,6 +1316,31 @@ static Err read_back(sph_ctx* ctx, const void* d, size_t bytes, const void** h) 
     return Err{};
 }
 
+// Block summaries of the particle array (kept for every tree, so that
+// whether a partner is read in cell order depends on that pair entry alone,
+// not on the other sets of a batch).
+static Err block_summaries(sph_ctx* ctx, sph_tree* t) {
+    hipStream_t st = ctx->stream;
+    t->blkbits = nullptr;
+    t->blkbox = nullptr;
+    t->nblk = 0;
+    if (t->n <= 0) return Err{};
+    const int64_t nb = (t->n + BLK_PART - 1) / BLK_PART;
+    void* p;
+    ERRTRY(t->alloc(t->b_blk, (sizeof(uint64_t) + 2 * sizeof(float4)) * nb, &p));
+    t->blkbox = (float4*)p;
+    t->blkbits = (uint64_t*)(t->blkbox + 2 * nb);
+    t->nblk = nb;
+    HIPTRY(fill_u32((uint32_t*)t->blkbits, 2 * nb, 0u, st));
+    hipLaunchKernelGGL(k_top_starts, dim3(nblk(t->ncells, 256)), dim3(256), 0, st, t->cells, t->ncells,
+                       (unsigned long long*)t->blkbits);
+    HIPTRY(hipGetLastError());
+    hipLaunchKernelGGL(k_block_box, dim3((unsigned)std::min<int64_t>(nblk(nb, 4), 65535)), dim3(256), 0, st, t->pos,
+                       t->n, (const unsigned long long*)t->blkbits, nb, t->blkbox);
+    HIPTRY(hipGetLastError());
+    return Err{};
+}
+
 Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* prm) {
     hipStream_t st = ctx->stream;
     // ---- validate the host description ---------------------------------
@@ -1206,7 +1357,8 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     if (n > 0 && (!in->x || !in->y || !in->z || !in->h || !in->m || !in->u || !in->vx || !in->vy || !in->vz))
         return Err{SPH_E_ARG, "null particle array"};
     if (prm->n_split < 1 || !(prm->split_frac >= 0.f && prm->split_frac <= 1.f) || !(prm->h_slack >= 0.f) ||
-        prm->max_depth < 0 || prm->max_depth > 16 || prm->top_coarsen < 0 || prm->top_coarsen > 8)
+        prm->max_depth < 0 || prm->max_depth > 16 || prm->top_coarsen < 0 || prm->top_coarsen > 8 ||
+        prm->piece_records < -1)
         return Err{SPH_E_ARG, "bad decomposition parameters"};
     t->prm = *prm;
     t->nsets = in->nsets;
@@ -1533,16 +1685,42 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         t->ncsr = ne;
         t->ncsr_dev = nullptr;
     }
-    // chunk count (total[0], untouched since its scan), leaves, largest leaf
+    // heavy chunks: pieces per chunk, the pieces and heavy chunks in total[18], total[19]
+    const int piece_rec = prm->piece_records == 0 ? 16384 : prm->piece_records;
+    const bool pieces = piece_rec > 0 && chunk_cap < ((int64_t)1 << 27);
+    ERRTRY(t->alloc(t->b_piece, 2 * sizeof(uint32_t) * chunk_cap, (void**)&t->pcount));
+    t->poff = t->pcount + chunk_cap;
+    HIPTRY(fill_u32(total + 18, 2, 0u, st));
+    if (pieces) {
+        hipLaunchKernelGGL(k_chunk_cost, dim3(nblk(chunk_cap, 4)), dim3(256), 0, st, t->chunks, total, chunk_cap,
+                           t->cells, d_sets, t->csr_off, t->csr, (float)piece_rec, t->pcount, t->poff, total + 18);
+        HIPTRY(hipGetLastError());
+    } else {
+        HIPTRY(fill_u32(t->pcount, chunk_cap, 0u, st));
+    }
+    // chunk count (total[0], untouched since its scan), leaves, largest
+    // leaf, pieces, heavy chunks
     static_assert(sizeof(int) == sizeof(uint32_t), "layout of the count words");
-    ERRTRY(read_back(ctx, total, 18 * sizeof(uint32_t), &rb));
+    ERRTRY(read_back(ctx, total, 20 * sizeof(uint32_t), &rb));
     const uint32_t nchunks = ((const uint32_t*)rb)[0];
     t->nleaves = ((const int*)rb)[16];
     t->max_leaf = ((const int*)rb)[17];
+    t->npieces = ((const uint32_t*)rb)[18];
+    t->nheavy = ((const uint32_t*)rb)[19];
     t->nchunks = nchunks;
     if ((int64_t)nchunks > chunk_cap) return Err{SPH_E_STATE, "internal: chunk count above its bound"};
+    t->plist = nullptr;
+    t->part = nullptr;
+    if (t->npieces > 0) {
+        ERRTRY(t->alloc(t->b_plist, sizeof(uint32_t) * t->npieces, (void**)&t->plist));
+        ERRTRY(t->alloc(t->b_part, sizeof(double) * PART_WORDS * CHUNK * t->npieces, (void**)&t->part));
+        hipLaunchKernelGGL(k_piece_emit, dim3(nblk(nchunks, 256)), dim3(256), 0, st, total, t->pcount, t->poff,
+                           t->plist);
+        HIPTRY(hipGetLastError());
+    }
     // every non-empty leaf holds exactly one final self task
     t->npairs = nfinal - t->nleaves;
+    ERRTRY(block_summaries(ctx, t));
     t->built = true;
     ev_mark(ctx, "build");
     return Err{};
@@ -1585,6 +1763,11 @@ Err refresh_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in) {
     hipLaunchKernelGGL(k_particle_bound, dim3(gch), dim3(256), 0, st, t->chunks, nchw, t->cells, t->d_sets, t->ph,
                        t->bound, viol);
     HIPTRY(hipGetLastError());
+    if (t->blkbox) {
+        hipLaunchKernelGGL(k_block_box, dim3((unsigned)std::min<int64_t>(nblk(t->nblk, 4), 65535)), dim3(256), 0, st,
+                           t->pos, n, (const unsigned long long*)t->blkbits, t->nblk, t->blkbox);
+        HIPTRY(hipGetLastError());
+    }
     if (t->sorted) {
         const int64_t ne = t->nsegent >= 0 ? t->nsegent : (int64_t)NAXES * n;
         if (ne > 0) {

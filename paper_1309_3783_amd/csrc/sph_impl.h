@@ -136,7 +136,7 @@ struct sph_tree {
     sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_plo, b_pv, b_ph, b_hdec, b_pu,
         b_bound, b_mix, b_rs, b_cell, b_taskA, b_taskB, b_final, b_chunk, b_csr, b_csr2, b_csroff,
         b_segoff, b_seglist, b_segproj, b_segidx, b_bigk, b_bigv, b_sc, b_dens, b_force, b_solve,
-        b_red, b_misc, b_saved, b_split, b_counts, b_iperm, b_owned;
+        b_red, b_misc, b_saved, b_split, b_counts, b_iperm, b_owned, b_blk, b_piece, b_plist, b_part;
 
     // ---- sizes (host) --------------------------------------------------
     int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nchunks = 0, max_leaf = 0;
@@ -165,6 +165,22 @@ struct sph_tree {
     int4* chunks = nullptr;           // work chunks: (leaf, first particle, count, top cell of the leaf)
     uint32_t *csr_off = nullptr, *segoff = nullptr, *seglist = nullptr, *segidx = nullptr;
     float4* segpos = nullptr;   // sorted lists: the particle records (x, y, z, m) in list order
+    // the particle array in blocks of 64 (aligned to particle indices): per
+    // block a bit per particle that starts a top cell, and the bounding box
+    // of the positions (2 float4: min, max; the whole space when the block
+    // holds particles of two top cells); null for an empty tree
+    uint64_t* blkbits = nullptr;
+    float4* blkbox = nullptr;
+    int64_t nblk = 0;
+    // heavy chunks: per chunk the number of pieces it is handed out in (0:
+    // with the others; 1: first, whole; 2..: first, split), the first slot of
+    // its pieces; the list of pieces (chunk << 5 | piece) and per piece the
+    // partial sums of its 64 particles (PART_WORDS doubles each)
+    uint32_t* pcount = nullptr;
+    uint32_t* poff = nullptr;
+    uint32_t* plist = nullptr;
+    double* part = nullptr;
+    int64_t npieces = 0, nheavy = 0;
     uint32_t *sc_a = nullptr, *sc_b = nullptr, *sc_c = nullptr, *sc_d = nullptr, *sc_tmp = nullptr;
     uint32_t* split_idx = nullptr;   // split flags of one level, scanned in place
     uint32_t* d_counts = nullptr;    // [0] sorted-list entries when not read back (nsegent < 0)
@@ -216,7 +232,8 @@ struct sph_tree {
         return {&b_sets, &b_small, &b_key, &b_key2, &b_val, &b_val2, &b_perm, &b_pos, &b_plo, &b_pv, &b_ph, &b_hdec,
                 &b_pu, &b_bound, &b_mix, &b_rs, &b_cell, &b_taskA, &b_taskB, &b_final, &b_chunk, &b_csr,
                 &b_csr2, &b_csroff, &b_segoff, &b_seglist, &b_segproj, &b_segidx, &b_bigk, &b_bigv, &b_sc,
-                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts, &b_iperm, &b_owned};
+                &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts, &b_iperm, &b_owned,
+                &b_blk, &b_piece, &b_plist, &b_part};
     }
 
     // Drop every buffer (the tree must be built again).  Library-owned

@@ -98,6 +98,12 @@ __device__ __forceinline__ int next_chunk(int* __restrict__ ctr, int nchunks, co
     return -1;
 }
 
+// Heavy chunks go first: wave w of the grid's W takes pieces w, w + W, ...
+// of the piece list before it turns to the chunk ranges (the grid is
+// resident at once, so no counter is needed: one atomic on one word from
+// every wave at the start would serialise).  Chunks with pieces are skipped
+// in the ranges.
+
 // The chunks that still hold particles in Newton state 1 (active), listed
 // per work range for the next density pass: one thread per chunk, blocks
 // within one range, one atomic per block.  lcount must be zero on entry; the
@@ -296,6 +302,13 @@ struct DensArgs {
     const uint32_t* segoff;
     const float4* segpos;
     const uint32_t* segidx;
+    const float4* blkbox;   // block boxes of the particle array (null: no cell is read in cell order)
+    int cellord;            // long sweeps may read the partner in cell order
+    int skip;               // ... passing over its blocks out of reach (0: test every record, same results)
+    const uint32_t* pcount; // heavy chunks: pieces per chunk (0: handed out with the others)
+    const uint32_t* plist;  // the pieces (chunk << 5 | piece), handed out first
+    int npieces;
+    double* part;           // partial sums of the pieces of split chunks
     const int32_t* status;
     float *rho, *drho, *nw, *dnw;
     int32_t* nngb;
@@ -334,7 +347,7 @@ __device__ __forceinline__ int wave_count(int v) {
 }
 // ... and added up once per wave when it leaves the kernel, into one of 8
 // counters 128 bytes apart (one same-address atomic per wave step from the
-// whole GPU would serialise).
+// whole GPU would serialise); the records loaded go to the word after each.
 __device__ __forceinline__ void flush_work(unsigned long long* work, unsigned long long v) {
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(work + 16 * (blockIdx.x & 7), v);
 }
@@ -475,25 +488,35 @@ struct SweepTab {
     int o[2 * DBATCH + 1];
 };
 
+// A part is a sweep of a sorted list (z = +1 ascending, -1 descending, x
+// its first list position, y its length) or a read of a partner's particles
+// in cell order (z = 0, x its first particle, y its count).
+constexpr int SCAN_MIN = 256;   // swept records from which a partner may be read in cell order ...
+constexpr int SCAN_RATIO = 2;   // ... if it holds at most this many times as many particles
+
 // Builds the descriptors of entries [e0, e0 + n) of cell cA (n <= DBATCH);
-// returns their number, *total the number of records they cover.  bx:
+// returns their number, *total the number of records they cover,
+// *cellorder whether some part is read in cell order.  bx:
 // largest o_k x_k over the chunk's particles per axis and sign (bx[0..2] =
 // max x, bx[3..5] = -min x); hmax: largest h of the chunk.
 template <class P>
 __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cell& cA, float L0, const Frame& fr,
                                             uint32_t e0, int n, const float (&bx)[6], float hmax, SweepTab& T,
-                                            int* total) {
+                                            int* total, bool* cellorder) {
     const int lane = threadIdx.x & 63;
     int4 q0 = make_int4(0, 0, 0, 0), q1 = q0;
     float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0;
     float lim0 = 0.f, lim1 = 0.f;
     int code = 13;
+    int bfirst = 0, bcount = 0;
     if (lane < n) {
         const uint64_t key = a.csr[e0 + lane];
         const int B = (int)((key >> 5) & 0xFFFFFFFFull);
         code = (int)(key & 31);
         const PairGeo g = pair_geo(cA, code, L0);
         const Cell cB = a.cells[B];
+        bfirst = cB.first;
+        bcount = cB.count;
         const uint32_t so = a.segoff[(int64_t)B * NAXES + g.axis];
         const int ox = ocx(code), oy = ocy(code), oz = ocz(code);
         // largest o . x over the box (x and the shifted records share the
@@ -533,7 +556,19 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
         }
         return lo;
     };
-    const int c0 = prefix(q0, lim0), c1 = prefix(q1, lim1);
+    int c0 = prefix(q0, lim0), c1 = prefix(q1, lim1);
+    // a partner with a long swept prefix that is not much longer than the
+    // partner itself is read in cell order instead, as one part with the
+    // larger radius: the blocks of it beyond the chunk's reach are then
+    // passed over (skip_blocks)
+    const bool scan = a.cellord && c0 + c1 >= SCAN_MIN && bcount <= SCAN_RATIO * (c0 + c1);
+    if (scan) {
+        q0 = make_int4(bfirst, bcount, 0, 0);
+        f0.w = fmaxf(f0.w, f1.w);
+        c0 = bcount;
+        c1 = 0;
+    }
+    *cellorder = __ballot(scan) != 0ull;
     const bool ne0 = c0 > 0, ne1 = c1 > 0;
     const uint64_t b0 = __ballot(ne0), b1 = __ballot(ne1);
     const int pos = bits_below(b0) + bits_below(b1);
@@ -564,8 +599,73 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
     return nd;
 }
 
+// Parts read in cell order: the records from sequence index g0 on are
+// particles in blocks of 64 whose bounding boxes (and, for the force, the
+// largest h) are known.  One block per lane is tested against the chunk's
+// bounding box with the part's cutoff radius, bounded by the block's largest
+// h where the records' own h bound their reach (the test the walk applies
+// to each record of such a part, on the block's extremes: a block out of
+// reach holds no record within reach, by the monotonicity of the rounded
+// arithmetic).  Returns the new g0: past the leading blocks out
+// of reach, rounded down to a multiple of 64 records from the old one, so
+// that the records are loaded in the same groups of 64 as without the test
+// and the staged sequence is bitwise the same.  *hold receives the sequence
+// index before which no block needs to be tested again (the end of the run
+// of blocks kept from the first kept one).
+template <class P>
+__device__ __forceinline__ int skip_blocks(const float4* __restrict__ blkbox, const SweepTab& T, int nd, int g0,
+                                           float lox, float loy, float loz, const float (&bx)[6], float hmax,
+                                           float tiny, int* hold) {
+    constexpr int BLK = 64;   // particles per block
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = nd - 1;   // the part holding g0 (wave-uniform)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T.o[mid] <= g0) lo = mid;
+        else hi = mid - 1;
+    }
+    const int pend = T.o[lo + 1];
+    const int4 dq = T.q[lo];
+    if (dq.z != 0 || pend - g0 < 2 * BLK) {
+        *hold = pend;
+        return g0;
+    }
+    const float4 df = T.f[lo];
+    const int q0 = dq.x + (g0 - T.o[lo]);      // particle of record g0
+    const int b0 = q0 / BLK, blast = (q0 + (pend - g0) - 1) / BLK;
+    const int bl = b0 + lane;
+    const bool valid = bl <= blast;
+    bool keep = false;
+    if (valid) {
+        const float4 mn = blkbox[2 * bl], mx = blkbox[2 * bl + 1];
+        const float gx = fmaxf(fmaxf(lox - (mx.x + df.x), (mn.x + df.x) - bx[0]), 0.f);
+        const float gy = fmaxf(fmaxf(loy - (mx.y + df.y), (mn.y + df.y) - bx[1]), 0.f);
+        const float gz = fmaxf(fmaxf(loz - (mx.z + df.z), (mn.z + df.z) - bx[2]), 0.f);
+        keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) <= P::blk_rad2(df.w, mn.w, hmax, tiny);
+    }
+    const uint64_t vm = __ballot(valid), km = __ballot(keep);
+    // sequence index of the first record of block b0 + k (at most the part's end)
+    auto first_of = [&](int k) { return min(pend, g0 + (b0 + k) * BLK - q0); };
+    const int nv = __popcll(vm);   // the valid lanes are 0 .. nv-1
+    int to;
+    if (km == 0) {
+        to = first_of(nv);
+        *hold = to;
+    } else {
+        // from the first block kept to the first block out of reach after it
+        const int f = __builtin_ctzll(km);
+        const uint64_t after = vm & ~km & (~0ull << f);
+        *hold = first_of(after ? __builtin_ctzll(after) : nv);
+        to = f == 0 ? g0 : first_of(f);
+    }
+    return g0 + ((to - g0) & ~(BLK - 1));
+}
+
 // The walk of one chunk, in one frame (origin oA relative to the leaf's top
-// cell; the lanes' coordinates are in that frame): the leaf's self task, then
+// cell; the lanes' coordinates are in that frame), or of piece k of P of a
+// split chunk (pm = k | P << 5; 1 << 5 for a whole chunk: the piece takes
+// the blocks of 64 self-task particles and the groups of 64 swept records
+// whose index is k mod P): the leaf's self task, then
 // the pair tasks of the leaf and of its ancestors; each pair task sweeps the partner's sorted
 // list (small-h part, then large-h part) up to the largest reach of the
 // chunk along the pair axis, bounded by the bounding box of its particles
@@ -573,13 +673,15 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
 // staged in sequence, each step filling the current tile; written as one
 // loop so that the tile processing is inlined once.
 template <class P>
-__device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds& S, SweepTab& T,
-                                     const typename P::Lane& L, typename P::Acc& acc, int leaf, const Frame& fr,
-                                     int R, int rep, bool act) {
+__device__ __forceinline__ int walk(const typename P::Args& a, typename P::Lds& S, SweepTab& T,
+                                    const typename P::Lane& L, typename P::Acc& acc, int leaf, const Frame& fr,
+                                    int R, int rep, bool act, int pm) {
     const int lane = threadIdx.x & 63;
+    int nread = 0;   // records loaded (wave-uniform)
     const Cell C = a.cells[leaf];
-    int sbase = C.first;                 // next record of the self task
     const int cend = C.first + C.count;
+    const int pk = pm & 31, pn = pm >> 5;
+    int sbase = C.first + 64 * pk;   // next record of the self task
     // bounding box and largest h of the lanes' particles
     float bx[6];
     bx[0] = wave_max_dpp(act ? L.x.x : -INFINITY);
@@ -595,6 +697,7 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
     float L0 = (float)a.sets[C.set].L0;
     uint32_t e = a.csr_off[A], e1 = a.csr_off[A + 1];
     int nd = 0, tot = 0, g0 = 0;     // descriptors of the batch, their records, records loaded
+    int hold = 0;                    // records before this index need no block test
     int fill = 0;
     bool tself = false;   // the current tile holds records of the self task
     // a record is staged only if it lies within the cutoff of the chunk's
@@ -613,6 +716,7 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
         float Sx = 0.f, Sy = 0.f, Sz = 0.f, rad2 = 0.f;
         uint32_t q = 0;                     // where it was read: list position (or particle) and part
         int dl = -1;
+        bool co = false;                    // a record of a part read in cell order
         typename P::Pre pre{};
         if (sbase < cend) {
             // a block of the self task
@@ -626,31 +730,48 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
             Sz = -oA.z;
             rad2 = rself2;
             self = true;
-            sbase += nuse;
+            sbase += 64 * pn;   // (a piece: the next block of its own)
+            nread += nuse;
         } else {
             // next batch of entries: of this cell, or of its ancestors
             // (a batch may sweep no records at all)
-            while (g0 >= tot) {
-                while (e >= e1 && A >= 0) {
-                    A = cA.parent;
-                    if (A >= 0) {
-                        cA = a.cells[A];
-                        L0 = (float)a.sets[cA.set].L0;
-                        e = a.csr_off[A];
-                        e1 = a.csr_off[A + 1];
+            for (;;) {
+                while (g0 >= tot) {
+                    while (e >= e1 && A >= 0) {
+                        A = cA.parent;
+                        if (A >= 0) {
+                            cA = a.cells[A];
+                            L0 = (float)a.sets[cA.set].L0;
+                            e = a.csr_off[A];
+                            e1 = a.csr_off[A + 1];
+                        }
                     }
+                    if (A < 0) {
+                        done = true;
+                        break;
+                    }
+                    const int n = (int)min(e1 - e, (uint32_t)DBATCH);
+                    bool co_any;
+                    nd = build_sweeps<P>(a, cA, L0, fr, e, n, bx, hmax, T, &tot, &co_any);
+                    e += n;
+                    g0 = 0;
+                    hold = co_any ? 0 : tot;   // blocks are tested in parts read in cell order only
                 }
-                if (A < 0) {
-                    done = true;
-                    break;
+                if (done) break;
+                if (pn > 1) {
+                    // a piece takes the groups of 64 records k, k + P, ...
+                    const int r = ((g0 >> 6) - pk) % pn;
+                    if (r != 0) g0 += 64 * (pn - (r < 0 ? r + pn : r));
+                    if (g0 >= tot) continue;
                 }
-                const int n = (int)min(e1 - e, (uint32_t)DBATCH);
-                nd = build_sweeps<P>(a, cA, L0, fr, e, n, bx, hmax, T, &tot);
-                e += n;
-                g0 = 0;
+                if (!a.skip || g0 < hold) break;
+                // pass over the blocks of a part read in cell order that lie
+                // beyond the chunk's reach
+                g0 = skip_blocks<P>(a.blkbox, T, nd, g0, lox, loy, loz, bx, hmax, tiny, &hold);
             }
             // the next 64 records of the batch's sequence
             if (!done) nuse = min(64, tot - g0);
+            nread += nuse;
             if (lane < nuse) {
                 const int g = g0 + lane;
                 int lo = 0, hi = nd - 1;   // the last part starting at or before g
@@ -662,10 +783,16 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
                 const int4 dq = T.q[lo];
                 const float4 df = T.f[lo];
                 const int k = g - T.o[lo];
-                q = (uint32_t)dq.x + (uint32_t)(dq.z > 0 ? k : dq.y - 1 - k);
+                q = (uint32_t)dq.x + (uint32_t)(dq.z >= 0 ? k : dq.y - 1 - k);
                 dl = lo;
-                pj = a.segpos[q];
-                j = a.segidx[q];
+                if (dq.z == 0) {
+                    pj = a.pos[q];
+                    j = q;
+                    co = true;
+                } else {
+                    pj = a.segpos[q];
+                    j = a.segidx[q];
+                }
                 Sx = df.x;
                 Sy = df.y;
                 Sz = df.z;
@@ -673,9 +800,11 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
             }
             g0 += nuse;
         }
-        // the records' own data bound their reach only where some part
-        // reaches more than 20% beyond the chunk's cutoff (wave-uniform)
-        const bool early = P::kPre && __ballot(lane < nuse && rad2 > rwide2) != 0ull;
+        // the records' own data bound their reach where some part reaches
+        // more than 20% beyond the chunk's cutoff, and always in parts read
+        // in cell order, whose blocks are passed over by the same bound
+        // (wave-uniform)
+        const bool early = P::kPre && __ballot(lane < nuse && (rad2 > rwide2 || co)) != 0ull;
         if (early) pre = P::pre(a, j, lane < nuse);
         // the records within reach, packed: the first ones complete the
         // current tile, the others start the next
@@ -709,13 +838,16 @@ __device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds&
                 P::stage(S, slot - room, q, a.pos[q], -oA.x, -oA.y, -oA.z, a, pre, false, fr.lo);
             } else {
                 const float4 df = T.f[dl];
-                const uint32_t jj = a.segidx[q];
-                P::stage(S, slot - room, jj, a.segpos[q], df.x, df.y, df.z, a, pre, false, fr.lo);
+                const bool cell_order = T.q[dl].z == 0;
+                const uint32_t jj = cell_order ? q : a.segidx[q];
+                const float4 pq = cell_order ? a.pos[q] : a.segpos[q];
+                P::stage(S, slot - room, jj, pq, df.x, df.y, df.z, a, pre, false, fr.lo);
             }
         }
         fill += m - first;
         tself = tself || (self && m > first);
     }
+    return nread;
 }
 
 // ---------------------------------------------------------------------------
@@ -755,6 +887,7 @@ struct DensP {
     static constexpr bool kPre = false;
     static __device__ __forceinline__ Pre pre(const Args&, uint32_t, bool) { return Pre{}; }
     static __device__ __forceinline__ float rad2(float part2, const Pre&, float, float) { return part2; }
+    static __device__ __forceinline__ float blk_rad2(float part2, float, float, float) { return part2; }
     static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
                                                  float Sz, const Args& a, const Pre&, bool, bool uselo) {
         const float4 lo = uselo ? a.plo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -781,6 +914,21 @@ struct DensP {
     }
 };
 
+// The outputs of a target from its sums over the partners (the self term
+// m_i f(0) added here).
+template <bool HASH>
+__device__ __forceinline__ void dens_write(const DensArgs& a, int p, float hi, float mi, double sf, double sg,
+                                           double sw, double sq, int nn, uint64_t hs) {
+    const float hinv = 1.f / hi;
+    const float h3 = hi * hi * hi;
+    a.rho[p] = C8PI / h3 * (float)((double)mi + sf);
+    a.drho[p] = -C8PI / (h3 * hi) * (float)(3.0 * (double)mi + sg);
+    a.nw[p] = (32.f / 3.f) * (float)(1.0 + sw);
+    a.dnw[p] = -(32.f / 3.f) * hinv * (float)sq;
+    a.nngb[p] = nn;
+    if (HASH) a.hash[p] = hs;
+}
+
 template <bool SOLVE, bool HASH>
 __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k_density(DensArgs a) {
     using P = DensP<HASH>;
@@ -798,10 +946,30 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
     int leaf = 0, p0 = 0, cnt = 0;
     uint64_t pend = 0;
     unsigned long long done_work = 0;   // pair evaluations of this wave
+    unsigned long long done_reads = 0;  // records its walks loaded
+    int pnext = uni(blockIdx.x * (BLK / 64) + w);   // this wave's next piece of a heavy chunk
+    // the current piece: k | P << 5 (1 << 5: a whole chunk) and its slot (-1:
+    // the sums go out directly)
+    int pm = 1 << 5, pslot = -1;
     for (;;) {
         if (pend == 0) {
-            const int item = next_chunk(a.counter, a.nchunks, a.list, a.lcount, home, grp);
-            if (item < 0) break;
+            int item;
+            pm = 1 << 5;
+            pslot = -1;
+            if (pnext < a.npieces) {
+                const uint32_t v = a.plist[pnext];
+                item = uni((int)(v >> 5));
+                const int pn = uni((int)a.pcount[item]);
+                if (pn > 1) {
+                    pm = uni((int)(v & 31)) | pn << 5;
+                    pslot = pnext;
+                }
+                pnext += gridDim.x * (BLK / 64);
+            } else {
+                item = next_chunk(a.counter, a.nchunks, a.list, a.lcount, home, grp);
+                if (item < 0) break;
+                if (a.npieces > 0 && a.pcount[item] != 0) continue;   // handed out as pieces
+            }
             const int4 ch = a.chunks[item];
             leaf = uni(ch.x);
             p0 = uni(ch.y);
@@ -839,26 +1007,58 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
         L.h = act ? a.ph[p] : 1.f;
         L.hinv = 1.f / L.h;
         typename P::Acc acc;
-        walk<P>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act);
+        done_reads += (unsigned long long)walk<P>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act, pm);
 
         const double sf = comb_d(acc.tf, R), sg = comb_d(acc.tg, R);
         const double sw = comb_d(acc.tw, R), sq = comb_d(acc.tq, R);
         const int nn = comb_i(acc.nn, R);
         const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
         if (act && rep == 0) {
-            const float hi = L.h, hinv = L.hinv;
-            const float h3 = hi * hi * hi;
-            const float mi = L.x.w;
-            a.rho[p] = C8PI / h3 * (float)((double)mi + sf);
-            a.drho[p] = -C8PI / (h3 * hi) * (float)(3.0 * (double)mi + sg);
-            a.nw[p] = (32.f / 3.f) * (float)(1.0 + sw);
-            a.dnw[p] = -(32.f / 3.f) * hinv * (float)sq;
-            a.nngb[p] = nn;
-            if (HASH) a.hash[p] = hs;
+            if (pslot >= 0) {
+                double* q = a.part + (size_t)pslot * PART_WORDS * CHUNK + pick;
+                q[0 * CHUNK] = sf;
+                q[1 * CHUNK] = sg;
+                q[2 * CHUNK] = sw;
+                q[3 * CHUNK] = sq;
+                q[4 * CHUNK] = (double)nn;
+                q[5 * CHUNK] = __longlong_as_double((long long)hs);
+            } else {
+                dens_write<HASH>(a, p, L.h, L.x.w, sf, sg, sw, sq, nn, hs);
+            }
         }
         done_work += (unsigned long long)wave_count(act && rep == 0 ? nn : 0);
     }
     flush_work(a.work, done_work);
+    flush_work(a.work + 1, done_reads);
+}
+
+// Split chunks: the partial sums of the pieces, added in piece order, give
+// the outputs of the chunk's particles that took part (one wave per piece
+// slot; the slot of piece 0 does the chunk).
+template <bool SOLVE, bool HASH>
+__global__ __launch_bounds__(256) void k_density_pieces(DensArgs a) {
+    const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= a.npieces) return;
+    const uint32_t v = a.plist[i];
+    const int c = (int)(v >> 5), pn = (int)a.pcount[c];
+    if ((v & 31u) != 0u || pn < 2) return;
+    const int4 ch = a.chunks[c];
+    if (lane >= ch.z) return;
+    const int p = ch.y + lane;
+    if (SOLVE ? a.active[p] != 1 : (a.owned && a.owned[p] == 0)) return;
+    double sf = 0.0, sg = 0.0, sw = 0.0, sq = 0.0;
+    int nn = 0;
+    uint64_t hs = 0;
+    for (int k = 0; k < pn; ++k) {
+        const double* q = a.part + (size_t)(i + k) * PART_WORDS * CHUNK + lane;
+        sf += q[0 * CHUNK];
+        sg += q[1 * CHUNK];
+        sw += q[2 * CHUNK];
+        sq += q[3 * CHUNK];
+        nn += (int)q[4 * CHUNK];
+        hs += (uint64_t)__double_as_longlong(q[5 * CHUNK]);
+    }
+    dens_write<HASH>(a, p, a.ph[p], a.pos[p].w, sf, sg, sw, sq, nn, hs);
 }
 
 // ---------------------------------------------------------------------------
@@ -881,6 +1081,13 @@ struct ForceArgs {
     const uint32_t* segoff;
     const float4* segpos;
     const uint32_t* segidx;
+    const float4* blkbox;   // block boxes of the particle array (null: no cell is read in cell order)
+    int cellord;            // long sweeps may read the partner in cell order
+    int skip;               // ... passing over its blocks out of reach (0: test every record, same results)
+    const uint32_t* pcount; // heavy chunks: pieces per chunk (0: handed out with the others)
+    const uint32_t* plist;  // the pieces (chunk << 5 | piece), handed out first
+    int npieces;
+    double* part;           // partial sums of the pieces of split chunks
     float alpha;
     float *ax, *ay, *az, *du, *vsig, *S;
     int32_t* nf;
@@ -940,6 +1147,11 @@ struct ForceP {
     }
     static __device__ __forceinline__ float rad2(float part2, const Pre& p, float hmax, float tiny) {
         const float r = fmaf(fmaxf(hmax, p.f.x), 1.000002f, tiny);
+        return fminf(part2, r * r);
+    }
+    // the same for a block of records whose largest h is hb
+    static __device__ __forceinline__ float blk_rad2(float part2, float hb, float hmax, float tiny) {
+        const float r = fmaf(fmaxf(hmax, hb), 1.000002f, tiny);
         return fminf(part2, r * r);
     }
     static __device__ __forceinline__ void stage(Lds& S, int slot, uint32_t j, const float4& pj, float Sx, float Sy,
@@ -1002,10 +1214,30 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
     int leaf = 0, p0 = 0, cnt = 0;
     uint64_t pend = 0;
     unsigned long long done_work = 0;   // pair evaluations of this wave
+    unsigned long long done_reads = 0;  // records its walks loaded
+    int pnext = uni(blockIdx.x * (BLK / 64) + w);   // this wave's next piece of a heavy chunk
+    // the current piece: k | P << 5 (1 << 5: a whole chunk) and its slot (-1:
+    // the sums go out directly)
+    int pm = 1 << 5, pslot = -1;
     for (;;) {
         if (pend == 0) {
-            const int item = next_chunk(a.counter, a.nchunks, nullptr, nullptr, home, grp);
-            if (item < 0) break;
+            int item;
+            pm = 1 << 5;
+            pslot = -1;
+            if (pnext < a.npieces) {
+                const uint32_t v = a.plist[pnext];
+                item = uni((int)(v >> 5));
+                const int pn = uni((int)a.pcount[item]);
+                if (pn > 1) {
+                    pm = uni((int)(v & 31)) | pn << 5;
+                    pslot = pnext;
+                }
+                pnext += gridDim.x * (BLK / 64);
+            } else {
+                item = next_chunk(a.counter, a.nchunks, nullptr, nullptr, home, grp);
+                if (item < 0) break;
+                if (a.npieces > 0 && a.pcount[item] != 0) continue;   // handed out as pieces
+            }
             const int4 ch = a.chunks[item];
             leaf = uni(ch.x);
             p0 = uni(ch.y);
@@ -1049,26 +1281,75 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
         L.c = fi.z;
         L.alpha = a.alpha;
         typename P::Acc acc;
-        walk<P>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act);
+        done_reads += (unsigned long long)walk<P>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act, pm);
 
-        const float ax = (float)comb_d(acc.tx, R), ay = (float)comb_d(acc.ty, R);
-        const float az = (float)comb_d(acc.tz, R), du = comb_f(acc.du, R);
+        const double tx = comb_d(acc.tx, R), ty = comb_d(acc.ty, R), tz = comb_d(acc.tz, R);
+        const float du = comb_f(acc.du, R);
         const float vs = comb_max(acc.vs, R), Ss = comb_f(acc.S, R);
         const int nn = comb_i(acc.nn, R);
         const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
         if (act && rep == 0) {
-            a.ax[p] = ax;
-            a.ay[p] = ay;
-            a.az[p] = az;
-            a.du[p] = du;
-            a.vsig[p] = vs;
-            a.S[p] = Ss;
-            a.nf[p] = nn;
-            if (HASH) a.hash[p] = hs;
+            if (pslot >= 0) {
+                double* q = a.part + (size_t)pslot * PART_WORDS * CHUNK + pick;
+                q[0 * CHUNK] = tx;
+                q[1 * CHUNK] = ty;
+                q[2 * CHUNK] = tz;
+                q[3 * CHUNK] = (double)du;
+                q[4 * CHUNK] = (double)vs;
+                q[5 * CHUNK] = (double)Ss;
+                q[6 * CHUNK] = (double)nn;
+                q[7 * CHUNK] = __longlong_as_double((long long)hs);
+            } else {
+                a.ax[p] = (float)tx;
+                a.ay[p] = (float)ty;
+                a.az[p] = (float)tz;
+                a.du[p] = du;
+                a.vsig[p] = vs;
+                a.S[p] = Ss;
+                a.nf[p] = nn;
+                if (HASH) a.hash[p] = hs;
+            }
         }
         done_work += (unsigned long long)wave_count(act && rep == 0 ? nn : 0);
     }
     flush_work(a.work, done_work);
+    flush_work(a.work + 1, done_reads);
+}
+
+template <bool HASH>
+__global__ __launch_bounds__(256) void k_force_pieces(ForceArgs a) {
+    const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= a.npieces) return;
+    const uint32_t v = a.plist[i];
+    const int c = (int)(v >> 5), pn = (int)a.pcount[c];
+    if ((v & 31u) != 0u || pn < 2) return;
+    const int4 ch = a.chunks[c];
+    if (lane >= ch.z) return;
+    const int p = ch.y + lane;
+    if (a.owned && a.owned[p] == 0) return;
+    double tx = 0.0, ty = 0.0, tz = 0.0;
+    float du = 0.f, vs = 0.f, Ss = 0.f;
+    int nn = 0;
+    uint64_t hs = 0;
+    for (int k = 0; k < pn; ++k) {
+        const double* q = a.part + (size_t)(i + k) * PART_WORDS * CHUNK + lane;
+        tx += q[0 * CHUNK];
+        ty += q[1 * CHUNK];
+        tz += q[2 * CHUNK];
+        du += (float)q[3 * CHUNK];
+        vs = fmaxf(vs, (float)q[4 * CHUNK]);
+        Ss += (float)q[5 * CHUNK];
+        nn += (int)q[6 * CHUNK];
+        hs += (uint64_t)__double_as_longlong(q[7 * CHUNK]);
+    }
+    a.ax[p] = (float)tx;
+    a.ay[p] = (float)ty;
+    a.az[p] = (float)tz;
+    a.du[p] = du;
+    a.vsig[p] = vs;
+    a.S[p] = Ss;
+    a.nf[p] = nn;
+    if (HASH) a.hash[p] = hs;
 }
 
 // ---------------------------------------------------------------------------
@@ -1520,6 +1801,13 @@ static DensArgs dens_args(sph_tree* t, int* counter, const int* lcount) {
     a.csr_off = t->csr_off;
     a.segoff = t->segoff;
     a.segpos = t->segpos;
+    a.blkbox = t->blkbox;
+    a.cellord = t->blkbox && !(t->prm.flags & SPH_FLAG_SORTED_ONLY);
+    a.skip = a.cellord && !(t->prm.flags & SPH_FLAG_NO_BLOCK_SKIP);
+    a.pcount = t->pcount;
+    a.plist = t->plist;
+    a.npieces = (int)t->npieces;
+    a.part = t->part;
     a.segidx = t->segidx;
     a.status = t->status;
     a.rho = t->rho;
@@ -1557,6 +1845,29 @@ static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, bool listed, i
         if (t->hash) hipLaunchKernelGGL((k_density<false, true>), g, b, 0, st, a);
         else hipLaunchKernelGGL((k_density<false, false>), g, b, 0, st, a);
     }
+    if (t->npieces > 0) {
+        const dim3 gp(nblk(t->npieces, 4));
+        if (solve) {
+            if (t->hash) hipLaunchKernelGGL((k_density_pieces<true, true>), gp, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_density_pieces<true, false>), gp, dim3(256), 0, st, a);
+        } else {
+            if (t->hash) hipLaunchKernelGGL((k_density_pieces<false, true>), gp, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_density_pieces<false, false>), gp, dim3(256), 0, st, a);
+        }
+    }
+}
+
+// The largest h of each block of 64 particles (the force records' h, into
+// the w of the block's lower corner), for the block test of the force pass.
+__global__ __launch_bounds__(256) void k_block_h(const float4* __restrict__ frec, int64_t n, int64_t nb,
+                                                 float4* __restrict__ box) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += (int64_t)gridDim.x * 4) {
+        const int64_t e = b * 64 + lane;
+        float v = e < n ? frec[e].x : 0.f;
+        for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+        if (lane == 0) box[2 * b].w = v;
+    }
 }
 
 static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
@@ -1566,6 +1877,9 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
                        t->prm.gamma, t->frec, t->pv);
     hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph, t->segoff,
                        t->segidx);
+    if (t->blkbox)
+        hipLaunchKernelGGL(k_block_h, dim3((unsigned)std::min<int64_t>(nblk(t->nblk, 4), 65535)), dim3(256), 0, st,
+                           t->frec, n, t->nblk, t->blkbox);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
     ev_mark(ctx, "ghost");
     ForceArgs a;
@@ -1584,6 +1898,13 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.csr_off = t->csr_off;
     a.segoff = t->segoff;
     a.segpos = t->segpos;
+    a.blkbox = t->blkbox;
+    a.cellord = t->blkbox && !(t->prm.flags & SPH_FLAG_SORTED_ONLY);
+    a.skip = a.cellord && !(t->prm.flags & SPH_FLAG_NO_BLOCK_SKIP);
+    a.pcount = t->pcount;
+    a.plist = t->plist;
+    a.npieces = (int)t->npieces;
+    a.part = t->part;
     a.segidx = t->segidx;
     a.alpha = t->prm.alpha;
     a.ax = t->fax;
@@ -1599,6 +1920,11 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
     if (t->hash) hipLaunchKernelGGL((k_force<true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_force<false>), g, b, 0, st, a);
+    if (t->npieces > 0) {
+        const dim3 gp(nblk(t->npieces, 4));
+        if (t->hash) hipLaunchKernelGGL((k_force_pieces<true>), gp, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_force_pieces<false>), gp, dim3(256), 0, st, a);
+    }
 }
 
 // A Newton step of every active particle.
@@ -1864,15 +2190,18 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
     val((uint64_t)t->nchunks);
     val((uint64_t)t->ncells);
     val((uint64_t)t->nred);
+    val((uint64_t)t->npieces);
     val(t->hash ? 1 : 0);
     val(fbits(t->prm.alpha) | (fbits(t->prm.gamma) << 32));
+    val(t->prm.flags);
     val(fbits(t->prm.n_target) | (fbits(t->prm.h_tol) << 32));
     val((uint64_t)(uint32_t)t->prm.blocks_per_cu | ((uint64_t)(uint32_t)t->prm.max_replicas << 32));
     val((uint64_t)ctx->n_cu);
     const void* ptrs[] = {ctx->d_counter, t->d_sets, t->cells, t->chunks, t->csr, t->csr_off, t->segoff,
                           t->segpos, t->segidx, t->pos, t->plo, t->pv, t->ph, t->pu, t->bound, t->mix, t->iperm,
                           t->perm, t->owned, t->rho, t->hashd, t->lo, t->active, t->alist, t->status, t->frec,
-                          t->hashf, t->partial, t->d_red, t->sums_int, t->part_cnt};
+                          t->hashf, t->partial, t->d_red, t->sums_int, t->part_cnt, t->blkbox, t->pcount,
+                          t->plist, t->part};
     key.insert(key.end(), ptrs, ptrs + sizeof(ptrs) / sizeof(ptrs[0]));
     if (!t->gexec || key != t->gkey) {
         ++t->graph_captures;

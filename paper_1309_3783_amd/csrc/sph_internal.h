@@ -17,6 +17,8 @@ constexpr int MAX_SETS = 1 << 12;     // set id bits in the particle key
 constexpr int KEY_BITS_PER_DIM = 17;  // log2(top grid) + max depth must fit
 constexpr int SEG_LDS_MAX = 4096;     // largest (cell, axis) list sorted in LDS
 constexpr int CHUNK = 64;             // target particles per work item (one wave)
+constexpr int PIECE_MAX = 16;         // pieces a heavy chunk is split into at most
+constexpr int PART_WORDS = 8;         // partial sums of a particle in one piece (doubles)
 constexpr int SMALL_H_DIV = 8;        // sorted lists split at h = cell edge / 8
 
 // Orders a wavefront's LDS writes before its later LDS reads (the wave runs

@@ -264,6 +264,38 @@ def plummer_mixture(n: int, seed: int, n_clumps: int = 64, bg_frac: float = 0.2,
                     "bg_frac": bg_frac, "a": a.tolist(), "centre": centre.tolist(), "snap": snap})
 
 
+def clump_by_face(n_bg: int, n_clump: int, seed: int, radius: float = 0.03,
+                  centre=(0.535, 0.375, 0.375), velocity: bool = False, snap: bool = True) -> ParticleSet:
+    """A uniform background of n_bg particles and one uniform ball of
+    n_clump particles just past the plane x = 1/2, which is a face of the
+    top cells for every power-of-two top grid: the sparse cells on the other
+    side of that plane reach the whole ball (densities differ by the ratio
+    of the two number densities, h by its cube root)."""
+    rng = _rng(seed)
+    c = np.asarray(centre, dtype=np.float64)
+
+    def ball(k, r):
+        rr = radius * np.cbrt(r.random(k))
+        return c + rr[:, None] * _iso(r, k)
+
+    pos = np.concatenate([rng.random((n_bg, 3)), ball(n_clump, rng)], axis=0)
+    is_bg = np.arange(n_bg + n_clump) < n_bg
+
+    def redraw(idx, r):
+        out = np.empty((idx.size, 3))
+        nb = int(is_bg[idx].sum())
+        out[is_bg[idx]] = r.random((nb, 3))
+        out[~is_bg[idx]] = ball(idx.size - nb, r)
+        return out
+
+    pos = _snap_unique(pos, redraw, rng, snap)
+    dens = np.full(n_bg + n_clump, float(n_bg))
+    dens[~is_bg] += n_clump / (4.0 / 3.0 * math.pi * radius ** 3)
+    return _finish(pos, n_bg + n_clump, rng, h_for_density(dens), velocity,
+                   {"recipe": "clump_by_face", "seed": seed, "n_bg": n_bg, "n_clump": n_clump,
+                    "radius": radius, "centre": list(centre), "snap": snap})
+
+
 def plummer_number_density(pos, n_bg, per, a, rmax, centre):
     """Analytic number density of the truncated-Plummer mixture at ``pos``
     (each clump contributes only inside its truncation radius, so only the

@@ -15,9 +15,10 @@ FORCE_TOL = 1e-4
 SUM_TOL = 1e-5
 
 
-def run_fixed(sph, ctx, sets, hs, **prm_kw):
-    """build -> sort -> density -> force at the given h; numpy results per set."""
-    prm = sph.params(flags=sph.SPH_FLAG_PAIR_HASH, **prm_kw)
+def run_fixed(sph, ctx, sets, hs, flags=0, **prm_kw):
+    """build -> sort -> density -> force at the given h; numpy results per set
+    (flags: SPH_FLAG_* added to the pair-hash flag)."""
+    prm = sph.params(flags=sph.SPH_FLAG_PAIR_HASH | flags, **prm_kw)
     batch = sph.batch_from_sets(sets, h=hs)
     tree = sph.Tree(ctx)
     tree.build_cells(batch, prm)

@@ -1,0 +1,111 @@
+"""GPU tests of heavy chunks: chunks whose walks are estimated to read many
+partner records are handed out first, and the heaviest are split into
+pieces over their pair entries whose partial sums are added in piece order.
+
+* with small pieces (many chunks split, up to 16 pieces each) the results
+  match the oracle element by element (pair sets and counts bit-exact), and
+  are bitwise the same run to run;
+* against no heavy-chunk handling (piece_records = -1): the same pair sets
+  and counts, the sums to rounding; through the Newton solve of h as well;
+* a set of independent pieces inside a batch is bitwise the same as alone.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import _inputs as I  # noqa: E402
+
+import sphinputs  # noqa: E402
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from _checks import full_check, run_fixed  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def sph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1309_3783_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(sph):
+    return sph.Context(0)
+
+
+def _clump():
+    ps = sphinputs.clump_by_face(8000, 30000, 91, velocity=True)
+    return I.fixed_h_case(ps)
+
+
+def test_split_chunks_against_oracle(sph, ctx):
+    ps, h = _clump()
+    g, rd, rf, tree = full_check(sph, ctx, ps, h, piece_records=512)
+    st = tree.stats()
+    print(f"heavy chunks {st['heavy_chunks']}, pieces {st['pieces']} of {st['chunks']} chunks")
+    assert st["pieces"] > st["heavy_chunks"] > 0
+
+
+def test_split_chunks_match_unsplit_and_repeat(sph, ctx):
+    ps, h = _clump()
+    (a,), ta = run_fixed(sph, ctx, [ps], [h], piece_records=512)
+    (b,), _ = run_fixed(sph, ctx, [ps], [h], piece_records=512)
+    (u,), tu = run_fixed(sph, ctx, [ps], [h], piece_records=-1)
+    assert ta.stats()["pieces"] > 0 and tu.stats()["pieces"] == 0
+    for k in a[0]:
+        assert np.array_equal(a[0][k], b[0][k]), k
+    for k in a[1]:
+        assert np.array_equal(a[1][k], b[1][k]), k
+    for k in ("nngb", "hash"):
+        assert np.array_equal(a[0][k], u[0][k]), k
+    for k in ("nforce", "hash"):
+        assert np.array_equal(a[1][k], u[1][k]), k
+    assert np.allclose(a[0]["rho"], u[0]["rho"], rtol=2e-6, atol=0)
+    scale = np.maximum(a[1]["S"], 1e-30)
+    for k in ("ax", "ay", "az", "dudt"):
+        assert np.max(np.abs(a[1][k] - u[1][k]) / scale) < 1e-5, k
+    assert np.max(np.abs(a[1]["S"] - u[1]["S"]) / scale) < 1e-5
+    assert np.array_equal(a[1]["vsig"], u[1]["vsig"])
+
+
+def test_split_chunks_through_the_solve(sph, ctx):
+    """The Newton passes hand out the pieces of chunks that still have
+    active particles: the solved h meets the target for every particle, and
+    the oracle reproduces density and force at the GPU's h."""
+    from _checks import at_gpu_h
+    ps = sphinputs.clump_by_face(8000, 30000, 92, velocity=True, snap=False)
+    batch = sph.batch_from_sets([ps])
+    dout = sph.DensityOut(ps.n, "cuda")
+    fout = sph.ForceOut(ps.n, 1, "cuda")
+    tree = sph.Tree(ctx)
+    st, nu, it = sph.solve_with_rebuild(tree, batch, sph.params(piece_records=1024), dout)
+    assert st == sph.SPH_OK and nu == 0
+    assert tree.stats()["pieces"] > 0
+    tree.force(fout)
+    torch.cuda.synchronize()
+    gd = {k: getattr(dout, k).cpu().numpy() for k in ("rho", "nw", "nngb", "h")}
+    gf = {k: getattr(fout, k).cpu().numpy() for k in ("ax", "ay", "az", "nforce")}
+    assert np.abs(gd["nw"] - 48.0).max() <= 0.5 + 1e-4
+    k, excl = at_gpu_h(ps, gd, gf)
+    print(f"[at gpu h] compared {k}, excluded near a cutoff {excl}")
+    assert k >= 0.99 * ps.n
+
+
+def test_split_set_in_a_batch_equals_alone(sph, ctx):
+    ps, h = _clump()
+    u = sphinputs.uniform(5000, 93, velocity=True)
+    u, hu = I.fixed_h_case(u)
+    (alone,), t1 = run_fixed(sph, ctx, [ps], [h], piece_records=512)
+    res, t2 = run_fixed(sph, ctx, [u, ps], [hu, h], piece_records=512)
+    assert t1.stats()["pieces"] > 0
+    for k in alone[0]:
+        assert np.array_equal(alone[0][k], res[1][0][k]), k
+    for k in ("ax", "ay", "az", "dudt", "S", "nforce", "hash"):
+        assert np.array_equal(alone[1][k], res[1][1][k]), k
