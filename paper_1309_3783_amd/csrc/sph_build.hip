@@ -1316,15 +1316,16 @@ static Err read_back(sph_ctx* ctx, const void* d, size_t bytes, const void** h) 
     return Err{};
 }
 
-// Block summaries of the particle array (kept for every tree, so that
-// whether a partner is read in cell order depends on that pair entry alone,
-// not on the other sets of a batch).
+// Block summaries of the particle array, for a tree whose interaction
+// kernels may read partners in cell order (whether one is read so depends
+// on that pair entry alone: a tree without them has no partner that would
+// qualify).
 static Err block_summaries(sph_ctx* ctx, sph_tree* t) {
     hipStream_t st = ctx->stream;
     t->blkbits = nullptr;
     t->blkbox = nullptr;
     t->nblk = 0;
-    if (t->n <= 0) return Err{};
+    if (t->n <= 0 || !t->ext()) return Err{};
     const int64_t nb = (t->n + BLK_PART - 1) / BLK_PART;
     void* p;
     ERRTRY(t->alloc(t->b_blk, (sizeof(uint64_t) + 2 * sizeof(float4)) * nb, &p));
@@ -1686,18 +1687,22 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         t->ncsr_dev = nullptr;
     }
     // heavy chunks: pieces per chunk, the pieces and heavy chunks in total[18], total[19]
+    // (a one-level tree is estimated only once its largest leaf is known
+    // to allow a heavy chunk: its partners are leaves, at most 26 of them)
     const int piece_rec = prm->piece_records == 0 ? 16384 : prm->piece_records;
     const bool pieces = piece_rec > 0 && chunk_cap < ((int64_t)1 << 27);
     ERRTRY(t->alloc(t->b_piece, 2 * sizeof(uint32_t) * chunk_cap, (void**)&t->pcount));
     t->poff = t->pcount + chunk_cap;
     HIPTRY(fill_u32(total + 18, 2, 0u, st));
-    if (pieces) {
+    auto chunk_cost = [&]() -> Err {
         hipLaunchKernelGGL(k_chunk_cost, dim3(nblk(chunk_cap, 4)), dim3(256), 0, st, t->chunks, total, chunk_cap,
                            t->cells, d_sets, t->csr_off, t->csr, (float)piece_rec, t->pcount, t->poff, total + 18);
         HIPTRY(hipGetLastError());
-    } else {
-        HIPTRY(fill_u32(t->pcount, chunk_cap, 0u, st));
-    }
+        return Err{};
+    };
+    const bool cost_now = pieces && t->nlevels > 1;
+    if (cost_now) ERRTRY(chunk_cost());
+    else HIPTRY(fill_u32(t->pcount, chunk_cap, 0u, st));
     // chunk count (total[0], untouched since its scan), leaves, largest
     // leaf, pieces, heavy chunks
     static_assert(sizeof(int) == sizeof(uint32_t), "layout of the count words");
@@ -1709,6 +1714,12 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     t->nheavy = ((const uint32_t*)rb)[19];
     t->nchunks = nchunks;
     if ((int64_t)nchunks > chunk_cap) return Err{SPH_E_STATE, "internal: chunk count above its bound"};
+    if (pieces && !cost_now && 27 * t->max_leaf >= piece_rec) {
+        ERRTRY(chunk_cost());
+        ERRTRY(read_back(ctx, total + 18, 2 * sizeof(uint32_t), &rb));
+        t->npieces = ((const uint32_t*)rb)[0];
+        t->nheavy = ((const uint32_t*)rb)[1];
+    }
     t->plist = nullptr;
     t->part = nullptr;
     if (t->npieces > 0) {

@@ -181,6 +181,10 @@ struct sph_tree {
     uint32_t* plist = nullptr;
     double* part = nullptr;
     int64_t npieces = 0, nheavy = 0;
+    // whether the interaction kernels need the code for heavy chunks and
+    // cell-order reads: the tree has heavy chunks, or some partner cell may
+    // hold SCAN_MIN particles (a one-level tree's partners are its leaves)
+    bool ext() const { return npieces > 0 || !(nlevels == 1 && max_leaf < sph::SCAN_MIN); }
     uint32_t *sc_a = nullptr, *sc_b = nullptr, *sc_c = nullptr, *sc_d = nullptr, *sc_tmp = nullptr;
     uint32_t* split_idx = nullptr;   // split flags of one level, scanned in place
     uint32_t* d_counts = nullptr;    // [0] sorted-list entries when not read back (nsegent < 0)

@@ -491,7 +491,7 @@ struct SweepTab {
 // A part is a sweep of a sorted list (z = +1 ascending, -1 descending, x
 // its first list position, y its length) or a read of a partner's particles
 // in cell order (z = 0, x its first particle, y its count).
-constexpr int SCAN_MIN = 256;   // swept records from which a partner may be read in cell order ...
+// (a partner is read in cell order from SCAN_MIN swept records ...)
 constexpr int SCAN_RATIO = 2;   // ... if it holds at most this many times as many particles
 
 // Builds the descriptors of entries [e0, e0 + n) of cell cA (n <= DBATCH);
@@ -499,7 +499,7 @@ constexpr int SCAN_RATIO = 2;   // ... if it holds at most this many times as ma
 // *cellorder whether some part is read in cell order.  bx:
 // largest o_k x_k over the chunk's particles per axis and sign (bx[0..2] =
 // max x, bx[3..5] = -min x); hmax: largest h of the chunk.
-template <class P>
+template <class P, bool EXT>
 __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cell& cA, float L0, const Frame& fr,
                                             uint32_t e0, int n, const float (&bx)[6], float hmax, SweepTab& T,
                                             int* total, bool* cellorder) {
@@ -561,7 +561,7 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
     // partner itself is read in cell order instead, as one part with the
     // larger radius: the blocks of it beyond the chunk's reach are then
     // passed over (skip_blocks)
-    const bool scan = a.cellord && c0 + c1 >= SCAN_MIN && bcount <= SCAN_RATIO * (c0 + c1);
+    const bool scan = EXT && a.cellord && c0 + c1 >= SCAN_MIN && bcount <= SCAN_RATIO * (c0 + c1);
     if (scan) {
         q0 = make_int4(bfirst, bcount, 0, 0);
         f0.w = fmaxf(f0.w, f1.w);
@@ -665,19 +665,20 @@ __device__ __forceinline__ int skip_blocks(const float4* __restrict__ blkbox, co
 // cell; the lanes' coordinates are in that frame), or of piece k of P of a
 // split chunk (pm = k | P << 5; 1 << 5 for a whole chunk: the piece takes
 // the blocks of 64 self-task particles and the groups of 64 swept records
-// whose index is k mod P): the leaf's self task, then
-// the pair tasks of the leaf and of its ancestors; each pair task sweeps the partner's sorted
+// whose index is k mod P): the leaf's self task, then the pair tasks of the
+// leaf and of its ancestors; each pair task sweeps the partner's sorted
 // list (small-h part, then large-h part) up to the largest reach of the
 // chunk along the pair axis, bounded by the bounding box of its particles
-// plus the largest cutoff.  The swept records of a batch of pair tasks are
-// staged in sequence, each step filling the current tile; written as one
-// loop so that the tile processing is inlined once.
-template <class P>
-__device__ __forceinline__ int walk(const typename P::Args& a, typename P::Lds& S, SweepTab& T,
+// plus the largest cutoff, or (EXT) reads a dense partner in cell order.
+// The swept records of a batch of pair tasks are staged in sequence, each
+// step filling the current tile; written as one loop so that the tile
+// processing is inlined once.  The records loaded are added to *nread (a
+// word of the wave's in LDS, by its first lane).
+template <class P, bool EXT>
+__device__ __forceinline__ void walk(const typename P::Args& a, typename P::Lds& S, SweepTab& T,
                                     const typename P::Lane& L, typename P::Acc& acc, int leaf, const Frame& fr,
-                                    int R, int rep, bool act, int pm) {
+                                    int R, int rep, bool act, int pm, unsigned long long* nread) {
     const int lane = threadIdx.x & 63;
-    int nread = 0;   // records loaded (wave-uniform)
     const Cell C = a.cells[leaf];
     const int cend = C.first + C.count;
     const int pk = pm & 31, pn = pm >> 5;
@@ -731,7 +732,7 @@ __device__ __forceinline__ int walk(const typename P::Args& a, typename P::Lds& 
             rad2 = rself2;
             self = true;
             sbase += 64 * pn;   // (a piece: the next block of its own)
-            nread += nuse;
+            if (lane == 0) *nread += (unsigned long long)nuse;
         } else {
             // next batch of entries: of this cell, or of its ancestors
             // (a batch may sweep no records at all)
@@ -752,26 +753,26 @@ __device__ __forceinline__ int walk(const typename P::Args& a, typename P::Lds& 
                     }
                     const int n = (int)min(e1 - e, (uint32_t)DBATCH);
                     bool co_any;
-                    nd = build_sweeps<P>(a, cA, L0, fr, e, n, bx, hmax, T, &tot, &co_any);
+                    nd = build_sweeps<P, EXT>(a, cA, L0, fr, e, n, bx, hmax, T, &tot, &co_any);
                     e += n;
                     g0 = 0;
                     hold = co_any ? 0 : tot;   // blocks are tested in parts read in cell order only
                 }
                 if (done) break;
-                if (pn > 1) {
+                if (EXT && pn > 1) {
                     // a piece takes the groups of 64 records k, k + P, ...
                     const int r = ((g0 >> 6) - pk) % pn;
                     if (r != 0) g0 += 64 * (pn - (r < 0 ? r + pn : r));
                     if (g0 >= tot) continue;
                 }
-                if (!a.skip || g0 < hold) break;
+                if (!EXT || !a.skip || g0 < hold) break;
                 // pass over the blocks of a part read in cell order that lie
                 // beyond the chunk's reach
                 g0 = skip_blocks<P>(a.blkbox, T, nd, g0, lox, loy, loz, bx, hmax, tiny, &hold);
             }
             // the next 64 records of the batch's sequence
             if (!done) nuse = min(64, tot - g0);
-            nread += nuse;
+            if (lane == 0) *nread += (unsigned long long)nuse;
             if (lane < nuse) {
                 const int g = g0 + lane;
                 int lo = 0, hi = nd - 1;   // the last part starting at or before g
@@ -785,7 +786,7 @@ __device__ __forceinline__ int walk(const typename P::Args& a, typename P::Lds& 
                 const int k = g - T.o[lo];
                 q = (uint32_t)dq.x + (uint32_t)(dq.z >= 0 ? k : dq.y - 1 - k);
                 dl = lo;
-                if (dq.z == 0) {
+                if (EXT && dq.z == 0) {
                     pj = a.pos[q];
                     j = q;
                     co = true;
@@ -838,7 +839,7 @@ __device__ __forceinline__ int walk(const typename P::Args& a, typename P::Lds& 
                 P::stage(S, slot - room, q, a.pos[q], -oA.x, -oA.y, -oA.z, a, pre, false, fr.lo);
             } else {
                 const float4 df = T.f[dl];
-                const bool cell_order = T.q[dl].z == 0;
+                const bool cell_order = EXT && T.q[dl].z == 0;
                 const uint32_t jj = cell_order ? q : a.segidx[q];
                 const float4 pq = cell_order ? a.pos[q] : a.segpos[q];
                 P::stage(S, slot - room, jj, pq, df.x, df.y, df.z, a, pre, false, fr.lo);
@@ -847,7 +848,6 @@ __device__ __forceinline__ int walk(const typename P::Args& a, typename P::Lds& 
         fill += m - first;
         tself = tself || (self && m > first);
     }
-    return nread;
 }
 
 // ---------------------------------------------------------------------------
@@ -929,12 +929,17 @@ __device__ __forceinline__ void dens_write(const DensArgs& a, int p, float hi, f
     if (HASH) a.hash[p] = hs;
 }
 
-template <bool SOLVE, bool HASH>
+// EXT: the tree may have heavy chunks or partners read in cell order (the
+// kernel without that code keeps more registers for the common case).
+template <bool SOLVE, bool HASH, bool EXT>
 __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k_density(DensArgs a) {
     using P = DensP<HASH>;
     __shared__ typename P::Lds s_l[BLK / 64];
     __shared__ SweepTab s_t[BLK / 64];
     __shared__ int s_pick[BLK / 64][64];
+    // the wave's pair evaluations and records loaded (kept in LDS, not in
+    // registers through the walk)
+    __shared__ unsigned long long s_cnt[BLK / 64][2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     typename P::Lds& S = s_l[w];
     const int home = blockIdx.x & (NGRP - 1);
@@ -945,8 +950,10 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
     // each frame's packed into the first slots
     int leaf = 0, p0 = 0, cnt = 0;
     uint64_t pend = 0;
-    unsigned long long done_work = 0;   // pair evaluations of this wave
-    unsigned long long done_reads = 0;  // records its walks loaded
+    if (lane == 0) {
+        s_cnt[w][0] = 0ull;
+        s_cnt[w][1] = 0ull;
+    }
     int pnext = uni(blockIdx.x * (BLK / 64) + w);   // this wave's next piece of a heavy chunk
     // the current piece: k | P << 5 (1 << 5: a whole chunk) and its slot (-1:
     // the sums go out directly)
@@ -956,7 +963,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
             int item;
             pm = 1 << 5;
             pslot = -1;
-            if (pnext < a.npieces) {
+            if (EXT && pnext < a.npieces) {
                 const uint32_t v = a.plist[pnext];
                 item = uni((int)(v >> 5));
                 const int pn = uni((int)a.pcount[item]);
@@ -968,7 +975,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
             } else {
                 item = next_chunk(a.counter, a.nchunks, a.list, a.lcount, home, grp);
                 if (item < 0) break;
-                if (a.npieces > 0 && a.pcount[item] != 0) continue;   // handed out as pieces
+                if (EXT && a.npieces > 0 && a.pcount[item] != 0) continue;   // handed out as pieces
             }
             const int4 ch = a.chunks[item];
             leaf = uni(ch.x);
@@ -1007,14 +1014,14 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
         L.h = act ? a.ph[p] : 1.f;
         L.hinv = 1.f / L.h;
         typename P::Acc acc;
-        done_reads += (unsigned long long)walk<P>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act, pm);
+        walk<P, EXT>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act, pm, &s_cnt[w][1]);
 
         const double sf = comb_d(acc.tf, R), sg = comb_d(acc.tg, R);
         const double sw = comb_d(acc.tw, R), sq = comb_d(acc.tq, R);
         const int nn = comb_i(acc.nn, R);
         const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
         if (act && rep == 0) {
-            if (pslot >= 0) {
+            if (EXT && pslot >= 0) {
                 double* q = a.part + (size_t)pslot * PART_WORDS * CHUNK + pick;
                 q[0 * CHUNK] = sf;
                 q[1 * CHUNK] = sg;
@@ -1026,10 +1033,13 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
                 dens_write<HASH>(a, p, L.h, L.x.w, sf, sg, sw, sq, nn, hs);
             }
         }
-        done_work += (unsigned long long)wave_count(act && rep == 0 ? nn : 0);
+        const int npair = wave_count(act && rep == 0 ? nn : 0);
+        if (lane == 0) s_cnt[w][0] += (unsigned long long)npair;
     }
-    flush_work(a.work, done_work);
-    flush_work(a.work + 1, done_reads);
+    if (lane == 0) {
+        flush_work(a.work, s_cnt[w][0]);
+        flush_work(a.work + 1, s_cnt[w][1]);
+    }
 }
 
 // Split chunks: the partial sums of the pieces, added in piece order, give
@@ -1199,12 +1209,15 @@ struct ForceP {
     }
 };
 
-template <bool HASH>
+template <bool HASH, bool EXT>
 __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k_force(ForceArgs a) {
     using P = ForceP<HASH>;
     __shared__ typename P::Lds s_l[BLK / 64];
     __shared__ SweepTab s_t[BLK / 64];
     __shared__ int s_pick[BLK / 64][64];
+    // the wave's pair evaluations and records loaded (kept in LDS, not in
+    // registers through the walk)
+    __shared__ unsigned long long s_cnt[BLK / 64][2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     typename P::Lds& S = s_l[w];
     const int home = blockIdx.x & (NGRP - 1);
@@ -1213,8 +1226,10 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
     // frame's packed into the first slots)
     int leaf = 0, p0 = 0, cnt = 0;
     uint64_t pend = 0;
-    unsigned long long done_work = 0;   // pair evaluations of this wave
-    unsigned long long done_reads = 0;  // records its walks loaded
+    if (lane == 0) {
+        s_cnt[w][0] = 0ull;
+        s_cnt[w][1] = 0ull;
+    }
     int pnext = uni(blockIdx.x * (BLK / 64) + w);   // this wave's next piece of a heavy chunk
     // the current piece: k | P << 5 (1 << 5: a whole chunk) and its slot (-1:
     // the sums go out directly)
@@ -1224,7 +1239,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
             int item;
             pm = 1 << 5;
             pslot = -1;
-            if (pnext < a.npieces) {
+            if (EXT && pnext < a.npieces) {
                 const uint32_t v = a.plist[pnext];
                 item = uni((int)(v >> 5));
                 const int pn = uni((int)a.pcount[item]);
@@ -1236,7 +1251,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
             } else {
                 item = next_chunk(a.counter, a.nchunks, nullptr, nullptr, home, grp);
                 if (item < 0) break;
-                if (a.npieces > 0 && a.pcount[item] != 0) continue;   // handed out as pieces
+                if (EXT && a.npieces > 0 && a.pcount[item] != 0) continue;   // handed out as pieces
             }
             const int4 ch = a.chunks[item];
             leaf = uni(ch.x);
@@ -1281,15 +1296,16 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
         L.c = fi.z;
         L.alpha = a.alpha;
         typename P::Acc acc;
-        done_reads += (unsigned long long)walk<P>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act, pm);
+        walk<P, EXT>(a, S, s_t[w], L, acc, leaf, fr, R, rep, act, pm, &s_cnt[w][1]);
 
-        const double tx = comb_d(acc.tx, R), ty = comb_d(acc.ty, R), tz = comb_d(acc.tz, R);
         const float du = comb_f(acc.du, R);
         const float vs = comb_max(acc.vs, R), Ss = comb_f(acc.S, R);
         const int nn = comb_i(acc.nn, R);
         const uint64_t hs = HASH ? comb_u64(acc.hs, R) : 0ull;
-        if (act && rep == 0) {
-            if (pslot >= 0) {
+        if (EXT && pslot >= 0) {
+            // a piece: its FP64 sums to its slot
+            const double tx = comb_d(acc.tx, R), ty = comb_d(acc.ty, R), tz = comb_d(acc.tz, R);
+            if (act && rep == 0) {
                 double* q = a.part + (size_t)pslot * PART_WORDS * CHUNK + pick;
                 q[0 * CHUNK] = tx;
                 q[1 * CHUNK] = ty;
@@ -1299,10 +1315,14 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
                 q[5 * CHUNK] = (double)Ss;
                 q[6 * CHUNK] = (double)nn;
                 q[7 * CHUNK] = __longlong_as_double((long long)hs);
-            } else {
-                a.ax[p] = (float)tx;
-                a.ay[p] = (float)ty;
-                a.az[p] = (float)tz;
+            }
+        } else {
+            const float ax = (float)comb_d(acc.tx, R), ay = (float)comb_d(acc.ty, R);
+            const float az = (float)comb_d(acc.tz, R);
+            if (act && rep == 0) {
+                a.ax[p] = ax;
+                a.ay[p] = ay;
+                a.az[p] = az;
                 a.du[p] = du;
                 a.vsig[p] = vs;
                 a.S[p] = Ss;
@@ -1310,10 +1330,13 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(5))) void k
                 if (HASH) a.hash[p] = hs;
             }
         }
-        done_work += (unsigned long long)wave_count(act && rep == 0 ? nn : 0);
+        const int npair = wave_count(act && rep == 0 ? nn : 0);
+        if (lane == 0) s_cnt[w][0] += (unsigned long long)npair;
     }
-    flush_work(a.work, done_work);
-    flush_work(a.work + 1, done_reads);
+    if (lane == 0) {
+        flush_work(a.work, s_cnt[w][0]);
+        flush_work(a.work + 1, s_cnt[w][1]);
+    }
 }
 
 template <bool HASH>
@@ -1824,6 +1847,8 @@ static DensArgs dens_args(sph_tree* t, int* counter, const int* lcount) {
 // listed: a Newton pass after the first, over the chunks that still hold
 // active particles (k_chunk_list; its counts sit in the context's counter
 // block after the force counters, zeroed here with the density counters)
+static bool ext_kernels(const sph_tree* t) { return t->ext(); }
+
 static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, bool listed, int* counter) {
     hipStream_t st = ctx->stream;
     int* lcount = nullptr;
@@ -1838,12 +1863,22 @@ static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, bool listed, i
     }
     DensArgs a = dens_args(t, counter, lcount);
     dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
-    if (solve) {
-        if (t->hash) hipLaunchKernelGGL((k_density<true, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_density<true, false>), g, b, 0, st, a);
+    if (ext_kernels(t)) {
+        if (solve) {
+            if (t->hash) hipLaunchKernelGGL((k_density<true, true, true>), g, b, 0, st, a);
+            else hipLaunchKernelGGL((k_density<true, false, true>), g, b, 0, st, a);
+        } else {
+            if (t->hash) hipLaunchKernelGGL((k_density<false, true, true>), g, b, 0, st, a);
+            else hipLaunchKernelGGL((k_density<false, false, true>), g, b, 0, st, a);
+        }
     } else {
-        if (t->hash) hipLaunchKernelGGL((k_density<false, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_density<false, false>), g, b, 0, st, a);
+        if (solve) {
+            if (t->hash) hipLaunchKernelGGL((k_density<true, true, false>), g, b, 0, st, a);
+            else hipLaunchKernelGGL((k_density<true, false, false>), g, b, 0, st, a);
+        } else {
+            if (t->hash) hipLaunchKernelGGL((k_density<false, true, false>), g, b, 0, st, a);
+            else hipLaunchKernelGGL((k_density<false, false, false>), g, b, 0, st, a);
+        }
     }
     if (t->npieces > 0) {
         const dim3 gp(nblk(t->npieces, 4));
@@ -1877,7 +1912,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
                        t->prm.gamma, t->frec, t->pv);
     hipLaunchKernelGGL(k_cell_hcur, dim3(nblk(t->ncells, 4)), dim3(256), 0, st, t->cells, t->ncells, t->ph, t->segoff,
                        t->segidx);
-    if (t->blkbox)
+    if (t->blkbox && t->ext())
         hipLaunchKernelGGL(k_block_h, dim3((unsigned)std::min<int64_t>(nblk(t->nblk, 4), 65535)), dim3(256), 0, st,
                            t->frec, n, t->nblk, t->blkbox);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
@@ -1918,8 +1953,13 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.work = (unsigned long long*)(t->work_ctr + 256);
     a.rmax = rmax_of(t);
     dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
-    if (t->hash) hipLaunchKernelGGL((k_force<true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_force<false>), g, b, 0, st, a);
+    if (ext_kernels(t)) {
+        if (t->hash) hipLaunchKernelGGL((k_force<true, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_force<false, true>), g, b, 0, st, a);
+    } else {
+        if (t->hash) hipLaunchKernelGGL((k_force<true, false>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((k_force<false, false>), g, b, 0, st, a);
+    }
     if (t->npieces > 0) {
         const dim3 gp(nblk(t->npieces, 4));
         if (t->hash) hipLaunchKernelGGL((k_force_pieces<true>), gp, dim3(256), 0, st, a);
