@@ -88,7 +88,8 @@ typedef struct {
     float gamma;         /* adiabatic index (5/3) */
     float alpha;         /* viscosity coefficient (2.0) */
     uint32_t flags;      /* SPH_FLAG_* */
-    int32_t blocks_per_cu; /* persistent interaction kernels: blocks of 4 wavefronts per CU (0 = 8) */
+    int32_t blocks_per_cu; /* persistent interaction kernels: blocks of 4 wavefronts per CU, at most as
+                              many as fit on a CU at once (0 = as many as fit) */
     int32_t max_replicas;  /* lanes per target particle for small chunks: 1, 2, 4, 8 or 16 (0 = 16) */
     int32_t top_coarsen;   /* with top_grid 0: this many levels coarser than the largest allowed top grid
                               (at least 2 cells per side remain) (0) */

@@ -3,7 +3,7 @@
 Times the graph pipeline over a grid of launch and decomposition parameters
 on the actual batch (or a sample of it) and keeps the fastest:
   * n_split        -- leaf size (split count of Section III-B, 400 by default)
-  * blocks_per_cu  -- resident persistent blocks (4 wavefronts each) per CU
+  * blocks_per_cu  -- resident persistent blocks (4 wavefronts each) per CU (0: as many as fit)
   * max_replicas   -- lanes per target particle for small chunks
   * h_slack        -- room left for h to grow before the cells must be
                       rebuilt (more room: fewer rebuilds, larger cells)
@@ -26,7 +26,7 @@ from . import pipeline as P
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuned.json")
 
-GRID = {"n_split": [200, 400, 800], "blocks_per_cu": [4, 8, 16], "max_replicas": [4, 16], "h_slack": [0.2, 0.3],
+GRID = {"n_split": [200, 400, 800], "blocks_per_cu": [0, 3, 4], "max_replicas": [4, 16], "h_slack": [0.2, 0.3],
         "top_coarsen": [0, 1]}
 
 

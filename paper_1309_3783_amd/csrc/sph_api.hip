@@ -120,6 +120,7 @@ sph_status sph_ctx_create(sph_ctx** out, int device, void* stream) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;
+    sph::query_occupancy(c);
     if (hipMalloc(&c->d_counter, sph_ctx::CTR_WORDS * sizeof(int32_t)) != hipSuccess) {
         delete c;
         return SPH_E_WORKSPACE;

@@ -15,6 +15,9 @@ struct sph_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int n_cu = 256;
+    // blocks of each persistent kernel that fit on a CU at once (occupancy,
+    // asked once per kernel)
+    std::map<const void*, int> resident;
     std::string last_error;
     bool timing = false;
     // stage events of the calls since the timings were last read: a pool
@@ -439,6 +442,7 @@ inline void ev_mark(sph_ctx* ctx, const char* name) {
     ++ctx->nev;
 }
 
+void query_occupancy(sph_ctx* ctx);
 Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params* prm);
 Err sort_pairs(sph_ctx* ctx, sph_tree* t);
 Err refresh_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in);

@@ -1798,10 +1798,32 @@ static int rmax_of(const sph_tree* t) {
     return (r == 1 || r == 2 || r == 4 || r == 8 || r == 16) ? r : 16;
 }
 
-static int persistent_blocks(sph_ctx* ctx, const sph_tree* t, int64_t items) {
-    int64_t want = (items + 3) / 4;
-    int bpc = t->prm.blocks_per_cu > 0 ? t->prm.blocks_per_cu : 8;
-    int64_t cap = (int64_t)ctx->n_cu * bpc;
+// The resident blocks per CU of every persistent interaction kernel, asked
+// when the context is made (not under a graph capture).
+void query_occupancy(sph_ctx* ctx) {
+    const void* ks[] = {(const void*)k_density<true, true, true>,   (const void*)k_density<true, false, true>,
+                        (const void*)k_density<false, true, true>,  (const void*)k_density<false, false, true>,
+                        (const void*)k_density<true, true, false>,  (const void*)k_density<true, false, false>,
+                        (const void*)k_density<false, true, false>, (const void*)k_density<false, false, false>,
+                        (const void*)k_force<true, true>,           (const void*)k_force<false, true>,
+                        (const void*)k_force<true, false>,          (const void*)k_force<false, false>};
+    for (const void* k : ks) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, BLK, 0) != hipSuccess || nb < 1) nb = 4;
+        ctx->resident[k] = nb;
+    }
+}
+
+// Grid of a persistent interaction kernel: at most as many blocks as fit on
+// the GPU at once (blocks beyond that would only start when others leave,
+// at the end of the pass, and the pieces of heavy chunks are dealt to every
+// wave of the grid up front), fewer if blocks_per_cu asks for fewer.
+static int persistent_blocks(sph_ctx* ctx, const sph_tree* t, int64_t items, const void* kernel) {
+    const auto it = ctx->resident.find(kernel);
+    int bpc = it != ctx->resident.end() ? it->second : 4;
+    if (t->prm.blocks_per_cu > 0) bpc = std::min(bpc, t->prm.blocks_per_cu);
+    const int64_t want = (items + 3) / 4;
+    const int64_t cap = (int64_t)ctx->n_cu * bpc;
     return (int)std::max<int64_t>(1, std::min(want, cap));
 }
 
@@ -1862,24 +1884,15 @@ static void launch_density(sph_ctx* ctx, sph_tree* t, bool solve, bool listed, i
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, counter, NGRP * CSTRIDE);
     }
     DensArgs a = dens_args(t, counter, lcount);
-    dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
+    void (*kern)(DensArgs);
     if (ext_kernels(t)) {
-        if (solve) {
-            if (t->hash) hipLaunchKernelGGL((k_density<true, true, true>), g, b, 0, st, a);
-            else hipLaunchKernelGGL((k_density<true, false, true>), g, b, 0, st, a);
-        } else {
-            if (t->hash) hipLaunchKernelGGL((k_density<false, true, true>), g, b, 0, st, a);
-            else hipLaunchKernelGGL((k_density<false, false, true>), g, b, 0, st, a);
-        }
+        if (solve) kern = t->hash ? k_density<true, true, true> : k_density<true, false, true>;
+        else kern = t->hash ? k_density<false, true, true> : k_density<false, false, true>;
     } else {
-        if (solve) {
-            if (t->hash) hipLaunchKernelGGL((k_density<true, true, false>), g, b, 0, st, a);
-            else hipLaunchKernelGGL((k_density<true, false, false>), g, b, 0, st, a);
-        } else {
-            if (t->hash) hipLaunchKernelGGL((k_density<false, true, false>), g, b, 0, st, a);
-            else hipLaunchKernelGGL((k_density<false, false, false>), g, b, 0, st, a);
-        }
+        if (solve) kern = t->hash ? k_density<true, true, false> : k_density<true, false, false>;
+        else kern = t->hash ? k_density<false, true, false> : k_density<false, false, false>;
     }
+    hipLaunchKernelGGL(kern, dim3(persistent_blocks(ctx, t, t->nchunks, (const void*)kern)), dim3(BLK), 0, st, a);
     if (t->npieces > 0) {
         const dim3 gp(nblk(t->npieces, 4));
         if (solve) {
@@ -1952,14 +1965,10 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.hash = t->hashf;
     a.work = (unsigned long long*)(t->work_ctr + 256);
     a.rmax = rmax_of(t);
-    dim3 g(persistent_blocks(ctx, t, t->nchunks)), b(BLK);
-    if (ext_kernels(t)) {
-        if (t->hash) hipLaunchKernelGGL((k_force<true, true>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_force<false, true>), g, b, 0, st, a);
-    } else {
-        if (t->hash) hipLaunchKernelGGL((k_force<true, false>), g, b, 0, st, a);
-        else hipLaunchKernelGGL((k_force<false, false>), g, b, 0, st, a);
-    }
+    void (*kern)(ForceArgs);
+    if (ext_kernels(t)) kern = t->hash ? k_force<true, true> : k_force<false, true>;
+    else kern = t->hash ? k_force<true, false> : k_force<false, false>;
+    hipLaunchKernelGGL(kern, dim3(persistent_blocks(ctx, t, t->nchunks, (const void*)kern)), dim3(BLK), 0, st, a);
     if (t->npieces > 0) {
         const dim3 gp(nblk(t->npieces, 4));
         if (t->hash) hipLaunchKernelGGL((k_force_pieces<true>), gp, dim3(256), 0, st, a);
