@@ -860,13 +860,16 @@ __global__ void k_csr_offsets(const uint64_t* __restrict__ keys, int64_t ne, int
 // ---------------------------------------------------------------------------
 // Sorted lists per (cell, axis).
 // ---------------------------------------------------------------------------
+// Partners of more than max_sorted particles are read in cell order by the
+// interaction kernels and get no sorted list.
 __global__ void k_seg_need(const uint64_t* __restrict__ ent, int64_t ne, const uint32_t* __restrict__ ne_dev,
-                           uint32_t* __restrict__ need) {
+                           const Cell* __restrict__ cells, int max_sorted, uint32_t* __restrict__ need) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne || (ne_dev && e >= (int64_t)*ne_dev)) return;
     uint64_t k = ent[e];
     if (k == ~0ull) return;   // self entry
     int src = (int)((k >> CSR_SRC_SHIFT) & 0xFFFFFFFFull);
+    if (cells[src].count > max_sorted) return;
     int sg;
     int ax = axis_of((int)(k & 31), &sg);
     need[(int64_t)src * NAXES + ax] = 1u;
@@ -874,7 +877,6 @@ __global__ void k_seg_need(const uint64_t* __restrict__ ent, int64_t ne, const u
 
 // Long lists up to this length are sorted in LDS by one block each; longer
 // ones by the global radix sort.
-constexpr int SEG_LARGE_MAX = 16384;
 
 // Per (cell, axis) list: its length where some pair entry needs it (0
 // elsewhere), and its sort class: 65..SEG_LDS_MAX entries (a wave or a block
@@ -1818,6 +1820,9 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     // (and whose 13 n entries cannot reach 2^32: past that the total is read
     // back to be checked)
     const bool flat = t->nlevels == 1 && t->max_leaf <= 64 && (int64_t)NAXES * t->n < ((int64_t)1 << 32);
+    // partners longer than the LDS sorts take are read in cell order where
+    // the kernels can (not with SPH_FLAG_SORTED_ONLY)
+    t->max_sorted = t->ext() && !(t->prm.flags & SPH_FLAG_SORTED_ONLY) ? SEG_LARGE_MAX : INT32_MAX;
     uint32_t* need = t->sc_a;
     uint32_t* mid_idx = t->sc_c;
     uint32_t* big_idx = t->sc_d;
@@ -1826,7 +1831,8 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     HIPTRY(fill_u32(t->d_counts + 8, 2, 0u, st));
     const int64_t ne = t->ncsr;
     if (ne > 0) {
-        hipLaunchKernelGGL(k_seg_need, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, t->ncsr_dev, need);
+        hipLaunchKernelGGL(k_seg_need, dim3(nblk(ne, 256)), dim3(256), 0, st, t->csr, ne, t->ncsr_dev, t->cells,
+                           t->max_sorted, need);
         HIPTRY(hipGetLastError());
     }
     if (nca > 0) {

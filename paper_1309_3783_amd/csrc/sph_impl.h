@@ -184,6 +184,7 @@ struct sph_tree {
     uint32_t* plist = nullptr;
     double* part = nullptr;
     int64_t npieces = 0, nheavy = 0;
+    int32_t max_sorted = INT32_MAX;   // partners with more particles have no sorted lists (read in cell order)
     // whether the interaction kernels need the code for heavy chunks and
     // cell-order reads: the tree has heavy chunks, or some partner cell may
     // hold SCAN_MIN particles (a one-level tree's partners are its leaves)

@@ -304,6 +304,7 @@ struct DensArgs {
     const uint32_t* segidx;
     const float4* blkbox;   // block boxes of the particle array (null: no cell is read in cell order)
     int cellord;            // long sweeps may read the partner in cell order
+    int max_sorted;         // partners of more particles have no sorted lists: always read in cell order
     int skip;               // ... passing over its blocks out of reach (0: test every record, same results)
     const uint32_t* pcount; // heavy chunks: pieces per chunk (0: handed out with the others)
     const uint32_t* plist;  // the pieces (chunk << 5 | piece), handed out first
@@ -509,6 +510,7 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
     float lim0 = 0.f, lim1 = 0.f;
     int code = 13;
     int bfirst = 0, bcount = 0;
+    bool unsorted = false;   // a partner without sorted lists, within reach
     if (lane < n) {
         const uint64_t key = a.csr[e0 + lane];
         const int B = (int)((key >> 5) & 0xFFFFFFFFull);
@@ -541,6 +543,21 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
         const float dr = 2.f * a.sets[cA.set].drift * g.dn;
         lim0 = tb + fmaf(P::cut(hmax, cB.hcur) * g.dn, 1.000002f, tiny) + dr;
         lim1 = tb + fmaf(P::cut(hmax, cB.hcur_l) * g.dn, 1.000002f, tiny) + dr;
+        if (EXT && cB.count > a.max_sorted) {
+            // a partner without sorted lists: read in cell order unless its
+            // cell lies wholly beyond the reach along the pair direction (its
+            // corner nearest the chunk, relative to its top cell, is exact)
+            const int l = cB.level;
+            const float e = ldexpf(L0, -l);
+            const float cx = (float)(cB.ix - ((cB.ix >> l) << l)) * e;
+            const float cy = (float)(cB.iy - ((cB.iy >> l) << l)) * e;
+            const float cz = (float)(cB.iz - ((cB.iz >> l) << l)) * e;
+            const float pmin = (ox > 0 ? cx + Dx : (ox < 0 ? -(cx + e + Dx) : 0.f)) +
+                               (oy > 0 ? cy + Dy : (oy < 0 ? -(cy + e + Dy) : 0.f)) +
+                               (oz > 0 ? cz + Dz : (oz < 0 ? -(cz + e + Dz) : 0.f));
+            unsorted = pmin <= fmaxf(lim0, lim1) + tiny;
+            q0.y = q1.y = 0;
+        }
     }
     // the swept prefix of each part: the first record (in sweep order)
     // beyond the limit, by bisection
@@ -561,7 +578,7 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
     // partner itself is read in cell order instead, as one part with the
     // larger radius: the blocks of it beyond the chunk's reach are then
     // passed over (skip_blocks)
-    const bool scan = EXT && a.cellord && c0 + c1 >= SCAN_MIN && bcount <= SCAN_RATIO * (c0 + c1);
+    const bool scan = EXT && a.cellord && (unsorted || (c0 + c1 >= SCAN_MIN && bcount <= SCAN_RATIO * (c0 + c1)));
     if (scan) {
         q0 = make_int4(bfirst, bcount, 0, 0);
         f0.w = fmaxf(f0.w, f1.w);
@@ -1093,6 +1110,7 @@ struct ForceArgs {
     const uint32_t* segidx;
     const float4* blkbox;   // block boxes of the particle array (null: no cell is read in cell order)
     int cellord;            // long sweeps may read the partner in cell order
+    int max_sorted;         // partners of more particles have no sorted lists: always read in cell order
     int skip;               // ... passing over its blocks out of reach (0: test every record, same results)
     const uint32_t* pcount; // heavy chunks: pieces per chunk (0: handed out with the others)
     const uint32_t* plist;  // the pieces (chunk << 5 | piece), handed out first
@@ -1848,6 +1866,7 @@ static DensArgs dens_args(sph_tree* t, int* counter, const int* lcount) {
     a.segpos = t->segpos;
     a.blkbox = t->blkbox;
     a.cellord = t->blkbox && !(t->prm.flags & SPH_FLAG_SORTED_ONLY);
+    a.max_sorted = t->max_sorted;
     a.skip = a.cellord && !(t->prm.flags & SPH_FLAG_NO_BLOCK_SKIP);
     a.pcount = t->pcount;
     a.plist = t->plist;
@@ -1948,6 +1967,7 @@ static void launch_force(sph_ctx* ctx, sph_tree* t, int* counter) {
     a.segpos = t->segpos;
     a.blkbox = t->blkbox;
     a.cellord = t->blkbox && !(t->prm.flags & SPH_FLAG_SORTED_ONLY);
+    a.max_sorted = t->max_sorted;
     a.skip = a.cellord && !(t->prm.flags & SPH_FLAG_NO_BLOCK_SKIP);
     a.pcount = t->pcount;
     a.plist = t->plist;

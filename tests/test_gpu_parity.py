@@ -102,10 +102,13 @@ def test_deep_refinement(sph, ctx):
     assert st["levels"] >= 4, st
 
 
-def test_large_cells_use_long_list_sorts(sph, ctx):
+@pytest.mark.parametrize("sorted_only", [True, False])
+def test_large_cells_use_long_list_sorts(sph, ctx, sorted_only):
     # two top cells per side, no refinement: (cell, axis) lists of ~5000
     # particles (set 0: one block each, sorted in LDS) and of ~20000 (set 1:
-    # past the LDS sorts, through the global radix sort), in one batch
+    # past the LDS sorts: through the global radix sort with
+    # SPH_FLAG_SORTED_ONLY, else read in cell order without sorted lists),
+    # in one batch
     sets, hs = [], []
     for n, seed in ((40000, 8), (160000, 9)):
         ps = sphinputs.uniform(n, seed, velocity=True)
@@ -113,9 +116,12 @@ def test_large_cells_use_long_list_sorts(sph, ctx):
         ps = I.redraw_ties_uniform(ps, h0, seed=100 + seed)
         sets.append(ps)
         hs.append(h0)
-    res, tree = run_fixed(sph, ctx, sets, hs, top_grid=2, n_split=1 << 30)
+    flags = sph.SPH_FLAG_SORTED_ONLY if sorted_only else 0
+    res, tree = run_fixed(sph, ctx, sets, hs, flags=flags, top_grid=2, n_split=1 << 30)
     st = tree.stats()
     assert st["top_grid"] == 2 and st["max_leaf"] > 16384, st
+    # set 1's 8 x 13 lists of ~20000 entries are sorted or absent
+    assert (st["sorted_entries"] > 13 * 160000) == sorted_only, st
     for ps, h, (g, gf) in zip(sets, hs, res):
         assert ps.n / 8 > 4096
         rd, rf = I.oracle_reference(ps, h)
