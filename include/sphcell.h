@@ -236,8 +236,12 @@ sph_status sph_build_cells_static(sph_ctx* ctx, sph_tree* t, const sph_input* in
  * source side of a pair task, the particle indices sorted by their
  * projection on the task's cell-pair axis (one of 13 directions), stored per
  * (cell, axis) and reused by every density and force pass until the next
- * build.  Synchronises the stream once, to read the list sizes back; the
- * sorts themselves are enqueued after that and not waited for. */
+ * build.  In a tree with more than one level, or with a leaf of 256
+ * particles or more, a cell of more than 4096 particles gets no lists
+ * (unless SPH_FLAG_SORTED_ONLY): the passes read it in cell order, past its
+ * 64-particle blocks out of reach.  Synchronises the stream once, to read
+ * the list sizes back; the sorts themselves are enqueued after that and not
+ * waited for. */
 sph_status sph_sort_pairs(sph_ctx* ctx, sph_tree* t);
 
 /* Section II-C, last paragraph (the sorted indices reused over several time

@@ -1820,9 +1820,11 @@ Err sort_pairs(sph_ctx* ctx, sph_tree* t) {
     // (and whose 13 n entries cannot reach 2^32: past that the total is read
     // back to be checked)
     const bool flat = t->nlevels == 1 && t->max_leaf <= 64 && (int64_t)NAXES * t->n < ((int64_t)1 << 32);
-    // partners longer than the LDS sorts take are read in cell order where
-    // the kernels can (not with SPH_FLAG_SORTED_ONLY)
-    t->max_sorted = t->ext() && !(t->prm.flags & SPH_FLAG_SORTED_ONLY) ? SEG_LARGE_MAX : INT32_MAX;
+    // partners longer than a block's LDS sort takes are read in cell order
+    // where the kernels can (not with SPH_FLAG_SORTED_ONLY): on a clustered
+    // set with h over three decades this halves the sort stage and leaves
+    // the interaction passes as they were (from 1024 they slow down)
+    t->max_sorted = t->ext() && !(t->prm.flags & SPH_FLAG_SORTED_ONLY) ? SEG_LDS_MAX : INT32_MAX;
     uint32_t* need = t->sc_a;
     uint32_t* mid_idx = t->sc_c;
     uint32_t* big_idx = t->sc_d;

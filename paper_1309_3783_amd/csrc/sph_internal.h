@@ -20,7 +20,7 @@ constexpr int CHUNK = 64;             // target particles per work item (one wav
 constexpr int PIECE_MAX = 16;         // pieces a heavy chunk is split into at most
 constexpr int PART_WORDS = 8;         // partial sums of a particle in one piece (doubles)
 constexpr int SCAN_MIN = 256;         // swept records from which a partner may be read in cell order
-constexpr int SEG_LARGE_MAX = 16384;  // longest list sorted in LDS (longer: radix sort, or read in cell order)
+constexpr int SEG_LARGE_MAX = 16384;  // longest list sorted in LDS (longer: radix sort)
 constexpr int SMALL_H_DIV = 8;        // sorted lists split at h = cell edge / 8
 
 // Orders a wavefront's LDS writes before its later LDS reads (the wave runs

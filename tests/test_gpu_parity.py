@@ -105,10 +105,10 @@ def test_deep_refinement(sph, ctx):
 @pytest.mark.parametrize("sorted_only", [True, False])
 def test_large_cells_use_long_list_sorts(sph, ctx, sorted_only):
     # two top cells per side, no refinement: (cell, axis) lists of ~5000
-    # particles (set 0: one block each, sorted in LDS) and of ~20000 (set 1:
-    # past the LDS sorts: through the global radix sort with
-    # SPH_FLAG_SORTED_ONLY, else read in cell order without sorted lists),
-    # in one batch
+    # particles (set 0) and of ~20000 (set 1), in one batch.  With
+    # SPH_FLAG_SORTED_ONLY set 0's are sorted in LDS by one block each and
+    # set 1's go through the global radix sort; by default partners of more
+    # than 4096 particles have no sorted lists and are read in cell order
     sets, hs = [], []
     for n, seed in ((40000, 8), (160000, 9)):
         ps = sphinputs.uniform(n, seed, velocity=True)
