@@ -165,7 +165,7 @@ sph_status sph_ctx_sync(sph_ctx* ctx);
  * the two stages' inputs and outputs plus the decomposition of Section II-B
  * and the sorted lists of Section II-C): an estimate for sets like uniform,
  * lattice and clumpy mixtures with up to ~3 decades of h (per particle:
- * ~275 B of particle state, ~580 B of sorted lists, ~240 B of radix scratch
+ * ~323 B of particle state, ~580 B of sorted lists, ~240 B of radix scratch
  * for the longest lists, ~120 B of cells, tasks and interaction lists, ~60 B
  * of partial sums of split heavy chunks; plus 4 KiB per set and 24 MiB).  The need depends
  * on the data; a build that finds the workspace too small fails with
@@ -222,7 +222,7 @@ sph_status sph_build_cells(sph_ctx* ctx, sph_tree* t, const sph_input* in, const
  * device array of 128 MiB per GPU, held until the process ends -- so that
  * neither this call nor the later calls on the tree (sort, density, solve,
  * force) allocate.  Sets needing more than the scratch holds
- * (sph_workspace_size above 128 MiB, roughly 85 000 particles) are refused
+ * (sph_workspace_size above 128 MiB, roughly 82 000 particles) are refused
  * with SPH_E_CAPACITY; a build that still runs out fails with
  * SPH_E_WORKSPACE.  One tree per GPU can hold the scratch: the calls of a
  * tree that held it before another tree took it fail with SPH_E_STATE (build

@@ -162,8 +162,9 @@ sph_status sph_workspace_size(int64_t n, int32_t nsets, const sph_params* p, siz
     (void)p;
     // Per particle: 124 B of cell-ordered state (keys and values twice,
     // permutations, position and remainder, velocity, h, u, bounds, pair-hash
-    // terms), 28 B density, 13 B solve, 52 B force, 41 B saved Newton state,
-    // 16 B of radix and scan scratch: ~275 B.  Sorted lists: 20 B per entry,
+    // terms), 48 B of the caller's data packed for the gather, 28 B density,
+    // 13 B solve, 52 B force, 41 B saved Newton state, 16 B of radix and
+    // scan scratch: ~323 B.  Sorted lists: 20 B per entry,
     // 13 entries per particle and tree level that holds pair tasks (29 per
     // particle on a clustered set with h over three decades: 580 B), plus
     // 24 B of radix keys and values per entry of the lists longer than
@@ -172,8 +173,8 @@ sph_status sph_workspace_size(int64_t n, int32_t nsets, const sph_params* p, siz
     // piece, ~37 B per particle on the clustered mixture (a piece per ~110
     // particles): 60 B.  Plus the set tables and a fixed reserve.  Measured
     // peaks: 548 B per particle on a 10^6 lattice, 1169 B on the 8*10^6
-    // clustered mixture.
-    const double per = 275.0 + 580.0 + 240.0 + 120.0 + 60.0;
+    // clustered mixture, before the packed records.
+    const double per = 323.0 + 580.0 + 240.0 + 120.0 + 60.0;
     *bytes = (size_t)(per * (double)n) + (size_t)nsets * 4096 + ((size_t)24 << 20);
     return SPH_OK;
 }

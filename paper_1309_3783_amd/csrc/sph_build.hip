@@ -130,28 +130,47 @@ __device__ inline int64_t fine_coord(double x, double box, int64_t R) {
     return k < 0 ? 0 : (k >= R ? R - 1 : k);
 }
 
+// The caller's particle data of one particle, packed in caller order (so
+// that the gather into cell order reads one 48-byte record per particle
+// instead of nine scattered words).
+struct InRec {
+    double x, y, z;
+    float h, m, u, vx, vy, vz;
+};
+static_assert(sizeof(InRec) == 48, "packed input record");
+
 __global__ void k_keys(const SetInfo* sets, int nsets, int64_t n, const double* __restrict__ x,
-                       const double* __restrict__ y, const double* __restrict__ z, int bmax,
-                       uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+                       const double* __restrict__ y, const double* __restrict__ z, const float* __restrict__ h,
+                       const float* __restrict__ m, const float* __restrict__ u, const float* __restrict__ vx,
+                       const float* __restrict__ vy, const float* __restrict__ vz, int bmax,
+                       uint64_t* __restrict__ key, uint32_t* __restrict__ val, InRec* __restrict__ rec) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int s = set_of_particle(sets, nsets, i);
     const SetInfo S = sets[s];
     int64_t R = (int64_t)1 << (S.lgG + S.depth);
-    uint64_t ix = (uint64_t)fine_coord(x[i], S.box, R);
-    uint64_t iy = (uint64_t)fine_coord(y[i], S.box, R);
-    uint64_t iz = (uint64_t)fine_coord(z[i], S.box, R);
+    const double xi = x[i], yi = y[i], zi = z[i];
+    uint64_t ix = (uint64_t)fine_coord(xi, S.box, R);
+    uint64_t iy = (uint64_t)fine_coord(yi, S.box, R);
+    uint64_t iz = (uint64_t)fine_coord(zi, S.box, R);
     key[i] = ((uint64_t)s << (3 * bmax)) | (morton3(ix, iy, iz) << S.key_shift);
     val[i] = (uint32_t)i;
+    InRec r;
+    r.x = xi;
+    r.y = yi;
+    r.z = zi;
+    r.h = h[i];
+    r.m = m[i];
+    r.u = u[i];
+    r.vx = vx[i];
+    r.vy = vy[i];
+    r.vz = vz[i];
+    rec[i] = r;
 }
 
 __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
                          const uint64_t* __restrict__ key, const uint32_t* __restrict__ val,
-                         const double* __restrict__ x, const double* __restrict__ y,
-                         const double* __restrict__ z, const float* __restrict__ h,
-                         const float* __restrict__ m, const float* __restrict__ u,
-                         const float* __restrict__ vx, const float* __restrict__ vy,
-                         const float* __restrict__ vz, float slack, float4* __restrict__ pos,
+                         const InRec* __restrict__ rec, float slack, float4* __restrict__ pos,
                          float4* __restrict__ plo, float* __restrict__ ph, float* __restrict__ hdec, float* __restrict__ pu,
                          float4* __restrict__ pv, uint32_t* __restrict__ perm, uint32_t* __restrict__ iperm,
                          uint64_t* __restrict__ mix) {
@@ -161,7 +180,8 @@ __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
     int s = nsets > 1 ? (int)(key[p] >> (3 * bmax)) : 0;
     const SetInfo S = sets[s];
     int64_t R = (int64_t)1 << (S.lgG + S.depth);
-    double xs[3] = {x[i], y[i], z[i]};
+    const InRec r = rec[i];
+    double xs[3] = {r.x, r.y, r.z};
     float o[3], lo[3];
     for (int d = 0; d < 3; ++d) {
         double w = xs[d] - S.box * floor(xs[d] / S.box);
@@ -173,13 +193,13 @@ __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
         o[d] = (float)off;
         lo[d] = (float)(off - (double)o[d]);
     }
-    pos[p] = make_float4(o[0], o[1], o[2], m[i]);
+    pos[p] = make_float4(o[0], o[1], o[2], r.m);
     plo[p] = make_float4(lo[0], lo[1], lo[2], 0.f);
-    float hh = h[i];
+    const float hh = r.h;
     ph[p] = hh;
     hdec[p] = hh * (1.0f + slack);
-    pu[p] = u[i];
-    pv[p] = make_float4(vx[i], vy[i], vz[i], 0.f);
+    pu[p] = r.u;
+    pv[p] = make_float4(r.vx, r.vy, r.vz, 0.f);
     perm[p] = i;
     iperm[i] = (uint32_t)p;
     mix[p] = splitmix64((uint64_t)((int64_t)i - S.first));
@@ -1484,9 +1504,11 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
     ERRTRY(t->alloc(t->b_mix, sizeof(uint64_t) * nn, (void**)&t->mix));
     ERRTRY(t->alloc(t->b_rs, sizeof(uint32_t) * std::max(radix_tmp_words(nn), radix_tmp_words(1 << 20)),
                     (void**)&t->rs_tmp));
+    InRec* rec;
+    ERRTRY(t->alloc(t->b_inrec, sizeof(InRec) * nn, (void**)&rec));
     if (n > 0) {
-        hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, in->x, in->y, in->z, bmax,
-                           t->key2, t->val2);
+        hipLaunchKernelGGL(k_keys, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, in->x, in->y, in->z, in->h,
+                           in->m, in->u, in->vx, in->vy, in->vz, bmax, t->key2, t->val2, rec);
         HIPTRY(hipGetLastError());
         bool alt = false;
         HIPTRY(radix_sort(t->key2, t->val2, t->key, t->val, n, t->key_bits, t->rs_tmp, st, &alt));
@@ -1497,8 +1519,8 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
             std::swap(t->b_val, t->b_val2);
         }
         hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, st, d_sets, S, n, bmax, t->key,
-                           t->val, in->x, in->y, in->z, in->h, in->m, in->u, in->vx, in->vy, in->vz,
-                           prm->h_slack, t->pos, t->plo, t->ph, t->hdec, t->pu, t->pv, t->perm, t->iperm, t->mix);
+                           t->val, rec, prm->h_slack, t->pos, t->plo, t->ph, t->hdec, t->pu, t->pv, t->perm,
+                           t->iperm, t->mix);
         HIPTRY(hipGetLastError());
     }
 

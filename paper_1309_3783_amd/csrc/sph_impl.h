@@ -139,7 +139,7 @@ struct sph_tree {
     sph::DevBuf b_sets, b_small, b_key, b_key2, b_val, b_val2, b_perm, b_pos, b_plo, b_pv, b_ph, b_hdec, b_pu,
         b_bound, b_mix, b_rs, b_cell, b_taskA, b_taskB, b_final, b_chunk, b_csr, b_csr2, b_csroff,
         b_segoff, b_seglist, b_segproj, b_segidx, b_bigk, b_bigv, b_sc, b_dens, b_force, b_solve,
-        b_red, b_misc, b_saved, b_split, b_counts, b_iperm, b_owned, b_blk, b_piece, b_plist, b_part;
+        b_red, b_misc, b_saved, b_split, b_counts, b_iperm, b_owned, b_blk, b_piece, b_plist, b_part, b_inrec;
 
     // ---- sizes (host) --------------------------------------------------
     int64_t ncells = 0, ntasks = 0, npairs = 0, nsegent = 0, nchunks = 0, max_leaf = 0;
@@ -241,7 +241,7 @@ struct sph_tree {
                 &b_pu, &b_bound, &b_mix, &b_rs, &b_cell, &b_taskA, &b_taskB, &b_final, &b_chunk, &b_csr,
                 &b_csr2, &b_csroff, &b_segoff, &b_seglist, &b_segproj, &b_segidx, &b_bigk, &b_bigv, &b_sc,
                 &b_dens, &b_force, &b_solve, &b_red, &b_misc, &b_saved, &b_split, &b_counts, &b_iperm, &b_owned,
-                &b_blk, &b_piece, &b_plist, &b_part};
+                &b_blk, &b_piece, &b_plist, &b_part, &b_inrec};
     }
 
     // Drop every buffer (the tree must be built again).  Library-owned
