@@ -679,7 +679,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (the library has no multi-GPU path); --gpus must be 1"}))
         sys.exit(2)
     if args.config == "share":
         import paper_1309_3783_amd as sph
