@@ -95,7 +95,8 @@ typedef struct {
                               (at least 2 cells per side remain) (0) */
     int32_t piece_records; /* heavy chunks: a chunk whose walk is estimated to read at least this many
                               partner records is handed out before the others, split into 8 pieces
-                              (16 from twice as many records); 0 = 16384, -1 = off */
+                              (16 from twice as many records); 0 = 16384, -1 = off.  A tree on which
+                              the pieces would outnumber both its chunks and 4096 gets none */
     int32_t reserved[1];
 } sph_params;
 
