@@ -167,8 +167,9 @@ sph_status sph_ctx_sync(sph_ctx* ctx);
  * and the sorted lists of Section II-C): an estimate for sets like uniform,
  * lattice and clumpy mixtures with up to ~3 decades of h (per particle:
  * ~323 B of particle state, ~580 B of sorted lists, ~240 B of radix scratch
- * for the longest lists, ~120 B of cells, tasks and interaction lists, ~60 B
- * of partial sums of split heavy chunks; plus 4 KiB per set and 24 MiB).  The need depends
+ * for the longest lists, ~120 B of cells, tasks and interaction lists, up to
+ * 64 B of partial sums of split heavy chunks; plus 4 KiB per set and
+ * 24 MiB).  The need depends
  * on the data; a build that finds the workspace too small fails with
  * SPH_E_WORKSPACE and reports what it needs (sph_tree_workspace_needed).
  * sph_footprint(n, p) = sph_workspace_size(n, 1, p): the size admission
