@@ -2,12 +2,14 @@
 partner records are handed out first, and the heaviest are split into
 pieces over their pair entries whose partial sums are added in piece order.
 
-* with small pieces (many chunks split, up to 16 pieces each) the results
+* with a low threshold (4096 records: many chunks split, 8-16 pieces each)
+  the results
   match the oracle element by element (pair sets and counts bit-exact), and
   are bitwise the same run to run;
 * against no heavy-chunk handling (piece_records = -1): the same pair sets
   and counts, the sums to rounding; through the Newton solve of h as well;
-* a set of independent pieces inside a batch is bitwise the same as alone.
+* a set of independent pieces inside a batch is bitwise the same as alone;
+* a tree whose pieces would outnumber its chunks gets none.
 """
 import os
 import sys
@@ -47,7 +49,7 @@ def _clump():
 
 def test_split_chunks_against_oracle(sph, ctx):
     ps, h = _clump()
-    g, rd, rf, tree = full_check(sph, ctx, ps, h, piece_records=512)
+    g, rd, rf, tree = full_check(sph, ctx, ps, h, piece_records=4096)
     st = tree.stats()
     print(f"heavy chunks {st['heavy_chunks']}, pieces {st['pieces']} of {st['chunks']} chunks")
     assert st["pieces"] > st["heavy_chunks"] > 0
@@ -55,8 +57,8 @@ def test_split_chunks_against_oracle(sph, ctx):
 
 def test_split_chunks_match_unsplit_and_repeat(sph, ctx):
     ps, h = _clump()
-    (a,), ta = run_fixed(sph, ctx, [ps], [h], piece_records=512)
-    (b,), _ = run_fixed(sph, ctx, [ps], [h], piece_records=512)
+    (a,), ta = run_fixed(sph, ctx, [ps], [h], piece_records=4096)
+    (b,), _ = run_fixed(sph, ctx, [ps], [h], piece_records=4096)
     (u,), tu = run_fixed(sph, ctx, [ps], [h], piece_records=-1)
     assert ta.stats()["pieces"] > 0 and tu.stats()["pieces"] == 0
     for k in a[0]:
@@ -85,7 +87,7 @@ def test_split_chunks_through_the_solve(sph, ctx):
     dout = sph.DensityOut(ps.n, "cuda")
     fout = sph.ForceOut(ps.n, 1, "cuda")
     tree = sph.Tree(ctx)
-    st, nu, it = sph.solve_with_rebuild(tree, batch, sph.params(piece_records=1024), dout)
+    st, nu, it = sph.solve_with_rebuild(tree, batch, sph.params(piece_records=4096), dout)
     assert st == sph.SPH_OK and nu == 0
     assert tree.stats()["pieces"] > 0
     tree.force(fout)
@@ -102,8 +104,8 @@ def test_split_set_in_a_batch_equals_alone(sph, ctx):
     ps, h = _clump()
     u = sphinputs.uniform(5000, 93, velocity=True)
     u, hu = I.fixed_h_case(u)
-    (alone,), t1 = run_fixed(sph, ctx, [ps], [h], piece_records=512)
-    res, t2 = run_fixed(sph, ctx, [u, ps], [hu, h], piece_records=512)
+    (alone,), t1 = run_fixed(sph, ctx, [ps], [h], piece_records=4096)
+    res, t2 = run_fixed(sph, ctx, [u, ps], [hu, h], piece_records=4096)
     assert t1.stats()["pieces"] > 0
     for k in alone[0]:
         assert np.array_equal(alone[0][k], res[1][0][k]), k
@@ -119,7 +121,7 @@ def test_refresh_with_split_chunks_and_cell_order(sph, ctx):
     from _checks import check_density, check_force
     ps0 = sphinputs.clump_by_face(8000, 30000, 94, velocity=True, snap=False)
     _, h0 = I.fixed_h_case(ps0)
-    prm = sph.params(flags=sph.SPH_FLAG_PAIR_HASH, h_slack=0.5, piece_records=512)
+    prm = sph.params(flags=sph.SPH_FLAG_PAIR_HASH, h_slack=0.5, piece_records=4096)
     tree = sph.Tree(ctx)
     tree.build_cells(sph.batch_from_sets([ps0], h=[h0]), prm)
     tree.sort_pairs()
@@ -142,3 +144,18 @@ def test_refresh_with_split_chunks_and_cell_order(sph, ctx):
     rd, rf = I.oracle_reference(ps, h)
     check_density(ps, h, g_d, rd)
     check_force(ps, g_f, rf)
+
+
+def test_pieces_bounded_by_the_chunks(sph, ctx):
+    # a threshold of 64 records makes nearly every chunk heavy, with 16
+    # pieces each: more pieces than chunks, so none are made and the
+    # results are those without heavy-chunk handling, bitwise
+    ps, h = _clump()
+    (a,), ta = run_fixed(sph, ctx, [ps], [h], piece_records=64)
+    (u,), _ = run_fixed(sph, ctx, [ps], [h], piece_records=-1)
+    st = ta.stats()
+    assert st["pieces"] == 0 and st["heavy_chunks"] == 0, st
+    for k in a[0]:
+        assert np.array_equal(a[0][k], u[0][k]), k
+    for k in a[1]:
+        assert np.array_equal(a[1][k], u[1][k]), k
