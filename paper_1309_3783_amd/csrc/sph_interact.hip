@@ -574,10 +574,10 @@ __device__ __forceinline__ int build_sweeps(const typename P::Args& a, const Cel
         return lo;
     };
     int c0 = prefix(q0, lim0), c1 = prefix(q1, lim1);
-    // a partner with a long swept prefix that is not much longer than the
-    // partner itself is read in cell order instead, as one part with the
-    // larger radius: the blocks of it beyond the chunk's reach are then
-    // passed over (skip_blocks)
+    // a partner without sorted lists, or with a long swept prefix that is
+    // not much longer than the partner itself, is read in cell order
+    // instead, as one part with the larger radius: the blocks of it beyond
+    // the chunk's reach are then passed over (skip_blocks)
     const bool scan = EXT && a.cellord && (unsorted || (c0 + c1 >= SCAN_MIN && bcount <= SCAN_RATIO * (c0 + c1)));
     if (scan) {
         q0 = make_int4(bfirst, bcount, 0, 0);
