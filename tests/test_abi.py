@@ -89,3 +89,37 @@ def test_workspace_size_host_only():
     assert L.sph_tree_set_workspace(None, None, None, 0) == binding.SPH_E_ARG
     assert L.sph_tree_workspace_needed(None, C.byref(out)) == binding.SPH_E_ARG
     assert L.sph_build_cells_static(None, None, None, None) == binding.SPH_E_ARG
+
+
+def _header_text():
+    return open(os.path.join(ROOT, "include", "sphcell.h")).read()
+
+
+def test_params_struct_matches_the_header():
+    # the ctypes mirror of sph_params lists the header's fields in order,
+    # with arrays of the same length
+    src = re.sub(r"/\*.*?\*/", "", _header_text(), flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\} sph_params;", src, flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        m = re.match(r"(\w+)\s+(\w+)(?:\[(\d+)\])?$", decl)
+        assert m, decl
+        fields.append((m.group(2), int(m.group(3)) if m.group(3) else 1))
+    mirror = [(n, getattr(t, "_length_", 1)) for n, t in binding.sph_params._fields_]
+    assert fields == mirror
+
+
+def test_flag_values_match_the_header():
+    defs = dict(re.findall(r"#define (SPH_FLAG_\w+) (\d+)u", _header_text()))
+    assert set(defs) == {"SPH_FLAG_PAIR_HASH", "SPH_FLAG_RESUME", "SPH_FLAG_NO_BLOCK_SKIP", "SPH_FLAG_SORTED_ONLY"}
+    for name, v in defs.items():
+        assert getattr(binding, name) == int(v), name
+
+
+def test_counters_reject_a_null_context():
+    L = sph.lib()
+    assert L.sph_last_work(None, None, None) == binding.SPH_E_ARG
+    assert L.sph_last_reads(None, None, None) == binding.SPH_E_ARG
