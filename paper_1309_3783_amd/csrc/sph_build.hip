@@ -168,6 +168,27 @@ __global__ void k_keys(const SetInfo* sets, int nsets, int64_t n, const double* 
     rec[i] = r;
 }
 
+// The same packing alone (a refresh: the keys are the build's).
+__global__ void k_pack_inputs(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                              const double* __restrict__ z, const float* __restrict__ h,
+                              const float* __restrict__ m, const float* __restrict__ u,
+                              const float* __restrict__ vx, const float* __restrict__ vy,
+                              const float* __restrict__ vz, InRec* __restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    InRec r;
+    r.x = x[i];
+    r.y = y[i];
+    r.z = z[i];
+    r.h = h[i];
+    r.m = m[i];
+    r.u = u[i];
+    r.vx = vx[i];
+    r.vy = vy[i];
+    r.vz = vz[i];
+    rec[i] = r;
+}
+
 __global__ void k_gather(const SetInfo* sets, int nsets, int64_t n, int bmax,
                          const uint64_t* __restrict__ key, const uint32_t* __restrict__ val,
                          const InRec* __restrict__ rec, float slack, float4* __restrict__ pos,
@@ -709,11 +730,7 @@ __global__ __launch_bounds__(256) void k_particle_bound(const int4* __restrict__
 constexpr int REFRESH_BLOCKS = 2048;
 __global__ __launch_bounds__(256) void k_refresh(const int4* __restrict__ chunks, const uint32_t* __restrict__ nch_dev,
                                                  const Cell* __restrict__ cells, const SetInfo* sets,
-                                                 const uint32_t* __restrict__ perm, const double* __restrict__ x,
-                                                 const double* __restrict__ y, const double* __restrict__ z,
-                                                 const float* __restrict__ h, const float* __restrict__ m,
-                                                 const float* __restrict__ u, const float* __restrict__ vx,
-                                                 const float* __restrict__ vy, const float* __restrict__ vz,
+                                                 const uint32_t* __restrict__ perm, const InRec* __restrict__ rec,
                                                  float slack, float4* __restrict__ pos, float4* __restrict__ plo,
                                                  float* __restrict__ ph, float* __restrict__ hdec,
                                                  float* __restrict__ pu, float4* __restrict__ pv,
@@ -729,8 +746,8 @@ __global__ __launch_bounds__(256) void k_refresh(const int4* __restrict__ chunks
         double d2 = 0.0;
         if (lane < ch.z) {
             const int64_t p = ch.y + lane;
-            const uint32_t i = perm[p];
-            const double xs[3] = {x[i], y[i], z[i]};
+            const InRec r = rec[perm[p]];
+            const double xs[3] = {r.x, r.y, r.z};
             const int tc[3] = {T.ix, T.iy, T.iz};
             const float4 o0 = pos[p], l0 = plo[p];
             const double old[3] = {(double)o0.x + (double)l0.x, (double)o0.y + (double)l0.y,
@@ -747,13 +764,13 @@ __global__ __launch_bounds__(256) void k_refresh(const int4* __restrict__ chunks
                 const double dd = off - old[d];
                 d2 += dd * dd;
             }
-            pos[p] = make_float4(o[0], o[1], o[2], m[i]);
+            pos[p] = make_float4(o[0], o[1], o[2], r.m);
             plo[p] = make_float4(lo[0], lo[1], lo[2], 0.f);
-            const float hh = h[i];
+            const float hh = r.h;
             ph[p] = hh;
             hdec[p] = hh * (1.0f + slack);
-            pu[p] = u[i];
-            pv[p] = make_float4(vx[i], vy[i], vz[i], 0.f);
+            pu[p] = r.u;
+            pv[p] = make_float4(r.vx, r.vy, r.vz, 0.f);
         }
         // rounded up so that the bound stays a bound
         float dm = (float)sqrt(d2);
@@ -1798,9 +1815,16 @@ Err refresh_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in) {
     HIPTRY(fill_u32(stepmax, S + 1, 0u, st));
     HIPTRY(fill_u32(nchw, 1, (uint32_t)t->nchunks, st));
     const unsigned gch = (unsigned)std::min<int64_t>(nblk(t->nchunks, 4), 8192);
-    hipLaunchKernelGGL(k_refresh, dim3((unsigned)std::min<int64_t>(gch, REFRESH_BLOCKS)), dim3(256), 0, st, t->chunks, nchw, t->cells, t->d_sets, t->perm, in->x,
-                       in->y, in->z, in->h, in->m, in->u, in->vx, in->vy, in->vz, t->prm.h_slack, t->pos, t->plo,
-                       t->ph, t->hdec, t->pu, t->pv, stepmax);
+    // the caller's data packed in caller order first (one record per
+    // particle for the refresh's reads in cell order)
+    InRec* rec = (InRec*)t->b_inrec.p;
+    if (!rec || t->b_inrec.cap < sizeof(InRec) * (size_t)n) return Err{SPH_E_STATE, "refresh: no build to refresh"};
+    hipLaunchKernelGGL(k_pack_inputs, dim3(nblk(n, 256)), dim3(256), 0, st, n, in->x, in->y, in->z, in->h, in->m,
+                       in->u, in->vx, in->vy, in->vz, rec);
+    HIPTRY(hipGetLastError());
+    hipLaunchKernelGGL(k_refresh, dim3((unsigned)std::min<int64_t>(gch, REFRESH_BLOCKS)), dim3(256), 0, st, t->chunks,
+                       nchw, t->cells, t->d_sets, t->perm, rec, t->prm.h_slack, t->pos, t->plo, t->ph, t->hdec, t->pu,
+                       t->pv, stepmax);
     HIPTRY(hipGetLastError());
     hipLaunchKernelGGL(k_drift_add, dim3(nblk(S, 256)), dim3(256), 0, st, t->d_sets, S, stepmax);
     HIPTRY(hipGetLastError());
