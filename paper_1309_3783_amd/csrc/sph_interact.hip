@@ -2260,6 +2260,9 @@ Err run_graph(sph_ctx* ctx, sph_tree* t, int k_iter, const sph_density_out* dout
     val((uint64_t)t->ncells);
     val((uint64_t)t->nred);
     val((uint64_t)t->npieces);
+    // which kernels (with or without the heavy-chunk and cell-order code)
+    // and which partners have sorted lists
+    val((uint64_t)t->ext() | ((uint64_t)(uint32_t)t->max_sorted << 1));
     val(t->hash ? 1 : 0);
     val(fbits(t->prm.alpha) | (fbits(t->prm.gamma) << 32));
     val(t->prm.flags);
