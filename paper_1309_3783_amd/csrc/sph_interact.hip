@@ -1527,13 +1527,36 @@ __device__ __forceinline__ int first_red_chunk(const int4* __restrict__ red, int
     return lo;
 }
 
-// ... then per set (status[3 + 2s]) and in total (status[1]): one block, one wavefront per set in turn, lanes
-// striding over the set's chunks; integer sums, written (not accumulated).
+// ... then per set (status[3 + 2s]) and in total (status[1]): one block;
+// with few sets the whole block sums each set in turn, otherwise one
+// wavefront per set, lanes striding over the set's chunks; integer sums,
+// written (not accumulated).
 constexpr int COUNT_BS = 1024;
 __global__ __launch_bounds__(COUNT_BS) void k_count_final(const int4* __restrict__ red, int nred,
                                                           const int32_t* __restrict__ part, int nsets,
                                                           int32_t* __restrict__ status) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ int s_w[COUNT_BS / 64];
+    if (nsets <= COUNT_BS / 64) {
+        int tot = 0;   // (thread 0)
+        for (int s = 0; s < nsets; ++s) {
+            const int r0 = first_red_chunk(red, nred, s);
+            int c = 0;
+            for (int r = r0 + (int)threadIdx.x; r < nred && red[r].x == s; r += COUNT_BS) c += part[r];
+            for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+            if (lane == 0) s_w[w] = c;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int t = 0;
+                for (int k = 0; k < COUNT_BS / 64; ++k) t += s_w[k];
+                status[3 + 2 * s] = t;
+                tot += t;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) status[1] = tot;
+        return;
+    }
     int tot = 0;
     for (int s = w; s < nsets; s += COUNT_BS / 64) {
         int c = 0;
@@ -1544,12 +1567,11 @@ __global__ __launch_bounds__(COUNT_BS) void k_count_final(const int4* __restrict
         if (lane == 0) status[3 + 2 * s] = c;
         tot += c;
     }
-    __shared__ int s_t[COUNT_BS / 64];
-    if (lane == 0) s_t[w] = tot;
+    if (lane == 0) s_w[w] = tot;
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
-        for (int k = 0; k < COUNT_BS / 64; ++k) t += s_t[k];
+        for (int k = 0; k < COUNT_BS / 64; ++k) t += s_w[k];
         status[1] = t;
     }
 }
