@@ -96,7 +96,8 @@ typedef struct {
     int32_t piece_records; /* heavy chunks: a chunk whose walk is estimated to read at least this many
                               partner records is handed out before the others, split into 8 pieces
                               (16 from twice as many records); 0 = 16384, -1 = off.  A tree on which
-                              the pieces would outnumber both its chunks and 4096 gets none */
+                              there would be more than one piece per 64 particles and more
+                              than 4096 pieces gets none */
     int32_t reserved[1];
 } sph_params;
 

@@ -171,7 +171,8 @@ sph_status sph_workspace_size(int64_t n, int32_t nsets, const sph_params* p, siz
     // 16384 (about 10 per particle there: 240 B).  Cells, tasks and
     // interaction lists: ~120 B.  Heavy chunks: 4 KiB of partial sums per
     // piece, ~37 B per particle on the clustered mixture (a piece per ~110
-    // particles), at most 64 B (no more pieces than chunks): 64 B.  Plus the set tables and a fixed reserve.  Measured
+    // particles), at most 64 B (one piece per 64 particles; 16 MiB on small
+    // sets, inside the fixed reserve): 64 B.  Plus the set tables and a fixed reserve.  Measured
     // peaks: 548 B per particle on a 10^6 lattice, 1169 B on the 8*10^6
     // clustered mixture, before the packed records.
     const double per = 323.0 + 580.0 + 240.0 + 120.0 + 64.0;

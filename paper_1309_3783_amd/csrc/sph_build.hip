@@ -1761,11 +1761,12 @@ Err build_tree(sph_ctx* ctx, sph_tree* t, const sph_input* in, const sph_params*
         t->npieces = ((const uint32_t*)rb)[0];
         t->nheavy = ((const uint32_t*)rb)[1];
     }
-    // the partial sums take 4 KiB per piece: a set on which pieces would
-    // outnumber the chunks (every chunk heavy: leaves far above the split
-    // size) is handed out without them, which bounds them by 64 B per
-    // particle
-    if (t->npieces > std::max<int64_t>((int64_t)nchunks, 4096)) {
+    // the partial sums take 4 KiB per piece: a tree on which there would be
+    // more than one piece per 64 particles (most chunks heavy: leaves far
+    // above the split size, or a threshold far below it) is handed out
+    // without them, which bounds them by 64 B per particle (16 MiB on sets
+    // below 262144 particles)
+    if (t->npieces > std::max<int64_t>(t->n / CHUNK, 4096)) {
         HIPTRY(fill_u32(t->pcount, chunk_cap, 0u, st));
         t->npieces = 0;
         t->nheavy = 0;

@@ -9,7 +9,7 @@ pieces over their pair entries whose partial sums are added in piece order.
 * against no heavy-chunk handling (piece_records = -1): the same pair sets
   and counts, the sums to rounding; through the Newton solve of h as well;
 * a set of independent pieces inside a batch is bitwise the same as alone;
-* a tree whose pieces would outnumber its chunks gets none.
+* a tree with more pieces than one per 64 particles (and than 4096) gets none.
 """
 import os
 import sys
@@ -146,10 +146,11 @@ def test_refresh_with_split_chunks_and_cell_order(sph, ctx):
     check_force(ps, g_f, rf)
 
 
-def test_pieces_bounded_by_the_chunks(sph, ctx):
+def test_pieces_bounded_per_particle(sph, ctx):
     # a threshold of 64 records makes nearly every chunk heavy, with 16
-    # pieces each: more pieces than chunks, so none are made and the
-    # results are those without heavy-chunk handling, bitwise
+    # pieces each: ~12000 pieces for 38000 particles, above both 38000/64
+    # and 4096, so none are made and the results are those without
+    # heavy-chunk handling, bitwise
     ps, h = _clump()
     (a,), ta = run_fixed(sph, ctx, [ps], [h], piece_records=64)
     (u,), _ = run_fixed(sph, ctx, [ps], [h], piece_records=-1)
