@@ -63,7 +63,7 @@ typedef struct sph_tree sph_tree;
 
 /* Flags for sph_params.flags */
 #define SPH_FLAG_PAIR_HASH 1u   /* also accumulate the pair-set hashes */
-#define SPH_FLAG_RESUME 2u      /* sph_solve_h after this build continues the Newton state saved when
+#define SPH_FLAG_RESUME 2u      /* sph_solve_h on a tree built with it continues the Newton state saved when
                                    the previous sph_solve_h on the same tree returned SPH_E_REBUILD
                                    (same particles); converged particles keep their density */
 #define SPH_FLAG_NO_BLOCK_SKIP 4u /* read every particle of a partner read in cell order instead of
