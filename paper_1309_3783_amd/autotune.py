@@ -40,7 +40,8 @@ def load_table() -> dict:
         try:
             with open(TABLE) as fh:
                 return json.load(fh)
-        except Exception:
+        except (OSError, ValueError):
+            # unreadable or half-written table: tune again
             return {}
     return {}
 
