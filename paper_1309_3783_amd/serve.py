@@ -83,6 +83,7 @@ class Scheduler:
 
     def admit(self, queue: collections.deque, lane: int = 0) -> list:
         chosen, free = [], self.budget - self.charged(lane)
+        head_waits = False
         for r in list(queue):
             if len(chosen) >= self.max_batch:
                 break
@@ -93,9 +94,12 @@ class Scheduler:
                 chosen.append(r)
                 free -= fp
             elif r is queue[0] and not chosen:
-                self.skips[r.rid] = self.skips.get(r.rid, 0) + 1
-                if self.skips[r.rid] > self.max_bypass:
-                    break                 # stop bypassing: wait for the head
+                if self.skips.get(r.rid, 0) >= self.max_bypass:
+                    break                 # bypassed often enough: wait for the head
+                head_waits = True
+        if head_waits and chosen:
+            # a bypass is counted only when requests behind the head go first
+            self.skips[queue[0].rid] = self.skips.get(queue[0].rid, 0) + 1
         for r in chosen:
             queue.remove(r)
         return chosen

@@ -84,3 +84,18 @@ def test_retained_lane_memory_is_charged():
     assert max(u for _, _, u in sch.log) <= 600_000
     assert [n for _, n, _ in sch.log[:2]] == [4, 2]
     assert len(sch.log) > 2 and max(n for _, n, _ in sch.log[2:]) <= 3
+
+
+def test_only_real_bypasses_count():
+    # A (600) runs on one lane until t = 0.6; B (900) waits from t = 0.001,
+    # alone in the queue at first (not a bypass).  Small requests arriving at
+    # 0.1, 0.25 and 0.4 (0.1 s each on the other lane) may go before B twice
+    # (max_bypass = 2); the third waits for B.
+    reqs = make([600, 900, 100, 100, 100], [0.0, 0.001, 0.1, 0.25, 0.4])
+    sch = Scheduler(FakeExecutor(lanes=2, base=0.0, per_particle=1e-3), budget_bytes=1000 * 100,
+                    footprint=fp, max_batch=1, max_bypass=2)
+    sch.run(reqs)
+    big = reqs[1]
+    assert [r.rid for r in reqs[2:] if r.t_start < big.t_start] == [2, 3]
+    assert big.t_start == 0.6 and reqs[4].t_start >= big.t_start
+    assert all(r.t_done > 0 for r in reqs)
