@@ -104,8 +104,9 @@ def measured_traffic(kernel, workload):
     if not os.path.exists(p):
         return None
     try:
-        d = json.load(open(p))
-    except Exception:
+        with open(p) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
         return None
     e = d.get("workloads", {}).get(workload, {}).get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
