@@ -1,7 +1,8 @@
-"""Host checks of the seeded input generators used by the GPU tests: the
-dense ball next to a top-cell face (the heavy-chunk and cell-order cases)
-is reproducible, lies where its recipe says, and its first-guess h follows
-the two number densities."""
+"""Host checks of the seeded input generators used by the GPU tests and
+the benchmark: the dense ball next to a top-cell face (the heavy-chunk and
+cell-order cases) and the Plummer-clump mixture (the multi-resolution
+workload) are reproducible, lie where their recipes say, and their
+first-guess h follows their number densities."""
 import numpy as np
 
 import sphinputs
@@ -28,3 +29,48 @@ def test_clump_by_face_recipe():
     assert np.allclose(a.h0[2000:], np.float32(h_bg / np.cbrt(ratio)), rtol=1e-6)
     # distinct positions
     assert len(np.unique(np.stack([a.x, a.y, a.z], axis=1), axis=0)) == a.n
+
+
+def test_plummer_mixture_recipe():
+    """One clump plus 20% background: reproducible; the clump's radii, drawn
+    by inverting its enclosed-mass fraction, follow the analytic number
+    density that gives the first-guess h (integrated over radial shells,
+    within Poisson noise), and that density integrates to the clump's
+    particle count."""
+    from scipy.integrate import simpson
+
+    n = 40000
+    a = sphinputs.plummer_mixture(n, 11, n_clumps=1)
+    b = sphinputs.plummer_mixture(n, 11, n_clumps=1)
+    for k in ("x", "y", "z", "h0"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+    n_bg, n_c = 8000, 32000
+    ac = float(a.meta["a"][0])
+    centre = np.array(a.meta["centre"][0])
+    rmax = min(20.0 * ac, 0.45)
+    pos = np.stack([a.x, a.y, a.z], axis=1)
+    assert pos.min() >= 0.0 and pos.max() < 1.0
+    d = pos[n_bg:] - centre
+    d -= np.round(d)
+    r = np.linalg.norm(d, axis=1)
+    assert r.max() <= rmax + 1e-6
+
+    def rho(rr):
+        pts = np.mod(centre + rr[:, None] * np.array([1.0, 0.0, 0.0]), 1.0)
+        return sphinputs.plummer_number_density(pts, n_bg, np.array([n_c]), np.array([ac]), np.array([rmax]),
+                                                centre[None, :]) - n_bg
+
+    def count(r0, r1):
+        rr = np.geomspace(max(r0, 1e-9 * rmax), r1, 4001)
+        return simpson(4.0 * np.pi * rr ** 2 * rho(rr), x=rr)
+
+    assert abs(count(0.0, rmax * (1 - 1e-12)) - n_c) < 1e-3 * n_c
+    edges = rmax * np.array([0.0, 0.02, 0.05, 0.1, 0.2, 0.4, 0.7, 1.0 - 1e-12])
+    for r0, r1 in zip(edges[:-1], edges[1:]):
+        exp = count(r0, r1)
+        got = np.count_nonzero((r >= r0) & (r < r1))
+        assert abs(got - exp) <= 5.0 * np.sqrt(exp) + 5.0, (r0, r1, got, exp)
+    # the first guess: h for the analytic density at each particle
+    dens = sphinputs.plummer_number_density(pos, n_bg, np.array([n_c]), np.array([ac]), np.array([rmax]),
+                                            centre[None, :])
+    assert np.array_equal(a.h0, np.float32(sphinputs.h_for_density(dens)).astype(np.float64))
