@@ -74,3 +74,25 @@ def test_plummer_mixture_recipe():
     dens = sphinputs.plummer_number_density(pos, n_bg, np.array([n_c]), np.array([ac]), np.array([rmax]),
                                             centre[None, :])
     assert np.array_equal(a.h0, np.float32(sphinputs.h_for_density(dens)).astype(np.float64))
+
+
+def test_jittered_lattice_recipe():
+    """The headline workload's generator (at 20^3): every particle within
+    the jitter of its own lattice point (periodic), positions on the 2^-24
+    grid and distinct, equal masses summing to one, and the first-guess h
+    that of the mean number density."""
+    ns, jit = 20, 0.1
+    a = sphinputs.lattice(ns, jit, 2)
+    assert a.n == ns ** 3
+    d = 1.0 / ns
+    g = (np.arange(ns) + 0.5) * d
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    base = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    pos = np.stack([a.x, a.y, a.z], axis=1)
+    off = pos - base
+    off -= np.round(off)
+    assert np.abs(off).max() <= jit * d + 2.0 ** -24
+    assert np.array_equal(pos * 2.0 ** 24, np.floor(pos * 2.0 ** 24))
+    assert len(np.unique(pos, axis=0)) == a.n
+    assert np.all(a.m == a.m[0]) and abs(a.m.sum() - 1.0) < 1e-6
+    assert np.all(a.h0 == np.float32(sphinputs.h_for_density(float(a.n))))
